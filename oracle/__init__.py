@@ -1,0 +1,161 @@
+"""FP64 CPU oracle for block-based pseudodifferential residual inpainting.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke``
+and by the ``cpu_baseline`` leg of ``bench.py``, never by the product
+package.  It shares no code with the GPU library and reads frames through the
+documented packed layout only (any object with ``width, height, fmt,
+block_size, chroma_shared, block_ptr, pos, values``).
+
+The C source ``pdinp_oracle.c`` holds two independent routes from the paper
+(Sec. 2.1-2.2): the plain definition, Eq. (1) solved per block, and the
+Green's-function route, Eqs. (2)-(4).  Both are pinned by ``tests/`` against
+facts the paper and the mathematics fix (closed forms, brute-force solves,
+textbook routines).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pdinp_oracle.c")
+LIB_PATH = os.path.join(_HERE, "_pdinp_oracle.so")
+_lock = threading.Lock()
+_lib_handle = None
+
+DIRECT = 0
+GREEN = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP, -O2, no fast-math)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def _lib():
+    global _lib_handle
+    with _lock:
+        if _lib_handle is None:
+            if not os.path.exists(LIB_PATH):
+                build(force=False)
+            L = ctypes.CDLL(LIB_PATH)
+            P = ctypes.c_void_p
+            i, d = ctypes.c_int, ctypes.c_double
+            L.orc_block_direct.argtypes = [i, i, i, i, P, P, P]
+            L.orc_block_direct.restype = i
+            L.orc_eigenvalues.argtypes = [i, i, i, d, P]
+            L.orc_eigenvalues.restype = None
+            L.orc_green_table.argtypes = [i, i, P, P]
+            L.orc_green_table.restype = None
+            L.orc_green.argtypes = [i, i, P, i, i, i, i]
+            L.orc_green.restype = d
+            L.orc_block_green.argtypes = [i, i, i, d, i, P, i, P, P, P, P]
+            L.orc_block_green.restype = i
+            L.orc_decode.argtypes = [i, i, i, i, P, P, P, i, i, i, d, P, i]
+            L.orc_decode.restype = i
+            _lib_handle = L
+    return _lib_handle
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def plane_dims(width: int, height: int, fmt: int) -> List[Tuple[int, int]]:
+    if fmt == 0:
+        return [(width, height)]
+    cw, ch = (width + 1) // 2, (height + 1) // 2
+    return [(width, height), (cw, ch), (cw, ch)]
+
+
+def block_direct(w: int, h: int, pos, r, s: int = 1) -> np.ndarray:
+    """Eq. (1) on one w x h block (plain definition); returns u as (h, w)."""
+    pos = np.ascontiguousarray(pos, dtype=np.uint16)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    u = np.zeros(w * h)
+    rc = _lib().orc_block_direct(w, h, int(s), int(pos.size), _ptr(pos), _ptr(r), _ptr(u))
+    if rc != 0:
+        raise ValueError("orc_block_direct failed")
+    return u.reshape(h, w)
+
+
+def eigenvalues(w: int, h: int, op: int = 0, s: float = 1.0) -> np.ndarray:
+    lam = np.zeros(w * h)
+    _lib().orc_eigenvalues(w, h, op, float(s), _ptr(lam))
+    return lam.reshape(h, w)
+
+
+def green_table(w: int, h: int, op: int = 0, s: float = 1.0) -> np.ndarray:
+    lam = np.ascontiguousarray(eigenvalues(w, h, op, s).ravel())
+    H = np.zeros((h + 1) * (w + 1))
+    _lib().orc_green_table(w, h, _ptr(lam), _ptr(H))
+    return H.reshape(h + 1, w + 1)
+
+
+def green_matrix(w: int, h: int, op: int = 0, s: float = 1.0) -> np.ndarray:
+    """The full N x N matrix G of one block shape, read from the table."""
+    H = np.ascontiguousarray(green_table(w, h, op, s).ravel())
+    L = _lib()
+    N = w * h
+    G = np.empty((N, N))
+    for a in range(N):
+        for b in range(N):
+            G[a, b] = L.orc_green(w, h, _ptr(H), a % w, a // w, b % w, b // w)
+    return G
+
+
+def block_green(w: int, h: int, pos, r, op: int = 0, s: float = 1.0):
+    """Green's route on one block.  r is (K,) or (nrhs, K).
+
+    Returns (c, a, u) with c (nrhs, K), a (nrhs,), u (nrhs, h, w)."""
+    pos = np.ascontiguousarray(pos, dtype=np.uint16)
+    r2 = np.atleast_2d(np.asarray(r, dtype=np.float64))
+    r2 = np.ascontiguousarray(r2)
+    nrhs, K = r2.shape[0], pos.size
+    c = np.zeros((nrhs, max(K, 1)))
+    a = np.zeros(nrhs)
+    u = np.zeros((nrhs, w * h))
+    rc = _lib().orc_block_green(w, h, op, float(s), K, _ptr(pos), nrhs, _ptr(r2),
+                                _ptr(c), _ptr(a), _ptr(u))
+    if rc != 0:
+        raise ValueError("orc_block_green failed")
+    return c[:, :K], a, u.reshape(nrhs, h, w)
+
+
+def decode(frame, method: int = DIRECT, op: int = 0, s: float = 1.0,
+           nthreads: int = 0) -> List[np.ndarray]:
+    """Decode a whole packed frame; returns one float64 (H, W) array per plane."""
+    dims = plane_dims(frame.width, frame.height, frame.fmt)
+    out = np.zeros(sum(W * H for W, H in dims))
+    bp = np.ascontiguousarray(frame.block_ptr, dtype=np.int32)
+    pos = np.ascontiguousarray(frame.pos, dtype=np.uint16)
+    vals = np.ascontiguousarray(frame.values, dtype=np.float32)
+    if pos.size == 0:
+        pos = np.zeros(1, np.uint16)
+    if vals.size == 0:
+        vals = np.zeros(1, np.float32)
+    rc = _lib().orc_decode(frame.width, frame.height, frame.fmt, frame.block_size,
+                           _ptr(bp), _ptr(pos), _ptr(vals), int(bool(frame.chroma_shared)),
+                           int(method), int(op), float(s), _ptr(out), int(nthreads))
+    if rc != 0:
+        raise ValueError("orc_decode failed")
+    planes, o = [], 0
+    for W, H in dims:
+        planes.append(out[o:o + W * H].reshape(H, W))
+        o += W * H
+    return planes
+
+
+def decode_flat(frame, **kw) -> np.ndarray:
+    """Like :func:`decode` but returns the concatenated planes (C-ABI layout)."""
+    return np.concatenate([p.ravel() for p in decode(frame, **kw)])

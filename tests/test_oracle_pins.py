@@ -1,0 +1,317 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+Each test names the mistake it is there to catch.  None of them re-types an
+oracle formula: the checks are hand-derived fixtures (tests/golden), closed
+forms, dense brute-force solves of Eq. (1) built a different way (tests/brute),
+textbook routines (numpy pinv, scipy DCT) and invariants.
+"""
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import brute
+import oracle
+from paper_2008_10273_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+SHAPES = [(2, 1), (1, 3), (3, 3), (4, 3), (3, 5), (6, 6), (7, 4), (8, 8), (5, 9)]
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            rows.append([float(Fraction(t)) for t in line.split()])
+    return rows
+
+
+# ---------------------------------------------------------------- golden
+
+def test_golden_green_path3():
+    """Hand-derived pinv of the 3x1 operator: catches a wrong omega weight,
+    a missing mirror image or a wrong fold of x + x' + 1 in the table."""
+    rows = _read_golden("green_path3.txt")
+    w, h = map(int, rows[0])
+    G = np.array(rows[1:])
+    np.testing.assert_allclose(oracle.green_matrix(w, h), G, atol=1e-13)
+
+
+@pytest.mark.parametrize("name", ["decode_4x1.txt", "decode_2x2.txt", "decode_3x2.txt"])
+def test_golden_decodes(name):
+    """Hand-solved Eq. (1) cases (the 3x2 one is non-square: catches a
+    transposed w/h), with c = A u at mask points and a = block mean."""
+    rows = _read_golden(name)
+    w, h = map(int, rows[0])
+    pos = np.array(rows[1], dtype=np.uint16)
+    r = np.array(rows[2])
+    u = np.array(rows[3:3 + h])
+    c_ref = np.array(rows[3 + h])
+    a_ref = rows[4 + h][0]
+    np.testing.assert_allclose(oracle.block_direct(w, h, pos, r), u, atol=1e-12)
+    c, a, ug = oracle.block_green(w, h, pos, r)
+    np.testing.assert_allclose(ug[0], u, atol=1e-12)
+    np.testing.assert_allclose(c[0], c_ref, atol=1e-12)
+    assert abs(a[0] - a_ref) < 1e-12
+
+
+# ------------------------------------------------------ textbook routines
+
+@pytest.mark.parametrize("w,h", SHAPES)
+@pytest.mark.parametrize("s", [1, 2])
+def test_green_matrix_is_pinv(w, h, s):
+    """G from the Toeplitz-plus-Hankel table equals numpy's pseudo-inverse of
+    A = (-L)^s: pins eigenvalues, weights, images and index order at once."""
+    G = oracle.green_matrix(w, h, 0, float(s))
+    np.testing.assert_allclose(G, np.linalg.pinv(brute.operator(w, h, s)), atol=1e-11)
+
+
+@pytest.mark.parametrize("w,h", [(4, 3), (6, 6), (5, 9)])
+def test_green_matrix_is_dct_diagonalised(w, h):
+    """Eq. (4): G = C^T diag(lambda) C with scipy's orthonormal DCT-II, for
+    the continuous-symbol operator too (op 1, which has no stencil form)."""
+    for op in (0, 1):
+        lam = oracle.eigenvalues(w, h, op, 1.0)
+        C = np.kron(brute.dct_matrix(h), brute.dct_matrix(w))
+        np.testing.assert_allclose(oracle.green_matrix(w, h, op, 1.0),
+                                   C.T @ np.diag(lam.ravel()) @ C, atol=1e-11)
+
+
+def test_eigenvalues_are_operator_spectrum():
+    """The discrete eigenvalues are the spectrum of -L (catches using the
+    continuous symbol by mistake, or swapped axes on a non-square block)."""
+    w, h = 5, 3
+    lam = oracle.eigenvalues(w, h, 0, 1.0).ravel()
+    mu = np.sort(np.linalg.eigvalsh(brute.neg_laplacian(w, h)))
+    got = np.sort(np.concatenate([[0.0], 1.0 / lam[1:]]))
+    np.testing.assert_allclose(got, mu, atol=1e-12)
+
+
+# --------------------------------------------------- brute-force Eq. (1)
+
+@pytest.mark.parametrize("w,h", SHAPES)
+@pytest.mark.parametrize("s", [1, 2])
+def test_direct_matches_dense_eq1(w, h, s):
+    """Banded solve of the plain definition vs one dense solve of Eq. (1)."""
+    rng = _rng(w * 100 + h * 10 + s)
+    N = w * h
+    for K in sorted({1, 2, max(1, N // 4), max(1, N // 2), N - 1 if N > 1 else 1, N}):
+        pos = np.sort(rng.choice(N, K, replace=False)).astype(np.uint16)
+        r = rng.uniform(-64, 64, K)
+        ref = brute.solve_eq1(w, h, pos, r, brute.operator(w, h, s))
+        np.testing.assert_allclose(oracle.block_direct(w, h, pos, r, s), ref, atol=1e-9)
+
+
+@pytest.mark.parametrize("w,h", SHAPES + [(16, 16), (16, 8), (16, 12)])
+@pytest.mark.parametrize("s", [1.0, 2.0])
+def test_green_route_matches_dense_eq1(w, h, s):
+    """The Green's route (Eqs. 2-3) reaches the plain definition (Eq. 1)."""
+    rng = _rng(7 * w + h)
+    N = w * h
+    A = brute.operator(w, h, int(s))
+    for K in sorted({1, min(3, N), max(1, N // 10), max(1, N // 2), N - 1 if N > 1 else 1, N}):
+        pos = np.sort(rng.choice(N, K, replace=False)).astype(np.uint16)
+        r = rng.uniform(-64, 64, (2, K))
+        c, a, u = oracle.block_green(w, h, pos, r, 0, s)
+        for t in range(2):
+            np.testing.assert_allclose(u[t], brute.solve_eq1(w, h, pos, r[t], A), atol=1e-9)
+
+
+@pytest.mark.parametrize("w,h", [(4, 3), (8, 8), (16, 12)])
+def test_eq4_dct_evaluation(w, h):
+    """u from Eq. (4), IDCT(lambda * DCT(M c)) + a with scipy, equals the
+    oracle's direct Green sum: pins the evaluation step."""
+    rng = _rng(w + h)
+    N = w * h
+    K = max(2, N // 8)
+    pos = np.sort(rng.choice(N, K, replace=False)).astype(np.uint16)
+    r = rng.uniform(-64, 64, K)
+    c, a, u = oracle.block_green(w, h, pos, r)
+    lam = oracle.eigenvalues(w, h, 0, 1.0)
+    np.testing.assert_allclose(brute.eq4_evaluate(w, h, pos, c[0], a[0], lam), u[0], atol=1e-10)
+
+
+# ------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("w,h", [(16, 16), (16, 8), (7, 5)])
+def test_single_point_gives_constant(w, h):
+    for p in (0, w * h - 1, (w * h) // 2):
+        pos = np.array([p], dtype=np.uint16)
+        np.testing.assert_allclose(oracle.block_direct(w, h, pos, [3.25]), 3.25, atol=1e-12)
+        c, a, u = oracle.block_green(w, h, pos, [3.25])
+        np.testing.assert_allclose(u[0], 3.25, atol=1e-12)
+        assert abs(c[0, 0]) < 1e-12
+
+
+def test_constant_data_gives_constant_and_zero_coefficients():
+    rng = _rng(3)
+    pos = np.sort(rng.choice(256, 20, replace=False)).astype(np.uint16)
+    c, a, u = oracle.block_green(16, 16, pos, np.full(20, -7.5))
+    np.testing.assert_allclose(u[0], -7.5, atol=1e-11)
+    np.testing.assert_allclose(c[0], 0.0, atol=1e-11)
+
+
+@pytest.mark.parametrize("w", [5, 16, 32])
+def test_row_block_is_linear_interpolation(w):
+    """On a w x 1 block the harmonic inpainting is piecewise-linear between
+    the mask points and constant beyond the outermost ones (numpy.interp)."""
+    rng = _rng(w)
+    for K in (2, 3, max(2, w // 3)):
+        pos = np.sort(rng.choice(w, K, replace=False))
+        r = rng.uniform(-64, 64, K)
+        ref = np.interp(np.arange(w), pos, r)
+        np.testing.assert_allclose(oracle.block_direct(w, 1, pos.astype(np.uint16), r)[0], ref, atol=1e-10)
+        np.testing.assert_allclose(oracle.block_direct(1, w, pos.astype(np.uint16), r)[:, 0], ref, atol=1e-10)
+        np.testing.assert_allclose(oracle.block_green(w, 1, pos.astype(np.uint16), r)[2][0, 0], ref, atol=1e-10)
+
+
+@pytest.mark.parametrize("w,h", [(16, 16), (16, 8), (9, 4)])
+def test_two_edge_columns_give_ramp(w, h):
+    """Full first and last columns with values 0 and w-1 give u(x,y) = x;
+    rows give u = y (catches x/y swaps)."""
+    pos = np.array(sorted([y * w for y in range(h)] + [y * w + w - 1 for y in range(h)]), np.uint16)
+    r = np.array([0.0 if p % w == 0 else w - 1.0 for p in pos])
+    ramp = np.tile(np.arange(w, dtype=float), (h, 1))
+    np.testing.assert_allclose(oracle.block_direct(w, h, pos, r), ramp, atol=1e-10)
+    np.testing.assert_allclose(oracle.block_green(w, h, pos, r)[2][0], ramp, atol=1e-10)
+    pos = np.array(list(range(w)) + list(range((h - 1) * w, h * w)), np.uint16)
+    r = np.array([0.0] * w + [h - 1.0] * w)
+    ramp = np.tile(np.arange(h, dtype=float)[:, None], (1, w))
+    np.testing.assert_allclose(oracle.block_green(w, h, pos, r)[2][0], ramp, atol=1e-10)
+
+
+def test_empty_and_full_masks():
+    """K = 0 gives u = 0 (reading); K = w*h gives u = r."""
+    np.testing.assert_array_equal(oracle.block_direct(4, 3, np.zeros(0, np.uint16), []), 0.0)
+    c, a, u = oracle.block_green(4, 3, np.zeros(0, np.uint16), np.zeros((1, 0)))
+    np.testing.assert_array_equal(u, 0.0)
+    r = np.arange(12, dtype=float) * 1.5 - 4
+    np.testing.assert_allclose(oracle.block_direct(4, 3, np.arange(12), r).ravel(), r, atol=1e-12)
+    np.testing.assert_allclose(oracle.block_green(4, 3, np.arange(12), r)[2][0].ravel(), r, atol=1e-10)
+
+
+# -------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("w,h", [(16, 16), (16, 12), (32, 32)])
+def test_invariants(w, h):
+    """Exact interpolation, maximum principle, harmonic off-mask, sum c = 0,
+    c = A u at the mask points (A u = M c), a = block mean, linearity."""
+    rng = _rng(w * h)
+    N = w * h
+    A = brute.neg_laplacian(w, h)
+    for K in (3, N // 20, N // 5):
+        pos = np.sort(rng.choice(N, K, replace=False)).astype(np.uint16)
+        r = rng.uniform(-64, 64, (2, K))
+        c, a, u = oracle.block_green(w, h, pos, r)
+        for t in range(2):
+            uf = u[t].ravel()
+            np.testing.assert_allclose(uf[pos], r[t], atol=1e-9)
+            assert r[t].min() - 1e-9 <= uf.min() and uf.max() <= r[t].max() + 1e-9
+            Au = A @ uf
+            off = np.setdiff1d(np.arange(N), pos)
+            np.testing.assert_allclose(Au[off], 0.0, atol=1e-9)
+            np.testing.assert_allclose(Au[pos], c[t], atol=1e-9)
+            assert abs(c[t].sum()) < 1e-9
+            assert abs(a[t] - uf.mean()) < 1e-9
+        np.testing.assert_allclose(u[0] * 2.0 - u[1] * 0.5,
+                                   oracle.block_green(w, h, pos, 2.0 * r[0] - 0.5 * r[1])[2][0], atol=1e-9)
+
+
+def test_dihedral_equivariance():
+    """Transposing / flipping a square block transposes / flips u."""
+    rng = _rng(11)
+    w = h = 8
+    pos = np.sort(rng.choice(64, 9, replace=False))
+    r = rng.uniform(-64, 64, 9)
+    u = oracle.block_direct(w, h, pos.astype(np.uint16), r)
+    x, y = pos % w, pos // w
+    for xf, yf, tr, fn in [
+        (x, y, True, lambda a: a.T),
+        (w - 1 - x, y, False, lambda a: a[:, ::-1]),
+        (x, h - 1 - y, False, lambda a: a[::-1, :]),
+    ]:
+        p2 = (xf * h + yf) if tr else (yf * w + xf)
+        order = np.argsort(p2)
+        u2 = oracle.block_green(w, h, p2[order].astype(np.uint16), r[order])[2][0]
+        np.testing.assert_allclose(u2, fn(u), atol=1e-10)
+
+
+# -------------------------------------------------------------- frames
+
+def test_frame_matches_per_block_solves():
+    """Frame decode = every block decoded alone and placed at its offset in
+    its plane; blocks are independent images (Sec. 2.2).  Catches block order,
+    plane offsets and the shared chroma value runs (Cr vs Cb)."""
+    fr = synth.random_frame(70, 37, synth.YUV420, 16, (0.02, 0.2), seed=5)
+    planes = oracle.decode(fr, method=oracle.DIRECT)
+    ref = [np.full(p.shape, np.nan) for p in planes]
+    for blk in fr.iter_blocks():
+        for vp, vals in zip(blk["planes"], blk["values"]):
+            u = brute.solve_eq1(blk["w"], blk["h"], blk["pos"], vals.astype(float),
+                                brute.neg_laplacian(blk["w"], blk["h"]))
+            ref[vp][blk["y0"]:blk["y0"] + blk["h"], blk["x0"]:blk["x0"] + blk["w"]] = u
+    for p, q in zip(planes, ref):
+        assert not np.isnan(q).any()
+        np.testing.assert_allclose(p, q, atol=1e-9)
+
+
+def test_frame_reproduces_field_at_mask_points():
+    """Exact interpolation at frame level: u equals the drawn residual field at
+    every mask pixel of every plane (pins value-run alignment)."""
+    fr = synth.random_frame(100, 60, synth.YUV420, 16, (0.01, 0.1), seed=1)
+    planes = oracle.decode(fr, method=oracle.GREEN)
+    for blk in fr.iter_blocks():
+        px = blk["x0"] + blk["pos"].astype(int) % blk["w"]
+        py = blk["y0"] + blk["pos"].astype(int) // blk["w"]
+        for vp in blk["planes"]:
+            np.testing.assert_allclose(planes[vp][py, px],
+                                       fr.fields[vp][py, px].astype(np.float32), atol=1e-9)
+
+
+def test_frame_routes_agree_and_locality():
+    fr = synth.config_frame(0)
+    a = oracle.decode(fr, method=oracle.DIRECT)[0]
+    b = oracle.decode(fr, method=oracle.GREEN)[0]
+    np.testing.assert_allclose(a, b, atol=1e-9)
+    # perturb the values of block 37 only
+    fr2 = synth.config_frame(0)
+    lo, hi = fr2.block_ptr[37], fr2.block_ptr[38]
+    fr2.values = fr2.values.copy()
+    fr2.values[lo:hi] += 10.0
+    c = oracle.decode(fr2, method=oracle.DIRECT)[0]
+    diff = np.abs(c - a) > 0
+    by, bx = divmod(37, 16)
+    expect = np.zeros_like(diff)
+    expect[by * 16:(by + 1) * 16, bx * 16:(bx + 1) * 16] = True
+    np.testing.assert_array_equal(diff, expect)
+
+
+def test_separate_chroma_masks():
+    fr = synth.random_frame(48, 40, synth.YUV420, 16, (0.05, 0.2), seed=9, chroma_shared=False)
+    a = oracle.decode(fr, method=oracle.DIRECT)
+    b = oracle.decode(fr, method=oracle.GREEN)
+    for p, q in zip(a, b):
+        np.testing.assert_allclose(p, q, atol=1e-9)
+
+
+def test_planted_mistake_is_caught():
+    """The pins are sharp: a perturbed table (a plausible wrong weight) breaks
+    the pseudo-inverse pin by far more than its tolerance."""
+    w, h = 4, 3
+    G = oracle.green_matrix(w, h)
+    P = np.linalg.pinv(brute.neg_laplacian(w, h))
+    assert np.abs(G - P).max() < 1e-11
+    lam = oracle.eigenvalues(w, h).ravel()
+    C = np.kron(brute.dct_matrix(h), brute.dct_matrix(w))
+    lam_bad = lam.copy()
+    lam_bad[1] *= 1.01
+    assert np.abs(C.T @ np.diag(lam_bad) @ C - P).max() > 1e-4
