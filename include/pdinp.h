@@ -1,0 +1,158 @@
+/*
+ * pdinp.h - C ABI of the MI355X residual decoder: block-based
+ * pseudodifferential inpainting of residual planes from sparse mask values
+ * (Andris, Peter, Kaja Mohideen, Weickert, Hoffmann, "Inpainting-based Video
+ * Compression in FullHD", SSVM 2021).
+ *
+ * The operation (Sec. 2.1-2.2 of the paper).  A plane is cut into b x b
+ * blocks (truncated at the right and bottom edges); each block is an
+ * independent image with mirrored boundaries.  Given K distinct mask pixels
+ * x_1..x_K of a block with values r_1..r_K, the decoded residual is
+ *     u(x) = sum_i c_i G(x, x_i) + a                      (Eq. 2 / Eq. 3)
+ * where G is the Green's function of the operator A (its pseudo-inverse,
+ * diagonalised by the DCT-II with eigenvalues lambda, Eq. 4) and (c, a) solve
+ * the (K+1) x (K+1) system  [G_K 1; 1^T 0] [c; a] = [r; 0]  (Sec. 2.2).
+ * For the harmonic operator A = -L this u is the unique solution of the
+ * inpainting problem of Eq. (1) on the block.
+ *
+ * All functions return 0 (PDI_OK) or a negative PDI_E* code; no exception
+ * crosses the ABI.  After a failed call `out` is unspecified and the context
+ * stays usable.
+ */
+#ifndef PDINP_H
+#define PDINP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define PDI_OK      0
+#define PDI_EINVAL (-1) /* null pointer, bad geometry, block size not 8/16/32, bad params */
+#define PDI_EMASK  (-2) /* position >= w*h, positions not strictly ascending, K > w*h */
+#define PDI_ENOMEM (-3) /* device allocation failed or HBM budget exceeded */
+#define PDI_EHIP   (-4) /* HIP runtime error; pdi_last_error() has the detail */
+#define PDI_EBUSY  (-5) /* server queue full / context busy */
+#define PDI_EVALUE (-6) /* a non-finite value (NaN/Inf) in `values` */
+#define PDI_ESOLVE (-7) /* a block's system broke down (non-finite solution) */
+
+/* Frame formats. */
+#define PDI_GRAY   0 /* one W x H plane */
+#define PDI_YUV420 1 /* Y (W x H), Cb, Cr (ceil(W/2) x ceil(H/2)) */
+
+/* Evaluation arithmetic for u(x) = sum c_i G(x, x_i) + a. */
+#define PDI_EVAL_FP32   0 /* FP32 matrix-core products (default) */
+#define PDI_EVAL_FP16   1 /* FP16 operands, FP32 accumulation */
+#define PDI_EVAL_BF16   2 /* BF16 operands, FP32 accumulation */
+#define PDI_EVAL_BF16X2 3 /* split BF16 (hi*hi + hi*lo + lo*hi), FP32 accumulation */
+
+/* Execution path. */
+#define PDI_PATH_AUTO  0 /* batched wave-level solves + matrix-core evaluation */
+#define PDI_PATH_PLAIN 1 /* one workgroup per block, FP32 solve, direct evaluation */
+
+/* Operators (the eigenvalues lambda = mu^-s define the operator, Sec. 2.2). */
+#define PDI_OP_DISCRETE   0 /* mu = 4 sin^2(pi p/2w) + 4 sin^2(pi q/2h): 5-point -L */
+#define PDI_OP_CONTINUOUS 1 /* mu = pi^2 (p^2/w^2 + q^2/h^2) */
+
+typedef struct pdi_ctx pdi_ctx;
+
+/* Frame geometry.  Planes are row-major with stride = plane width. */
+typedef struct {
+    int32_t width;
+    int32_t height;
+    int32_t format; /* PDI_GRAY or PDI_YUV420 */
+} pdi_frame;
+
+/* Packed mask (CSR over blocks).  Mask blocks are ordered: the Y blocks, then
+ * the chroma blocks once (chroma_shared != 0: one mask for Cb and Cr, as in
+ * Sec. 2.4 of the paper) or the Cb blocks then the Cr blocks; raster order
+ * inside each plane.  block_ptr[n_mask_blocks + 1] are int32 offsets into
+ * pos; pos[] holds in-block pixel indices y*w + x (w = width of that block),
+ * strictly ascending inside a block.  K = 0 is allowed (the block decodes to
+ * zero).  Both arrays are DEVICE pointers owned by the caller. */
+typedef struct {
+    const int32_t *block_ptr;
+    const uint16_t *pos;
+    int32_t n_mask_blocks;
+    int32_t chroma_shared;
+} pdi_mask;
+
+/* Parameters; pdi_default_params() gives the paper's harmonic operator. */
+typedef struct {
+    int32_t op;          /* PDI_OP_*; default PDI_OP_DISCRETE */
+    double s;            /* lambda = mu^-s; 1.0 = harmonic (default), 2.0 = biharmonic */
+    int32_t eval_dtype;  /* PDI_EVAL_*; default PDI_EVAL_FP32 */
+    int32_t refine;      /* 0 off, 1 auto (small pivot ratio), 2 always; default 1 */
+    int32_t validate;    /* 1: check masks/values on the device, report at pdi_sync */
+    int32_t path;        /* PDI_PATH_*; default PDI_PATH_AUTO */
+    double refine_tau;   /* auto-refine when min/max pivot < tau; default 1/64 */
+} pdi_params;
+
+/* Fill *p with the defaults. */
+void pdi_default_params(pdi_params *p);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the
+ * library's own device allocations (0 = no cap).  The context owns the table
+ * cache, the workspace and the device status word.  Use one context per host
+ * thread and per concurrently used stream (or serialise externally).
+ * Returns PDI_EINVAL (bad device / null out), PDI_EHIP, PDI_ENOMEM. */
+int pdi_create(pdi_ctx **out, int device, size_t hbm_budget_bytes);
+
+/* Release the context and every device allocation it owns (synchronises). */
+void pdi_destroy(pdi_ctx *ctx);
+
+/* Decode the residual planes of one frame (hot path, asynchronous on
+ * `stream`, a hipStream_t; NULL = the null stream).
+ *   values: DEVICE float32 array: the Y values aligned with the Y part of
+ *     pos, then the Cb values aligned with the chroma part, then the Cr
+ *     values (aligned with the chroma part again when chroma_shared).
+ *   block_size: 8, 16 or 32.
+ *   params: NULL for the defaults.
+ *   out: DEVICE float32 array of W*H (+ 2 * ceil(W/2)*ceil(H/2) for YUV420)
+ *     elements, planes Y, Cb, Cr back to back, row-major.
+ * The library keeps no reference to caller memory after the stream work
+ * completes.  Host-side checks (geometry, params, mask block count) return
+ * PDI_EINVAL synchronously; with validate=1 mask/value errors found on the
+ * device are reported by the next pdi_sync as PDI_EMASK / PDI_EVALUE.
+ * The first call for a new frame geometry allocates (not capturable); later
+ * calls with the same geometry and params launch kernels only. */
+int decode_residual(pdi_ctx *ctx, const pdi_frame *frame, const pdi_mask *mask,
+                    const float *values, int block_size, const pdi_params *params,
+                    float *out, void *stream);
+
+/* Wait for `stream`, then read and clear the device status word.
+ * Returns PDI_OK, PDI_EMASK, PDI_EVALUE, PDI_ESOLVE or PDI_EHIP. */
+int pdi_sync(pdi_ctx *ctx, void *stream);
+
+/* Text of the last error of this context (never NULL). */
+const char *pdi_last_error(pdi_ctx *ctx);
+
+/* Host helper: number of mask blocks, value count and output size of a
+ * frame geometry (for sizing buffers).  Pointers may be NULL. */
+int pdi_frame_info(const pdi_frame *frame, int block_size, int chroma_shared,
+                   int32_t *n_mask_blocks, int64_t *out_elems);
+
+/* Host helper: pack the paper's dense form (Sec. 2.1: mask m and image f,
+ * row-major per plane) into the CSR layout above.  HOST pointers.
+ *   m: uint8 mask planes back to back (Y, then C for a shared chroma mask,
+ *      else Cb, Cr); f: float32 planes Y, Cb, Cr back to back.
+ *   block_ptr: n_mask_blocks + 1 entries; pos / values: capacity in
+ *   *pos_cap / *val_cap, replaced by the counts written.
+ * Returns PDI_EINVAL on bad geometry, PDI_ENOMEM if a capacity is short. */
+int pdi_pack_dense(const pdi_frame *frame, const uint8_t *m, const float *f,
+                   int block_size, int chroma_shared, int32_t *block_ptr,
+                   uint16_t *pos, int64_t *pos_cap, float *values, int64_t *val_cap);
+
+/* Host-side validation of a HOST copy of a packed mask and values: returns
+ * PDI_OK, PDI_EINVAL, PDI_EMASK or PDI_EVALUE (no device work). */
+int pdi_validate_host(const pdi_frame *frame, int block_size, const int32_t *block_ptr,
+                      const uint16_t *pos, int32_t n_mask_blocks, int32_t chroma_shared,
+                      const float *values);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDINP_H */

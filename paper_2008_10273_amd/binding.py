@@ -1,0 +1,215 @@
+"""Thin ctypes binding of ``libpdinp.so`` (include/pdinp.h), same names.
+
+Argument marshalling only: every step of the decode runs in the library's
+HIP kernels.  Device buffers are passed as raw pointers (``tensor.data_ptr()``)
+and streams as ``hipStream_t`` handles (``torch.cuda.Stream.cuda_stream``).
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdinp.so")
+
+PDI_OK, PDI_EINVAL, PDI_EMASK, PDI_ENOMEM, PDI_EHIP, PDI_EBUSY, PDI_EVALUE, PDI_ESOLVE = 0, -1, -2, -3, -4, -5, -6, -7
+PDI_GRAY, PDI_YUV420 = 0, 1
+PDI_EVAL_FP32, PDI_EVAL_FP16, PDI_EVAL_BF16, PDI_EVAL_BF16X2 = 0, 1, 2, 3
+PDI_PATH_AUTO, PDI_PATH_PLAIN = 0, 1
+PDI_OP_DISCRETE, PDI_OP_CONTINUOUS = 0, 1
+
+ERROR_NAMES = {0: "PDI_OK", -1: "PDI_EINVAL", -2: "PDI_EMASK", -3: "PDI_ENOMEM", -4: "PDI_EHIP",
+               -5: "PDI_EBUSY", -6: "PDI_EVALUE", -7: "PDI_ESOLVE"}
+
+EXPORTS = ["pdi_default_params", "pdi_create", "pdi_destroy", "decode_residual", "pdi_sync",
+           "pdi_last_error", "pdi_frame_info", "pdi_pack_dense", "pdi_validate_host"]
+
+
+class pdi_frame(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("format", ctypes.c_int32)]
+
+
+class pdi_mask(ctypes.Structure):
+    _fields_ = [("block_ptr", ctypes.c_void_p), ("pos", ctypes.c_void_p),
+                ("n_mask_blocks", ctypes.c_int32), ("chroma_shared", ctypes.c_int32)]
+
+
+class pdi_params(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("s", ctypes.c_double), ("eval_dtype", ctypes.c_int32),
+                ("refine", ctypes.c_int32), ("validate", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("refine_tau", ctypes.c_double)]
+
+
+class PdiError(RuntimeError):
+    def __init__(self, code: int, msg: str = ""):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the built library (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2008_10273_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64p = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)
+        L.pdi_default_params.argtypes = [ctypes.POINTER(pdi_params)]
+        L.pdi_default_params.restype = None
+        L.pdi_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), i32, ctypes.c_size_t]
+        L.pdi_create.restype = i32
+        L.pdi_destroy.argtypes = [P]
+        L.pdi_destroy.restype = None
+        L.decode_residual.argtypes = [P, ctypes.POINTER(pdi_frame), ctypes.POINTER(pdi_mask), P, i32,
+                                      ctypes.POINTER(pdi_params), P, P]
+        L.decode_residual.restype = i32
+        L.pdi_sync.argtypes = [P, P]
+        L.pdi_sync.restype = i32
+        L.pdi_last_error.argtypes = [P]
+        L.pdi_last_error.restype = ctypes.c_char_p
+        L.pdi_frame_info.argtypes = [ctypes.POINTER(pdi_frame), i32, i32, ctypes.POINTER(ctypes.c_int32), i64p]
+        L.pdi_frame_info.restype = i32
+        L.pdi_pack_dense.argtypes = [ctypes.POINTER(pdi_frame), P, P, i32, i32, P, P, i64p, P, i64p]
+        L.pdi_pack_dense.restype = i32
+        L.pdi_validate_host.argtypes = [ctypes.POINTER(pdi_frame), i32, P, P, ctypes.c_int32,
+                                        ctypes.c_int32, P]
+        L.pdi_validate_host.restype = i32
+        _lib = L
+    return _lib
+
+
+def default_params(**kw) -> pdi_params:
+    p = pdi_params()
+    lib().pdi_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def pdi_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
+    h = ctypes.c_void_p()
+    rc = lib().pdi_create(ctypes.byref(h), device, hbm_budget_bytes)
+    if rc != PDI_OK:
+        raise PdiError(rc, "pdi_create")
+    return h.value
+
+
+def pdi_destroy(ctx: int) -> None:
+    lib().pdi_destroy(ctx)
+
+
+def pdi_last_error(ctx: int) -> str:
+    return lib().pdi_last_error(ctx).decode()
+
+
+def decode_residual(ctx: int, width: int, height: int, fmt: int, block_ptr: int, pos: int,
+                    n_mask_blocks: int, chroma_shared: bool, values: int, block_size: int,
+                    params: Optional[pdi_params], out: int, stream: int = 0) -> int:
+    """Raw call: all buffer arguments are device addresses (ints)."""
+    fr = pdi_frame(width, height, fmt)
+    mk = pdi_mask(block_ptr, pos, n_mask_blocks, int(bool(chroma_shared)))
+    return lib().decode_residual(ctx, ctypes.byref(fr), ctypes.byref(mk), values, block_size,
+                                 ctypes.byref(params) if params is not None else None, out, stream)
+
+
+def pdi_sync(ctx: int, stream: int = 0) -> int:
+    return lib().pdi_sync(ctx, stream)
+
+
+def pdi_frame_info(width: int, height: int, fmt: int, block_size: int, chroma_shared: bool):
+    fr = pdi_frame(width, height, fmt)
+    n = ctypes.c_int32()
+    e = ctypes.c_int64()
+    rc = lib().pdi_frame_info(ctypes.byref(fr), block_size, int(bool(chroma_shared)),
+                              ctypes.byref(n), ctypes.byref(e))
+    return rc, n.value, e.value
+
+
+def pdi_validate_host(width, height, fmt, block_size, block_ptr, pos, chroma_shared, values) -> int:
+    """block_ptr / pos / values are numpy arrays (host)."""
+    import numpy as np
+    bp = np.ascontiguousarray(block_ptr, dtype=np.int32)
+    ps = np.ascontiguousarray(pos, dtype=np.uint16)
+    vs = np.ascontiguousarray(values, dtype=np.float32)
+    fr = pdi_frame(width, height, fmt)
+    return lib().pdi_validate_host(ctypes.byref(fr), block_size, bp.ctypes.data, ps.ctypes.data,
+                                   int(bp.size - 1), int(bool(chroma_shared)), vs.ctypes.data)
+
+
+def pdi_pack_dense(width, height, fmt, block_size, chroma_shared, m, f):
+    """Host packing of dense masks/planes (numpy) into (block_ptr, pos, values)."""
+    import numpy as np
+    rc, nb, nel = pdi_frame_info(width, height, fmt, block_size, chroma_shared)
+    if rc != PDI_OK:
+        raise PdiError(rc, "pdi_frame_info")
+    m = np.ascontiguousarray(m, dtype=np.uint8)
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    bp = np.zeros(nb + 1, np.int32)
+    cap = int(m.size)
+    pos = np.zeros(max(cap, 1), np.uint16)
+    vals = np.zeros(max(2 * cap, 1), np.float32)
+    pc, vc = ctypes.c_int64(pos.size), ctypes.c_int64(vals.size)
+    fr = pdi_frame(width, height, fmt)
+    rc = lib().pdi_pack_dense(ctypes.byref(fr), m.ctypes.data, f.ctypes.data, block_size,
+                              int(bool(chroma_shared)), bp.ctypes.data, pos.ctypes.data,
+                              ctypes.byref(pc), vals.ctypes.data, ctypes.byref(vc))
+    if rc != PDI_OK:
+        raise PdiError(rc, "pdi_pack_dense")
+    return bp, pos[:pc.value].copy(), vals[:vc.value].copy()
+
+
+class Decoder:
+    """Convenience wrapper: a context plus torch device buffers for frames."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        import torch  # device memory and streams only
+        self.torch = torch
+        self.device = device
+        self.ctx = pdi_create(device, hbm_budget_bytes)
+
+    def close(self):
+        if self.ctx:
+            pdi_destroy(self.ctx)
+            self.ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def upload(self, frame):
+        """Copy a packed frame (synth.Frame-like) to the device; returns a dict."""
+        import numpy as np
+        torch = self.torch
+        dev = torch.device("cuda", self.device)
+        bp = torch.from_numpy(np.ascontiguousarray(frame.block_ptr, np.int32)).to(dev)
+        pos = np.ascontiguousarray(frame.pos, np.uint16).view(np.int16)
+        pos_t = torch.from_numpy(pos if pos.size else np.zeros(1, np.int16)).to(dev)
+        vals = np.ascontiguousarray(frame.values, np.float32)
+        vals_t = torch.from_numpy(vals if vals.size else np.zeros(1, np.float32)).to(dev)
+        rc, nb, nel = pdi_frame_info(frame.width, frame.height, frame.fmt, frame.block_size,
+                                     frame.chroma_shared)
+        out = torch.empty(nel, dtype=torch.float32, device=dev)
+        return dict(frame=frame, block_ptr=bp, pos=pos_t, values=vals_t, out=out,
+                    n_mask_blocks=int(frame.block_ptr.shape[0] - 1))
+
+    def decode(self, d, params: Optional[pdi_params] = None, stream=None, out=None, check=True) -> int:
+        fr = d["frame"]
+        out = d["out"] if out is None else out
+        s = stream.cuda_stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
+        rc = decode_residual(self.ctx, fr.width, fr.height, fr.fmt, d["block_ptr"].data_ptr(),
+                             d["pos"].data_ptr(), d["n_mask_blocks"], fr.chroma_shared,
+                             d["values"].data_ptr(), fr.block_size, params, out.data_ptr(), s)
+        if check and rc != PDI_OK:
+            raise PdiError(rc, pdi_last_error(self.ctx))
+        return rc
+
+    def sync(self, stream=None) -> int:
+        s = stream.cuda_stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
+        return pdi_sync(self.ctx, s)

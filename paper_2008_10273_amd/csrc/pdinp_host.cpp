@@ -1,0 +1,565 @@
+// Host side of the C ABI declared in include/pdinp.h: context, per-shape
+// tables, argument checks and kernel orchestration.  Every step of the
+// decode itself runs in the kernels of pdinp_kernels.hip.
+#include "../../include/pdinp.h"
+#include "pdinp_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct TableSet {
+  float *tab32 = nullptr;
+  double *tab64 = nullptr;
+  size_t bytes = 0;
+  int tab32_floats = 0;
+  int nshapes = 0;
+  pdi::ShapeDev s[pdi::kMaxShapes];
+  int group_shape[pdi::kMaxGroups][4];
+};
+
+using TableKey = std::tuple<int, int, int, int, int, int, double>;  // W,H,fmt,b,shared,op,s
+
+}  // namespace
+
+struct pdi_ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t used = 0;
+  std::string err;
+  int *status = nullptr;    // device status word
+  int *counters = nullptr;  // device counters [4]
+  int *deferred = nullptr;  // device list of deferred mask blocks
+  int deferred_cap = 0;
+  float *slots = nullptr;
+  long long slot_floats = 0;
+  std::map<TableKey, TableSet> tables;
+};
+
+namespace {
+
+int set_err(pdi_ctx *c, int code, const char *fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+int hip_fail(pdi_ctx *c, hipError_t e, const char *what) {
+  return set_err(c, PDI_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int dev_alloc(pdi_ctx *c, void **p, size_t bytes, const char *what) {
+  if (c->budget && c->used + bytes > c->budget)
+    return set_err(c, PDI_ENOMEM, "%s: %zu bytes exceed the HBM budget (%zu of %zu used)", what,
+                   bytes, c->used, c->budget);
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return set_err(c, PDI_ENOMEM, "%s: hipMalloc(%zu) failed: %s", what, bytes, hipGetErrorString(e));
+  }
+  c->used += bytes;
+  return PDI_OK;
+}
+
+void dev_free(pdi_ctx *c, void *p, size_t bytes) {
+  if (p) {
+    (void)hipFree(p);
+    c->used -= bytes;
+  }
+}
+
+struct PlaneGeom {
+  int W, H;
+};
+
+int planes_of(const pdi_frame *f, PlaneGeom *pg) {
+  if (f->format == PDI_GRAY) {
+    pg[0] = {f->width, f->height};
+    return 1;
+  }
+  int cw = (f->width + 1) / 2, ch = (f->height + 1) / 2;
+  pg[0] = {f->width, f->height};
+  pg[1] = {cw, ch};
+  pg[2] = {cw, ch};
+  return 3;
+}
+
+// Mask-plane groups: (mask plane, value planes).
+int groups_of(const pdi_frame *f, int shared, int mplane[3], int vpl[3][2], int nv[3]) {
+  if (f->format == PDI_GRAY) {
+    mplane[0] = 0; vpl[0][0] = 0; nv[0] = 1;
+    return 1;
+  }
+  if (shared) {
+    mplane[0] = 0; vpl[0][0] = 0; nv[0] = 1;
+    mplane[1] = 1; vpl[1][0] = 1; vpl[1][1] = 2; nv[1] = 2;
+    return 2;
+  }
+  for (int g = 0; g < 3; ++g) { mplane[g] = g; vpl[g][0] = g; nv[g] = 1; }
+  return 3;
+}
+
+int check_geometry(const pdi_frame *f, int b) {
+  if (!f) return PDI_EINVAL;
+  if (f->width <= 0 || f->height <= 0) return PDI_EINVAL;
+  if (f->format != PDI_GRAY && f->format != PDI_YUV420) return PDI_EINVAL;
+  if (b != 8 && b != 16 && b != 32) return PDI_EINVAL;
+  if ((long long)f->width * f->height > (1LL << 31) / 2) return PDI_EINVAL;
+  return PDI_OK;
+}
+
+long long mask_blocks_of(const pdi_frame *f, int b, int shared) {
+  PlaneGeom pg[3];
+  planes_of(f, pg);
+  int mp[3], vp[3][2], nv[3];
+  int ng = groups_of(f, shared, mp, vp, nv);
+  long long n = 0;
+  for (int g = 0; g < ng; ++g)
+    n += (long long)((pg[mp[g]].W + b - 1) / b) * ((pg[mp[g]].H + b - 1) / b);
+  return n;
+}
+
+// ---------------------------------------------------------------- tables
+//
+// For a w x h block with mirrored boundaries the operator is diagonalised by
+// the 2D DCT-II (Eq. 4); with the orthonormal basis
+//   phi_p(x) = sqrt(om_p) cos(pi p (x + 1/2) / n),  om_0 = 1/n, om_p = 2/n,
+// the Green's function is G(x, x') = sum_pq lam_pq phi_p(x) phi_p(x')
+// phi_q(y) phi_q(y').  Because phi_p(x) phi_p(x') = om_p/2 [cos(pi p (x-x')/n)
+// + cos(pi p (x+x'+1)/n)], G is a quarter of the sum of
+//   Hc(alpha, beta) = sum_pq lam_pq om_p om_q cos(pi p alpha/w) cos(pi q beta/h)
+// over the four (alpha, beta) pairs built from |x-x'| and x+x'+1 (the latter
+// reflected into [0, n] by the 2n period) - the Toeplitz-plus-Hankel
+// structure of Sec. 2.2.  The tables below store Hc/4.
+
+double eig_mu(int op, int p, int q, int w, int h) {
+  if (op == PDI_OP_CONTINUOUS)
+    return kPi * kPi * ((double)p * p / ((double)w * w) + (double)q * q / ((double)h * h));
+  double a = std::sin(kPi * p / (2.0 * w)), b = std::sin(kPi * q / (2.0 * h));
+  return 4.0 * a * a + 4.0 * b * b;
+}
+
+void build_shape_tables(int w, int h, int op, double s, std::vector<double> &lam,
+                        std::vector<double> &hc) {
+  lam.assign((size_t)w * h, 0.0);
+  for (int q = 0; q < h; ++q)
+    for (int p = 0; p < w; ++p)
+      lam[(size_t)q * w + p] = (p == 0 && q == 0) ? 0.0 : std::pow(eig_mu(op, p, q, w, h), -s);
+  // separable evaluation: first over p for every (q, alpha), then over q
+  std::vector<double> cw((size_t)(w + 1) * w), ch((size_t)(h + 1) * h);
+  for (int a = 0; a <= w; ++a)
+    for (int p = 0; p < w; ++p)
+      cw[(size_t)a * w + p] = (p == 0 ? 1.0 : 2.0) / w * std::cos(kPi * p * a / w);
+  for (int bb = 0; bb <= h; ++bb)
+    for (int q = 0; q < h; ++q)
+      ch[(size_t)bb * h + q] = (q == 0 ? 1.0 : 2.0) / h * std::cos(kPi * q * bb / h);
+  std::vector<double> t((size_t)h * (w + 1));  // t[q][alpha] = sum_p lam_qp cw
+  for (int q = 0; q < h; ++q)
+    for (int a = 0; a <= w; ++a) {
+      double acc = 0.0;
+      for (int p = 0; p < w; ++p) acc += lam[(size_t)q * w + p] * cw[(size_t)a * w + p];
+      t[(size_t)q * (w + 1) + a] = acc;
+    }
+  hc.assign((size_t)(w + 1) * (h + 1), 0.0);
+  for (int bb = 0; bb <= h; ++bb)
+    for (int a = 0; a <= w; ++a) {
+      double acc = 0.0;
+      for (int q = 0; q < h; ++q) acc += ch[(size_t)bb * h + q] * t[(size_t)q * (w + 1) + a];
+      hc[(size_t)bb * (w + 1) + a] = 0.25 * acc;
+    }
+}
+
+// Orthonormal DCT-II matrix of size n, rows = frequency, cols = position,
+// zero padded to 16 x 16.
+void dct16(int n, float *out) {
+  for (int p = 0; p < 16; ++p)
+    for (int x = 0; x < 16; ++x) {
+      double v = 0.0;
+      if (p < n && x < n) v = std::sqrt((p == 0 ? 1.0 : 2.0) / n) * std::cos(kPi * p * (x + 0.5) / n);
+      out[p * 16 + x] = (float)v;
+    }
+}
+
+int get_tables(pdi_ctx *c, const pdi_frame *f, int b, int shared, const pdi_params &P,
+               TableSet **out) {
+  TableKey key{f->width, f->height, f->format, b, shared, P.op, P.s};
+  auto it = c->tables.find(key);
+  if (it != c->tables.end()) {
+    *out = &it->second;
+    return PDI_OK;
+  }
+  TableSet ts;
+  PlaneGeom pg[3];
+  planes_of(f, pg);
+  int mp[3], vp[3][2], nv[3];
+  int ng = groups_of(f, shared, mp, vp, nv);
+  std::vector<std::pair<int, int>> shapes;
+  for (int g = 0; g < ng; ++g) {
+    int W = pg[mp[g]].W, H = pg[mp[g]].H;
+    int rw = W % b ? W % b : b, rh = H % b ? H % b : b;
+    int cand[4][2] = {{b < W ? b : W, b < H ? b : H}, {rw, b < H ? b : H}, {b < W ? b : W, rh}, {rw, rh}};
+    for (int k = 0; k < 4; ++k) {
+      int id = -1;
+      for (size_t t = 0; t < shapes.size(); ++t)
+        if (shapes[t].first == cand[k][0] && shapes[t].second == cand[k][1]) id = (int)t;
+      if (id < 0) {
+        if ((int)shapes.size() >= pdi::kMaxShapes) return set_err(c, PDI_EINVAL, "too many block shapes");
+        shapes.push_back({cand[k][0], cand[k][1]});
+        id = (int)shapes.size() - 1;
+      }
+      ts.group_shape[g][k] = id;
+    }
+  }
+  ts.nshapes = (int)shapes.size();
+  std::vector<float> t32;
+  std::vector<double> t64;
+  for (int k = 0; k < ts.nshapes; ++k) {
+    int w = shapes[k].first, h = shapes[k].second;
+    std::vector<double> lam, hc;
+    build_shape_tables(w, h, P.op, P.s, lam, hc);
+    pdi::ShapeDev &S = ts.s[k];
+    S.w = w;
+    S.h = h;
+    S.hc32 = (int)t32.size();
+    for (double v : hc) t32.push_back((float)v);
+    while (t32.size() % 4) t32.push_back(0.f);
+    S.hc64 = (int)t64.size();
+    for (double v : hc) t64.push_back(v);
+    if (b <= 16) {
+      S.dw = (int)t32.size();
+      t32.resize(t32.size() + 256);
+      dct16(w, &t32[S.dw]);
+      S.dh = (int)t32.size();
+      t32.resize(t32.size() + 256);
+      dct16(h, &t32[S.dh]);
+      S.lam = (int)t32.size();
+      t32.resize(t32.size() + 256, 0.f);
+      for (int q = 0; q < h; ++q)
+        for (int p = 0; p < w; ++p) t32[S.lam + q * 16 + p] = (float)lam[(size_t)q * w + p];
+    } else {
+      S.dw = S.dh = S.lam = -1;
+    }
+  }
+  ts.tab32_floats = (int)t32.size();
+  size_t b32 = t32.size() * sizeof(float), b64 = t64.size() * sizeof(double);
+  int rc = dev_alloc(c, (void **)&ts.tab32, b32, "tables");
+  if (rc) return rc;
+  rc = dev_alloc(c, (void **)&ts.tab64, b64, "tables");
+  if (rc) { dev_free(c, ts.tab32, b32); return rc; }
+  ts.bytes = b32 + b64;
+  hipError_t e = hipMemcpy(ts.tab32, t32.data(), b32, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ts.tab64, t64.data(), b64, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    dev_free(c, ts.tab32, b32);
+    dev_free(c, ts.tab64, b64);
+    return hip_fail(c, e, "table upload");
+  }
+  auto res = c->tables.emplace(key, ts);
+  *out = &res.first->second;
+  return PDI_OK;
+}
+
+int ensure_workspace(pdi_ctx *c, int n_items, int b) {
+  if (n_items > c->deferred_cap) {
+    dev_free(c, c->deferred, sizeof(int) * (size_t)c->deferred_cap);
+    c->deferred = nullptr;
+    c->deferred_cap = 0;
+    int rc = dev_alloc(c, (void **)&c->deferred, sizeof(int) * (size_t)n_items, "deferred list");
+    if (rc) return rc;
+    c->deferred_cap = n_items;
+  }
+  // Global-memory systems for K > kLdsKMax: (K+1) rows of K+1+2 floats with
+  // K <= b*b - 1 (K = b*b is decoded by copying the values).
+  int nmax = b * b;
+  long long need = (long long)nmax * (nmax + 2);
+  if (nmax > pdi::kLdsKMax + 1 && need > c->slot_floats) {
+    dev_free(c, c->slots, sizeof(float) * (size_t)c->slot_floats * pdi::kDeferredGrid);
+    c->slots = nullptr;
+    c->slot_floats = 0;
+    int rc = dev_alloc(c, (void **)&c->slots, sizeof(float) * (size_t)need * pdi::kDeferredGrid,
+                       "system slots");
+    if (rc) return rc;
+    c->slot_floats = need;
+  }
+  return PDI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pdi_default_params(pdi_params *p) {
+  if (!p) return;
+  p->op = PDI_OP_DISCRETE;
+  p->s = 1.0;
+  p->eval_dtype = PDI_EVAL_FP32;
+  p->refine = 1;
+  p->validate = 0;
+  p->path = PDI_PATH_AUTO;
+  p->refine_tau = 1.0 / 64.0;
+}
+
+int pdi_create(pdi_ctx **out, int device, size_t hbm_budget_bytes) {
+  if (!out) return PDI_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return PDI_EINVAL;
+  pdi_ctx *c = new (std::nothrow) pdi_ctx();
+  if (!c) return PDI_ENOMEM;
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) { delete c; return PDI_EHIP; }
+  int rc = dev_alloc(c, (void **)&c->status, sizeof(int) * 4, "status");
+  if (!rc) rc = dev_alloc(c, (void **)&c->counters, sizeof(int) * 8, "counters");
+  if (rc) { pdi_destroy(c); return rc; }
+  if (hipMemset(c->status, 0, sizeof(int) * 4) != hipSuccess ||
+      hipMemset(c->counters, 0, sizeof(int) * 8) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    pdi_destroy(c);
+    return PDI_EHIP;
+  }
+  *out = c;
+  return PDI_OK;
+}
+
+void pdi_destroy(pdi_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto &kv : c->tables) {
+    dev_free(c, kv.second.tab32, sizeof(float) * (size_t)kv.second.tab32_floats);
+    (void)hipFree(kv.second.tab64);
+  }
+  (void)hipFree(c->status);
+  (void)hipFree(c->counters);
+  (void)hipFree(c->deferred);
+  (void)hipFree(c->slots);
+  delete c;
+}
+
+const char *pdi_last_error(pdi_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int pdi_frame_info(const pdi_frame *frame, int block_size, int chroma_shared,
+                   int32_t *n_mask_blocks, int64_t *out_elems) {
+  if (check_geometry(frame, block_size)) return PDI_EINVAL;
+  PlaneGeom pg[3];
+  int np = planes_of(frame, pg);
+  if (n_mask_blocks) *n_mask_blocks = (int32_t)mask_blocks_of(frame, block_size, chroma_shared && frame->format == PDI_YUV420);
+  if (out_elems) {
+    int64_t n = 0;
+    for (int i = 0; i < np; ++i) n += (int64_t)pg[i].W * pg[i].H;
+    *out_elems = n;
+  }
+  return PDI_OK;
+}
+
+int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, const float *values,
+                    int block_size, const pdi_params *params, float *out, void *stream) {
+  if (!c) return PDI_EINVAL;
+  if (!frame || !mask || !out) return set_err(c, PDI_EINVAL, "null frame, mask or out");
+  if (check_geometry(frame, block_size))
+    return set_err(c, PDI_EINVAL, "bad geometry %dx%d format %d block %d", frame->width,
+                   frame->height, frame->format, block_size);
+  pdi_params P;
+  pdi_default_params(&P);
+  if (params) P = *params;
+  if (P.op != PDI_OP_DISCRETE && P.op != PDI_OP_CONTINUOUS) return set_err(c, PDI_EINVAL, "bad op");
+  if (!(P.s > 0.0) || !(P.s <= 8.0)) return set_err(c, PDI_EINVAL, "s must be in (0, 8]");
+  if (P.eval_dtype < PDI_EVAL_FP32 || P.eval_dtype > PDI_EVAL_BF16X2) return set_err(c, PDI_EINVAL, "bad eval_dtype");
+  if (P.refine < 0 || P.refine > 2) return set_err(c, PDI_EINVAL, "bad refine");
+  if (P.path != PDI_PATH_AUTO && P.path != PDI_PATH_PLAIN) return set_err(c, PDI_EINVAL, "bad path");
+  if (!(P.refine_tau >= 0.0) || !(P.refine_tau <= 1.0)) return set_err(c, PDI_EINVAL, "bad refine_tau");
+  int shared = (frame->format == PDI_YUV420 && mask->chroma_shared) ? 1 : 0;
+  long long nitems = mask_blocks_of(frame, block_size, shared);
+  if (nitems != mask->n_mask_blocks)
+    return set_err(c, PDI_EINVAL, "n_mask_blocks %d, geometry needs %lld", mask->n_mask_blocks, nitems);
+  if (!mask->block_ptr || (!mask->pos) || !values)
+    return set_err(c, PDI_EINVAL, "null block_ptr, pos or values");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+
+  TableSet *ts = nullptr;
+  int rc = get_tables(c, frame, block_size, shared, P, &ts);
+  if (rc) return rc;
+  rc = ensure_workspace(c, (int)nitems, block_size);
+  if (rc) return rc;
+
+  pdi::FrameDev F;
+  std::memset(&F, 0, sizeof F);
+  F.b = block_size;
+  F.n_items = (int)nitems;
+  F.shared = shared;
+  F.validate = P.validate ? 1 : 0;
+  F.refine = P.refine;
+  F.tau = (float)P.refine_tau;
+  F.eval = P.eval_dtype;
+  PlaneGeom pg[3];
+  planes_of(frame, pg);
+  long long poff[3] = {0, 0, 0};
+  for (int i = 1; i < 3; ++i) poff[i] = poff[i - 1] + (long long)pg[i - 1].W * pg[i - 1].H;
+  int mp[3], vp[3][2], nv[3];
+  F.ngroups = groups_of(frame, shared, mp, vp, nv);
+  int first = 0;
+  F.chroma_first = -1;
+  for (int g = 0; g < F.ngroups; ++g) {
+    pdi::GroupDev &G = F.g[g];
+    G.first = first;
+    G.W = pg[mp[g]].W;
+    G.H = pg[mp[g]].H;
+    G.nbx = (G.W + block_size - 1) / block_size;
+    G.nby = (G.H + block_size - 1) / block_size;
+    G.nv = nv[g];
+    for (int k = 0; k < nv[g]; ++k) { G.vplane[k] = vp[g][k]; G.out_off[k] = poff[vp[g][k]]; }
+    for (int k = 0; k < 4; ++k) G.shape[k] = ts->group_shape[g][k];
+    if (mp[g] == 1) F.chroma_first = first;
+    first += G.nbx * G.nby;
+  }
+  F.nshapes = ts->nshapes;
+  for (int k = 0; k < ts->nshapes; ++k) F.s[k] = ts->s[k];
+  F.tab32_floats = ts->tab32_floats;
+  F.block_ptr = mask->block_ptr;
+  F.pos = mask->pos;
+  F.values = values;
+  F.out = out;
+  F.tab32 = ts->tab32;
+  F.tab64 = ts->tab64;
+  F.deferred = c->deferred;
+  F.counters = c->counters;
+  F.status = c->status;
+  F.slots = c->slots;
+  F.slot_floats = c->slot_floats;
+
+  hipStream_t s = (hipStream_t)stream;
+  if (P.path == PDI_PATH_AUTO && block_size <= 16)
+    e = pdi::launch_fast(F, s);
+  else
+    e = pdi::launch_plain_all(F, s);
+  if (e == hipSuccess) e = pdi::launch_general_deferred(F, s);
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return PDI_OK;
+}
+
+int pdi_sync(pdi_ctx *c, void *stream) {
+  if (!c) return PDI_EINVAL;
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  int st = 0;
+  e = hipMemcpy(&st, c->status, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "status read");
+  if (st) {
+    e = hipMemset(c->status, 0, sizeof(int));
+    if (e == hipSuccess) e = hipMemset(c->counters, 0, sizeof(int) * 8);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(c, e, "status reset");
+    if (st & pdi::kStatusMask) return set_err(c, PDI_EMASK, "device validation: bad mask positions");
+    if (st & pdi::kStatusValue) return set_err(c, PDI_EVALUE, "device validation: non-finite value");
+    return set_err(c, PDI_ESOLVE, "a block system broke down (non-finite solution)");
+  }
+  return PDI_OK;
+}
+
+int pdi_validate_host(const pdi_frame *frame, int block_size, const int32_t *block_ptr,
+                      const uint16_t *pos, int32_t n_mask_blocks, int32_t chroma_shared,
+                      const float *values) {
+  if (check_geometry(frame, block_size) || !block_ptr) return PDI_EINVAL;
+  int shared = (frame->format == PDI_YUV420 && chroma_shared) ? 1 : 0;
+  if (mask_blocks_of(frame, block_size, shared) != n_mask_blocks) return PDI_EINVAL;
+  PlaneGeom pg[3];
+  planes_of(frame, pg);
+  int mp[3], vp[3][2], nv[3];
+  int ng = groups_of(frame, shared, mp, vp, nv);
+  if (block_ptr[0] != 0) return PDI_EMASK;
+  int m = 0;
+  long long chroma_first_ptr = -1, chroma_nnz = 0;
+  for (int g = 0; g < ng; ++g) {
+    int W = pg[mp[g]].W, H = pg[mp[g]].H, b = block_size;
+    if (mp[g] == 1) chroma_first_ptr = block_ptr[m];
+    for (int by = 0; by < (H + b - 1) / b; ++by)
+      for (int bx = 0; bx < (W + b - 1) / b; ++bx, ++m) {
+        int w = W - bx * b < b ? W - bx * b : b, h = H - by * b < b ? H - by * b : b;
+        int lo = block_ptr[m], hi = block_ptr[m + 1];
+        if (hi < lo || hi - lo > w * h) return PDI_EMASK;
+        if (!pos && hi > lo) return PDI_EINVAL;
+        for (int i = lo; i < hi; ++i) {
+          if (pos[i] >= w * h) return PDI_EMASK;
+          if (i > lo && pos[i] <= pos[i - 1]) return PDI_EMASK;
+        }
+      }
+  }
+  long long nnz = block_ptr[n_mask_blocks];
+  if (shared) chroma_nnz = nnz - chroma_first_ptr;
+  long long nval = nnz + chroma_nnz;
+  if (nval > 0 && !values) return PDI_EINVAL;
+  for (long long i = 0; i < nval; ++i)
+    if (!std::isfinite(values[i])) return PDI_EVALUE;
+  return PDI_OK;
+}
+
+int pdi_pack_dense(const pdi_frame *frame, const uint8_t *m, const float *f, int block_size,
+                   int chroma_shared, int32_t *block_ptr, uint16_t *pos, int64_t *pos_cap,
+                   float *values, int64_t *val_cap) {
+  if (check_geometry(frame, block_size) || !m || !f || !block_ptr || !pos || !pos_cap ||
+      !values || !val_cap)
+    return PDI_EINVAL;
+  int shared = (frame->format == PDI_YUV420 && chroma_shared) ? 1 : 0;
+  PlaneGeom pg[3];
+  int np = planes_of(frame, pg);
+  long long foff[3] = {0, 0, 0};
+  for (int i = 1; i < np; ++i) foff[i] = foff[i - 1] + (long long)pg[i - 1].W * pg[i - 1].H;
+  int mp[3], vp[3][2], nv[3];
+  int ng = groups_of(frame, shared, mp, vp, nv);
+  // mask planes back to back: Y, then C (shared) or Cb, Cr
+  long long moff[3] = {0, 0, 0};
+  for (int g = 1; g < ng; ++g) moff[g] = moff[g - 1] + (long long)pg[mp[g - 1]].W * pg[mp[g - 1]].H;
+  long long np_ = 0, nvv = 0;
+  int mb = 0;
+  block_ptr[0] = 0;
+  std::vector<float> cr;  // shared Cr values follow all other values
+  for (int g = 0; g < ng; ++g) {
+    int W = pg[mp[g]].W, H = pg[mp[g]].H, b = block_size;
+    for (int by = 0; by < (H + b - 1) / b; ++by)
+      for (int bx = 0; bx < (W + b - 1) / b; ++bx) {
+        int w = W - bx * b < b ? W - bx * b : b, h = H - by * b < b ? H - by * b : b;
+        for (int y = 0; y < h; ++y)
+          for (int x = 0; x < w; ++x) {
+            long long px = (long long)(by * b + y) * W + bx * b + x;
+            if (!m[moff[g] + px]) continue;
+            if (np_ >= *pos_cap || nvv >= *val_cap) return PDI_ENOMEM;
+            pos[np_++] = (uint16_t)(y * w + x);
+            values[nvv++] = f[foff[vp[g][0]] + px];
+            if (nv[g] == 2) cr.push_back(f[foff[vp[g][1]] + px]);
+          }
+        block_ptr[++mb] = (int32_t)np_;
+      }
+  }
+  for (float v : cr) {
+    if (nvv >= *val_cap) return PDI_ENOMEM;
+    values[nvv++] = v;
+  }
+  *pos_cap = np_;
+  *val_cap = nvv;
+  return PDI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Internal descriptors shared by the host side (pdinp_host.cpp) and the
+// gfx950 kernels (pdinp_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdi {
+
+constexpr int kMaxShapes = 8;   // distinct (w, h) block shapes per frame
+constexpr int kMaxGroups = 3;   // mask-plane groups: Y, (C) or (Cb, Cr)
+constexpr int kFastKMax = 31;   // largest K of the wave-level path (R <= 32 rows)
+constexpr int kLdsKMax = 96;    // largest K whose bordered system fits in LDS (general path)
+constexpr int kDeferredGrid = 64;  // persistent workgroups of the general path
+constexpr int kWaveItems = 4;      // blocks per wave in the wave-level path
+
+// Device status bits (OR-ed by kernels, read by pdi_sync).
+constexpr int kStatusMask = 1;
+constexpr int kStatusValue = 2;
+constexpr int kStatusSolve = 4;
+
+// Per distinct block shape: offsets of its tables in the table buffers.
+struct ShapeDev {
+  int w, h;
+  int hc32;  // FP32 compact Green table, (w+1)*(h+1), quarter-scaled (floats)
+  int hc64;  // same in FP64 (doubles)
+  int dw;    // DCT-II matrix rows p < 16, cols x < 16, zero padded (floats)
+  int dh;    // DCT-II matrix rows q, cols y, zero padded (floats)
+  int lam;   // eigenvalues lam[q*16 + p], zero padded, lam_00 = 0 (floats)
+};
+
+// Per mask-plane group (Y; shared chroma; or Cb and Cr separately).
+struct GroupDev {
+  int first;            // first mask-block index of the group
+  int W, H, nbx, nby;   // geometry of the plane the mask lives on
+  int nv;               // value sets decoded with this mask (1, or 2 for shared chroma)
+  int vplane[2];        // value planes (0 = Y, 1 = Cb, 2 = Cr)
+  long long out_off[2]; // output offset of each value plane (floats)
+  int shape[4];         // shape ids: full, right edge, bottom edge, corner
+};
+
+struct FrameDev {
+  int b;
+  int n_items;       // mask blocks
+  int ngroups;
+  int shared;        // shared chroma mask
+  int chroma_first;  // first chroma mask block (shared Cr values are addressed from it)
+  int nshapes;
+  int validate;
+  int refine;        // 0 off, 1 auto, 2 always
+  float tau;         // auto-refine threshold on min/max pivot
+  int eval;          // PDI_EVAL_*
+  GroupDev g[kMaxGroups];
+  ShapeDev s[kMaxShapes];
+  int tab32_floats;  // size of the FP32 table buffer (floats)
+  // buffers
+  const int32_t *block_ptr;
+  const uint16_t *pos;
+  const float *values;
+  float *out;
+  const float *tab32;
+  const double *tab64;
+  int *deferred;   // list of mask blocks left to the general path
+  int *counters;   // [0] deferred count, [1] done workgroups
+  int *status;     // device status word
+  float *slots;    // global-memory systems for K > kLdsKMax, one slot per workgroup
+  long long slot_floats;
+};
+
+// Launchers (pdinp_kernels.hip).  All asynchronous on `stream`.
+hipError_t launch_fast(const FrameDev &f, hipStream_t stream);
+hipError_t launch_plain_all(const FrameDev &f, hipStream_t stream);
+hipError_t launch_general_deferred(const FrameDev &f, hipStream_t stream);
+
+}  // namespace pdi

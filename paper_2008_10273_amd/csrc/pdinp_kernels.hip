@@ -1,0 +1,672 @@
+// gfx950 kernels of the residual decoder.
+//
+// Per block (Sec. 2.2 of the paper): assemble the kernel matrix G_K over the
+// K mask points from the Green's function, solve the bordered (K+1) system
+// [G_K 1; 1^T 0][c; a] = [r; 0], and evaluate u(x) = sum_i c_i G(x, x_i) + a
+// at every pixel of the block.
+//
+// Two paths:
+//  * k_fast - wave-level, 4 blocks per wave, one 16-lane DPP row per block,
+//    a lane holds one (K <= 15) or two (K <= 31) rows of the bordered
+//    system in VGPRs.  Gauss-Jordan elimination without pivoting (the
+//    leading K x K block is SPD, and the last pivot is -1^T G_K^-1 1 != 0);
+//    pivot rows are broadcast with DPP row_newbcast.  The evaluation uses the
+//    DCT-II factorisation of G (Eq. 4): V = Dw[:,X] diag(c) Dh[:,Y]^T (inner
+//    dimension K), U = Dh^T (lam .* V^T) Dw, as chained 16x16x4 FP32 MFMAs.
+//  * k_general - one 256-thread workgroup per block, system in LDS (or a
+//    global slot for large K), Gauss-Jordan with barriers, direct
+//    evaluation through the Green table.  It is the plain per-block path,
+//    and the fallback for blocks the fast path does not take.
+#include "pdinp_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace pdi {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ items
+
+struct Item {
+  int K, base, w, h, x0, y0, shape, nv, W;
+  long long vbase0, vbase1, obase0, obase1;
+  __device__ __forceinline__ long long vbase(int v) const { return v ? vbase1 : vbase0; }
+  __device__ __forceinline__ long long obase(int v) const { return v ? obase1 : obase0; }
+};
+
+__device__ __forceinline__ Item load_item(const FrameDev &f, int m) {
+  Item it;
+  int g = 0;
+  if (f.ngroups > 1 && m >= f.g[1].first) g = 1;
+  if (f.ngroups > 2 && m >= f.g[2].first) g = 2;
+  const GroupDev &G = f.g[g];
+  const int b = f.b;
+  int l = m - G.first;
+  int bx = l % G.nbx, by = l / G.nbx;
+  it.x0 = bx * b;
+  it.y0 = by * b;
+  it.w = min(b, G.W - it.x0);
+  it.h = min(b, G.H - it.y0);
+  int e = ((bx == G.nbx - 1) && (G.W % b) ? 1 : 0) + ((by == G.nby - 1) && (G.H % b) ? 2 : 0);
+  it.shape = G.shape[e];
+  int lo = f.block_ptr[m], hi = f.block_ptr[m + 1];
+  it.K = hi - lo;
+  it.base = lo;
+  it.nv = G.nv;
+  it.W = G.W;
+  const long long pix = (long long)it.y0 * G.W + it.x0;
+  it.vbase0 = lo;
+  it.obase0 = G.out_off[0] + pix;
+  if (G.nv > 1) {
+    // a shared chroma mask: the Cr run follows every other value
+    it.vbase1 = f.shared ? (long long)f.block_ptr[f.n_items] + (lo - f.block_ptr[f.chroma_first]) : lo;
+    it.obase1 = G.out_off[1] + pix;
+  } else {
+    it.vbase1 = it.vbase0;
+    it.obase1 = it.obase0;
+  }
+  return it;
+}
+
+// Green's function from the quarter-scaled compact table of a w x h shape:
+// G(x_a, x_b) = sum over the 4 (alpha, beta) pairs from |x_a - x_b| and the
+// reflected x_a + x_b + 1 per axis.
+template <typename T>
+__device__ __forceinline__ T green_tab(const T *tab, int w, int h, int xa, int ya, int xb, int yb) {
+  const int W1 = w + 1;
+  int dx = abs(xa - xb), dy = abs(ya - yb);
+  int sx = xa + xb + 1, sy = ya + yb + 1;
+  sx = min(sx, 2 * w - sx);
+  sy = min(sy, 2 * h - sy);
+  return (tab[dy * W1 + dx] + tab[dy * W1 + sx]) + (tab[sy * W1 + dx] + tab[sy * W1 + sx]);
+}
+
+__device__ __forceinline__ void push_deferred(const FrameDev &f, int m, int K, int w, int h) {
+  if (K > kLdsKMax && K < w * h) {
+    int idx = atomicAdd(&f.counters[1], 1);
+    f.deferred[f.n_items - 1 - idx] = m;
+  } else {
+    int idx = atomicAdd(&f.counters[0], 1);
+    f.deferred[idx] = m;
+  }
+}
+
+// ------------------------------------------------------- general per-block
+
+constexpr int kGenThreads = 256;
+constexpr int kGenMaxK = 1024;  // b = 32: at most 32*32 points
+constexpr int kTabMax = 33 * 33;
+
+struct GenShared {
+  float M[(kLdsKMax + 1) * (kLdsKMax + 3)];
+  float tab[kTabMax];
+  short px[kGenMaxK], py[kGenMaxK];
+  float c[2][kGenMaxK];
+  float fcol[kGenMaxK + 1];
+  float rho[kGenMaxK + 1];
+  double red[kGenThreads / 64];
+  float redf[2][kGenThreads / 64];
+  int flag;
+};
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int wid = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < kGenThreads / 64; ++i) s += red[i];
+  return s;
+}
+
+// Decode one block with a whole workgroup.  M points at LDS (K <= kLdsKMax)
+// or at a global slot (ld = row stride).
+__device__ void general_block(const FrameDev &f, int m, GenShared &sh, float *M) {
+  const int tid = threadIdx.x;
+  const Item it = load_item(f, m);
+  const int K = it.K, w = it.w, h = it.h, N = w * h;
+  const ShapeDev S = f.s[it.shape];
+  float *out = f.out;
+
+  if (tid == 0) sh.flag = 0;
+  __syncthreads();
+  if (K < 0 || K > N) {
+    if (tid == 0) atomicOr(f.status, kStatusMask);
+    for (int v = 0; v < it.nv; ++v)
+      for (int p = tid; p < N; p += kGenThreads) out[it.obase(v) + (p / w) * it.W + p % w] = 0.f;
+    return;
+  }
+  if (f.validate) {
+    int bad = 0;
+    for (int i = tid; i < K; i += kGenThreads) {
+      int p = f.pos[it.base + i];
+      if (p >= N || (i > 0 && f.pos[it.base + i - 1] >= p)) bad |= kStatusMask;
+      for (int v = 0; v < it.nv; ++v)
+        if (!isfinite(f.values[it.vbase(v) + i])) bad |= kStatusValue;
+    }
+    if (bad) { atomicOr(f.status, bad); atomicOr(&sh.flag, 1); }
+    __syncthreads();
+    if (sh.flag) {
+      for (int v = 0; v < it.nv; ++v)
+        for (int p = tid; p < N; p += kGenThreads) out[it.obase(v) + (p / w) * it.W + p % w] = 0.f;
+      return;
+    }
+  }
+  if (K == 0) {
+    for (int v = 0; v < it.nv; ++v)
+      for (int p = tid; p < N; p += kGenThreads) out[it.obase(v) + (p / w) * it.W + p % w] = 0.f;
+    return;
+  }
+  if (K == N) {  // every pixel known: u = r (the system is singular here)
+    for (int v = 0; v < it.nv; ++v)
+      for (int i = tid; i < K; i += kGenThreads) {
+        int p = min((int)f.pos[it.base + i], N - 1);
+        out[it.obase(v) + (p / w) * it.W + p % w] = f.values[it.vbase(v) + i];
+      }
+    return;
+  }
+
+  for (int i = tid; i < (w + 1) * (h + 1); i += kGenThreads) sh.tab[i] = f.tab32[S.hc32 + i];
+  for (int i = tid; i < K; i += kGenThreads) {
+    int p = min((int)f.pos[it.base + i], N - 1);
+    sh.px[i] = (short)(p % w);
+    sh.py[i] = (short)(p / w);
+  }
+  __syncthreads();
+
+  // Bordered system, rows 0..K, columns 0..K then the value columns.
+  const int n = K + 1, ld = n + it.nv;
+  const int lane = tid & 63, wid = tid >> 6;
+  for (int i = wid; i < n; i += kGenThreads / 64)
+    for (int k = lane; k < ld; k += 64) {
+      float v;
+      if (k < K) v = (i < K) ? green_tab(sh.tab, w, h, sh.px[i], sh.py[i], sh.px[k], sh.py[k]) : 1.f;
+      else if (k == K) v = (i < K) ? 1.f : 0.f;
+      else v = (i < K) ? f.values[it.vbase(k - n) + i] : 0.f;
+      M[(long long)i * ld + k] = v;
+    }
+
+  // Gauss-Jordan without pivoting; the multiplier of row i at step j is kept
+  // in M[i][j] for the refinement replay.
+  for (int j = 0; j < n; ++j) {
+    __syncthreads();
+    const float piv = M[(long long)j * ld + j];
+    const float rp = 1.0f / piv;
+    for (int i = tid; i < n; i += kGenThreads) sh.fcol[i] = (i == j) ? 0.f : M[(long long)i * ld + j] * rp;
+    __syncthreads();
+    for (int i = wid; i < n; i += kGenThreads / 64) {
+      if (i == j) continue;
+      const float fi = sh.fcol[i];
+      for (int k = j + 1 + lane; k < ld; k += 64)
+        M[(long long)i * ld + k] = fmaf(-fi, M[(long long)j * ld + k], M[(long long)i * ld + k]);
+      if (lane == 0) M[(long long)i * ld + j] = fi;
+    }
+  }
+  __syncthreads();
+
+  // Solution and pivot ratio over the SPD block.
+  float dmin = 3.0e38f, dmax = 0.f;
+  for (int i = tid; i < K; i += kGenThreads) {
+    float d = fabsf(M[(long long)i * ld + i]);
+    dmin = fminf(dmin, d);
+    dmax = fmaxf(dmax, d);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    dmin = fminf(dmin, __shfl_xor(dmin, o));
+    dmax = fmaxf(dmax, __shfl_xor(dmax, o));
+  }
+  if (lane == 0) { sh.redf[0][wid] = dmin; sh.redf[1][wid] = dmax; }
+  for (int v = 0; v < it.nv; ++v)
+    for (int i = tid; i < n; i += kGenThreads) {
+      float x = M[(long long)i * ld + n + v] / M[(long long)i * ld + i];
+      if (i < K) sh.c[v][i] = x; else sh.rho[v] = x;  // rho[0..nv) holds a until reused
+    }
+  __syncthreads();
+  dmin = fminf(fminf(sh.redf[0][0], sh.redf[0][1]), fminf(sh.redf[0][2], sh.redf[0][3]));
+  dmax = fmaxf(fmaxf(sh.redf[1][0], sh.redf[1][1]), fmaxf(sh.redf[1][2], sh.redf[1][3]));
+  float a_v[2] = {sh.rho[0], it.nv > 1 ? sh.rho[1] : 0.f};
+  const bool refine = (f.refine == 2) || (f.refine == 1 && !(dmin >= f.tau * dmax));
+
+  if (refine) {
+    const double *tab64 = f.tab64 + S.hc64;
+    for (int v = 0; v < it.nv; ++v) {
+      __syncthreads();
+      // FP64 residual of the bordered system: rho_i = r_i - a - sum_k G_ik c_k,
+      // rho_K = -sum_k c_k.
+      double cs = 0.0;
+      for (int i = tid; i < K; i += kGenThreads) cs += (double)sh.c[v][i];
+      cs = block_sum(cs, sh.red);
+      for (int i = tid; i < K; i += kGenThreads) {
+        double acc = 0.0;
+        for (int k = 0; k < K; ++k)
+          acc += green_tab(tab64, w, h, (int)sh.px[i], (int)sh.py[i], (int)sh.px[k], (int)sh.py[k]) *
+                 (double)sh.c[v][k];
+        double r = (double)f.values[it.vbase(v) + i];
+        sh.rho[i] = (float)(r - (double)a_v[v] - acc);
+      }
+      if (tid == 0) sh.rho[K] = (float)(-cs);
+      // Replay the elimination on rho, then divide by the pivots.
+      for (int j = 0; j < n; ++j) {
+        __syncthreads();
+        const float tj = sh.rho[j];
+        __syncthreads();
+        for (int i = tid; i < n; i += kGenThreads)
+          if (i != j) sh.rho[i] = fmaf(-M[(long long)i * ld + j], tj, sh.rho[i]);
+      }
+      __syncthreads();
+      for (int i = tid; i < K; i += kGenThreads) sh.c[v][i] += sh.rho[i] / M[(long long)i * ld + i];
+      a_v[v] += sh.rho[K] / M[(long long)K * ld + K];
+    }
+    __syncthreads();
+  }
+
+  // Direct evaluation u(x) = sum_i c_i G(x, x_i) + a.
+  bool bad = false;
+  for (int p = tid; p < N; p += kGenThreads) {
+    const int xx = p % w, yy = p / w;
+    float acc0 = 0.f, acc1 = 0.f;
+    for (int i = 0; i < K; ++i) {
+      float g = green_tab(sh.tab, w, h, xx, yy, (int)sh.px[i], (int)sh.py[i]);
+      acc0 = fmaf(sh.c[0][i], g, acc0);
+      if (it.nv > 1) acc1 = fmaf(sh.c[1][i], g, acc1);
+    }
+    float u0 = acc0 + a_v[0];
+    bad |= !isfinite(u0);
+    out[it.obase0 + (long long)yy * it.W + xx] = u0;
+    if (it.nv > 1) {
+      float u1 = acc1 + a_v[1];
+      bad |= !isfinite(u1);
+      out[it.obase1 + (long long)yy * it.W + xx] = u1;
+    }
+  }
+  if (bad) atomicOr(f.status, kStatusSolve);
+}
+
+// One workgroup per mask block (the plain per-block path).  Blocks whose
+// system does not fit in LDS go to the large list.
+__global__ __launch_bounds__(kGenThreads) void k_plain_all(FrameDev f) {
+  __shared__ GenShared sh;
+  const int m = blockIdx.x;
+  if (m >= f.n_items) return;
+  const Item it = load_item(f, m);
+  if (it.K > kLdsKMax && it.K < it.w * it.h) {
+    if (threadIdx.x == 0) push_deferred(f, m, it.K, it.w, it.h);
+    return;
+  }
+  general_block(f, m, sh, sh.M);
+}
+
+// Persistent pass over the deferred lists; the last workgroup clears the
+// counters for the next decode on this context.
+__global__ __launch_bounds__(kGenThreads) void k_general_deferred(FrameDev f) {
+  __shared__ GenShared sh;
+  const int nmed = f.counters[0];
+  const int nlarge = f.counters[1];
+  for (int idx = blockIdx.x; idx < nmed; idx += gridDim.x) {
+    __syncthreads();
+    general_block(f, f.deferred[idx], sh, sh.M);
+  }
+  if (blockIdx.x < kDeferredGrid) {
+    float *slot = f.slots + (long long)blockIdx.x * f.slot_floats;
+    for (int idx = blockIdx.x; idx < nlarge; idx += kDeferredGrid) {
+      __syncthreads();
+      general_block(f, f.deferred[f.n_items - 1 - idx], sh, slot);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    int done = atomicAdd(&f.counters[2], 1);
+    if (done == (int)gridDim.x - 1) {
+      atomicExch(&f.counters[0], 0);
+      atomicExch(&f.counters[1], 0);
+      atomicExch(&f.counters[2], 0);
+      __threadfence();
+    }
+  }
+}
+
+// -------------------------------------------------------- wave-level path
+
+// Broadcast lane `src` of every 16-lane row (DPP row_newbcast).  `src` must
+// fold to a constant after unrolling.
+__device__ __forceinline__ int bcast_i(int x, int src) {
+#define PDI_NB(n) case n: return __builtin_amdgcn_update_dpp(0, x, 0x150 + n, 0xF, 0xF, false);
+  switch (src & 15) {
+    PDI_NB(0) PDI_NB(1) PDI_NB(2) PDI_NB(3) PDI_NB(4) PDI_NB(5) PDI_NB(6) PDI_NB(7)
+    PDI_NB(8) PDI_NB(9) PDI_NB(10) PDI_NB(11) PDI_NB(12) PDI_NB(13) PDI_NB(14) PDI_NB(15)
+  }
+#undef PDI_NB
+  return x;
+}
+__device__ __forceinline__ float bcast_f(float x, int src) {
+  return __builtin_bit_cast(float, bcast_i(__builtin_bit_cast(int, x), src));
+}
+
+// Reductions over the 16 lanes of a DPP row.
+__device__ __forceinline__ float row_min(float v) {
+  for (int o = 8; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 16));
+  return v;
+}
+__device__ __forceinline__ float row_max(float v) {
+  for (int o = 8; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 16));
+  return v;
+}
+
+struct WaveStage {
+  int x[kWaveItems][32];
+  int y[kWaveItems][32];
+  float c[kWaveItems][2][32];
+  float a[kWaveItems][2];
+};
+
+constexpr int kFastThreads = 256;
+constexpr int kFastWaves = kFastThreads / 64;
+
+// Solve the bordered systems of the wave's 4 blocks (R = 16 or 32 rows per
+// block) and leave x, y, c, a of every row in the wave's stage.
+template <int R, int NV>
+__device__ __forceinline__ void fast_solve(const FrameDev &f, const Item &it, bool ok, int t,
+                                           int gi, int Kw, const float *stab, WaveStage &st) {
+  constexpr int NS = R / 16;
+  const int K = ok ? it.K : 0;
+  const int w = it.w, h = it.h, N = w * h;
+  const ShapeDev S = f.s[it.shape];
+  const float *tab = stab + S.hc32;
+  int xr[NS], yr[NS];
+  float rv[NS][NV];
+  int bad = 0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = t + 16 * s;
+    xr[s] = 0;
+    yr[s] = 0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) rv[s][v] = 0.f;
+    if (i < K) {
+      int p = f.pos[it.base + i];
+      if (f.validate) {
+        if (p >= N || (i > 0 && (int)f.pos[it.base + i - 1] >= p)) bad |= kStatusMask;
+      }
+      p = min(p, N - 1);
+      xr[s] = p % w;
+      yr[s] = p / w;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        rv[s][v] = (v < it.nv) ? f.values[it.vbase(v) + i] : 0.f;
+        if (f.validate && !isfinite(rv[s][v])) bad |= kStatusValue;
+      }
+    }
+  }
+  if (bad) atomicOr(f.status, bad);
+
+  // Assembly: row i of [G_K 1; 1^T 0], identity on padding rows.
+  float A[NS][R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int xk = bcast_i(xr[k >> 4], k & 15);
+    const int yk = bcast_i(yr[k >> 4], k & 15);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int i = t + 16 * s;
+      float g = green_tab(tab, w, h, xr[s], yr[s], xk, yk);
+      float v = (k < K) ? g : (k == K ? 1.f : 0.f);
+      if (i == K) v = (k < K) ? 1.f : 0.f;
+      if (i > K) v = (i == k) ? 1.f : 0.f;
+      A[s][k] = v;
+    }
+  }
+  float T[NS][NV];
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) T[s][v] = rv[s][v];
+
+  // Gauss-Jordan; multipliers stay in A[s][j] for the refinement replay.
+  float diag[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) diag[s] = 1.f;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    if (j <= Kw) {
+    const int jl = j & 15, js = j >> 4;
+    const float piv = bcast_f(A[js][j], jl);
+    const float rp = 1.0f / piv;
+    float fs[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const bool isj = (s == js) && (t == jl);
+      fs[s] = isj ? 0.f : A[s][j] * rp;
+      if (isj) diag[s] = piv;
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      if (k > j) {
+        const float bk = bcast_f(A[js][k], jl);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) A[s][k] = fmaf(-fs[s], bk, A[s][k]);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const float bt = bcast_f(T[js][v], jl);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) T[s][v] = fmaf(-fs[s], bt, T[s][v]);
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const bool isj = (s == js) && (t == jl);
+      A[s][j] = isj ? A[s][j] : fs[s];
+    }
+    }
+  }
+  float X[NS][NV];
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) X[s][v] = T[s][v] / diag[s];
+
+  // Pivot ratio of the SPD part (rows < K) decides the FP64 refinement.
+  float dmin = 3.0e38f, dmax = 0.f;
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+    if (t + 16 * s < K) { dmin = fminf(dmin, fabsf(diag[s])); dmax = fmaxf(dmax, fabsf(diag[s])); }
+  dmin = row_min(dmin);
+  dmax = row_max(dmax);
+  const bool need = ok && ((f.refine == 2) || (f.refine == 1 && !(dmin >= f.tau * dmax)));
+  if (__builtin_amdgcn_read_exec() & __ballot(need)) {
+    const double *tab64 = f.tab64 + S.hc64;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      // FP64 residual rho = [r; 0] - [G_K 1; 1^T 0][c; a].
+      double acc[NS], csum = 0.0, a = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        if (k <= Kw) {
+          const int xk = bcast_i(xr[k >> 4], k & 15);
+          const int yk = bcast_i(yr[k >> 4], k & 15);
+          const double ck = (double)bcast_f(X[k >> 4][v], k & 15);
+          if (k < K) {
+            csum += ck;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) acc[s] += green_tab(tab64, w, h, xr[s], yr[s], xk, yk) * ck;
+          }
+          if (k == K) a = ck;
+        }
+      }
+      float rho[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int i = t + 16 * s;
+        double r = 0.0;
+        if (i < K) r = (double)rv[s][v] - a - acc[s];
+        else if (i == K) r = -csum;
+        rho[s] = (float)r;
+      }
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (j <= Kw) {
+          const int jl = j & 15, js = j >> 4;
+          const float tj = bcast_f(rho[js], jl);
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const bool isj = (s == js) && (t == jl);
+            rho[s] = isj ? rho[s] : fmaf(-A[s][j], tj, rho[s]);
+          }
+        }
+      }
+      if (need) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) X[s][v] += rho[s] / diag[s];
+      }
+    }
+  }
+
+  // Stage x, y, c (rows < K) and a (row K) for the evaluation.
+  bool fin = true;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = t + 16 * s;
+    if (i < K) {
+      st.x[gi][i] = xr[s];
+      st.y[gi][i] = yr[s];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) { st.c[gi][v][i] = X[s][v]; fin &= isfinite(X[s][v]); }
+    } else if (i == K) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) { st.a[gi][v] = X[s][v]; fin &= isfinite(X[s][v]); }
+    }
+  }
+  if (ok && !fin) atomicOr(f.status, kStatusSolve);
+}
+
+// u = Dh^T (lam .* (Dw[:,X] diag(c) Dh[:,Y]^T)^T) Dw + a on one block, FP32
+// MFMA 16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]; the result
+// D[4(l/16)+r][l%16] sits in register r.
+__device__ __forceinline__ void fast_eval_block(const FrameDev &f, const float *stab,
+                                                const WaveStage &st, int gi, int lane, int K,
+                                                int shape, int nv, int w, int h, int W,
+                                                long long ob0, long long ob1) {
+  const ShapeDev S = f.s[shape];
+  const float *Dw = stab + S.dw, *Dh = stab + S.dh, *lam = stab + S.lam;
+  const int lo = lane & 15, hi = lane >> 4;
+  float lam4[4], dwb[4], dha[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int pq = 4 * hi + j;
+    lam4[j] = lam[lo * 16 + pq];  // lam[q][p], q = lo, p = 4 hi + j
+    dwb[j] = Dw[pq * 16 + lo];    // Dw[p][x], p = 4 hi + j, x = lo
+    dha[j] = Dh[pq * 16 + lo];    // Dh[q][y], q = 4 hi + j, y = lo
+  }
+  const int nch = (K + 3) >> 2;
+  for (int v = 0; v < nv; ++v) {
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int ch = 0; ch < nch; ++ch) {
+      const int i = ch * 4 + hi;
+      float aop = 0.f, bop = 0.f;
+      if (i < K) {
+        const int xi = st.x[gi][i], yi = st.y[gi][i];
+        aop = st.c[gi][v][i] * Dw[lo * 16 + xi];  // A[p][i], p = lo
+        bop = Dh[lo * 16 + yi];                   // B[i][q], q = lo
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
+    }
+    // acc[j] = V^T[p = 4 hi + j][q = lo]; scale by lam[q][p].
+    f4 Sx = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Sx = __builtin_amdgcn_mfma_f32_16x16x4f32(acc[j] * lam4[j], dwb[j], Sx, 0, 0, 0);
+    // Sx[j] = S[q = 4 hi + j][x = lo]
+    f4 U = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) U = __builtin_amdgcn_mfma_f32_16x16x4f32(dha[j], Sx[j], U, 0, 0, 0);
+    const float a = st.a[gi][v];
+    const long long ob = v ? ob1 : ob0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int y = 4 * hi + j, x = lo;
+      if (x < w && y < h) f.out[ob + (long long)y * W + x] = U[j] + a;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kFastThreads) void k_fast(FrameDev f) {
+  extern __shared__ float stab[];
+  __shared__ WaveStage stage[kFastWaves];
+  for (int i = threadIdx.x; i < f.tab32_floats; i += kFastThreads) stab[i] = f.tab32[i];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int gi = lane >> 4, t = lane & 15;
+  const int m = (blockIdx.x * kFastWaves + wv) * kWaveItems + gi;
+  const bool valid = m < f.n_items;
+  Item it;
+  if (valid) it = load_item(f, m);
+  else { it.K = 0; it.w = it.h = 1; it.nv = 1; it.shape = 0; it.base = 0; it.W = 1; it.x0 = it.y0 = 0;
+         it.vbase0 = it.vbase1 = it.obase0 = it.obase1 = 0; }
+  const bool ok = valid && it.K >= 1 && it.K <= kFastKMax && it.K < it.w * it.h;
+  if (valid && !ok && t == 0) push_deferred(f, m, it.K, it.w, it.h);
+
+  int kw = ok ? it.K : 0, nvw = ok ? it.nv : 0;
+  for (int o = 32; o > 0; o >>= 1) {
+    kw = max(kw, __shfl_xor(kw, o));
+    nvw = max(nvw, __shfl_xor(nvw, o));
+  }
+  const int Kw = __builtin_amdgcn_readfirstlane(kw);
+  const int NVw = __builtin_amdgcn_readfirstlane(nvw);
+  if (Kw == 0) return;
+  WaveStage &st = stage[wv];
+  if (Kw <= 15) {
+    if (NVw == 1) fast_solve<16, 1>(f, it, ok, t, gi, Kw, stab, st);
+    else fast_solve<16, 2>(f, it, ok, t, gi, Kw, stab, st);
+  } else {
+    if (NVw == 1) fast_solve<32, 1>(f, it, ok, t, gi, Kw, stab, st);
+    else fast_solve<32, 2>(f, it, ok, t, gi, Kw, stab, st);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  const unsigned long long okmask = __ballot(ok);
+#pragma unroll
+  for (int g2 = 0; g2 < kWaveItems; ++g2) {
+    if (!((okmask >> (16 * g2)) & 1ull)) continue;
+    const int K2 = __builtin_amdgcn_readlane(it.K, 16 * g2);
+    const int shape2 = __builtin_amdgcn_readlane(it.shape, 16 * g2);
+    const int nv2 = __builtin_amdgcn_readlane(it.nv, 16 * g2);
+    const int w2 = __builtin_amdgcn_readlane(it.w, 16 * g2);
+    const int h2 = __builtin_amdgcn_readlane(it.h, 16 * g2);
+    const int W2 = __builtin_amdgcn_readlane(it.W, 16 * g2);
+    const long long ob0 = ((long long)__builtin_amdgcn_readlane((int)(it.obase0 >> 32), 16 * g2) << 32) |
+                          (unsigned)__builtin_amdgcn_readlane((int)it.obase0, 16 * g2);
+    const long long ob1 = ((long long)__builtin_amdgcn_readlane((int)(it.obase1 >> 32), 16 * g2) << 32) |
+                          (unsigned)__builtin_amdgcn_readlane((int)it.obase1, 16 * g2);
+    fast_eval_block(f, stab, st, g2, lane, K2, shape2, nv2, w2, h2, W2, ob0, ob1);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_fast(const FrameDev &f, hipStream_t stream) {
+  const int per_block = kFastWaves * kWaveItems;
+  const int grid = (f.n_items + per_block - 1) / per_block;
+  if (grid == 0) return hipSuccess;
+  size_t lds = sizeof(float) * (size_t)f.tab32_floats;
+  hipLaunchKernelGGL(k_fast, dim3(grid), dim3(kFastThreads), lds, stream, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_all(const FrameDev &f, hipStream_t stream) {
+  if (f.n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plain_all, dim3(f.n_items), dim3(kGenThreads), 0, stream, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_general_deferred(const FrameDev &f, hipStream_t stream) {
+  hipLaunchKernelGGL(k_general_deferred, dim3(512), dim3(kGenThreads), 0, stream, f);
+  return hipGetLastError();
+}
+
+}  // namespace pdi

@@ -1,0 +1,199 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: every pixel within 0.5 grey levels of the oracle and identical 8-bit
+rounding (round half to even, clamp to [-128, 127]) on at least 99.9% of the
+pixels (the acceptance target of this decoder); for FP32 arithmetic also a
+tighter bound FP32_TOL derived from the arithmetic: relative error of a
+backward-stable FP32 solve ~ cond(G_K) * 2^-24 with cond(G_K) < 10^3 for the
+masks drawn here, times the value range 64, times 2 for solve + evaluation
+-> 7.6e-3, rounded up to 1e-2.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_10273_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-2
+
+
+@pytest.fixture(scope="module")
+def dec():
+    from paper_2008_10273_amd import binding
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = binding.Decoder(0)
+    yield d
+    d.close()
+
+
+def _q8(x):
+    return np.clip(np.rint(x), -128, 127)
+
+
+def gpu_decode(dec, fr, check_sync=True, **kw):
+    from paper_2008_10273_amd import binding
+    d = dec.upload(fr)
+    params = binding.default_params(**kw)
+    dec.decode(d, params)
+    rc = dec.sync()
+    if check_sync:
+        assert rc == 0, binding.pdi_last_error(dec.ctx)
+    return d["out"].cpu().numpy().astype(np.float64), rc
+
+
+def compare(got, ref):
+    err = np.abs(got - ref)
+    agree = float(np.mean(_q8(got) == _q8(ref)))
+    return float(err.max()) if err.size else 0.0, agree
+
+
+def check(dec, fr, tol=FP32_TOL, method=oracle.DIRECT, **kw):
+    print(f"case {fr.width}x{fr.height} fmt={fr.fmt} b={fr.block_size} shared={fr.chroma_shared} {kw}", flush=True)
+    got, _ = gpu_decode(dec, fr, **kw)
+    ref = oracle.decode_flat(fr, method=method)
+    assert np.all(np.isfinite(got))
+    mx, agree = compare(got, ref)
+    print(f"  max|err|={mx:.3e} round-agree={agree * 100:.4f}%", flush=True)
+    assert mx <= 0.5 and agree >= 0.999
+    assert mx <= tol
+    return mx, agree
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_config0(dec, path):
+    check(dec, synth.config_frame(0), path=path)
+
+
+@pytest.mark.parametrize("W,H,fmt,b,shared,dens", [
+    (70, 37, synth.YUV420, 16, True, (0.01, 0.12)),
+    (70, 37, synth.YUV420, 16, False, (0.01, 0.12)),
+    (53, 41, synth.GRAY, 8, False, (0.05, 0.45)),
+    (100, 67, synth.YUV420, 8, True, (0.02, 0.3)),
+    (96, 80, synth.YUV420, 16, True, (0.05, 0.5)),     # K up to 128: LDS general path
+    (64, 48, synth.GRAY, 16, False, (0.4, 0.95)),      # K > 96: global-slot path
+    (77, 45, synth.YUV420, 32, True, (0.02, 0.1)),     # b32 edge shapes
+    (64, 64, synth.GRAY, 32, False, (0.1, 0.2)),       # b32, K > 96
+    (15, 9, synth.GRAY, 16, False, (0.1, 0.5)),        # plane smaller than one block
+])
+@pytest.mark.parametrize("path", [0, 1])
+def test_ragged_frames(dec, W, H, fmt, b, shared, dens, path):
+    fr = synth.random_frame(W, H, fmt, b, dens, seed=W * H + b, chroma_shared=shared)
+    check(dec, fr, path=path)
+
+
+def _custom_frame(W, H, b, counts_fn, seed=0):
+    """GRAY frame whose block k gets counts_fn(k, w*h) random points."""
+    rng = np.random.default_rng(seed)
+    field = rng.uniform(-64, 64, (H, W))
+    m = np.zeros((H, W), bool)
+    for k, (x0, y0, w, h) in enumerate(synth.block_grid(W, H, b)):
+        K = counts_fn(k, w * h)
+        idx = rng.choice(w * h, K, replace=False)
+        m[y0 + idx // w, x0 + idx % w] = True
+    return synth.pack_dense(W, H, synth.GRAY, b, [m], [field])
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_empty_full_and_extreme_blocks(dec, path):
+    """K = 0 (u = 0), K = 1 (constant), K = w*h (u = r), K = w*h - 1 and a
+    mix of every K class in one frame."""
+    choices = lambda k, n: [0, 1, n, n - 1, 2, 31, 32, 15, 16, 96, 97, n // 2][k % 12] if n > 97 else min(n, k % 5)
+    fr = _custom_frame(64 + 13, 48 + 7, 16, choices, seed=3)
+    check(dec, fr, path=path)
+    fr = _custom_frame(40, 24, 8, lambda k, n: [0, 1, n, n - 1, 7, 31][k % 6], seed=4)
+    check(dec, fr, path=path)
+
+
+@pytest.mark.parametrize("refine", [0, 1, 2])
+def test_refine_modes(dec, refine):
+    fr = synth.random_frame(96, 64, synth.YUV420, 16, (0.01, 0.12), seed=11)
+    mx, _ = check(dec, fr, refine=refine)
+    if refine == 2:
+        assert mx <= 1e-3
+
+
+def test_clustered_mask_refinement(dec):
+    """A dense cluster of points is the ill-conditioned case; refinement
+    must bring the error down to FP32 level."""
+    W = H = 32
+    m = np.zeros((H, W), bool)
+    m[4:8, 4:8] = True  # 16-point cluster in block 0
+    m[20:23, 18:21] = True
+    m[0, 31] = True
+    rng = np.random.default_rng(2)
+    field = rng.uniform(-64, 64, (H, W))
+    fr = synth.pack_dense(W, H, synth.GRAY, 16, [m], [field])
+    for refine in (1, 2):
+        check(dec, fr, refine=refine)
+
+
+def test_biharmonic_and_continuous_operators(dec):
+    fr = synth.random_frame(64, 40, synth.GRAY, 16, (0.03, 0.12), seed=21)
+    check(dec, fr, method=oracle.DIRECT, s=2.0)
+    check(dec, fr, method=oracle.GREEN, op=1)
+
+
+def test_config1_full_frame(dec):
+    fr = synth.config_frame(1, keep_fields=False)
+    check(dec, fr)
+
+
+def test_config2_full_frame(dec):
+    fr = synth.config_frame(2, keep_fields=False)
+    check(dec, fr)
+
+
+def test_deterministic(dec):
+    fr = synth.random_frame(200, 120, synth.YUV420, 16, (0.01, 0.2), seed=5)
+    a, _ = gpu_decode(dec, fr)
+    b, _ = gpu_decode(dec, fr)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_device_validation(dec):
+    from paper_2008_10273_amd import binding
+    fr = synth.config_frame(0)
+    bad = synth.config_frame(0)
+    bad.pos = bad.pos.copy()
+    bad.pos[20] = bad.pos[19]  # duplicate inside block 1
+    _, rc = gpu_decode(dec, bad, check_sync=False, validate=1)
+    assert rc == binding.PDI_EMASK
+    bad = synth.config_frame(0)
+    bad.pos = bad.pos.copy()
+    bad.pos[40] = 300  # outside a 16x16 block
+    _, rc = gpu_decode(dec, bad, check_sync=False, validate=1)
+    assert rc == binding.PDI_EMASK
+    bad = synth.config_frame(0)
+    bad.values = bad.values.copy()
+    bad.values[3] = np.inf
+    _, rc = gpu_decode(dec, bad, check_sync=False, validate=1)
+    assert rc == binding.PDI_EVALUE
+    # the context stays usable
+    check(dec, fr)
+
+
+def test_too_many_points_is_flagged(dec):
+    from paper_2008_10273_amd import binding
+    fr = synth.pack_dense(16, 16, synth.GRAY, 16, [np.ones((16, 16), bool)], [np.zeros((16, 16))])
+    fr.block_ptr = np.array([0, 257], np.int32)
+    fr.pos = np.concatenate([fr.pos, np.array([0], np.uint16)])
+    fr.values = np.zeros(257, np.float32)
+    _, rc = gpu_decode(dec, fr, check_sync=False)
+    assert rc == binding.PDI_EMASK
+
+
+def test_host_errors(dec):
+    from paper_2008_10273_amd import binding
+    fr = synth.config_frame(0)
+    d = dec.upload(fr)
+    d["n_mask_blocks"] = 255
+    assert dec.decode(d, check=False) == binding.PDI_EINVAL
+    d["n_mask_blocks"] = 256
+    for bad in (dict(eval_dtype=9), dict(s=-1.0), dict(refine=5), dict(path=4)):
+        assert dec.decode(d, binding.default_params(**bad), check=False) == binding.PDI_EINVAL
+    assert dec.decode(d, check=False) == 0
+    assert dec.sync() == 0
