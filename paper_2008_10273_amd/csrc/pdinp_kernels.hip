@@ -94,6 +94,7 @@ __device__ __forceinline__ void push_deferred(const FrameDev &f, int m, int K, i
 // ------------------------------------------------------- general per-block
 
 constexpr int kGenThreads = 256;
+constexpr int kGeneralGrid = 128;  // persistent workgroups over the deferred lists
 constexpr int kGenMaxK = 1024;  // b = 32: at most 32*32 points
 constexpr int kTabMax = 33 * 33;
 
@@ -314,15 +315,16 @@ __global__ __launch_bounds__(kGenThreads) void k_general_deferred(FrameDev f) {
       general_block(f, f.deferred[f.n_items - 1 - idx], sh, slot);
     }
   }
+  // Every workgroup has read both counts before it gets here; the last one
+  // to arrive clears them for the next decode (the kernel boundary orders
+  // these writes before any later kernel on the stream).
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    int done = atomicAdd(&f.counters[2], 1);
+    int done = __hip_atomic_fetch_add(&f.counters[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (done == (int)gridDim.x - 1) {
-      atomicExch(&f.counters[0], 0);
-      atomicExch(&f.counters[1], 0);
-      atomicExch(&f.counters[2], 0);
-      __threadfence();
+      __hip_atomic_store(&f.counters[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&f.counters[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&f.counters[2], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
@@ -332,7 +334,7 @@ __global__ __launch_bounds__(kGenThreads) void k_general_deferred(FrameDev f) {
 // Broadcast lane `src` of every 16-lane row (DPP row_newbcast).  `src` must
 // fold to a constant after unrolling.
 __device__ __forceinline__ int bcast_i(int x, int src) {
-#define PDI_NB(n) case n: return __builtin_amdgcn_update_dpp(0, x, 0x150 + n, 0xF, 0xF, false);
+#define PDI_NB(n) case n: return __builtin_amdgcn_mov_dpp(x, 0x150 + n, 0xF, 0xF, true);
   switch (src & 15) {
     PDI_NB(0) PDI_NB(1) PDI_NB(2) PDI_NB(3) PDI_NB(4) PDI_NB(5) PDI_NB(6) PDI_NB(7)
     PDI_NB(8) PDI_NB(9) PDI_NB(10) PDI_NB(11) PDI_NB(12) PDI_NB(13) PDI_NB(14) PDI_NB(15)
@@ -363,27 +365,30 @@ struct WaveStage {
 
 constexpr int kFastThreads = 256;
 constexpr int kFastWaves = kFastThreads / 64;
+constexpr int kFastItems = kFastWaves * kWaveItems;  // blocks per workgroup
 
 // Solve the bordered systems of the wave's 4 blocks (R = 16 or 32 rows per
-// block) and leave x, y, c, a of every row in the wave's stage.
-template <int R, int NV>
-__device__ __forceinline__ void fast_solve(const FrameDev &f, const Item &it, bool ok, int t,
+// block, two value columns) and leave x, y, c, a of every row in the wave's
+// stage.  Returns false for a block whose pivots call for FP64 refinement;
+// such blocks are left to the general path, which refines.
+template <int R>
+__device__ __forceinline__ bool fast_solve(const FrameDev &f, const Item &it, bool ok, int t,
                                            int gi, int Kw, const float *stab, WaveStage &st) {
-  constexpr int NS = R / 16;
+  constexpr int NS = (R + 15) / 16;
+  constexpr int NV = 2;
   const int K = ok ? it.K : 0;
   const int w = it.w, h = it.h, N = w * h;
   const ShapeDev S = f.s[it.shape];
   const float *tab = stab + S.hc32;
   int xr[NS], yr[NS];
-  float rv[NS][NV];
+  float T[NS][NV];
   int bad = 0;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int i = t + 16 * s;
     xr[s] = 0;
     yr[s] = 0;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) rv[s][v] = 0.f;
+    T[s][0] = T[s][1] = 0.f;
     if (i < K) {
       int p = f.pos[it.base + i];
       if (f.validate) {
@@ -392,11 +397,9 @@ __device__ __forceinline__ void fast_solve(const FrameDev &f, const Item &it, bo
       p = min(p, N - 1);
       xr[s] = p % w;
       yr[s] = p / w;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        rv[s][v] = (v < it.nv) ? f.values[it.vbase(v) + i] : 0.f;
-        if (f.validate && !isfinite(rv[s][v])) bad |= kStatusValue;
-      }
+      T[s][0] = f.values[it.vbase0 + i];
+      if (it.nv > 1) T[s][1] = f.values[it.vbase1 + i];
+      if (f.validate && !(isfinite(T[s][0]) && isfinite(T[s][1]))) bad |= kStatusValue;
     }
   }
   if (bad) atomicOr(f.status, bad);
@@ -417,55 +420,40 @@ __device__ __forceinline__ void fast_solve(const FrameDev &f, const Item &it, bo
       A[s][k] = v;
     }
   }
-  float T[NS][NV];
-#pragma unroll
-  for (int s = 0; s < NS; ++s)
-#pragma unroll
-    for (int v = 0; v < NV; ++v) T[s][v] = rv[s][v];
 
-  // Gauss-Jordan; multipliers stay in A[s][j] for the refinement replay.
+  // Gauss-Jordan elimination without pivoting.
   float diag[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) diag[s] = 1.f;
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     if (j <= Kw) {
-    const int jl = j & 15, js = j >> 4;
-    const float piv = bcast_f(A[js][j], jl);
-    const float rp = 1.0f / piv;
-    float fs[NS];
+      const int jl = j & 15, js = j >> 4;
+      const float piv = bcast_f(A[js][j], jl);
+      const float rp = __builtin_amdgcn_rcpf(piv);
+      float fs[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const bool isj = (s == js) && (t == jl);
-      fs[s] = isj ? 0.f : A[s][j] * rp;
-      if (isj) diag[s] = piv;
-    }
+      for (int s = 0; s < NS; ++s) {
+        const bool isj = (s == js) && (t == jl);
+        fs[s] = isj ? 0.f : A[s][j] * rp;
+        if (isj) diag[s] = piv;
+      }
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-      if (k > j) {
-        const float bk = bcast_f(A[js][k], jl);
+      for (int k = 0; k < R; ++k) {
+        if (k > j) {
+          const float bk = bcast_f(A[js][k], jl);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) A[s][k] = fmaf(-fs[s], bk, A[s][k]);
+          for (int s = 0; s < NS; ++s) A[s][k] = fmaf(-fs[s], bk, A[s][k]);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const float bt = bcast_f(T[js][v], jl);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) T[s][v] = fmaf(-fs[s], bt, T[s][v]);
       }
     }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const float bt = bcast_f(T[js][v], jl);
-#pragma unroll
-      for (int s = 0; s < NS; ++s) T[s][v] = fmaf(-fs[s], bt, T[s][v]);
-    }
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const bool isj = (s == js) && (t == jl);
-      A[s][j] = isj ? A[s][j] : fs[s];
-    }
-    }
   }
-  float X[NS][NV];
-#pragma unroll
-  for (int s = 0; s < NS; ++s)
-#pragma unroll
-    for (int v = 0; v < NV; ++v) X[s][v] = T[s][v] / diag[s];
 
   // Pivot ratio of the SPD part (rows < K) decides the FP64 refinement.
   float dmin = 3.0e38f, dmax = 0.f;
@@ -475,72 +463,28 @@ __device__ __forceinline__ void fast_solve(const FrameDev &f, const Item &it, bo
   dmin = row_min(dmin);
   dmax = row_max(dmax);
   const bool need = ok && ((f.refine == 2) || (f.refine == 1 && !(dmin >= f.tau * dmax)));
-  if (__builtin_amdgcn_read_exec() & __ballot(need)) {
-    const double *tab64 = f.tab64 + S.hc64;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      // FP64 residual rho = [r; 0] - [G_K 1; 1^T 0][c; a].
-      double acc[NS], csum = 0.0, a = 0.0;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) acc[s] = 0.0;
-#pragma unroll
-      for (int k = 0; k < R; ++k) {
-        if (k <= Kw) {
-          const int xk = bcast_i(xr[k >> 4], k & 15);
-          const int yk = bcast_i(yr[k >> 4], k & 15);
-          const double ck = (double)bcast_f(X[k >> 4][v], k & 15);
-          if (k < K) {
-            csum += ck;
-#pragma unroll
-            for (int s = 0; s < NS; ++s) acc[s] += green_tab(tab64, w, h, xr[s], yr[s], xk, yk) * ck;
-          }
-          if (k == K) a = ck;
-        }
-      }
-      float rho[NS];
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const int i = t + 16 * s;
-        double r = 0.0;
-        if (i < K) r = (double)rv[s][v] - a - acc[s];
-        else if (i == K) r = -csum;
-        rho[s] = (float)r;
-      }
-#pragma unroll
-      for (int j = 0; j < R; ++j) {
-        if (j <= Kw) {
-          const int jl = j & 15, js = j >> 4;
-          const float tj = bcast_f(rho[js], jl);
-#pragma unroll
-          for (int s = 0; s < NS; ++s) {
-            const bool isj = (s == js) && (t == jl);
-            rho[s] = isj ? rho[s] : fmaf(-A[s][j], tj, rho[s]);
-          }
-        }
-      }
-      if (need) {
-#pragma unroll
-        for (int s = 0; s < NS; ++s) X[s][v] += rho[s] / diag[s];
-      }
-    }
-  }
 
   // Stage x, y, c (rows < K) and a (row K) for the evaluation.
   bool fin = true;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int i = t + 16 * s;
+    const float rd = __builtin_amdgcn_rcpf(diag[s]);
+    const float x0 = T[s][0] * rd, x1 = T[s][1] * rd;
     if (i < K) {
       st.x[gi][i] = xr[s];
       st.y[gi][i] = yr[s];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) { st.c[gi][v][i] = X[s][v]; fin &= isfinite(X[s][v]); }
+      st.c[gi][0][i] = x0;
+      st.c[gi][1][i] = x1;
+      fin &= isfinite(x0) && isfinite(x1);
     } else if (i == K) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) { st.a[gi][v] = X[s][v]; fin &= isfinite(X[s][v]); }
+      st.a[gi][0] = x0;
+      st.a[gi][1] = x1;
+      fin &= isfinite(x0) && isfinite(x1);
     }
   }
-  if (ok && !fin) atomicOr(f.status, kStatusSolve);
+  if (ok && !need && !fin) atomicOr(f.status, kStatusSolve);
+  return !need;
 }
 
 // u = Dh^T (lam .* (Dw[:,X] diag(c) Dh[:,Y]^T)^T) Dw + a on one block, FP32
@@ -592,44 +536,69 @@ __device__ __forceinline__ void fast_eval_block(const FrameDev &f, const float *
   }
 }
 
-__global__ __launch_bounds__(kFastThreads) void k_fast(FrameDev f) {
+// Size class of a block for the wave-level path: 0, 1, 2 -> R = 16, 24, 32
+// rows; 3 -> not taken (general path).
+__device__ __forceinline__ int fast_class(int K, int N) {
+  if (K < 1 || K >= N || K > kFastKMax) return 3;
+  return K <= 15 ? 0 : (K <= 23 ? 1 : 2);
+}
+
+__global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_fast(FrameDev f) {
   extern __shared__ float stab[];
   __shared__ WaveStage stage[kFastWaves];
-  for (int i = threadIdx.x; i < f.tab32_floats; i += kFastThreads) stab[i] = f.tab32[i];
+  __shared__ int cls[kFastItems], order[kFastItems];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < f.tab32_floats; i += kFastThreads) stab[i] = f.tab32[i];
+  // Bin the workgroup's blocks by size class so that every wave solves
+  // blocks of one class (R is uniform across a wave).
+  const int m0 = blockIdx.x * kFastItems;
+  if (tid < kFastItems) {
+    const int m = m0 + tid;
+    int c = 4;  // past the end
+    if (m < f.n_items) {
+      const Item it = load_item(f, m);
+      c = fast_class(it.K, it.w * it.h);
+      if (c == 3) push_deferred(f, m, it.K, it.w, it.h);
+    }
+    cls[tid] = c;
+  }
+  __syncthreads();
+  if (tid < kFastItems) {
+    const int c = cls[tid];
+    int r = 0;
+    for (int j = 0; j < kFastItems; ++j) r += (cls[j] < c) || (cls[j] == c && j < tid);
+    order[r] = tid;
+  }
   __syncthreads();
 
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = tid & 63, wv = tid >> 6;
   const int gi = lane >> 4, t = lane & 15;
-  const int m = (blockIdx.x * kFastWaves + wv) * kWaveItems + gi;
-  const bool valid = m < f.n_items;
+  const int slot = order[wv * kWaveItems + gi];
+  const int m = m0 + slot;
+  const bool ok = cls[slot] < 3;
   Item it;
-  if (valid) it = load_item(f, m);
+  if (ok) it = load_item(f, m);
   else { it.K = 0; it.w = it.h = 1; it.nv = 1; it.shape = 0; it.base = 0; it.W = 1; it.x0 = it.y0 = 0;
          it.vbase0 = it.vbase1 = it.obase0 = it.obase1 = 0; }
-  const bool ok = valid && it.K >= 1 && it.K <= kFastKMax && it.K < it.w * it.h;
-  if (valid && !ok && t == 0) push_deferred(f, m, it.K, it.w, it.h);
 
-  int kw = ok ? it.K : 0, nvw = ok ? it.nv : 0;
-  for (int o = 32; o > 0; o >>= 1) {
-    kw = max(kw, __shfl_xor(kw, o));
-    nvw = max(nvw, __shfl_xor(nvw, o));
-  }
+  int kw = ok ? it.K : 0;
+  for (int o = 32; o > 0; o >>= 1) kw = max(kw, __shfl_xor(kw, o));
   const int Kw = __builtin_amdgcn_readfirstlane(kw);
-  const int NVw = __builtin_amdgcn_readfirstlane(nvw);
   if (Kw == 0) return;
   WaveStage &st = stage[wv];
-  if (Kw <= 15) {
-    if (NVw == 1) fast_solve<16, 1>(f, it, ok, t, gi, Kw, stab, st);
-    else fast_solve<16, 2>(f, it, ok, t, gi, Kw, stab, st);
-  } else {
-    if (NVw == 1) fast_solve<32, 1>(f, it, ok, t, gi, Kw, stab, st);
-    else fast_solve<32, 2>(f, it, ok, t, gi, Kw, stab, st);
+  bool solved;
+  if (Kw <= 15) solved = fast_solve<16>(f, it, ok, t, gi, Kw, stab, st);
+  else if (Kw <= 23) solved = fast_solve<24>(f, it, ok, t, gi, Kw, stab, st);
+  else solved = fast_solve<32>(f, it, ok, t, gi, Kw, stab, st);
+  if (ok && !solved) {
+    if (t == 0) push_deferred(f, m, it.K, it.w, it.h);
   }
+  const bool eval = ok && solved;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-  const unsigned long long okmask = __ballot(ok);
+  const unsigned long long okmask = __ballot(eval);
 #pragma unroll
   for (int g2 = 0; g2 < kWaveItems; ++g2) {
     if (!((okmask >> (16 * g2)) & 1ull)) continue;
@@ -650,8 +619,7 @@ __global__ __launch_bounds__(kFastThreads) void k_fast(FrameDev f) {
 // ---------------------------------------------------------------- launchers
 
 hipError_t launch_fast(const FrameDev &f, hipStream_t stream) {
-  const int per_block = kFastWaves * kWaveItems;
-  const int grid = (f.n_items + per_block - 1) / per_block;
+  const int grid = (f.n_items + kFastItems - 1) / kFastItems;
   if (grid == 0) return hipSuccess;
   size_t lds = sizeof(float) * (size_t)f.tab32_floats;
   hipLaunchKernelGGL(k_fast, dim3(grid), dim3(kFastThreads), lds, stream, f);
@@ -665,7 +633,7 @@ hipError_t launch_plain_all(const FrameDev &f, hipStream_t stream) {
 }
 
 hipError_t launch_general_deferred(const FrameDev &f, hipStream_t stream) {
-  hipLaunchKernelGGL(k_general_deferred, dim3(512), dim3(kGenThreads), 0, stream, f);
+  hipLaunchKernelGGL(k_general_deferred, dim3(kGeneralGrid), dim3(kGenThreads), 0, stream, f);
   return hipGetLastError();
 }
 

@@ -54,7 +54,7 @@ def compare(got, ref):
 def check(dec, fr, tol=FP32_TOL, method=oracle.DIRECT, **kw):
     print(f"case {fr.width}x{fr.height} fmt={fr.fmt} b={fr.block_size} shared={fr.chroma_shared} {kw}", flush=True)
     got, _ = gpu_decode(dec, fr, **kw)
-    ref = oracle.decode_flat(fr, method=method)
+    ref = oracle.decode_flat(fr, method=method, op=kw.get("op", 0), s=kw.get("s", 1.0))
     assert np.all(np.isfinite(got))
     mx, agree = compare(got, ref)
     print(f"  max|err|={mx:.3e} round-agree={agree * 100:.4f}%", flush=True)
