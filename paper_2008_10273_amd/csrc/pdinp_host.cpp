@@ -245,18 +245,29 @@ int get_tables(pdi_ctx *c, const pdi_frame *f, int b, int shared, const pdi_para
     S.hc64 = (int)t64.size();
     for (double v : hc) t64.push_back(v);
     if (b <= 16) {
-      S.dw = (int)t32.size();
-      t32.resize(t32.size() + 256);
-      dct16(w, &t32[S.dw]);
-      S.dh = (int)t32.size();
-      t32.resize(t32.size() + 256);
-      dct16(h, &t32[S.dh]);
-      S.lam = (int)t32.size();
-      t32.resize(t32.size() + 256, 0.f);
+      // Row-pair table: J[(y*h + y')*(w+1) + a] = Hc(a,|y-y'|)/4 + Hc(a, refl(y+y'+1))/4,
+      // so that G(x, x') = J[..][|x-x'|] + J[..][refl(x+x'+1)].
+      const int W1 = w + 1;
+      S.fast = (int)t32.size();
+      S.jt_floats = (h * h * W1 + 3) & ~3;
+      t32.resize(t32.size() + S.jt_floats + 768, 0.f);
+      float *J = &t32[S.fast];
+      for (int y = 0; y < h; ++y)
+        for (int y2 = 0; y2 < h; ++y2) {
+          int dy = y > y2 ? y - y2 : y2 - y;
+          int sy = y + y2 + 1;
+          if (sy > h) sy = 2 * h - sy;
+          for (int a = 0; a <= w; ++a)
+            J[(y * h + y2) * W1 + a] = (float)(hc[(size_t)dy * W1 + a] + hc[(size_t)sy * W1 + a]);
+        }
+      float *D = J + S.jt_floats;
+      dct16(w, D);
+      dct16(h, D + 256);
       for (int q = 0; q < h; ++q)
-        for (int p = 0; p < w; ++p) t32[S.lam + q * 16 + p] = (float)lam[(size_t)q * w + p];
+        for (int p = 0; p < w; ++p) D[512 + q * 16 + p] = (float)lam[(size_t)q * w + p];
     } else {
-      S.dw = S.dh = S.lam = -1;
+      S.fast = -1;
+      S.jt_floats = 0;
     }
   }
   ts.tab32_floats = (int)t32.size();
@@ -436,6 +447,34 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
   }
   F.nshapes = ts->nshapes;
   for (int k = 0; k < ts->nshapes; ++k) F.s[k] = ts->s[k];
+  // Shape-homogeneous runs of blocks for the wave-level path.
+  F.nsegs = 0;
+  F.fast_wgs = 0;
+  F.fast_lds = 0;
+  for (int g = 0; g < F.ngroups; ++g) {
+    const pdi::GroupDev &G = F.g[g];
+    const int b = block_size, nbxf = G.W / b, nbyf = G.H / b;
+    const int rw = G.W % b, rh = G.H % b;
+    const int segs[4][4] = {{0, nbxf, 0, nbyf},                      // full
+                            {nbxf, rw ? 1 : 0, 0, nbyf},             // right edge
+                            {0, nbxf, nbyf, rh ? 1 : 0},             // bottom edge
+                            {nbxf, rw ? 1 : 0, nbyf, rh ? 1 : 0}};   // corner
+    for (int e = 0; e < 4; ++e) {
+      const int nx = segs[e][1], ny = segs[e][3];
+      if (nx <= 0 || ny <= 0) continue;
+      pdi::SegDev &S = F.seg[F.nsegs++];
+      S.group = g;
+      S.shape = G.shape[e];
+      S.bx0 = segs[e][0];
+      S.nx = nx;
+      S.by0 = segs[e][2];
+      S.count = nx * ny;
+      S.first_wg = F.fast_wgs;
+      F.fast_wgs += (S.count + 15) / 16;
+      const pdi::ShapeDev &SH = ts->s[S.shape];
+      if (SH.jt_floats + 768 > F.fast_lds) F.fast_lds = SH.jt_floats + 768;
+    }
+  }
   F.tab32_floats = ts->tab32_floats;
   F.block_ptr = mask->block_ptr;
   F.pos = mask->pos;

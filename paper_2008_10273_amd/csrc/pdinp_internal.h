@@ -21,12 +21,21 @@ constexpr int kStatusSolve = 4;
 // Per distinct block shape: offsets of its tables in the table buffers.
 struct ShapeDev {
   int w, h;
-  int hc32;  // FP32 compact Green table, (w+1)*(h+1), quarter-scaled (floats)
-  int hc64;  // same in FP64 (doubles)
-  int dw;    // DCT-II matrix rows p < 16, cols x < 16, zero padded (floats)
-  int dh;    // DCT-II matrix rows q, cols y, zero padded (floats)
-  int lam;   // eigenvalues lam[q*16 + p], zero padded, lam_00 = 0 (floats)
+  int hc32;       // FP32 compact Green table, (w+1)*(h+1), quarter-scaled (floats)
+  int hc64;       // same in FP64 (doubles)
+  int fast;       // fast-path block (b <= 16), -1 otherwise: the row-pair table
+                  // J[(y*h + y')*(w+1) + alpha] (jt_floats floats), then the
+                  // zero-padded 16x16 DCT-II matrices Dw[p][x], Dh[q][y] and the
+                  // eigenvalues lam[q][p] (256 floats each)
+  int jt_floats;  // size of J rounded up to a multiple of 4
 };
+
+// A run of blocks of one shape: block columns bx0 .. bx0+nx-1, rows by0 ..,
+// `count` blocks in raster order, served by workgroups first_wg .. .
+struct SegDev {
+  int group, shape, bx0, nx, by0, count, first_wg;
+};
+constexpr int kMaxSegs = 4 * kMaxGroups;
 
 // Per mask-plane group (Y; shared chroma; or Cb and Cr separately).
 struct GroupDev {
@@ -51,6 +60,10 @@ struct FrameDev {
   int eval;          // PDI_EVAL_*
   GroupDev g[kMaxGroups];
   ShapeDev s[kMaxShapes];
+  SegDev seg[kMaxSegs];
+  int nsegs;
+  int fast_wgs;      // workgroups of the wave-level path
+  int fast_lds;      // its dynamic LDS (floats): largest J + 768
   int tab32_floats;  // size of the FP32 table buffer (floats)
   // buffers
   const int32_t *block_ptr;
@@ -60,7 +73,7 @@ struct FrameDev {
   const float *tab32;
   const double *tab64;
   int *deferred;   // list of mask blocks left to the general path
-  int *counters;   // [0] deferred count, [1] done workgroups
+  int *counters;   // [0] medium count, [1] large count, [2] finished workgroups
   int *status;     // device status word
   float *slots;    // global-memory systems for K > kLdsKMax, one slot per workgroup
   long long slot_floats;

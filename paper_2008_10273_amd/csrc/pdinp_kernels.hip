@@ -332,7 +332,10 @@ __global__ __launch_bounds__(kGenThreads) void k_general_deferred(FrameDev f) {
 // -------------------------------------------------------- wave-level path
 
 // Broadcast lane `src` of every 16-lane row (DPP row_newbcast).  `src` must
-// fold to a constant after unrolling.
+// fold to a constant after unrolling.  Callers whose consumers are VOP2 ALU
+// instructions pass the result through pin_v(): row_newbcast folded into
+// other VOP2 instructions gave wrong results on gfx950, so every broadcast
+// stays a standalone v_mov_b32_dpp (tests/test_isa.py checks the ISA).
 __device__ __forceinline__ int bcast_i(int x, int src) {
 #define PDI_NB(n) case n: return __builtin_amdgcn_mov_dpp(x, 0x150 + n, 0xF, 0xF, true);
   switch (src & 15) {
@@ -342,6 +345,9 @@ __device__ __forceinline__ int bcast_i(int x, int src) {
 #undef PDI_NB
   return x;
 }
+// Empty statement that takes and "returns" v: the value is materialised in a
+// VGPR here, so its producer cannot be merged into its consumers.
+__device__ __forceinline__ void pin_v(int &v) { asm volatile("" : "+v"(v)); }
 __device__ __forceinline__ float bcast_f(float x, int src) {
   return __builtin_bit_cast(float, bcast_i(__builtin_bit_cast(int, x), src));
 }
@@ -356,30 +362,48 @@ __device__ __forceinline__ float row_max(float v) {
   return v;
 }
 
-struct WaveStage {
-  int x[kWaveItems][32];
-  int y[kWaveItems][32];
-  float c[kWaveItems][2][32];
-  float a[kWaveItems][2];
-};
-
 constexpr int kFastThreads = 256;
 constexpr int kFastWaves = kFastThreads / 64;
 constexpr int kFastItems = kFastWaves * kWaveItems;  // blocks per workgroup
 
-// Solve the bordered systems of the wave's 4 blocks (R = 16 or 32 rows per
-// block, two value columns) and leave x, y, c, a of every row in the wave's
-// stage.  Returns false for a block whose pivots call for FP64 refinement;
-// such blocks are left to the general path, which refines.
+// A block of the workgroup, as staged by the prologue.
+struct FastItem {
+  int m, K, base, cls, nv;
+  int pad_;
+  long long vb0, vb1, ob0, ob1;
+};
+
+// Evaluation operands of one mask point (16 bytes: one LDS read).
+struct FastPoint {
+  int x, y;
+  float c0, c1;
+};
+
+struct FastStage {
+  FastPoint p[kWaveItems][32];
+  float a[kWaveItems][2];
+};
+
+// Size class of a block for the wave-level path: 0, 1, 2 -> R = 16, 24, 32
+// rows; 3 -> not taken (general path).
+__device__ __forceinline__ int fast_class(int K, int N) {
+  if (K < 1 || K >= N || K > kFastKMax) return 3;
+  return K <= 15 ? 0 : (K <= 23 ? 1 : 2);
+}
+
+// Solve the bordered systems of the wave's 4 blocks (R = 16, 24 or 32 rows
+// per block, two value columns) and stage the evaluation operands.  J is the
+// row-pair Green table of the workgroup's shape (LDS).  Returns false for a
+// block whose pivots call for FP64 refinement; such blocks are left to the
+// general path, which refines.
 template <int R>
-__device__ __forceinline__ bool fast_solve(const FrameDev &f, const Item &it, bool ok, int t,
-                                           int gi, int Kw, const float *stab, WaveStage &st) {
+__device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *items, int slot, bool ok,
+                                           int t, int gi, int Kw, int w, int h, const float *J,
+                                           FastStage &st) {
   constexpr int NS = (R + 15) / 16;
   constexpr int NV = 2;
-  const int K = ok ? it.K : 0;
-  const int w = it.w, h = it.h, N = w * h;
-  const ShapeDev S = f.s[it.shape];
-  const float *tab = stab + S.hc32;
+  const int K = ok ? items[slot].K : 0;
+  const int N = w * h, W1 = w + 1;
   int xr[NS], yr[NS];
   float T[NS][NV];
   int bad = 0;
@@ -390,34 +414,79 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const Item &it, bo
     yr[s] = 0;
     T[s][0] = T[s][1] = 0.f;
     if (i < K) {
-      int p = f.pos[it.base + i];
+      const int base = items[slot].base;
+      int p = f.pos[base + i];
       if (f.validate) {
-        if (p >= N || (i > 0 && (int)f.pos[it.base + i - 1] >= p)) bad |= kStatusMask;
+        if (p >= N || (i > 0 && (int)f.pos[base + i - 1] >= p)) bad |= kStatusMask;
       }
       p = min(p, N - 1);
       xr[s] = p % w;
       yr[s] = p / w;
-      T[s][0] = f.values[it.vbase0 + i];
-      if (it.nv > 1) T[s][1] = f.values[it.vbase1 + i];
+      T[s][0] = f.values[items[slot].vb0 + i];
+      if (items[slot].nv > 1) T[s][1] = f.values[items[slot].vb1 + i];
       if (f.validate && !(isfinite(T[s][0]) && isfinite(T[s][1]))) bad |= kStatusValue;
     }
   }
   if (bad) atomicOr(f.status, bad);
 
-  // Assembly: row i of [G_K 1; 1^T 0], identity on padding rows.
-  float A[NS][R];
+  // Assembly of row i of [G_K 1; 1^T 0] (identity on padding rows):
+  // G(x_i, x_k) = J[y_i, y_k][|x_i - x_k|] + J[y_i, y_k][refl(x_i + x_k + 1)].
+  int yrow[NS], ycol[NS], xi1[NS], xcr[NS];
 #pragma unroll
-  for (int k = 0; k < R; ++k) {
-    const int xk = bcast_i(xr[k >> 4], k & 15);
-    const int yk = bcast_i(yr[k >> 4], k & 15);
+  for (int s = 0; s < NS; ++s) {
+    yrow[s] = yr[s] * h * W1;
+    ycol[s] = yr[s] * W1;
+    xi1[s] = xr[s] + 1;
+    xcr[s] = 2 * w - 1 - xr[s];
+  }
+  // The table lookups are unconditional (every index is in range) so that
+  // they issue back to back; the border and padding pattern is applied by
+  // selects afterwards.
+  float A[NS][R];
+  constexpr int KC = 8;  // columns whose lookups are issued together
+#pragma unroll
+  for (int k0 = 0; k0 < R; k0 += KC) {
+    float g1[NS][KC], g2[NS][KC];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const int k = k0 + kk;
+      int xk = bcast_i(xr[k >> 4], k & 15);
+      int yk = bcast_i(ycol[k >> 4], k & 15);
+      pin_v(xk);
+      pin_v(yk);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int base = yrow[s] + yk;
+        const int a1 = (int)__usad((unsigned)xr[s], (unsigned)xk, (unsigned)base);
+        const int a2 = base + min(xi1[s] + xk, xcr[s] - xk);
+        g1[s][kk] = J[a1];
+        g2[s][kk] = J[a2];
+      }
+    }
+    // Empty statements that take every looked-up value: the compiler keeps
+    // all lookups of the chunk ahead of them (one wait instead of one per
+    // entry).  They emit no instruction.
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      const int i = t + 16 * s;
-      float g = green_tab(tab, w, h, xr[s], yr[s], xk, yk);
-      float v = (k < K) ? g : (k == K ? 1.f : 0.f);
-      if (i == K) v = (k < K) ? 1.f : 0.f;
-      if (i > K) v = (i == k) ? 1.f : 0.f;
-      A[s][k] = v;
+      asm volatile("" : "+v"(g1[s][0]), "+v"(g1[s][1]), "+v"(g1[s][2]), "+v"(g1[s][3]),
+                        "+v"(g1[s][4]), "+v"(g1[s][5]), "+v"(g1[s][6]), "+v"(g1[s][7]));
+      asm volatile("" : "+v"(g2[s][0]), "+v"(g2[s][1]), "+v"(g2[s][2]), "+v"(g2[s][3]),
+                        "+v"(g2[s][4]), "+v"(g2[s][5]), "+v"(g2[s][6]), "+v"(g2[s][7]));
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) A[s][k0 + kk] = g1[s][kk] + g2[s][kk];
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = t + 16 * s;
+    const bool prow = i < K, brow = i == K;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const float inner = prow ? A[s][k] : (brow ? 1.f : 0.f);            // columns k < K
+      const float outer = ((k == K) && prow) || (i > K && i == k) ? 1.f : 0.f;  // columns k >= K
+      A[s][k] = (k < K) ? inner : outer;
     }
   }
 
@@ -464,20 +533,23 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const Item &it, bo
   dmax = row_max(dmax);
   const bool need = ok && ((f.refine == 2) || (f.refine == 1 && !(dmin >= f.tau * dmax)));
 
-  // Stage x, y, c (rows < K) and a (row K) for the evaluation.
+  // Stage (x, y, c) of rows < K, zeros for the other rows up to R, and a.
   bool fin = true;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int i = t + 16 * s;
     const float rd = __builtin_amdgcn_rcpf(diag[s]);
     const float x0 = T[s][0] * rd, x1 = T[s][1] * rd;
-    if (i < K) {
-      st.x[gi][i] = xr[s];
-      st.y[gi][i] = yr[s];
-      st.c[gi][0][i] = x0;
-      st.c[gi][1][i] = x1;
-      fin &= isfinite(x0) && isfinite(x1);
-    } else if (i == K) {
+    if (i < R) {
+      FastPoint P;
+      P.x = i < K ? xr[s] : 0;
+      P.y = i < K ? yr[s] : 0;
+      P.c0 = i < K ? x0 : 0.f;
+      P.c1 = i < K ? x1 : 0.f;
+      st.p[gi][i] = P;
+    }
+    if (i < K) fin &= isfinite(x0) && isfinite(x1);
+    if (i == K) {
       st.a[gi][0] = x0;
       st.a[gi][1] = x1;
       fin &= isfinite(x0) && isfinite(x1);
@@ -487,15 +559,15 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const Item &it, bo
   return !need;
 }
 
-// u = Dh^T (lam .* (Dw[:,X] diag(c) Dh[:,Y]^T)^T) Dw + a on one block, FP32
-// MFMA 16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]; the result
-// D[4(l/16)+r][l%16] sits in register r.
-__device__ __forceinline__ void fast_eval_block(const FrameDev &f, const float *stab,
-                                                const WaveStage &st, int gi, int lane, int K,
-                                                int shape, int nv, int w, int h, int W,
-                                                long long ob0, long long ob1) {
-  const ShapeDev S = f.s[shape];
-  const float *Dw = stab + S.dw, *Dh = stab + S.dh, *lam = stab + S.lam;
+// u = Dh^T (lam .* (Dw[:,X] diag(c) Dh[:,Y]^T)^T) Dw + a for the wave's 4
+// blocks (one shape), as interleaved FP32 MFMA 16x16x4 chains: lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; the result D[4(l/16)+r][l%16] is register r.
+template <int R>
+__device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, const FastStage &st,
+                                          int lane, unsigned okmask, int nvw, int w, int h,
+                                          int W, const long long ob[kWaveItems][2]) {
+  constexpr int nch = R / 4;  // staged rows K..R-1 hold zero coefficients
+  const float *Dw = D, *Dh = D + 256, *lam = D + 512;
   const int lo = lane & 15, hi = lane >> 4;
   float lam4[4], dwb[4], dha[4];
 #pragma unroll
@@ -505,68 +577,108 @@ __device__ __forceinline__ void fast_eval_block(const FrameDev &f, const float *
     dwb[j] = Dw[pq * 16 + lo];    // Dw[p][x], p = 4 hi + j, x = lo
     dha[j] = Dh[pq * 16 + lo];    // Dh[q][y], q = 4 hi + j, y = lo
   }
-  const int nch = (K + 3) >> 2;
-  for (int v = 0; v < nv; ++v) {
-    f4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int v = 0; v < nvw; ++v) {
+    f4 acc[kWaveItems];
+#pragma unroll
+    for (int g = 0; g < kWaveItems; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
     for (int ch = 0; ch < nch; ++ch) {
-      const int i = ch * 4 + hi;
-      float aop = 0.f, bop = 0.f;
-      if (i < K) {
-        const int xi = st.x[gi][i], yi = st.y[gi][i];
-        aop = st.c[gi][v][i] * Dw[lo * 16 + xi];  // A[p][i], p = lo
-        bop = Dh[lo * 16 + yi];                   // B[i][q], q = lo
+      float aop[kWaveItems], bop[kWaveItems];
+#pragma unroll
+      for (int g = 0; g < kWaveItems; ++g) {
+        const FastPoint P = st.p[g][ch * 4 + hi];
+        aop[g] = (v ? P.c1 : P.c0) * Dw[lo * 16 + P.x];  // A[p][i], p = lo
+        bop[g] = Dh[lo * 16 + P.y];                      // B[i][q], q = lo
       }
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
+#pragma unroll
+      for (int g = 0; g < kWaveItems; ++g)
+        acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[g], bop[g], acc[g], 0, 0, 0);
     }
-    // acc[j] = V^T[p = 4 hi + j][q = lo]; scale by lam[q][p].
-    f4 Sx = {0.f, 0.f, 0.f, 0.f};
+    // acc[g][j] = V^T[p = 4 hi + j][q = lo]; scale by lam[q][p], then
+    // S[q][x] = sum_p U^[q][p] Dw[p][x] and U[y][x] = sum_q Dh[q][y] S[q][x].
+    f4 Sx[kWaveItems], U[kWaveItems];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) Sx = __builtin_amdgcn_mfma_f32_16x16x4f32(acc[j] * lam4[j], dwb[j], Sx, 0, 0, 0);
-    // Sx[j] = S[q = 4 hi + j][x = lo]
-    f4 U = {0.f, 0.f, 0.f, 0.f};
+    for (int g = 0; g < kWaveItems; ++g) Sx[g] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int j = 0; j < 4; ++j) U = __builtin_amdgcn_mfma_f32_16x16x4f32(dha[j], Sx[j], U, 0, 0, 0);
-    const float a = st.a[gi][v];
-    const long long ob = v ? ob1 : ob0;
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int y = 4 * hi + j, x = lo;
-      if (x < w && y < h) f.out[ob + (long long)y * W + x] = U[j] + a;
+      for (int g = 0; g < kWaveItems; ++g)
+        Sx[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(acc[g][j] * lam4[j], dwb[j], Sx[g], 0, 0, 0);
+#pragma unroll
+    for (int g = 0; g < kWaveItems; ++g) U[g] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int g = 0; g < kWaveItems; ++g)
+        U[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(dha[j], Sx[g][j], U[g], 0, 0, 0);
+#pragma unroll
+    for (int g = 0; g < kWaveItems; ++g) {
+      if (!((okmask >> g) & 1u)) continue;
+      const float a = st.a[g][v];
+      const long long o = v ? ob[g][1] : ob[g][0];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int y = 4 * hi + j, x = lo;
+        if (x < w && y < h) f.out[o + (long long)y * W + x] = U[g][j] + a;
+      }
     }
   }
 }
 
-// Size class of a block for the wave-level path: 0, 1, 2 -> R = 16, 24, 32
-// rows; 3 -> not taken (general path).
-__device__ __forceinline__ int fast_class(int K, int N) {
-  if (K < 1 || K >= N || K > kFastKMax) return 3;
-  return K <= 15 ? 0 : (K <= 23 ? 1 : 2);
-}
-
-__global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_fast(FrameDev f) {
-  extern __shared__ float stab[];
-  __shared__ WaveStage stage[kFastWaves];
-  __shared__ int cls[kFastItems], order[kFastItems];
+__global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(3, 8)))
+void k_fast(FrameDev f) {
+  extern __shared__ float tabs[];  // J, Dw, Dh, lam of the workgroup's shape
+  __shared__ FastItem items[kFastItems];
+  __shared__ int order[kFastItems];
+  __shared__ FastStage stage[kFastWaves];
   const int tid = threadIdx.x;
-  for (int i = tid; i < f.tab32_floats; i += kFastThreads) stab[i] = f.tab32[i];
-  // Bin the workgroup's blocks by size class so that every wave solves
-  // blocks of one class (R is uniform across a wave).
-  const int m0 = blockIdx.x * kFastItems;
+  const int wg = blockIdx.x;
+  int si = 0;
+  while (si + 1 < f.nsegs && wg >= f.seg[si + 1].first_wg) ++si;
+  const SegDev sg = f.seg[si];
+  const ShapeDev S = f.s[sg.shape];
+  const GroupDev &G = f.g[sg.group];
+  const int w = S.w, h = S.h;
+
+  // Prologue: the shape's tables into LDS; the workgroup's 16 blocks
+  // (geometry from the segment, counts from block_ptr) into LDS records.
+  const int nt = S.jt_floats + 768;
+  for (int i = tid; i < nt; i += kFastThreads) tabs[i] = f.tab32[S.fast + i];
   if (tid < kFastItems) {
-    const int m = m0 + tid;
-    int c = 4;  // past the end
-    if (m < f.n_items) {
-      const Item it = load_item(f, m);
-      c = fast_class(it.K, it.w * it.h);
-      if (c == 3) push_deferred(f, m, it.K, it.w, it.h);
+    FastItem r;
+    r.cls = 4;
+    r.m = r.K = r.base = r.nv = r.pad_ = 0;
+    r.vb0 = r.vb1 = r.ob0 = r.ob1 = 0;
+    const int k = (wg - sg.first_wg) * kFastItems + tid;
+    if (k < sg.count) {
+      const int bx = sg.bx0 + k % sg.nx, by = sg.by0 + k / sg.nx;
+      const int m = G.first + by * G.nbx + bx;
+      const int lo = f.block_ptr[m], hi = f.block_ptr[m + 1];
+      r.m = m;
+      r.K = hi - lo;
+      r.base = lo;
+      r.nv = G.nv;
+      r.cls = fast_class(r.K, w * h);
+      const long long pix = (long long)(by * f.b) * G.W + bx * f.b;
+      r.vb0 = lo;
+      r.ob0 = G.out_off[0] + pix;
+      if (G.nv > 1) {
+        r.vb1 = f.shared ? (long long)f.block_ptr[f.n_items] + (lo - f.block_ptr[f.chroma_first]) : lo;
+        r.ob1 = G.out_off[1] + pix;
+      }
+      if (r.cls == 3) push_deferred(f, m, r.K, w, h);
     }
-    cls[tid] = c;
+    items[tid] = r;
   }
   __syncthreads();
+  // Bin by size class so that every wave solves blocks of one class.
   if (tid < kFastItems) {
-    const int c = cls[tid];
+    const int c = items[tid].cls;
     int r = 0;
-    for (int j = 0; j < kFastItems; ++j) r += (cls[j] < c) || (cls[j] == c && j < tid);
+    for (int j = 0; j < kFastItems; ++j) {
+      const int cj = items[j].cls;
+      r += (cj < c) || (cj == c && j < tid);
+    }
     order[r] = tid;
   }
   __syncthreads();
@@ -574,55 +686,50 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4,
   const int lane = tid & 63, wv = tid >> 6;
   const int gi = lane >> 4, t = lane & 15;
   const int slot = order[wv * kWaveItems + gi];
-  const int m = m0 + slot;
-  const bool ok = cls[slot] < 3;
-  Item it;
-  if (ok) it = load_item(f, m);
-  else { it.K = 0; it.w = it.h = 1; it.nv = 1; it.shape = 0; it.base = 0; it.W = 1; it.x0 = it.y0 = 0;
-         it.vbase0 = it.vbase1 = it.obase0 = it.obase1 = 0; }
-
-  int kw = ok ? it.K : 0;
-  for (int o = 32; o > 0; o >>= 1) kw = max(kw, __shfl_xor(kw, o));
-  const int Kw = __builtin_amdgcn_readfirstlane(kw);
-  if (Kw == 0) return;
-  WaveStage &st = stage[wv];
-  bool solved;
-  if (Kw <= 15) solved = fast_solve<16>(f, it, ok, t, gi, Kw, stab, st);
-  else if (Kw <= 23) solved = fast_solve<24>(f, it, ok, t, gi, Kw, stab, st);
-  else solved = fast_solve<32>(f, it, ok, t, gi, Kw, stab, st);
-  if (ok && !solved) {
-    if (t == 0) push_deferred(f, m, it.K, it.w, it.h);
+  const bool ok = items[slot].cls < 3;
+  int kw = ok ? items[slot].K : 0, nvw = ok ? items[slot].nv : 0;
+  for (int o = 32; o > 0; o >>= 1) {
+    kw = max(kw, __shfl_xor(kw, o));
+    nvw = max(nvw, __shfl_xor(nvw, o));
   }
+  const int Kw = __builtin_amdgcn_readfirstlane(kw);
+  const int NVw = __builtin_amdgcn_readfirstlane(nvw);
+  if (Kw == 0) return;
+  FastStage &st = stage[wv];
+  bool solved;
+  if (Kw <= 15) solved = fast_solve<16>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
+  else if (Kw <= 23) solved = fast_solve<24>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
+  else solved = fast_solve<32>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
+  if (ok && !solved && t == 0) push_deferred(f, items[slot].m, items[slot].K, w, h);
   const bool eval = ok && solved;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-  const unsigned long long okmask = __ballot(eval);
+  const unsigned long long em = __ballot(eval);
+  unsigned okmask = 0;
+  long long ob[kWaveItems][2];
 #pragma unroll
-  for (int g2 = 0; g2 < kWaveItems; ++g2) {
-    if (!((okmask >> (16 * g2)) & 1ull)) continue;
-    const int K2 = __builtin_amdgcn_readlane(it.K, 16 * g2);
-    const int shape2 = __builtin_amdgcn_readlane(it.shape, 16 * g2);
-    const int nv2 = __builtin_amdgcn_readlane(it.nv, 16 * g2);
-    const int w2 = __builtin_amdgcn_readlane(it.w, 16 * g2);
-    const int h2 = __builtin_amdgcn_readlane(it.h, 16 * g2);
-    const int W2 = __builtin_amdgcn_readlane(it.W, 16 * g2);
-    const long long ob0 = ((long long)__builtin_amdgcn_readlane((int)(it.obase0 >> 32), 16 * g2) << 32) |
-                          (unsigned)__builtin_amdgcn_readlane((int)it.obase0, 16 * g2);
-    const long long ob1 = ((long long)__builtin_amdgcn_readlane((int)(it.obase1 >> 32), 16 * g2) << 32) |
-                          (unsigned)__builtin_amdgcn_readlane((int)it.obase1, 16 * g2);
-    fast_eval_block(f, stab, st, g2, lane, K2, shape2, nv2, w2, h2, W2, ob0, ob1);
+  for (int g = 0; g < kWaveItems; ++g) {
+    okmask |= ((em >> (16 * g)) & 1ull) ? (1u << g) : 0u;
+    const int sg2 = __builtin_amdgcn_readlane(slot, 16 * g);
+    ob[g][0] = items[sg2].ob0;
+    ob[g][1] = items[sg2].ob1;
+  }
+  if (okmask) {
+    const float *D = tabs + S.jt_floats;
+    if (Kw <= 15) fast_eval<16>(f, D, st, lane, okmask, NVw, w, h, G.W, ob);
+    else if (Kw <= 23) fast_eval<24>(f, D, st, lane, okmask, NVw, w, h, G.W, ob);
+    else fast_eval<32>(f, D, st, lane, okmask, NVw, w, h, G.W, ob);
   }
 }
 
 // ---------------------------------------------------------------- launchers
 
 hipError_t launch_fast(const FrameDev &f, hipStream_t stream) {
-  const int grid = (f.n_items + kFastItems - 1) / kFastItems;
-  if (grid == 0) return hipSuccess;
-  size_t lds = sizeof(float) * (size_t)f.tab32_floats;
-  hipLaunchKernelGGL(k_fast, dim3(grid), dim3(kFastThreads), lds, stream, f);
+  if (f.fast_wgs == 0) return hipSuccess;
+  const size_t lds = sizeof(float) * (size_t)f.fast_lds;
+  hipLaunchKernelGGL(k_fast, dim3(f.fast_wgs), dim3(kFastThreads), lds, stream, f);
   return hipGetLastError();
 }
 
