@@ -46,6 +46,7 @@ struct pdi_ctx {
   int deferred_cap = 0;
   float *slots = nullptr;
   long long slot_floats = 0;
+  int slot_count = 0;
   std::map<TableKey, TableSet> tables;
 };
 
@@ -271,7 +272,9 @@ int get_tables(pdi_ctx *c, const pdi_frame *f, int b, int shared, const pdi_para
     }
   }
   ts.tab32_floats = (int)t32.size();
+  t32.resize(t32.size() + pdi::kTabPadFloats, 0.f);  // read-only padding for vector loads
   size_t b32 = t32.size() * sizeof(float), b64 = t64.size() * sizeof(double);
+  ts.tab32_floats = (int)t32.size();
   int rc = dev_alloc(c, (void **)&ts.tab32, b32, "tables");
   if (rc) return rc;
   rc = dev_alloc(c, (void **)&ts.tab64, b64, "tables");
@@ -289,7 +292,7 @@ int get_tables(pdi_ctx *c, const pdi_frame *f, int b, int shared, const pdi_para
   return PDI_OK;
 }
 
-int ensure_workspace(pdi_ctx *c, int n_items, int b) {
+int ensure_workspace(pdi_ctx *c, int n_items, int b, int nslots) {
   if (n_items > c->deferred_cap) {
     dev_free(c, c->deferred, sizeof(int) * (size_t)c->deferred_cap);
     c->deferred = nullptr;
@@ -298,18 +301,23 @@ int ensure_workspace(pdi_ctx *c, int n_items, int b) {
     if (rc) return rc;
     c->deferred_cap = n_items;
   }
-  // Global-memory systems for K > kLdsKMax: (K+1) rows of K+1+2 floats with
-  // K <= b*b - 1 (K = b*b is decoded by copying the values).
-  int nmax = b * b;
-  long long need = (long long)nmax * (nmax + 2);
-  if (nmax > pdi::kLdsKMax + 1 && need > c->slot_floats) {
-    dev_free(c, c->slots, sizeof(float) * (size_t)c->slot_floats * pdi::kDeferredGrid);
+  // Global-memory bordered systems: (K+1) rows of K+1+2 floats with
+  // K <= b*b - 1 (K = b*b is decoded by copying the values), one slot per
+  // workgroup that may need one.
+  const int nmax = b * b;
+  const long long need = (long long)nmax * (nmax + 2);
+  if (nslots < pdi::kDeferredGrid) nslots = pdi::kDeferredGrid;
+  if (need > c->slot_floats || nslots > c->slot_count) {
+    const long long nf = need > c->slot_floats ? need : c->slot_floats;
+    const int ns = nslots > c->slot_count ? nslots : c->slot_count;
+    dev_free(c, c->slots, sizeof(float) * (size_t)c->slot_floats * (size_t)c->slot_count);
     c->slots = nullptr;
     c->slot_floats = 0;
-    int rc = dev_alloc(c, (void **)&c->slots, sizeof(float) * (size_t)need * pdi::kDeferredGrid,
-                       "system slots");
+    c->slot_count = 0;
+    int rc = dev_alloc(c, (void **)&c->slots, sizeof(float) * (size_t)nf * (size_t)ns, "system slots");
     if (rc) return rc;
-    c->slot_floats = need;
+    c->slot_floats = nf;
+    c->slot_count = ns;
   }
   return PDI_OK;
 }
@@ -412,8 +420,6 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
   TableSet *ts = nullptr;
   int rc = get_tables(c, frame, block_size, shared, P, &ts);
   if (rc) return rc;
-  rc = ensure_workspace(c, (int)nitems, block_size);
-  if (rc) return rc;
 
   pdi::FrameDev F;
   std::memset(&F, 0, sizeof F);
@@ -475,6 +481,9 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
       if (SH.jt_floats + 768 > F.fast_lds) F.fast_lds = SH.jt_floats + 768;
     }
   }
+  const bool fast = (P.path == PDI_PATH_AUTO && block_size <= 16);
+  rc = ensure_workspace(c, (int)nitems, block_size, fast ? F.fast_wgs : 0);
+  if (rc) return rc;
   F.tab32_floats = ts->tab32_floats;
   F.block_ptr = mask->block_ptr;
   F.pos = mask->pos;
@@ -489,11 +498,12 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
   F.slot_floats = c->slot_floats;
 
   hipStream_t s = (hipStream_t)stream;
-  if (P.path == PDI_PATH_AUTO && block_size <= 16)
-    e = pdi::launch_fast(F, s);
-  else
+  if (fast) {
+    e = pdi::launch_fast(F, s);  // one launch: the workgroups also decode their leftover blocks
+  } else {
     e = pdi::launch_plain_all(F, s);
-  if (e == hipSuccess) e = pdi::launch_general_deferred(F, s);
+    if (e == hipSuccess) e = pdi::launch_general_deferred(F, s);
+  }
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   return PDI_OK;
 }

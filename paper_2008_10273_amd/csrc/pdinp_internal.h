@@ -12,6 +12,9 @@ constexpr int kFastKMax = 31;   // largest K of the wave-level path (R <= 32 row
 constexpr int kLdsKMax = 96;    // largest K whose bordered system fits in LDS (general path)
 constexpr int kDeferredGrid = 64;  // persistent workgroups of the general path
 constexpr int kWaveItems = 4;      // blocks per wave in the wave-level path
+// The FP32 table buffer is padded by this many floats so that the wave-level
+// path may read whole 16-byte vectors per thread past the last table.
+constexpr int kTabPadFloats = 6 * 256 * 4;
 
 // Device status bits (OR-ed by kernels, read by pdi_sync).
 constexpr int kStatusMask = 1;

@@ -98,16 +98,22 @@ constexpr int kGeneralGrid = 128;  // persistent workgroups over the deferred li
 constexpr int kGenMaxK = 1024;  // b = 32: at most 32*32 points
 constexpr int kTabMax = 33 * 33;
 
-struct GenShared {
-  float M[(kLdsKMax + 1) * (kLdsKMax + 3)];
-  float tab[kTabMax];
-  short px[kGenMaxK], py[kGenMaxK];
-  float c[2][kGenMaxK];
-  float fcol[kGenMaxK + 1];
-  float rho[kGenMaxK + 1];
+// Workgroup scratch of the general path for blocks of at most B x B pixels.
+template <int B>
+struct GenScratch {
+  float tab[(B + 1) * (B + 1)];
+  short px[B * B], py[B * B];
+  float c[2][B * B];
+  float fcol[B * B + 1];
+  float rho[B * B + 1];
   double red[kGenThreads / 64];
   float redf[2][kGenThreads / 64];
   int flag;
+};
+
+struct GenShared {
+  float M[(kLdsKMax + 1) * (kLdsKMax + 3)];
+  GenScratch<32> g;
 };
 
 __device__ __forceinline__ double block_sum(double v, double *red) {
@@ -123,7 +129,8 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 
 // Decode one block with a whole workgroup.  M points at LDS (K <= kLdsKMax)
 // or at a global slot (ld = row stride).
-__device__ void general_block(const FrameDev &f, int m, GenShared &sh, float *M) {
+template <int B>
+__device__ void general_block(const FrameDev &f, int m, GenScratch<B> &sh, float *M) {
   const int tid = threadIdx.x;
   const Item it = load_item(f, m);
   const int K = it.K, w = it.w, h = it.h, N = w * h;
@@ -295,7 +302,7 @@ __global__ __launch_bounds__(kGenThreads) void k_plain_all(FrameDev f) {
     if (threadIdx.x == 0) push_deferred(f, m, it.K, it.w, it.h);
     return;
   }
-  general_block(f, m, sh, sh.M);
+  general_block<32>(f, m, sh.g, sh.M);
 }
 
 // Persistent pass over the deferred lists; the last workgroup clears the
@@ -306,13 +313,13 @@ __global__ __launch_bounds__(kGenThreads) void k_general_deferred(FrameDev f) {
   const int nlarge = f.counters[1];
   for (int idx = blockIdx.x; idx < nmed; idx += gridDim.x) {
     __syncthreads();
-    general_block(f, f.deferred[idx], sh, sh.M);
+    general_block<32>(f, f.deferred[idx], sh.g, sh.M);
   }
   if (blockIdx.x < kDeferredGrid) {
     float *slot = f.slots + (long long)blockIdx.x * f.slot_floats;
     for (int idx = blockIdx.x; idx < nlarge; idx += kDeferredGrid) {
       __syncthreads();
-      general_block(f, f.deferred[f.n_items - 1 - idx], sh, slot);
+      general_block<32>(f, f.deferred[f.n_items - 1 - idx], sh.g, slot);
     }
   }
   // Every workgroup has read both counts before it gets here; the last one
@@ -365,6 +372,9 @@ __device__ __forceinline__ float row_max(float v) {
 constexpr int kFastThreads = 256;
 constexpr int kFastWaves = kFastThreads / 64;
 constexpr int kFastItems = kFastWaves * kWaveItems;  // blocks per workgroup
+// 16-byte table loads per thread: J (16*16*17 floats at most, rounded to 4)
+// plus the DCT matrices and eigenvalues (768 floats) of a b <= 16 shape.
+constexpr int kTabVec = ((16 * 16 * 17 + 3) / 4 + 768 / 4 + kFastThreads - 1) / kFastThreads;
 
 // A block of the workgroup, as staged by the prologue.
 struct FastItem {
@@ -627,10 +637,12 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
 
 __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(3, 8)))
 void k_fast(FrameDev f) {
-  extern __shared__ float tabs[];  // J, Dw, Dh, lam of the workgroup's shape
+  extern __shared__ __attribute__((aligned(16))) float tabs[];  // J, Dw, Dh, lam of the workgroup's shape
   __shared__ FastItem items[kFastItems];
   __shared__ int order[kFastItems];
+  __shared__ int defer[kFastItems];
   __shared__ FastStage stage[kFastWaves];
+  __shared__ GenScratch<16> gs;
   const int tid = threadIdx.x;
   const int wg = blockIdx.x;
   int si = 0;
@@ -640,10 +652,24 @@ void k_fast(FrameDev f) {
   const GroupDev &G = f.g[sg.group];
   const int w = S.w, h = S.h;
 
-  // Prologue: the shape's tables into LDS; the workgroup's 16 blocks
-  // (geometry from the segment, counts from block_ptr) into LDS records.
-  const int nt = S.jt_floats + 768;
-  for (int i = tid; i < nt; i += kFastThreads) tabs[i] = f.tab32[S.fast + i];
+  // Prologue: the shape's tables into LDS (16-byte loads, all in flight
+  // before the first store); the workgroup's 16 blocks (geometry from the
+  // segment, counts from block_ptr) into LDS records.
+  {
+    const int n4 = (S.jt_floats + 768) >> 2;
+    const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + S.fast);
+    f4 *dst = reinterpret_cast<f4 *>(tabs);
+    f4 buf[kTabVec];
+#pragma unroll
+    for (int r = 0; r < kTabVec; ++r) buf[r] = src[tid + r * kFastThreads];  // buffer is padded
+#pragma unroll
+    for (int r = 0; r < kTabVec; ++r) asm volatile("" : "+v"(buf[r]));  // all loads before any store
+#pragma unroll
+    for (int r = 0; r < kTabVec; ++r) {
+      const int i = tid + r * kFastThreads;
+      if (i < n4) dst[i] = buf[r];
+    }
+  }
   if (tid < kFastItems) {
     FastItem r;
     r.cls = 4;
@@ -666,9 +692,9 @@ void k_fast(FrameDev f) {
         r.vb1 = f.shared ? (long long)f.block_ptr[f.n_items] + (lo - f.block_ptr[f.chroma_first]) : lo;
         r.ob1 = G.out_off[1] + pix;
       }
-      if (r.cls == 3) push_deferred(f, m, r.K, w, h);
     }
     items[tid] = r;
+    defer[tid] = (r.cls == 3) ? 1 : 0;
   }
   __syncthreads();
   // Bin by size class so that every wave solves blocks of one class.
@@ -694,33 +720,47 @@ void k_fast(FrameDev f) {
   }
   const int Kw = __builtin_amdgcn_readfirstlane(kw);
   const int NVw = __builtin_amdgcn_readfirstlane(nvw);
-  if (Kw == 0) return;
-  FastStage &st = stage[wv];
-  bool solved;
-  if (Kw <= 15) solved = fast_solve<16>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
-  else if (Kw <= 23) solved = fast_solve<24>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
-  else solved = fast_solve<32>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
-  if (ok && !solved && t == 0) push_deferred(f, items[slot].m, items[slot].K, w, h);
-  const bool eval = ok && solved;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (Kw > 0) {
+    FastStage &st = stage[wv];
+    bool solved;
+    if (Kw <= 15) solved = fast_solve<16>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
+    else if (Kw <= 23) solved = fast_solve<24>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
+    else solved = fast_solve<32>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
+    if (ok && !solved && t == 0) defer[slot] = 1;
+    const bool eval = ok && solved;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-  const unsigned long long em = __ballot(eval);
-  unsigned okmask = 0;
-  long long ob[kWaveItems][2];
+    const unsigned long long em = __ballot(eval);
+    unsigned okmask = 0;
+    long long ob[kWaveItems][2];
 #pragma unroll
-  for (int g = 0; g < kWaveItems; ++g) {
-    okmask |= ((em >> (16 * g)) & 1ull) ? (1u << g) : 0u;
-    const int sg2 = __builtin_amdgcn_readlane(slot, 16 * g);
-    ob[g][0] = items[sg2].ob0;
-    ob[g][1] = items[sg2].ob1;
+    for (int g = 0; g < kWaveItems; ++g) {
+      okmask |= ((em >> (16 * g)) & 1ull) ? (1u << g) : 0u;
+      const int sg2 = __builtin_amdgcn_readlane(slot, 16 * g);
+      ob[g][0] = items[sg2].ob0;
+      ob[g][1] = items[sg2].ob1;
+    }
+    if (okmask) {
+      const float *D = tabs + S.jt_floats;
+      if (Kw <= 15) fast_eval<16>(f, D, st, lane, okmask, NVw, w, h, G.W, ob);
+      else if (Kw <= 23) fast_eval<24>(f, D, st, lane, okmask, NVw, w, h, G.W, ob);
+      else fast_eval<32>(f, D, st, lane, okmask, NVw, w, h, G.W, ob);
+    }
   }
-  if (okmask) {
-    const float *D = tabs + S.jt_floats;
-    if (Kw <= 15) fast_eval<16>(f, D, st, lane, okmask, NVw, w, h, G.W, ob);
-    else if (Kw <= 23) fast_eval<24>(f, D, st, lane, okmask, NVw, w, h, G.W, ob);
-    else fast_eval<32>(f, D, st, lane, okmask, NVw, w, h, G.W, ob);
+
+  // Blocks the waves did not take (K = 0, K = w*h, K > 31, invalid counts)
+  // or whose pivots asked for FP64 refinement: the whole workgroup runs the
+  // general algorithm on them, one at a time, with the bordered system in
+  // this workgroup's global slot.
+  __syncthreads();
+  float *slot_mem = f.slots + (long long)blockIdx.x * f.slot_floats;
+  for (int j = 0; j < kFastItems; ++j) {
+    if (defer[j]) {
+      __syncthreads();
+      general_block<16>(f, items[j].m, gs, slot_mem);
+    }
   }
 }
 
