@@ -359,6 +359,13 @@ __device__ __forceinline__ float bcast_f(float x, int src) {
   return __builtin_bit_cast(float, bcast_i(__builtin_bit_cast(int, x), src));
 }
 
+// The 64-bit value v of lane `src` (uniform result).
+__device__ __forceinline__ long long lane_i64(long long v, int src) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)v, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(v >> 32), src);
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
 // Reductions over the 16 lanes of a DPP row.
 __device__ __forceinline__ float row_min(float v) {
   for (int o = 8; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 16));
@@ -550,7 +557,7 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *it
     const int i = t + 16 * s;
     const float rd = __builtin_amdgcn_rcpf(diag[s]);
     const float x0 = T[s][0] * rd, x1 = T[s][1] * rd;
-    if (i < R) {
+    {  // every staged row past K holds zeros (16-point chunks may read up to row 31)
       FastPoint P;
       P.x = i < K ? xr[s] : 0;
       P.y = i < K ? yr[s] : 0;
@@ -575,7 +582,7 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *it
 template <int R>
 __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, const FastStage &st,
                                           int lane, unsigned okmask, int nvw, int w, int h,
-                                          int W, const long long ob[kWaveItems][2]) {
+                                          int W, long long ob0, long long ob1) {
   constexpr int nch = R / 4;  // staged rows K..R-1 hold zero coefficients
   const float *Dw = D, *Dh = D + 256, *lam = D + 512;
   const int lo = lane & 15, hi = lane >> 4;
@@ -625,13 +632,108 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
     for (int g = 0; g < kWaveItems; ++g) {
       if (!((okmask >> g) & 1u)) continue;
       const float a = st.a[g][v];
-      const long long o = v ? ob[g][1] : ob[g][0];
+      const long long o = lane_i64(v ? ob1 : ob0, 16 * g);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int y = 4 * hi + j, x = lo;
         if (x < w && y < h) f.out[o + (long long)y * W + x] = U[g][j] + a;
       }
     }
+  }
+}
+
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+
+// acc += A * B on a 16x16x16 MFMA with reduced-precision operands: lane l
+// supplies A[l%16][4(l/16)+e] = a[e] and B[4(l/16)+e][l%16] = b[e], e < 4.
+template <int EV>
+__device__ __forceinline__ f4 mma16(f4 acc, const float a[4], const float b[4]) {
+  if constexpr (EV == 1) {  // FP16 operands
+    h4 ha, hb;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) { ha[e] = (_Float16)a[e]; hb[e] = (_Float16)b[e]; }
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(ha, hb, acc, 0, 0, 0);
+  } else if constexpr (EV == 2) {  // BF16 operands
+    b4 ba, bb;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) { ba[e] = (__bf16)a[e]; bb[e] = (__bf16)b[e]; }
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ba, bb, acc, 0, 0, 0);
+  } else {  // split BF16: x = hi + lo, A B ~ hi*hi + hi*lo + lo*hi
+    b4 ah, al, bh, bl;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ah[e] = (__bf16)a[e];
+      al[e] = (__bf16)(a[e] - (float)ah[e]);
+      bh[e] = (__bf16)b[e];
+      bl[e] = (__bf16)(b[e] - (float)bh[e]);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+  }
+}
+
+// The evaluation of fast_eval with FP16 / BF16 / split-BF16 operands and
+// FP32 accumulation: one 16x16x16 MFMA per 16 points and one per transform.
+template <int R, int EV>
+__device__ __forceinline__ void fast_eval16(const FrameDev &f, const float *D, const FastStage &st,
+                                            int lane, unsigned okmask, int nvw, int w, int h,
+                                            int W, long long ob0, long long ob1) {
+  constexpr int nch = (R + 15) / 16;
+  const float *Dw = D, *Dh = D + 256, *lam = D + 512;
+  const int lo = lane & 15, hi = lane >> 4;
+  float lam4[4], dwb[4], dha[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int pq = 4 * hi + j;
+    lam4[j] = lam[lo * 16 + pq];
+    dwb[j] = Dw[pq * 16 + lo];
+    dha[j] = Dh[pq * 16 + lo];
+  }
+  for (int v = 0; v < nvw; ++v) {
+#pragma unroll 1
+    for (int g = 0; g < kWaveItems; ++g) {
+      if (!((okmask >> g) & 1u)) continue;
+      f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ch = 0; ch < nch; ++ch) {
+        float a[4], b[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const FastPoint P = st.p[g][ch * 16 + 4 * hi + e];
+          a[e] = (v ? P.c1 : P.c0) * Dw[lo * 16 + P.x];  // A[p = lo][i]
+          b[e] = Dh[lo * 16 + P.y];                      // B[i][q = lo]
+        }
+        acc = mma16<EV>(acc, a, b);
+      }
+      float a[4], sx[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[e] = acc[e] * lam4[e];  // U^[q = lo][p = 4 hi + e]
+      const f4 S = mma16<EV>(f4{0.f, 0.f, 0.f, 0.f}, a, dwb);  // S[q = 4 hi + r][x = lo]
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sx[e] = S[e];
+      const f4 U = mma16<EV>(f4{0.f, 0.f, 0.f, 0.f}, dha, sx);  // U[y = 4 hi + r][x = lo]
+      const float av = st.a[g][v];
+      const long long o = lane_i64(v ? ob1 : ob0, 16 * g);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int y = 4 * hi + j, x = lo;
+        if (x < w && y < h) f.out[o + (long long)y * W + x] = U[j] + av;
+      }
+    }
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void fast_eval_any(const FrameDev &f, const float *D, const FastStage &st,
+                                              int lane, unsigned okmask, int nvw, int w, int h, int W,
+                                              long long ob0, long long ob1) {
+  switch (f.eval) {
+    case 1: fast_eval16<R, 1>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1); break;
+    case 2: fast_eval16<R, 2>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1); break;
+    case 3: fast_eval16<R, 3>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1); break;
+    default: fast_eval<R>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1); break;
   }
 }
 
@@ -734,19 +836,14 @@ void k_fast(FrameDev f) {
 
     const unsigned long long em = __ballot(eval);
     unsigned okmask = 0;
-    long long ob[kWaveItems][2];
 #pragma unroll
-    for (int g = 0; g < kWaveItems; ++g) {
-      okmask |= ((em >> (16 * g)) & 1ull) ? (1u << g) : 0u;
-      const int sg2 = __builtin_amdgcn_readlane(slot, 16 * g);
-      ob[g][0] = items[sg2].ob0;
-      ob[g][1] = items[sg2].ob1;
-    }
+    for (int g = 0; g < kWaveItems; ++g) okmask |= ((em >> (16 * g)) & 1ull) ? (1u << g) : 0u;
+    const long long ob0 = items[slot].ob0, ob1 = items[slot].ob1;
     if (okmask) {
       const float *D = tabs + S.jt_floats;
-      if (Kw <= 15) fast_eval<16>(f, D, st, lane, okmask, NVw, w, h, G.W, ob);
-      else if (Kw <= 23) fast_eval<24>(f, D, st, lane, okmask, NVw, w, h, G.W, ob);
-      else fast_eval<32>(f, D, st, lane, okmask, NVw, w, h, G.W, ob);
+      if (Kw <= 15) fast_eval_any<16>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
+      else if (Kw <= 23) fast_eval_any<24>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
+      else fast_eval_any<32>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
     }
   }
 

@@ -197,3 +197,39 @@ def test_host_errors(dec):
         assert dec.decode(d, binding.default_params(**bad), check=False) == binding.PDI_EINVAL
     assert dec.decode(d, check=False) == 0
     assert dec.sync() == 0
+
+
+# Reduced-precision evaluation (the solve stays FP32).  Tolerances from the
+# operand unit roundoff u of each format over the three chained products of
+# the DCT-factored evaluation, each with magnitude up to ~64 grey levels:
+# 3 products * 2 operands * u * 64.  FP16: u = 2^-11 -> 0.19 (use 0.25);
+# BF16: u = 2^-8 -> 1.5; split BF16 keeps ~16 bits, so the FP32 bound holds.
+EVAL_TOL = {1: 0.25, 2: 1.5, 3: FP32_TOL}
+
+
+@pytest.mark.parametrize("ev", [1, 2, 3])
+@pytest.mark.parametrize("case", ["cfg0", "ragged420", "b8"])
+def test_eval_dtypes(dec, ev, case):
+    fr = {"cfg0": lambda: synth.config_frame(0),
+          "ragged420": lambda: synth.random_frame(70, 37, synth.YUV420, 16, (0.01, 0.12), seed=2606),
+          "b8": lambda: synth.random_frame(100, 67, synth.YUV420, 8, (0.02, 0.3), seed=3)}[case]()
+    got, _ = gpu_decode(dec, fr, eval_dtype=ev)
+    ref = oracle.decode_flat(fr)
+    mx, agree = compare(got, ref)
+    print(f"  eval {ev}: max|err|={mx:.3e} round-agree={agree * 100:.4f}%", flush=True)
+    assert mx <= EVAL_TOL[ev]
+    if ev == 3:  # split BF16 meets the acceptance bars
+        assert mx <= 0.5 and agree >= 0.999
+
+
+def test_eval_dtypes_config1(dec):
+    """FullHD frame: split BF16 within the bars; FP16 within 0.5 grey levels."""
+    fr = synth.config_frame(1, keep_fields=False)
+    ref = oracle.decode_flat(fr)
+    for ev in (1, 3):
+        got, _ = gpu_decode(dec, fr, eval_dtype=ev)
+        mx, agree = compare(got, ref)
+        print(f"  eval {ev}: max|err|={mx:.3e} round-agree={agree * 100:.4f}%", flush=True)
+        assert mx <= EVAL_TOL[ev] and mx <= 0.5
+        if ev == 3:
+            assert agree >= 0.999
