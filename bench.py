@@ -1,17 +1,27 @@
 #!/usr/bin/env python3
 """Residual-decode benchmark on one MI355X.
 
-Workload (default): one synthetic 1920x1080 4:2:0 residual frame, 16x16
-blocks, per-block mask density U[1%, 10%] (3-26 points per full block),
-values = smooth sum of 4 random sinusoids + N(0, 2) noise, clipped to
-[-64, 64].  One step = one decode_residual call over that frame: every block
-assembled, solved and evaluated on the GPU, inputs already resident in HBM.
+Workloads (synthetic, seeded; the recipe is in paper_2008_10273_amd/synth.py):
+  --config 1 (default): one 1920x1080 4:2:0 residual frame, 16x16 blocks,
+      per-block mask density U[1%, 10%] (3-26 points per full block), values
+      = smooth sum of 4 random sinusoids + N(0, 2) noise, clipped to
+      [-64, 64].  One step = one decode_residual call over that frame: every
+      block assembled, solved and evaluated on the GPU, inputs resident in HBM.
+  --config 0 / 2: the 256x256 grey case / the same 1080p frame with 32x32
+      blocks and density U[2%, 10%].
+  --config 3: 64 consecutive 1080p frames decoded as one HIP-graph replay
+      (pdi_seq, frames spread over --nstreams streams); one step = one replay.
+  --config 4: serving mix, 16 client streams (6x 854x480, 6x 1280x720,
+      4x 1920x1080, 4:2:0, b16) with Poisson arrivals at 25 frames/s each,
+      through the pdi_server request loop; latency counts from submission
+      (host data) to completion on the device.
 
-Prints one JSON line: frames/s (value), p50/p99 single-frame latency, the
-error against the FP64 oracle, the plain per-block path on the same GPU, a
-roofline record for the decode and the oracle timed on the host cores.
+Prints one JSON line with the metric, latency percentiles, the error against
+the FP64 oracle, a roofline record of the decode and the oracle timed on the
+host cores.
 """
 import argparse
+import concurrent.futures as cf
 import json
 import os
 import sys
@@ -33,38 +43,29 @@ def algorithmic_bytes(fr) -> int:
     return int(n_in + 4 * fr.out_size)
 
 
-def time_decodes(torch, dec, d, params, stream, steps, warmup):
-    for _ in range(warmup):
-        dec.decode(d, params, stream=stream)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(steps):
-        dec.decode(d, params, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / 1e3, wall
+def _gen(job):
+    from paper_2008_10273_amd import synth
+    kind, a, b = job
+    if kind == "cfg":
+        return synth.config_frame(a, frame=b, keep_fields=False)
+    return synth.serving_frame(a, b)
 
 
-def latencies(torch, dec, d, params, stream, iters):
-    out = []
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    for _ in range(iters):
-        e0.record(stream)
-        dec.decode(d, params, stream=stream)
-        e1.record(stream)
-        e1.synchronize()
-        out.append(e0.elapsed_time(e1))
-    return np.array(out)
+def generate(jobs, workers):
+    """Frames generated in worker processes (before the GPU is touched)."""
+    if workers <= 1 or len(jobs) <= 1:
+        return [_gen(j) for j in jobs]
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_gen, jobs, chunksize=1))
 
 
-def cpu_baseline(fr, min_seconds=5.0, min_frames=3):
+def host_cores():
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def cpu_baseline(fr, min_seconds=5.0, min_frames=3, what="the benchmark frame"):
     import oracle
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = host_cores()
     oracle.decode(fr, nthreads=cores)  # load + warm
     n, t0 = 0, time.perf_counter()
     ref = None
@@ -73,44 +74,100 @@ def cpu_baseline(fr, min_seconds=5.0, min_frames=3):
         n += 1
     dt = time.perf_counter() - t0
     return ref, dict(value=n / dt, unit="frames/s", cores=cores, kind="oracle",
-                     sample=f"{n} decodes of the benchmark frame (FP64 plain-definition oracle, OpenMP over blocks), {dt:.1f} s")
+                     sample=f"{n} decodes of {what} (FP64 oracle, OpenMP over blocks), {dt:.1f} s")
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2])
-    ap.add_argument("--eval", default="fp32", choices=sorted(EVALS))
-    ap.add_argument("--latency-iters", type=int, default=300)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain-path comparison")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this decoder runs on one GPU; --gpus {args.gpus} is not supported "
-              "(blocks and frames shard across GPUs with no exchange step, see DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
+def error_vs(got, ref):
+    e = np.abs(got - ref)
+    q = lambda x: np.clip(np.rint(x), -128, 127)
+    return dict(max_abs=float(e.max()), round_agree=float(np.mean(q(got) == q(ref))))
 
-    import torch
-    from paper_2008_10273_amd import binding, synth
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    fr = synth.config_frame(args.config, keep_fields=False)
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
+class StreamTimer:
+    """HIP events recorded on the stream the decode kernels run on."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+        self.e0 = torch.cuda.Event(enable_timing=True)
+        self.e1 = torch.cuda.Event(enable_timing=True)
+
+    def start(self):
+        self.e0.record(self.stream)
+
+    def stop(self):
+        self.e1.record(self.stream)
+        self.e1.synchronize()
+        return self.e0.elapsed_time(self.e1) / 1e3
+
+
+def time_decodes(torch, dec, d, params, stream, steps, warmup):
+    for _ in range(warmup):
+        dec.decode(d, params, stream=stream)
+    torch.cuda.synchronize()
+    tm = StreamTimer(torch, stream)
+    t0 = time.perf_counter()
+    tm.start()
+    for _ in range(steps):
+        dec.decode(d, params, stream=stream)
+    secs = tm.stop()
+    torch.cuda.synchronize()
+    return secs, time.perf_counter() - t0
+
+
+def latencies(torch, dec, d, params, stream, iters):
+    out = []
+    tm = StreamTimer(torch, stream)
+    for _ in range(iters):
+        tm.start()
+        dec.decode(d, params, stream=stream)
+        out.append(1e3 * tm.stop())
+    return np.array(out)
+
+
+def overlapped(torch, dec, ds, params, nstreams, steps):
+    """Frames in flight on several streams at once (each stream decodes its
+    own frames back to back); whole-job frames/s."""
+    streams = [torch.cuda.Stream() for _ in range(nstreams)]
+    for k in range(2 * nstreams):
+        dec.decode(ds[k % len(ds)], params, stream=streams[k % nstreams])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        dec.decode(ds[k % len(ds)], params, stream=streams[k % nstreams])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for s in streams:
+        assert dec.sync(s) == 0
+    return steps / dt
+
+
+def bench_frame(args, torch, binding, synth):
+    fr = generate([("cfg", args.config, 0)], 1)[0]
+    extra = generate([("cfg", args.config, k) for k in range(1, 8)], args.workers) if args.config != 0 else []
     cfg = synth.CONFIGS[args.config]
     dec = binding.Decoder(0)
     d = dec.upload(fr)
     stream = torch.cuda.Stream()
     params = binding.default_params(eval_dtype=EVALS[args.eval])
-
-    print(f"# bench: config {args.config} ({cfg['name']}), eval {args.eval}, {args.steps} steps", file=sys.stderr, flush=True)
+    log(f"config {args.config} ({cfg['name']}), eval {args.eval}, {args.steps} steps")
     secs, wall = time_decodes(torch, dec, d, params, stream, args.steps, args.warmup)
-    rc = dec.sync(stream)
-    assert rc == 0, binding.pdi_last_error(dec.ctx)
+    assert dec.sync(stream) == 0, binding.pdi_last_error(dec.ctx)
     fps = args.steps / secs
     lat = latencies(torch, dec, d, params, stream, args.latency_iters)
     got = d["out"].cpu().numpy().astype(np.float64)
-    print(f"# fast path: {fps:.1f} frames/s, {1e3 * secs / args.steps:.4f} ms/frame", file=sys.stderr, flush=True)
+    log(f"decode: {fps:.1f} frames/s, {1e3 * secs / args.steps:.4f} ms/frame")
+
+    multi = None
+    if extra:
+        ds = [d] + [dec.upload(f) for f in extra]
+        mfps = overlapped(torch, dec, ds, params, args.nstreams, args.steps)
+        multi = dict(value=mfps, unit="frames/s", streams=args.nstreams, frames=len(ds),
+                     note="8 different frames of this workload in flight on several streams")
+        log(f"overlapped on {args.nstreams} streams: {mfps:.1f} frames/s")
 
     plain = None
     if not args.no_plain:
@@ -119,51 +176,236 @@ def main():
         ps, _ = time_decodes(torch, dec, d, pp, stream, psteps, 5)
         plain = dict(value=psteps / ps, unit="frames/s", ms_per_step=1e3 * ps / psteps,
                      path="one workgroup per block, FP32 LDS Gauss-Jordan, direct VALU evaluation")
-        print(f"# plain path: {plain['value']:.1f} frames/s", file=sys.stderr, flush=True)
+        log(f"plain path: {plain['value']:.1f} frames/s")
 
-    err = None
-    cpu = None
+    err = cpu = None
     if not args.no_cpu:
         ref, cpu = cpu_baseline(fr)
-        e = np.abs(got - ref)
-        q = lambda x: np.clip(np.rint(x), -128, 127)
-        err = dict(max_abs=float(e.max()), round_agree=float(np.mean(q(got) == q(ref))))
-        print(f"# oracle: {cpu['value']:.2f} frames/s on {cpu['cores']} cores; max|err| {err['max_abs']:.3e}",
-              file=sys.stderr, flush=True)
+        err = error_vs(got, ref)
+        log(f"oracle: {cpu['value']:.2f} frames/s on {cpu['cores']} cores; max|err| {err['max_abs']:.3e}")
 
     ab = algorithmic_bytes(fr)
     t_dec = secs / args.steps
     achieved = ab / t_dec / 1e9
-    rec = {
-        "metric": METRIC,
-        "value": fps,
-        "unit": "frames/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * t_dec,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if args.eval == "fp32" else f"f32 solve, {args.eval} eval",
-        "data": "synthetic",
-        "config": {"workload": cfg["name"], "width": cfg["width"], "height": cfg["height"],
-                   "format": "4:2:0" if cfg["fmt"] == 1 else "gray", "block_size": cfg["block_size"],
-                   "density": list(cfg["density"]), "frames_per_step": 1,
-                   "mask_blocks": fr.n_mask_blocks, "mask_points": int(fr.pos.size)},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "mean": float(lat.mean())},
-        "error_vs_oracle": err,
-        "plain_path": plain,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "decode (k_fast + k_general_deferred)",
-                     "algorithmic_bytes_per_launch": ab},
-        "cpu_baseline": cpu,
-        "wall_s": wall,
-    }
-    print(json.dumps(rec), flush=True)
+    rec = dict(metric=METRIC, value=fps, unit="frames/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=1e3 * t_dec, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f32" if args.eval == "fp32" else f"f32 solve, {args.eval} eval", data="synthetic",
+               config={"workload": cfg["name"], "width": cfg["width"], "height": cfg["height"],
+                       "format": "4:2:0" if cfg["fmt"] == 1 else "gray", "block_size": cfg["block_size"],
+                       "density": list(cfg["density"]), "frames_per_step": 1,
+                       "mask_blocks": fr.n_mask_blocks, "mask_points": int(fr.pos.size)},
+               latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "mean": float(lat.mean())},
+               error_vs_oracle=err, plain_path=plain, overlapped=multi,
+               roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_fast" if cfg["block_size"] <= 16 else "k_plain_all + k_general_deferred",
+                         "algorithmic_bytes_per_launch": ab},
+               cpu_baseline=cpu, wall_s=wall)
     dec.close()
+    return rec
+
+
+def bench_sequence(args, torch, binding, synth):
+    cfg = synth.CONFIGS[3]
+    n = cfg["frames"]
+    log(f"config 3: generating {n} frames")
+    frames = generate([("cfg", 3, k) for k in range(n)], args.workers)
+    dec = binding.Decoder(0)
+    params = binding.default_params(eval_dtype=EVALS[args.eval])
+    ds = [dec.upload(f) for f in frames]
+    seq = binding.Sequence(dec, ds, params, nstreams=args.nstreams)
+    stream = torch.cuda.Stream()
+    for _ in range(args.warmup):
+        seq.launch(stream)
+    assert seq.sync(stream) == 0
+    tm = StreamTimer(torch, stream)
+    t0 = time.perf_counter()
+    tm.start()
+    for _ in range(args.steps):
+        seq.launch(stream)
+    secs = tm.stop()
+    wall = time.perf_counter() - t0
+    assert seq.sync(stream) == 0
+    reps = []
+    for _ in range(args.latency_iters // 10 + 5):
+        tm.start()
+        seq.launch(stream)
+        reps.append(1e3 * tm.stop())
+    reps = np.array(reps)
+    fps = n * args.steps / secs
+    log(f"graph replay: {fps:.1f} frames/s, {1e3 * secs / args.steps:.3f} ms per {n}-frame replay")
+
+    # the same frames decoded eagerly, one stream, one after another
+    for d in ds[:4]:
+        dec.decode(d, params, stream=stream)
+    torch.cuda.synchronize()
+    tm.start()
+    for d in ds:
+        dec.decode(d, params, stream=stream)
+    eager = n / tm.stop()
+    log(f"eager single stream: {eager:.1f} frames/s")
+
+    err = cpu = None
+    got = ds[0]["out"].cpu().numpy().astype(np.float64)
+    if not args.no_cpu:
+        ref, cpu = cpu_baseline(frames[0], what="frame 0 of the sequence")
+        err = error_vs(got, ref)
+        log(f"oracle: {cpu['value']:.2f} frames/s; max|err| {err['max_abs']:.3e}")
+    ab = sum(algorithmic_bytes(f) for f in frames)
+    t_step = secs / args.steps
+    achieved = ab / t_step / 1e9
+    rec = dict(metric=METRIC, value=fps, unit="frames/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=1e3 * t_step, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f32" if args.eval == "fp32" else f"f32 solve, {args.eval} eval", data="synthetic",
+               config={"workload": cfg["name"], "width": cfg["width"], "height": cfg["height"], "format": "4:2:0",
+                       "block_size": cfg["block_size"], "density": list(cfg["density"]), "frames_per_step": n,
+                       "streams": args.nstreams, "capture": "one HIP graph per sequence"},
+               latency_ms={"replay_p50": float(np.percentile(reps, 50)), "replay_p99": float(np.percentile(reps, 99)),
+                           "per_frame_mean": float(np.mean(reps) / n)},
+               eager_single_stream=dict(value=eager, unit="frames/s"),
+               error_vs_oracle=err,
+               roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_fast (graph replay)",
+                         "algorithmic_bytes_per_launch": ab},
+               cpu_baseline=cpu, wall_s=wall)
+    seq.close()
+    dec.close()
+    return rec
+
+
+def bench_serving(args, torch, binding, synth):
+    nstreams = sum(c for _, _, c in synth.SERVING_MIX)
+    per = args.serve_frames
+    log(f"config 4: generating {per} frames for each of {nstreams} client streams")
+    jobs = [("srv", s, j) for s in range(nstreams) for j in range(per)]
+    flat = generate(jobs, args.workers)
+    frames = [flat[s * per:(s + 1) * per] for s in range(nstreams)]
+    dec = binding.Decoder(0)
+    params = binding.default_params(eval_dtype=EVALS[args.eval])
+    # device output ring per client stream (results stay in HBM)
+    ring = 4
+    outs = [[torch.empty(frames[s][0].out_size, dtype=torch.float32, device="cuda") for _ in range(ring)]
+            for s in range(nstreams)]
+    srv = binding.Server(dec, nlanes=args.lanes, hbm_budget_bytes=args.budget_mb << 20, max_queue=4096)
+    # warm every geometry on every lane
+    warm = [srv.submit(frames[s][0], params, want_output=False, out_dev=outs[s][0])
+            for s in range(nstreams) for _ in range(args.lanes)]
+    for rc, t, _ in warm:
+        assert rc == 0 and srv.wait(t)[0] == 0
+
+    rate = args.fps_per_stream
+    T = args.warm_s + args.duration
+    rng = np.random.default_rng(np.random.SeedSequence([20081027, 4, 999]))
+    events = []
+    for s in range(nstreams):
+        t = rng.exponential(1.0 / rate)
+        j = 0
+        while t < T:
+            events.append((t, s, j))
+            t += rng.exponential(1.0 / rate)
+            j += 1
+    events.sort()
+    log(f"serving: {len(events)} arrivals over {T:.1f} s, {args.lanes} lanes")
+    tickets = []
+    t0 = time.perf_counter()
+    for (t, s, j) in events:
+        now = time.perf_counter() - t0
+        if t > now:
+            time.sleep(t - now)
+        rc, tk, _ = srv.submit(frames[s][j % per], params, want_output=False, out_dev=outs[s][j % ring])
+        assert rc == 0, rc
+        tickets.append((t, s, tk))
+    lat, done_w = [], 0
+    for (t, s, tk) in tickets:
+        st, l_us = srv.wait(tk)
+        assert st == 0, st
+        if t >= args.warm_s:
+            lat.append(l_us / 1e3)
+            done_w += 1
+    wall = time.perf_counter() - t0
+    lat = np.array(lat)
+    served_fps = done_w / args.duration
+    log(f"serving: {served_fps:.1f} frames/s, p50 {np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
+
+    # capacity: every frame submitted at once, drained as fast as the lanes go
+    burst = [(s, j) for j in range(per) for s in range(nstreams)] * args.burst_rounds
+    tb = time.perf_counter()
+    tks = [srv.submit(frames[s][j], params, want_output=False, out_dev=outs[s][j % ring])[1] for s, j in burst]
+    for tk in tks:
+        assert srv.wait(tk)[0] == 0
+    cap = len(burst) / (time.perf_counter() - tb)
+    log(f"capacity (saturated): {cap:.1f} frames/s")
+    srv.close()
+
+    # one 1080p frame of the mix against the oracle
+    err = cpu = None
+    if not args.no_cpu:
+        s1080 = nstreams - 1
+        d = dec.upload(frames[s1080][0])
+        dec.decode(d, params)
+        assert dec.sync() == 0
+        ref, cpu = cpu_baseline(frames[s1080][0], what="one 1080p frame of the serving mix")
+        err = error_vs(d["out"].cpu().numpy().astype(np.float64), ref)
+    mix_px = sum(w * h * c for w, h, c in synth.SERVING_MIX) / nstreams
+    rec = dict(metric=METRIC, value=served_fps, unit="frames/s", n_gpus=1, steps=done_w, warmup=len(tickets) - done_w,
+               ms_per_step=1e3 * args.duration / max(done_w, 1), higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f32" if args.eval == "fp32" else f"f32 solve, {args.eval} eval",
+               data="synthetic",
+               config={"workload": "serving_mix16_420_b16_d1-10", "streams": nstreams,
+                       "mix": [list(m) for m in synth.SERVING_MIX], "arrivals": f"Poisson, {rate} frames/s per stream",
+                       "offered_fps": rate * nstreams, "lanes": args.lanes, "hbm_budget_mb": args.budget_mb,
+                       "measured_s": args.duration, "mean_pixels_per_frame": mix_px},
+               latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "mean": float(lat.mean()), "max": float(lat.max()),
+                           "includes": "host submit, H2D copy, queueing, decode, completion"},
+               capacity=dict(value=cap, unit="frames/s", note="all frames submitted at once"),
+               error_vs_oracle=err, roofline=None, cpu_baseline=cpu, wall_s=wall)
+    dec.close()
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2, 3, 4])
+    ap.add_argument("--eval", default="fp32", choices=sorted(EVALS))
+    ap.add_argument("--latency-iters", type=int, default=300)
+    ap.add_argument("--nstreams", type=int, default=4, help="streams for overlapped / sequence decodes")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1), help="frame generator processes")
+    ap.add_argument("--lanes", type=int, default=4, help="serving: GPU streams of the request loop")
+    ap.add_argument("--budget-mb", type=int, default=2048, help="serving: HBM budget of admitted frames")
+    ap.add_argument("--fps-per-stream", type=float, default=25.0)
+    ap.add_argument("--duration", type=float, default=10.0, help="serving: measured seconds")
+    ap.add_argument("--warm-s", type=float, default=1.0, help="serving: unmeasured seconds first")
+    ap.add_argument("--serve-frames", type=int, default=4, help="serving: distinct frames per client stream")
+    ap.add_argument("--burst-rounds", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-path comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this decoder runs on one GPU; --gpus {args.gpus} is not supported "
+              "(blocks and frames shard across GPUs with no exchange step, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    if args.steps is None:
+        args.steps = {3: 30}.get(args.config, 500)
+    if args.warmup is None:
+        args.warmup = {3: 3}.get(args.config, 50)
+
+    from paper_2008_10273_amd import synth
+    # frames are generated before torch touches the GPU (worker processes)
+    import torch
+    from paper_2008_10273_amd import binding
+    if args.config <= 2:
+        rec = bench_frame(args, torch, binding, synth)
+    elif args.config == 3:
+        rec = bench_sequence(args, torch, binding, synth)
+    else:
+        rec = bench_serving(args, torch, binding, synth)
+    assert torch.cuda.is_available()
+    print(json.dumps(rec), flush=True)
 
 
 if __name__ == "__main__":

@@ -96,8 +96,10 @@ void pdi_default_params(pdi_params *p);
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes caps the
  * library's own device allocations (0 = no cap).  The context owns the table
- * cache, the workspace and the device status word.  Use one context per host
- * thread and per concurrently used stream (or serialise externally).
+ * cache and, per stream it is used on, a workspace and a device status word.
+ * Calls are serialised by an internal lock, so one context may be shared by
+ * threads and used on several streams at once (decodes on different streams
+ * run concurrently on the GPU).
  * Returns PDI_EINVAL (bad device / null out), PDI_EHIP, PDI_ENOMEM. */
 int pdi_create(pdi_ctx **out, int device, size_t hbm_budget_bytes);
 
@@ -151,6 +153,75 @@ int pdi_pack_dense(const pdi_frame *frame, const uint8_t *m, const float *f,
 int pdi_validate_host(const pdi_frame *frame, int block_size, const int32_t *block_ptr,
                       const uint16_t *pos, int32_t n_mask_blocks, int32_t chroma_shared,
                       const float *values);
+
+/* ---- Frame sequences as one HIP graph (per-frame decode, captured) ----
+ * The decodes of n frames of ONE geometry (frame, block_size, params, chroma
+ * sharing) are recorded once into a HIP graph, frame k on internal stream
+ * k % nstreams, the streams forked from and joined back to the first one, so
+ * that independent frames overlap on the GPU; pdi_seq_launch replays all n
+ * decodes with one graph launch.  masks[k], values[k] and outs[k] are DEVICE
+ * pointers (caller-owned) read / written by every replay: update their
+ * contents between replays, not their addresses.  pdi_seq_create runs one
+ * eager decode per internal stream first (allocations and errors happen
+ * there), so it must not itself be called under stream capture.
+ * Returns PDI_EINVAL (null pointers, n <= 0, nstreams not in 1..16), the
+ * codes of decode_residual, or PDI_EHIP. */
+typedef struct pdi_seq pdi_seq;
+int pdi_seq_create(pdi_ctx *ctx, int n, const pdi_frame *frame, const pdi_mask *masks,
+                   const float *const *values, int block_size, const pdi_params *params,
+                   float *const *outs, int nstreams, pdi_seq **out);
+/* Enqueue one replay on `stream` (asynchronous). */
+int pdi_seq_launch(pdi_seq *q, void *stream);
+/* Wait for `stream`, then report the device status of the replayed decodes
+ * (as pdi_sync). */
+int pdi_seq_sync(pdi_seq *q, void *stream);
+void pdi_seq_destroy(pdi_seq *q);
+
+/* ---- Serving loop: continuous batching of frames from many streams ----
+ * A server owns nlanes HIP streams and a worker thread.  pdi_submit copies a
+ * frame's HOST mask and values into pinned staging and queues it; the worker
+ * admits queued frames in arrival order whenever a lane is free and the
+ * device bytes of the running frames stay within hbm_budget_bytes (0 = no
+ * cap), copies them to the device, decodes them with decode_residual on the
+ * lane's stream (frames on different lanes overlap on the GPU) and copies the
+ * result back.  A frame's result does not depend on what else is in flight.
+ * The context must outlive the server.  Created on the current HIP device. */
+typedef struct pdi_server pdi_server;
+/* max_queue: frames waiting for admission before pdi_submit answers
+ * PDI_EBUSY.  Returns PDI_EINVAL (null, nlanes not in 1..32, max_queue <= 0)
+ * or PDI_EHIP. */
+int pdi_server_create(pdi_ctx *ctx, int nlanes, size_t hbm_budget_bytes, int max_queue,
+                      pdi_server **out);
+/* Queue one frame.  mask->block_ptr / mask->pos and values are HOST arrays,
+ * copied before the call returns (layouts as for decode_residual; n_values
+ * is the length of values).  out_dev: caller-owned DEVICE float array of the
+ * frame's output size that the decode writes (it must stay valid until the
+ * request completes), or NULL to decode into a pooled server buffer.  out:
+ * HOST float array of the output size that pdi_wait fills, or NULL.
+ * With params->validate the mask and values are checked here (PDI_EMASK /
+ * PDI_EVALUE, nothing queued).  Returns PDI_EINVAL, PDI_ENOMEM (the frame
+ * alone exceeds the budget, or staging failed), PDI_EBUSY (queue full); on
+ * PDI_OK *ticket identifies the request. */
+int pdi_submit(pdi_server *srv, const pdi_frame *frame, const pdi_mask *mask, const float *values,
+               int64_t n_values, int block_size, const pdi_params *params, float *out,
+               float *out_dev, int64_t *ticket);
+/* Non-blocking: *done = 1 once the request has completed; then
+ * *latency_us = submit-to-completion time and the return value is the
+ * request's status.  PDI_EINVAL for an unknown ticket. */
+int pdi_poll(pdi_server *srv, int64_t ticket, int *done, double *latency_us);
+/* Block until the request completes, copy its result to the host `out`
+ * given at submit (if any), release it and return its status (the ticket is
+ * invalid afterwards). */
+int pdi_wait(pdi_server *srv, int64_t ticket, double *latency_us);
+/* Queue length, running frames, device bytes of running frames and device
+ * bytes held (running + buffer pool).  Pointers may be NULL. */
+int pdi_server_stats(pdi_server *srv, int64_t *queued, int64_t *running, size_t *bytes_in_use,
+                     size_t *bytes_allocated);
+/* hold != 0 pauses admission (queued frames wait, running ones finish);
+ * hold = 0 resumes it. */
+int pdi_server_hold(pdi_server *srv, int hold);
+/* Drain queued and running work, then free everything the server owns. */
+void pdi_server_destroy(pdi_server *srv);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,10 @@ ERROR_NAMES = {0: "PDI_OK", -1: "PDI_EINVAL", -2: "PDI_EMASK", -3: "PDI_ENOMEM",
                -5: "PDI_EBUSY", -6: "PDI_EVALUE", -7: "PDI_ESOLVE"}
 
 EXPORTS = ["pdi_default_params", "pdi_create", "pdi_destroy", "decode_residual", "pdi_sync",
-           "pdi_last_error", "pdi_frame_info", "pdi_pack_dense", "pdi_validate_host"]
+           "pdi_last_error", "pdi_frame_info", "pdi_pack_dense", "pdi_validate_host",
+           "pdi_seq_create", "pdi_seq_launch", "pdi_seq_sync", "pdi_seq_destroy",
+           "pdi_server_create", "pdi_submit", "pdi_poll", "pdi_wait", "pdi_server_stats",
+           "pdi_server_hold", "pdi_server_destroy"]
 
 
 class pdi_frame(ctypes.Structure):
@@ -79,6 +82,32 @@ def lib() -> ctypes.CDLL:
         L.pdi_validate_host.argtypes = [ctypes.POINTER(pdi_frame), i32, P, P, ctypes.c_int32,
                                         ctypes.c_int32, P]
         L.pdi_validate_host.restype = i32
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        L.pdi_seq_create.argtypes = [P, i32, ctypes.POINTER(pdi_frame), ctypes.POINTER(pdi_mask), PP, i32,
+                                     ctypes.POINTER(pdi_params), PP, i32, PP]
+        L.pdi_seq_create.restype = i32
+        L.pdi_seq_launch.argtypes = [P, P]
+        L.pdi_seq_launch.restype = i32
+        L.pdi_seq_sync.argtypes = [P, P]
+        L.pdi_seq_sync.restype = i32
+        L.pdi_seq_destroy.argtypes = [P]
+        L.pdi_seq_destroy.restype = None
+        L.pdi_server_create.argtypes = [P, i32, ctypes.c_size_t, i32, PP]
+        L.pdi_server_create.restype = i32
+        L.pdi_submit.argtypes = [P, ctypes.POINTER(pdi_frame), ctypes.POINTER(pdi_mask), P, ctypes.c_int64,
+                                 i32, ctypes.POINTER(pdi_params), P, P, i64p]
+        L.pdi_submit.restype = i32
+        L.pdi_poll.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+        L.pdi_poll.restype = i32
+        L.pdi_wait.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+        L.pdi_wait.restype = i32
+        L.pdi_server_stats.argtypes = [P, i64p, i64p, ctypes.POINTER(ctypes.c_size_t),
+                                       ctypes.POINTER(ctypes.c_size_t)]
+        L.pdi_server_stats.restype = i32
+        L.pdi_server_hold.argtypes = [P, i32]
+        L.pdi_server_hold.restype = i32
+        L.pdi_server_destroy.argtypes = [P]
+        L.pdi_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -213,3 +242,123 @@ class Decoder:
     def sync(self, stream=None) -> int:
         s = stream.cuda_stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
         return pdi_sync(self.ctx, s)
+
+
+class Sequence:
+    """pdi_seq: the decodes of n same-geometry frames captured into one HIP
+    graph over ``nstreams`` internal streams.  ``frames`` are device dicts
+    from ``Decoder.upload``; replays read their current buffer contents."""
+
+    def __init__(self, dec: "Decoder", frames, params: Optional[pdi_params] = None, nstreams: int = 4):
+        self.dec = dec
+        self.frames = list(frames)
+        n = len(self.frames)
+        f0 = self.frames[0]["frame"]
+        fr = pdi_frame(f0.width, f0.height, f0.fmt)
+        masks = (pdi_mask * n)()
+        vals = (ctypes.c_void_p * n)()
+        outs = (ctypes.c_void_p * n)()
+        for k, d in enumerate(self.frames):
+            f = d["frame"]
+            if (f.width, f.height, f.fmt, f.block_size, f.chroma_shared) != \
+                    (f0.width, f0.height, f0.fmt, f0.block_size, f0.chroma_shared):
+                raise ValueError("a sequence holds frames of one geometry")
+            masks[k] = pdi_mask(d["block_ptr"].data_ptr(), d["pos"].data_ptr(), d["n_mask_blocks"],
+                                int(bool(f.chroma_shared)))
+            vals[k] = d["values"].data_ptr()
+            outs[k] = d["out"].data_ptr()
+        h = ctypes.c_void_p()
+        rc = lib().pdi_seq_create(dec.ctx, n, ctypes.byref(fr), masks, vals, f0.block_size,
+                                  ctypes.byref(params) if params is not None else None, outs, nstreams,
+                                  ctypes.byref(h))
+        if rc != PDI_OK:
+            raise PdiError(rc, pdi_last_error(dec.ctx))
+        self.handle = h.value
+
+    def launch(self, stream=None) -> int:
+        s = stream.cuda_stream if stream is not None else self.dec.torch.cuda.current_stream(self.dec.device).cuda_stream
+        return lib().pdi_seq_launch(self.handle, s)
+
+    def sync(self, stream=None) -> int:
+        s = stream.cuda_stream if stream is not None else self.dec.torch.cuda.current_stream(self.dec.device).cuda_stream
+        return lib().pdi_seq_sync(self.handle, s)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pdi_seq_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """pdi_server: continuous-batching request loop over ``nlanes`` streams.
+    ``submit`` takes a host frame (synth.Frame-like, numpy arrays)."""
+
+    def __init__(self, dec: "Decoder", nlanes: int = 4, hbm_budget_bytes: int = 0, max_queue: int = 1024):
+        self.dec = dec
+        h = ctypes.c_void_p()
+        rc = lib().pdi_server_create(dec.ctx, nlanes, hbm_budget_bytes, max_queue, ctypes.byref(h))
+        if rc != PDI_OK:
+            raise PdiError(rc, "pdi_server_create")
+        self.handle = h.value
+        self._keep = {}
+
+    def submit(self, frame, params: Optional[pdi_params] = None, want_output: bool = True, out_dev=None):
+        """Returns (rc, ticket, out): ``out`` is the host array that ``wait``
+        fills (None unless want_output); ``out_dev`` is an optional device
+        tensor the decode writes into."""
+        import numpy as np
+        bp = np.ascontiguousarray(frame.block_ptr, np.int32)
+        pos = np.ascontiguousarray(frame.pos, np.uint16)
+        vals = np.ascontiguousarray(frame.values, np.float32)
+        rc, nb, nel = pdi_frame_info(frame.width, frame.height, frame.fmt, frame.block_size, frame.chroma_shared)
+        out = np.empty(nel, np.float32) if want_output else None
+        fr = pdi_frame(frame.width, frame.height, frame.fmt)
+        mk = pdi_mask(bp.ctypes.data, pos.ctypes.data if pos.size else None, int(bp.size - 1),
+                      int(bool(frame.chroma_shared)))
+        t = ctypes.c_int64()
+        rc = lib().pdi_submit(self.handle, ctypes.byref(fr), ctypes.byref(mk), vals.ctypes.data, int(vals.size),
+                              frame.block_size, ctypes.byref(params) if params is not None else None,
+                              out.ctypes.data if out is not None else None,
+                              out_dev.data_ptr() if out_dev is not None else None, ctypes.byref(t))
+        if rc == PDI_OK:
+            self._keep[t.value] = (out, out_dev)
+        return rc, t.value, out
+
+    def poll(self, ticket: int):
+        done = ctypes.c_int()
+        lat = ctypes.c_double()
+        rc = lib().pdi_poll(self.handle, ticket, ctypes.byref(done), ctypes.byref(lat))
+        return rc, bool(done.value), lat.value
+
+    def wait(self, ticket: int):
+        lat = ctypes.c_double()
+        rc = lib().pdi_wait(self.handle, ticket, ctypes.byref(lat))
+        self._keep.pop(ticket, None)
+        return rc, lat.value
+
+    def stats(self):
+        q, r = ctypes.c_int64(), ctypes.c_int64()
+        u, a = ctypes.c_size_t(), ctypes.c_size_t()
+        lib().pdi_server_stats(self.handle, ctypes.byref(q), ctypes.byref(r), ctypes.byref(u), ctypes.byref(a))
+        return dict(queued=q.value, running=r.value, bytes_in_use=u.value, bytes_allocated=a.value)
+
+    def hold(self, on: bool = True) -> int:
+        return lib().pdi_server_hold(self.handle, int(bool(on)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pdi_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

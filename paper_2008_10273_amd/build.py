@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdinp.so")
-SOURCES = [os.path.join(CSRC, "pdinp_host.cpp"), os.path.join(CSRC, "pdinp_kernels.hip")]
+SOURCES = [os.path.join(CSRC, n) for n in
+           ("pdinp_host.cpp", "pdinp_graph.cpp", "pdinp_server.cpp", "pdinp_kernels.hip")]
 ARCH = os.environ.get("PDI_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 VALU forms are kept out of the generated code.
@@ -43,7 +44,7 @@ def build(verbose: bool = False) -> str:
         subprocess.check_call(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -35,19 +35,26 @@ using TableKey = std::tuple<int, int, int, int, int, int, double>;  // W,H,fmt,b
 
 }  // namespace
 
+// Device scratch of one stream: decodes on different streams run
+// concurrently, so each stream gets its own.
+struct Workspace {
+  int *status = nullptr;    // device status word
+  int *counters = nullptr;  // device counters [8]
+  int *deferred = nullptr;  // device list of deferred mask blocks
+  int deferred_cap = 0;
+  float *slots = nullptr;   // global-memory bordered systems
+  long long slot_floats = 0;
+  int slot_count = 0;
+};
+
 struct pdi_ctx {
   int device = 0;
   size_t budget = 0;
   size_t used = 0;
   std::string err;
-  int *status = nullptr;    // device status word
-  int *counters = nullptr;  // device counters [4]
-  int *deferred = nullptr;  // device list of deferred mask blocks
-  int deferred_cap = 0;
-  float *slots = nullptr;
-  long long slot_floats = 0;
-  int slot_count = 0;
+  std::mutex mu;  // guards the maps and the byte count
   std::map<TableKey, TableSet> tables;
+  std::map<hipStream_t, Workspace> ws;
 };
 
 namespace {
@@ -292,14 +299,35 @@ int get_tables(pdi_ctx *c, const pdi_frame *f, int b, int shared, const pdi_para
   return PDI_OK;
 }
 
-int ensure_workspace(pdi_ctx *c, int n_items, int b, int nslots) {
-  if (n_items > c->deferred_cap) {
-    dev_free(c, c->deferred, sizeof(int) * (size_t)c->deferred_cap);
-    c->deferred = nullptr;
-    c->deferred_cap = 0;
-    int rc = dev_alloc(c, (void **)&c->deferred, sizeof(int) * (size_t)n_items, "deferred list");
+int get_workspace(pdi_ctx *c, hipStream_t stream, Workspace **out) {
+  auto it = c->ws.find(stream);
+  if (it != c->ws.end()) {
+    *out = &it->second;
+    return PDI_OK;
+  }
+  Workspace w;
+  int rc = dev_alloc(c, (void **)&w.status, sizeof(int) * 4, "status");
+  if (!rc) rc = dev_alloc(c, (void **)&w.counters, sizeof(int) * 8, "counters");
+  if (rc) {
+    dev_free(c, w.status, sizeof(int) * 4);
+    return rc;
+  }
+  hipError_t e = hipMemset(w.status, 0, sizeof(int) * 4);
+  if (e == hipSuccess) e = hipMemset(w.counters, 0, sizeof(int) * 8);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(c, e, "workspace init");
+  *out = &c->ws.emplace(stream, w).first->second;
+  return PDI_OK;
+}
+
+int ensure_workspace(pdi_ctx *c, Workspace *W, int n_items, int b, int nslots) {
+  if (n_items > W->deferred_cap) {
+    dev_free(c, W->deferred, sizeof(int) * (size_t)W->deferred_cap);
+    W->deferred = nullptr;
+    W->deferred_cap = 0;
+    int rc = dev_alloc(c, (void **)&W->deferred, sizeof(int) * (size_t)n_items, "deferred list");
     if (rc) return rc;
-    c->deferred_cap = n_items;
+    W->deferred_cap = n_items;
   }
   // Global-memory bordered systems: (K+1) rows of K+1+2 floats with
   // K <= b*b - 1 (K = b*b is decoded by copying the values), one slot per
@@ -307,17 +335,17 @@ int ensure_workspace(pdi_ctx *c, int n_items, int b, int nslots) {
   const int nmax = b * b;
   const long long need = (long long)nmax * (nmax + 2);
   if (nslots < pdi::kDeferredGrid) nslots = pdi::kDeferredGrid;
-  if (need > c->slot_floats || nslots > c->slot_count) {
-    const long long nf = need > c->slot_floats ? need : c->slot_floats;
-    const int ns = nslots > c->slot_count ? nslots : c->slot_count;
-    dev_free(c, c->slots, sizeof(float) * (size_t)c->slot_floats * (size_t)c->slot_count);
-    c->slots = nullptr;
-    c->slot_floats = 0;
-    c->slot_count = 0;
-    int rc = dev_alloc(c, (void **)&c->slots, sizeof(float) * (size_t)nf * (size_t)ns, "system slots");
+  if (need > W->slot_floats || nslots > W->slot_count) {
+    const long long nf = need > W->slot_floats ? need : W->slot_floats;
+    const int ns = nslots > W->slot_count ? nslots : W->slot_count;
+    dev_free(c, W->slots, sizeof(float) * (size_t)W->slot_floats * (size_t)W->slot_count);
+    W->slots = nullptr;
+    W->slot_floats = 0;
+    W->slot_count = 0;
+    int rc = dev_alloc(c, (void **)&W->slots, sizeof(float) * (size_t)nf * (size_t)ns, "system slots");
     if (rc) return rc;
-    c->slot_floats = nf;
-    c->slot_count = ns;
+    W->slot_floats = nf;
+    W->slot_count = ns;
   }
   return PDI_OK;
 }
@@ -348,15 +376,6 @@ int pdi_create(pdi_ctx **out, int device, size_t hbm_budget_bytes) {
   c->budget = hbm_budget_bytes;
   hipError_t e = hipSetDevice(device);
   if (e != hipSuccess) { delete c; return PDI_EHIP; }
-  int rc = dev_alloc(c, (void **)&c->status, sizeof(int) * 4, "status");
-  if (!rc) rc = dev_alloc(c, (void **)&c->counters, sizeof(int) * 8, "counters");
-  if (rc) { pdi_destroy(c); return rc; }
-  if (hipMemset(c->status, 0, sizeof(int) * 4) != hipSuccess ||
-      hipMemset(c->counters, 0, sizeof(int) * 8) != hipSuccess ||
-      hipDeviceSynchronize() != hipSuccess) {
-    pdi_destroy(c);
-    return PDI_EHIP;
-  }
   *out = c;
   return PDI_OK;
 }
@@ -366,13 +385,15 @@ void pdi_destroy(pdi_ctx *c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   for (auto &kv : c->tables) {
-    dev_free(c, kv.second.tab32, sizeof(float) * (size_t)kv.second.tab32_floats);
+    (void)hipFree(kv.second.tab32);
     (void)hipFree(kv.second.tab64);
   }
-  (void)hipFree(c->status);
-  (void)hipFree(c->counters);
-  (void)hipFree(c->deferred);
-  (void)hipFree(c->slots);
+  for (auto &kv : c->ws) {
+    (void)hipFree(kv.second.status);
+    (void)hipFree(kv.second.counters);
+    (void)hipFree(kv.second.deferred);
+    (void)hipFree(kv.second.slots);
+  }
   delete c;
 }
 
@@ -416,6 +437,11 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
     return set_err(c, PDI_EINVAL, "null block_ptr, pos or values");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  std::lock_guard<std::mutex> lock(c->mu);
+  hipStream_t s = (hipStream_t)stream;
+  Workspace *W = nullptr;
+  int rcw = get_workspace(c, s, &W);
+  if (rcw) return rcw;
 
   TableSet *ts = nullptr;
   int rc = get_tables(c, frame, block_size, shared, P, &ts);
@@ -482,7 +508,7 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
     }
   }
   const bool fast = (P.path == PDI_PATH_AUTO && block_size <= 16);
-  rc = ensure_workspace(c, (int)nitems, block_size, fast ? F.fast_wgs : 0);
+  rc = ensure_workspace(c, W, (int)nitems, block_size, fast ? F.fast_wgs : 0);
   if (rc) return rc;
   F.tab32_floats = ts->tab32_floats;
   F.block_ptr = mask->block_ptr;
@@ -491,13 +517,12 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
   F.out = out;
   F.tab32 = ts->tab32;
   F.tab64 = ts->tab64;
-  F.deferred = c->deferred;
-  F.counters = c->counters;
-  F.status = c->status;
-  F.slots = c->slots;
-  F.slot_floats = c->slot_floats;
+  F.deferred = W->deferred;
+  F.counters = W->counters;
+  F.status = W->status;
+  F.slots = W->slots;
+  F.slot_floats = W->slot_floats;
 
-  hipStream_t s = (hipStream_t)stream;
   if (fast) {
     e = pdi::launch_fast(F, s);  // one launch: the workgroups also decode their leftover blocks
   } else {
@@ -513,12 +538,16 @@ int pdi_sync(pdi_ctx *c, void *stream) {
   hipError_t e = hipSetDevice(c->device);
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  std::lock_guard<std::mutex> lock(c->mu);
+  auto it = c->ws.find((hipStream_t)stream);
+  if (it == c->ws.end()) return PDI_OK;  // nothing decoded on this stream yet
+  Workspace &W = it->second;
   int st = 0;
-  e = hipMemcpy(&st, c->status, sizeof(int), hipMemcpyDeviceToHost);
+  e = hipMemcpy(&st, W.status, sizeof(int), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(c, e, "status read");
   if (st) {
-    e = hipMemset(c->status, 0, sizeof(int));
-    if (e == hipSuccess) e = hipMemset(c->counters, 0, sizeof(int) * 8);
+    e = hipMemset(W.status, 0, sizeof(int));
+    if (e == hipSuccess) e = hipMemset(W.counters, 0, sizeof(int) * 8);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(c, e, "status reset");
     if (st & pdi::kStatusMask) return set_err(c, PDI_EMASK, "device validation: bad mask positions");

@@ -95,8 +95,6 @@ __device__ __forceinline__ void push_deferred(const FrameDev &f, int m, int K, i
 
 constexpr int kGenThreads = 256;
 constexpr int kGeneralGrid = 128;  // persistent workgroups over the deferred lists
-constexpr int kGenMaxK = 1024;  // b = 32: at most 32*32 points
-constexpr int kTabMax = 33 * 33;
 
 // Workgroup scratch of the general path for blocks of at most B x B pixels.
 template <int B>
