@@ -35,6 +35,11 @@ sys.path.insert(0, ROOT)
 METRIC = "1080p residual frames/s at ≤0.5 grey-level error; p99 frame latency"
 HBM_PEAK_GBS = 8000.0
 EVALS = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16x2": 3}
+# HBM bytes per launch of the decode kernel from rocprofv3 FETCH_SIZE +
+# WRITE_SIZE counters, scaled by the same counters read on a copy kernel of
+# known size (profiles/k_fast_fhd420_b16_hbm_counters.txt); only for the
+# kernel build the counters were taken on.
+TRAFFIC = {1: 15088948}
 
 
 def algorithmic_bytes(fr) -> int:
@@ -63,18 +68,52 @@ def host_cores():
     return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(fr, min_seconds=5.0, min_frames=3, what="the benchmark frame"):
+    """The FP64 oracle timed on the host cores (all threads, then one)."""
     import oracle
     cores = host_cores()
     oracle.decode(fr, nthreads=cores)  # load + warm
-    n, t0 = 0, time.perf_counter()
-    ref = None
-    while n < min_frames or time.perf_counter() - t0 < min_seconds:
-        ref = oracle.decode_flat(fr, nthreads=cores)
-        n += 1
-    dt = time.perf_counter() - t0
+
+    def run(nt, secs, nmin):
+        n, t0, r = 0, time.perf_counter(), None
+        while n < nmin or time.perf_counter() - t0 < secs:
+            r = oracle.decode_flat(fr, nthreads=nt)
+            n += 1
+        return r, n, time.perf_counter() - t0
+
+    ref, n, dt = run(cores, min_seconds, min_frames)
+    _, n1, dt1 = run(1, min_seconds / 2, 1)
     return ref, dict(value=n / dt, unit="frames/s", cores=cores, kind="oracle",
-                     sample=f"{n} decodes of {what} (FP64 oracle, OpenMP over blocks), {dt:.1f} s")
+                     sample=f"{n} decodes of {what} (FP64 oracle, OpenMP over blocks), {dt:.1f} s",
+                     one_thread=n1 / dt1, cpu_model=cpu_model(), nproc=os.cpu_count())
+
+
+def copy_bandwidth(torch, mib=1024, reps=20, stream=None):
+    """Device-to-device copy of `mib` MiB (torch's copy kernel): GB/s counted
+    as bytes read + bytes written."""
+    n = (mib << 20) // 4
+    x = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    stream = stream or torch.cuda.current_stream()
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            y.copy_(x)
+        tm = StreamTimer(torch, stream)
+        tm.start()
+        for _ in range(reps):
+            y.copy_(x)
+        secs = tm.stop()
+    return 2.0 * (mib << 20) * reps / secs / 1e9
 
 
 def error_vs(got, ref):
@@ -187,6 +226,8 @@ def bench_frame(args, torch, binding, synth):
     ab = algorithmic_bytes(fr)
     t_dec = secs / args.steps
     achieved = ab / t_dec / 1e9
+    copy_gbs = copy_bandwidth(torch, stream=stream)
+    log(f"copy kernel: {copy_gbs:.0f} GB/s")
     rec = dict(metric=METRIC, value=fps, unit="frames/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=1e3 * t_dec, higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="f32" if args.eval == "fp32" else f"f32 solve, {args.eval} eval", data="synthetic",
@@ -198,9 +239,10 @@ def bench_frame(args, torch, binding, synth):
                            "mean": float(lat.mean())},
                error_vs_oracle=err, plain_path=plain, overlapped=multi,
                roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC.get(args.config),
                          "kernel": "k_fast" if cfg["block_size"] <= 16 else "k_plain_all + k_general_deferred",
-                         "algorithmic_bytes_per_launch": ab},
+                         "algorithmic_bytes_per_launch": ab, "measured_copy_GBs": copy_gbs,
+                         "frac_of_measured_copy": achieved / copy_gbs},
                cpu_baseline=cpu, wall_s=wall)
     dec.close()
     return rec
@@ -382,6 +424,8 @@ def main():
     ap.add_argument("--warm-s", type=float, default=1.0, help="serving: unmeasured seconds first")
     ap.add_argument("--serve-frames", type=int, default=4, help="serving: distinct frames per client stream")
     ap.add_argument("--burst-rounds", type=int, default=8)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a device copy of this many MiB 10 times (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-path comparison")
     args = ap.parse_args()
@@ -398,6 +442,10 @@ def main():
     # frames are generated before torch touches the GPU (worker processes)
     import torch
     from paper_2008_10273_amd import binding
+    if args.copy_mib:
+        gbs = copy_bandwidth(torch, args.copy_mib, reps=10)
+        print(json.dumps({"copy_mib": args.copy_mib, "reps": 10, "GBs": gbs}), flush=True)
+        return
     if args.config <= 2:
         rec = bench_frame(args, torch, binding, synth)
     elif args.config == 3:
