@@ -14,13 +14,19 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdinp.so")
 SOURCES = [os.path.join(CSRC, n) for n in
-           ("pdinp_host.cpp", "pdinp_graph.cpp", "pdinp_server.cpp", "pdinp_kernels.hip")]
+           ("pdinp_host.cpp", "pdinp_graph.cpp", "pdinp_server.cpp", "pdinp_kernels.hip",
+            "pdinp_wide.hip")]
 ARCH = os.environ.get("PDI_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 VALU forms are kept out of the generated code.
 HIPCC_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", f"--offload-arch={ARCH}",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-I", os.path.join(ROOT, "include")]
+
+
+# Per-source extra flags: the wave-per-block kernel keeps its rows in
+# registers, so its loops over columns must unroll completely.
+EXTRA_FLAGS = {"pdinp_wide.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
 
 
 def hipcc() -> str:
@@ -36,7 +42,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(build_dir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(build_dir, os.path.basename(src) + ".o")
-        cmd = [hipcc()] + HIPCC_FLAGS + ["-c", src, "-o", obj]
+        cmd = [hipcc()] + HIPCC_FLAGS + EXTRA_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
         if src.endswith(".cpp"):
             cmd = [hipcc()] + [f for f in HIPCC_FLAGS if not f.startswith("--offload-arch")] + ["-c", src, "-o", obj]
         if verbose:

@@ -1,0 +1,31 @@
+// Device helpers shared by the gfx950 kernel sources (HIP only).
+#pragma once
+#include "pdinp_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace pdi {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Hand a block to the general path: blocks whose bordered system fits in LDS
+// are listed from the front of the deferred list, larger ones from the back.
+__device__ __forceinline__ void push_deferred(const FrameDev &f, int m, int K, int w, int h) {
+  if (K > kLdsKMax && K < w * h) {
+    int idx = atomicAdd(&f.counters[1], 1);
+    f.deferred[f.n_items - 1 - idx] = m;
+  } else {
+    int idx = atomicAdd(&f.counters[0], 1);
+    f.deferred[idx] = m;
+  }
+}
+
+// Make this lane's LDS writes visible to the other lanes of its wave (no
+// instruction beyond the wait the writes need).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace pdi

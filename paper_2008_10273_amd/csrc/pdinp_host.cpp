@@ -197,13 +197,13 @@ void build_shape_tables(int w, int h, int op, double s, std::vector<double> &lam
 }
 
 // Orthonormal DCT-II matrix of size n, rows = frequency, cols = position,
-// zero padded to 16 x 16.
-void dct16(int n, float *out) {
-  for (int p = 0; p < 16; ++p)
-    for (int x = 0; x < 16; ++x) {
+// zero padded to ld x ld.
+void dct_padded(int n, int ld, float *out) {
+  for (int p = 0; p < ld; ++p)
+    for (int x = 0; x < ld; ++x) {
       double v = 0.0;
       if (p < n && x < n) v = std::sqrt((p == 0 ? 1.0 : 2.0) / n) * std::cos(kPi * p * (x + 0.5) / n);
-      out[p * 16 + x] = (float)v;
+      out[p * ld + x] = (float)v;
     }
 }
 
@@ -269,13 +269,23 @@ int get_tables(pdi_ctx *c, const pdi_frame *f, int b, int shared, const pdi_para
             J[(y * h + y2) * W1 + a] = (float)(hc[(size_t)dy * W1 + a] + hc[(size_t)sy * W1 + a]);
         }
       float *D = J + S.jt_floats;
-      dct16(w, D);
-      dct16(h, D + 256);
+      dct_padded(w, 16, D);
+      dct_padded(h, 16, D + 256);
       for (int q = 0; q < h; ++q)
         for (int p = 0; p < w; ++p) D[512 + q * 16 + p] = (float)lam[(size_t)q * w + p];
     } else {
-      S.fast = -1;
-      S.jt_floats = 0;
+      // Compact table, then Dw, Dh and lam zero-padded to 32 x 32.
+      const int W1 = w + 1;
+      S.fast = (int)t32.size();
+      S.jt_floats = (W1 * (h + 1) + 3) & ~3;
+      t32.resize(t32.size() + S.jt_floats + 3 * 1024, 0.f);
+      float *Hq = &t32[S.fast];
+      for (size_t i = 0; i < hc.size(); ++i) Hq[i] = (float)hc[i];
+      float *D = Hq + S.jt_floats;
+      dct_padded(w, 32, D);
+      dct_padded(h, 32, D + 1024);
+      for (int q = 0; q < h; ++q)
+        for (int p = 0; p < w; ++p) D[2048 + q * 32 + p] = (float)lam[(size_t)q * w + p];
     }
   }
   ts.tab32_floats = (int)t32.size();
@@ -479,7 +489,12 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
   }
   F.nshapes = ts->nshapes;
   for (int k = 0; k < ts->nshapes; ++k) F.s[k] = ts->s[k];
-  // Shape-homogeneous runs of blocks for the wave-level path.
+  // Shape-homogeneous runs of blocks for the batched paths: k_fast (b <= 16,
+  // 16 blocks per workgroup) or k_wide (b = 32, 4 blocks per workgroup).
+  const bool fast = (P.path == PDI_PATH_AUTO && block_size <= 16);
+  const bool wide = (P.path == PDI_PATH_AUTO && block_size == 32);
+  const int ipw = fast ? pdi::kFastItemsPerWG : pdi::kWideItems;
+  const int dct_floats = fast ? 3 * 256 : 3 * 1024;
   F.nsegs = 0;
   F.fast_wgs = 0;
   F.fast_lds = 0;
@@ -502,12 +517,11 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
       S.by0 = segs[e][2];
       S.count = nx * ny;
       S.first_wg = F.fast_wgs;
-      F.fast_wgs += (S.count + 15) / 16;
+      F.fast_wgs += (S.count + ipw - 1) / ipw;
       const pdi::ShapeDev &SH = ts->s[S.shape];
-      if (SH.jt_floats + 768 > F.fast_lds) F.fast_lds = SH.jt_floats + 768;
+      if (SH.jt_floats + dct_floats > F.fast_lds) F.fast_lds = SH.jt_floats + dct_floats;
     }
   }
-  const bool fast = (P.path == PDI_PATH_AUTO && block_size <= 16);
   rc = ensure_workspace(c, W, (int)nitems, block_size, fast ? F.fast_wgs : 0);
   if (rc) return rc;
   F.tab32_floats = ts->tab32_floats;
@@ -525,6 +539,9 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
 
   if (fast) {
     e = pdi::launch_fast(F, s);  // one launch: the workgroups also decode their leftover blocks
+  } else if (wide) {
+    e = pdi::launch_wide(F, s);  // leftover blocks go to the deferred list
+    if (e == hipSuccess) e = pdi::launch_general_deferred(F, s);
   } else {
     e = pdi::launch_plain_all(F, s);
     if (e == hipSuccess) e = pdi::launch_general_deferred(F, s);

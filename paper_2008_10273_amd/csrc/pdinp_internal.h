@@ -12,6 +12,9 @@ constexpr int kFastKMax = 31;   // largest K of the wave-level path (R <= 32 row
 constexpr int kLdsKMax = 96;    // largest K whose bordered system fits in LDS (general path)
 constexpr int kDeferredGrid = 64;  // persistent workgroups of the general path
 constexpr int kWaveItems = 4;      // blocks per wave in the wave-level path
+constexpr int kFastItemsPerWG = 16;  // blocks per workgroup of the wave-level path (b <= 16)
+constexpr int kWideItems = 4;        // blocks per workgroup of the wave-per-block path (b = 32)
+constexpr int kWideKMax = 103;       // largest K of the wave-per-block path
 // The FP32 table buffer is padded by this many floats so that the wave-level
 // path may read whole 16-byte vectors per thread past the last table.
 constexpr int kTabPadFloats = 6 * 256 * 4;
@@ -26,11 +29,13 @@ struct ShapeDev {
   int w, h;
   int hc32;       // FP32 compact Green table, (w+1)*(h+1), quarter-scaled (floats)
   int hc64;       // same in FP64 (doubles)
-  int fast;       // fast-path block (b <= 16), -1 otherwise: the row-pair table
+  int fast;       // block of the batched paths: for b <= 16 the row-pair table
                   // J[(y*h + y')*(w+1) + alpha] (jt_floats floats), then the
                   // zero-padded 16x16 DCT-II matrices Dw[p][x], Dh[q][y] and the
-                  // eigenvalues lam[q][p] (256 floats each)
-  int jt_floats;  // size of J rounded up to a multiple of 4
+                  // eigenvalues lam[q][p] (256 floats each); for b = 32 the
+                  // compact table (jt_floats floats) and the same three
+                  // matrices zero-padded to 32x32 (1024 floats each)
+  int jt_floats;  // size of the first table rounded up to a multiple of 4
 };
 
 // A run of blocks of one shape: block columns bx0 .. bx0+nx-1, rows by0 ..,
@@ -65,8 +70,8 @@ struct FrameDev {
   ShapeDev s[kMaxShapes];
   SegDev seg[kMaxSegs];
   int nsegs;
-  int fast_wgs;      // workgroups of the wave-level path
-  int fast_lds;      // its dynamic LDS (floats): largest J + 768
+  int fast_wgs;      // workgroups of the batched path (k_fast or k_wide)
+  int fast_lds;      // its dynamic LDS (floats): largest table block
   int tab32_floats;  // size of the FP32 table buffer (floats)
   // buffers
   const int32_t *block_ptr;
@@ -84,6 +89,7 @@ struct FrameDev {
 
 // Launchers (pdinp_kernels.hip).  All asynchronous on `stream`.
 hipError_t launch_fast(const FrameDev &f, hipStream_t stream);
+hipError_t launch_wide(const FrameDev &f, hipStream_t stream);
 hipError_t launch_plain_all(const FrameDev &f, hipStream_t stream);
 hipError_t launch_general_deferred(const FrameDev &f, hipStream_t stream);
 

@@ -17,13 +17,11 @@
 //    global slot for large K), Gauss-Jordan with barriers, direct
 //    evaluation through the Green table.  It is the plain per-block path,
 //    and the fallback for blocks the fast path does not take.
-#include "pdinp_internal.h"
+#include "pdinp_device.h"
 
 #include <hip/hip_runtime.h>
 
 namespace pdi {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ items
 
@@ -81,15 +79,6 @@ __device__ __forceinline__ T green_tab(const T *tab, int w, int h, int xa, int y
   return (tab[dy * W1 + dx] + tab[dy * W1 + sx]) + (tab[sy * W1 + dx] + tab[sy * W1 + sx]);
 }
 
-__device__ __forceinline__ void push_deferred(const FrameDev &f, int m, int K, int w, int h) {
-  if (K > kLdsKMax && K < w * h) {
-    int idx = atomicAdd(&f.counters[1], 1);
-    f.deferred[f.n_items - 1 - idx] = m;
-  } else {
-    int idx = atomicAdd(&f.counters[0], 1);
-    f.deferred[idx] = m;
-  }
-}
 
 // ------------------------------------------------------- general per-block
 

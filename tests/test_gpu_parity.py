@@ -108,6 +108,16 @@ def test_empty_full_and_extreme_blocks(dec, path):
     check(dec, fr, path=path)
 
 
+@pytest.mark.parametrize("path", [0, 1])
+def test_b32_point_counts(dec, path):
+    """32x32 blocks with K around the wave path's limits: one row per lane
+    up to K = 63, two from K = 64, the last K = 103, larger K and the
+    degenerate counts on the general path; plus truncated edge blocks."""
+    ks = [63, 64, 65, 102, 103, 104, 1, 2, 0, 1024, 1023, 31, 32, 33, 200, 96, 97]
+    fr = _custom_frame(32 * 6 + 7, 32 * 3 + 20, 32, lambda k, n: min(n, ks[k % len(ks)]), seed=8)
+    check(dec, fr, path=path)
+
+
 @pytest.mark.parametrize("refine", [0, 1, 2])
 def test_refine_modes(dec, refine):
     fr = synth.random_frame(96, 64, synth.YUV420, 16, (0.01, 0.12), seed=11)
@@ -208,11 +218,12 @@ EVAL_TOL = {1: 0.25, 2: 1.5, 3: FP32_TOL}
 
 
 @pytest.mark.parametrize("ev", [1, 2, 3])
-@pytest.mark.parametrize("case", ["cfg0", "ragged420", "b8"])
+@pytest.mark.parametrize("case", ["cfg0", "ragged420", "b8", "b32"])
 def test_eval_dtypes(dec, ev, case):
     fr = {"cfg0": lambda: synth.config_frame(0),
           "ragged420": lambda: synth.random_frame(70, 37, synth.YUV420, 16, (0.01, 0.12), seed=2606),
-          "b8": lambda: synth.random_frame(100, 67, synth.YUV420, 8, (0.02, 0.3), seed=3)}[case]()
+          "b8": lambda: synth.random_frame(100, 67, synth.YUV420, 8, (0.02, 0.3), seed=3),
+          "b32": lambda: synth.random_frame(150, 90, synth.YUV420, 32, (0.02, 0.1), seed=32)}[case]()
     got, _ = gpu_decode(dec, fr, eval_dtype=ev)
     ref = oracle.decode_flat(fr)
     mx, agree = compare(got, ref)
@@ -233,3 +244,16 @@ def test_eval_dtypes_config1(dec):
         assert mx <= EVAL_TOL[ev] and mx <= 0.5
         if ev == 3:
             assert agree >= 0.999
+
+
+def test_eval_dtypes_config2(dec):
+    """FullHD frame with 32x32 blocks: the error of every evaluation dtype."""
+    fr = synth.config_frame(2, keep_fields=False)
+    ref = oracle.decode_flat(fr)
+    for ev in (0, 1, 2, 3):
+        got, _ = gpu_decode(dec, fr, eval_dtype=ev)
+        mx, agree = compare(got, ref)
+        print(f"  eval {ev}: max|err|={mx:.3e} round-agree={agree * 100:.4f}%", flush=True)
+        assert mx <= (FP32_TOL if ev == 0 else EVAL_TOL[ev])
+        if ev in (0, 3):
+            assert mx <= 0.5 and agree >= 0.999
