@@ -192,7 +192,8 @@ def bench_frame(args, torch, binding, synth):
     d = dec.upload(fr)
     stream = torch.cuda.Stream()
     params = binding.default_params(eval_dtype=EVALS[args.eval])
-    log(f"config {args.config} ({cfg['name']}), eval {args.eval}, {args.steps} steps")
+    tune = dec.autotune(d, params, stream=stream)  # launch choice for this geometry (0: none to make)
+    log(f"config {args.config} ({cfg['name']}), eval {args.eval}, {args.steps} steps, autotune choice {tune}")
     secs, wall = time_decodes(torch, dec, d, params, stream, args.steps, args.warmup)
     assert dec.sync(stream) == 0, binding.pdi_last_error(dec.ctx)
     fps = args.steps / secs
@@ -234,7 +235,8 @@ def bench_frame(args, torch, binding, synth):
                config={"workload": cfg["name"], "width": cfg["width"], "height": cfg["height"],
                        "format": "4:2:0" if cfg["fmt"] == 1 else "gray", "block_size": cfg["block_size"],
                        "density": list(cfg["density"]), "frames_per_step": 1,
-                       "mask_blocks": fr.n_mask_blocks, "mask_points": int(fr.pos.size)},
+                       "mask_blocks": fr.n_mask_blocks, "mask_points": int(fr.pos.size),
+                       "blocks_per_workgroup": tune or None},
                latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "mean": float(lat.mean())},
                error_vs_oracle=err, plain_path=plain, overlapped=multi,

@@ -132,6 +132,19 @@ int pdi_sync(pdi_ctx *ctx, void *stream);
 /* Text of the last error of this context (never NULL). */
 const char *pdi_last_error(pdi_ctx *ctx);
 
+/* Measure the launch choices of the batched path for this frame geometry,
+ * operator and evaluation dtype on the given inputs (device pointers, as for
+ * decode_residual; `out` is overwritten) and keep the fastest in the context
+ * for later decode_residual calls with the same geometry and params.  The
+ * choices only change how blocks are grouped into workgroups, never a
+ * block's arithmetic, so results are bitwise the same with any choice.
+ * Synchronous (not capturable).  *choice (may be NULL) receives the blocks
+ * per workgroup chosen, or 0 when the path has no choices (block sizes 8 and
+ * 16, PDI_PATH_PLAIN), in which case the call is one decode + pdi_sync.
+ * Returns the codes of decode_residual / pdi_sync. */
+int pdi_autotune(pdi_ctx *ctx, const pdi_frame *frame, const pdi_mask *mask, const float *values,
+                 int block_size, const pdi_params *params, float *out, void *stream, int *choice);
+
 /* Host helper: number of mask blocks, value count and output size of a
  * frame geometry (for sizing buffers).  Pointers may be NULL. */
 int pdi_frame_info(const pdi_frame *frame, int block_size, int chroma_shared,

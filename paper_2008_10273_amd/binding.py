@@ -24,7 +24,7 @@ ERROR_NAMES = {0: "PDI_OK", -1: "PDI_EINVAL", -2: "PDI_EMASK", -3: "PDI_ENOMEM",
                -5: "PDI_EBUSY", -6: "PDI_EVALUE", -7: "PDI_ESOLVE"}
 
 EXPORTS = ["pdi_default_params", "pdi_create", "pdi_destroy", "decode_residual", "pdi_sync",
-           "pdi_last_error", "pdi_frame_info", "pdi_pack_dense", "pdi_validate_host",
+           "pdi_last_error", "pdi_frame_info", "pdi_pack_dense", "pdi_validate_host", "pdi_autotune",
            "pdi_seq_create", "pdi_seq_launch", "pdi_seq_sync", "pdi_seq_destroy",
            "pdi_server_create", "pdi_submit", "pdi_poll", "pdi_wait", "pdi_server_stats",
            "pdi_server_hold", "pdi_server_destroy"]
@@ -82,6 +82,9 @@ def lib() -> ctypes.CDLL:
         L.pdi_validate_host.argtypes = [ctypes.POINTER(pdi_frame), i32, P, P, ctypes.c_int32,
                                         ctypes.c_int32, P]
         L.pdi_validate_host.restype = i32
+        L.pdi_autotune.argtypes = [P, ctypes.POINTER(pdi_frame), ctypes.POINTER(pdi_mask), P, i32,
+                                   ctypes.POINTER(pdi_params), P, P, ctypes.POINTER(ctypes.c_int)]
+        L.pdi_autotune.restype = i32
         PP = ctypes.POINTER(ctypes.c_void_p)
         L.pdi_seq_create.argtypes = [P, i32, ctypes.POINTER(pdi_frame), ctypes.POINTER(pdi_mask), PP, i32,
                                      ctypes.POINTER(pdi_params), PP, i32, PP]
@@ -242,6 +245,20 @@ class Decoder:
     def sync(self, stream=None) -> int:
         s = stream.cuda_stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
         return pdi_sync(self.ctx, s)
+
+    def autotune(self, d, params: Optional[pdi_params] = None, stream=None) -> int:
+        """pdi_autotune on an uploaded frame; returns the launch choice."""
+        fr = d["frame"]
+        s = stream.cuda_stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
+        f = pdi_frame(fr.width, fr.height, fr.fmt)
+        mk = pdi_mask(d["block_ptr"].data_ptr(), d["pos"].data_ptr(), d["n_mask_blocks"], int(bool(fr.chroma_shared)))
+        ch = ctypes.c_int()
+        rc = lib().pdi_autotune(self.ctx, ctypes.byref(f), ctypes.byref(mk), d["values"].data_ptr(), fr.block_size,
+                                ctypes.byref(params) if params is not None else None, d["out"].data_ptr(), s,
+                                ctypes.byref(ch))
+        if rc != PDI_OK:
+            raise PdiError(rc, pdi_last_error(self.ctx))
+        return ch.value
 
 
 class Sequence:

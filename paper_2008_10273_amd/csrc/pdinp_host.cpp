@@ -32,6 +32,8 @@ struct TableSet {
 };
 
 using TableKey = std::tuple<int, int, int, int, int, int, double>;  // W,H,fmt,b,shared,op,s
+// Launch choice per geometry, operator and evaluation dtype (set by pdi_autotune).
+using TuneKey = std::tuple<int, int, int, int, int, int, double, int>;  // TableKey + eval
 
 }  // namespace
 
@@ -55,6 +57,7 @@ struct pdi_ctx {
   std::mutex mu;  // guards the maps and the byte count
   std::map<TableKey, TableSet> tables;
   std::map<hipStream_t, Workspace> ws;
+  std::map<TuneKey, int> tune;  // blocks per workgroup of the wave-per-block path
 };
 
 namespace {
@@ -493,7 +496,13 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
   // 16 blocks per workgroup) or k_wide (b = 32, 4 blocks per workgroup).
   const bool fast = (P.path == PDI_PATH_AUTO && block_size <= 16);
   const bool wide = (P.path == PDI_PATH_AUTO && block_size == 32);
-  const int ipw = fast ? pdi::kFastItemsPerWG : pdi::kWideItems;
+  int ipw = pdi::kFastItemsPerWG;
+  if (!fast) {
+    auto it = c->tune.find(TuneKey{frame->width, frame->height, frame->format, block_size, shared, P.op, P.s,
+                                   P.eval_dtype});
+    ipw = it != c->tune.end() ? it->second : pdi::kWideItemsDefault;
+  }
+  F.ipw = ipw;
   const int dct_floats = fast ? 3 * 256 : 3 * 1024;
   F.nsegs = 0;
   F.fast_wgs = 0;
@@ -572,6 +581,65 @@ int pdi_sync(pdi_ctx *c, void *stream) {
     return set_err(c, PDI_ESOLVE, "a block system broke down (non-finite solution)");
   }
   return PDI_OK;
+}
+
+int pdi_autotune(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, const float *values,
+                 int block_size, const pdi_params *params, float *out, void *stream, int *choice) {
+  if (!c || !frame || !mask) return PDI_EINVAL;
+  pdi_params P;
+  pdi_default_params(&P);
+  if (params) P = *params;
+  const int shared = (frame->format == PDI_YUV420 && mask->chroma_shared) ? 1 : 0;
+  const TuneKey key{frame->width, frame->height, frame->format, block_size, shared, P.op, P.s, P.eval_dtype};
+  if (choice) *choice = 0;
+  // Only the wave-per-block path (32 x 32 blocks) has launch choices.
+  if (!(P.path == PDI_PATH_AUTO && block_size == 32)) {
+    int rc = decode_residual(c, frame, mask, values, block_size, params, out, stream);
+    return rc ? rc : pdi_sync(c, stream);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(c, e, "autotune events");
+  }
+  const int cands[3] = {1, 2, 4};
+  int best = pdi::kWideItemsDefault, rc = PDI_OK;
+  float best_ms = 3.0e38f;
+  for (int cand : cands) {
+    {
+      std::lock_guard<std::mutex> lock(c->mu);
+      c->tune[key] = cand;
+    }
+    for (int r = 0; r < 2 && rc == PDI_OK; ++r) rc = decode_residual(c, frame, mask, values, block_size, params, out, stream);
+    if (rc == PDI_OK) rc = pdi_sync(c, stream);
+    if (rc != PDI_OK) break;
+    const int reps = 5;
+    e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && rc == PDI_OK; ++r) rc = decode_residual(c, frame, mask, values, block_size, params, out, stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess || rc != PDI_OK) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = cand;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  {
+    std::lock_guard<std::mutex> lock(c->mu);
+    c->tune[key] = best;
+  }
+  if (rc != PDI_OK) return rc;
+  if (e != hipSuccess) return hip_fail(c, e, "autotune timing");
+  if (choice) *choice = best;
+  return pdi_sync(c, stream);
 }
 
 int pdi_validate_host(const pdi_frame *frame, int block_size, const int32_t *block_ptr,

@@ -13,7 +13,7 @@ constexpr int kLdsKMax = 96;    // largest K whose bordered system fits in LDS (
 constexpr int kDeferredGrid = 64;  // persistent workgroups of the general path
 constexpr int kWaveItems = 4;      // blocks per wave in the wave-level path
 constexpr int kFastItemsPerWG = 16;  // blocks per workgroup of the wave-level path (b <= 16)
-constexpr int kWideItems = 4;        // blocks per workgroup of the wave-per-block path (b = 32)
+constexpr int kWideItemsDefault = 2;  // blocks per workgroup of the wave-per-block path (1, 2 or 4)
 constexpr int kWideKMax = 103;       // largest K of the wave-per-block path
 // The FP32 table buffer is padded by this many floats so that the wave-level
 // path may read whole 16-byte vectors per thread past the last table.
@@ -70,6 +70,7 @@ struct FrameDev {
   ShapeDev s[kMaxShapes];
   SegDev seg[kMaxSegs];
   int nsegs;
+  int ipw;           // blocks per workgroup of the batched path
   int fast_wgs;      // workgroups of the batched path (k_fast or k_wide)
   int fast_lds;      // its dynamic LDS (floats): largest table block
   int tab32_floats;  // size of the FP32 table buffer (floats)

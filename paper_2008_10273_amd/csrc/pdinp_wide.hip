@@ -21,14 +21,16 @@ namespace pdi {
 typedef float V32 __attribute__((ext_vector_type(32)));
 typedef float V8 __attribute__((ext_vector_type(8)));
 
-constexpr int kWideThreads = 256;
-constexpr int kWideWaves = kWideItems;          // one block per wave
 constexpr int kWideCap2 = kWideKMax + 1;       // n <= 104: rows i and i + 64 per lane
 constexpr int kWideStagePts = 112;             // evaluation points staged (multiple of 16)
+constexpr int kGroups = (kWideCap2 + 31) / 32; // 32-column groups of a row
+constexpr int kProw = 132;                     // stride of a published row (floats, 16-byte multiple)
 static_assert(kWideCap2 == 104, "row storage below holds 104 columns");
 
-// One row of the bordered system in VGPRs (columns 0 .. 103); indices are
-// compile-time constants after unrolling.
+// The lane's rows of the bordered system in VGPRs: row i (columns 0..103)
+// and row i + 64, of which only columns 64..103 are kept: its columns below
+// 64 lie in the lower triangle, which the elimination never reads.  Indices
+// are compile-time constants after unrolling.
 struct WRow {
   V32 q0, q1, q2;
   V8 t0;
@@ -42,6 +44,23 @@ struct WRow {
     else t0[k - 96] = v;
   }
 };
+struct WRowHi {
+  V32 q2;
+  V8 t0;
+  __device__ __forceinline__ float get(int k) const { return k < 64 ? 0.f : k < 96 ? q2[k - 64] : t0[k - 96]; }
+  __device__ __forceinline__ void set(int k, float v) {
+    if (k >= 64 && k < 96) q2[k - 64] = v;
+    else if (k >= 96) t0[k - 96] = v;
+  }
+};
+struct WRows {
+  WRow r0;
+  WRowHi r1;
+  __device__ __forceinline__ float get(int s, int k) const { return s ? r1.get(k) : r0.get(k); }
+  __device__ __forceinline__ void set(int s, int k, float v) {
+    if (s) r1.set(k, v); else r0.set(k, v);
+  }
+};
 
 struct WidePoint {
   int x, y;
@@ -50,7 +69,7 @@ struct WidePoint {
 
 // Per-wave LDS.
 struct alignas(16) WideStage {
-  float prow[128 + 4];  // published pivot row: columns 0..103, value columns at 128, 129
+  float prow[4 * 132];  // published block rows (stride kProw): columns 0..103, values at 128, 129
   int xy[kWideCap2];    // mask points: x | (y * (w + 1)) << 16
   WidePoint p[kWideStagePts];
   float a[2];
@@ -101,7 +120,7 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
   // row [1 ... 1 | 0] for i = K, zero rows past K.  G is the sum of four
   // quarter-scaled compact-table entries: (|dx|, |dy|) and the reflections
   // x_i + x_k + 1, y_i + y_k + 1 folded into [0, w] and [0, h].
-  WRow R[RS];
+  WRows R;
   const int xcr = 2 * w - 1, ycr = (2 * h - 1) * W1;
 #pragma unroll
   for (int c = 0; c < CAP / 8; ++c) {
@@ -116,7 +135,7 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
 #pragma unroll
         for (int s = 0; s < RS; ++s) {
           g[s][e] = 0.f;
-          if (s == 1 && !two) continue;
+          if (s == 1 && (c < 8 || !two)) continue;  // row set 1 needs columns >= 64 only
           const int dyw = (int)__usad((unsigned)ywr[s], (unsigned)ykw, 0u);
           const int syw = min(ywr[s] + ykw + W1, ycr - ywr[s] - ykw);
           const int dx = (int)__usad((unsigned)xr[s], (unsigned)xk, 0u);
@@ -132,81 +151,149 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
           const int k = 8 * c + e;
           const float inner = (i < K) ? g[s][e] : (i == K ? 1.f : 0.f);  // columns k < K
           const float outer = (k == K && i < K) ? 1.f : 0.f;              // columns k >= K
-          R[s].set(k, k < K ? inner : outer);
+          R.set(s, k, k < K ? inner : outer);
         }
       }
     }
   }
 
-  // Forward elimination.  At step j the owner of row j publishes its columns
-  // from the pivot's 8-column chunk on, and the value columns.
+  // Forward elimination in blocks of 4 pivots (rows j .. j+3; fewer at the
+  // end).  The 4 owner lanes publish their rows from the block's 32-column
+  // group on, with the value columns.  Every lane factors the 4 x 4 diagonal
+  // block A11 = L D L^T (the same arithmetic in every lane) and, with p_i =
+  // the block rows' column i (= row i's columns j..j+3, by symmetry), solves
+  // A11 c_i = p_i; a row inside the block uses only the pivots before it.
+  // Then row i -= sum_t c_i[t] * (block row t): a rank-4 update that leaves
+  // the Schur complement below the block and the U rows of the block.
   float d[RS];
 #pragma unroll
   for (int s = 0; s < RS; ++s) d[s] = 1.f;
   float dmin = 3.0e38f, dmax = 0.f;
-  const f4 *prow4 = reinterpret_cast<const f4 *>(st.prow);
 #pragma unroll
   for (int JS = 0; JS < RS; ++JS) {
     const int jend = min(n, 64 * JS + 64);
-    for (int j = 64 * JS; j < jend; ++j) {
-      const int jl = j & 63, jc = j >> 3;
-      if (lane == jl) {
+    for (int j = 64 * JS; j < jend; j += 4) {
+      const int bk = min(4, n - j), jl = j & 63, jg = j >> 5;
+      const int tw = lane - jl;  // this lane's row position in the block
+      if (tw >= 0 && tw < 4) {   // rows past n are zero rows: they publish zeros
+        float *dst = st.prow + tw * kProw;
 #pragma unroll
-        for (int c = 0; c < CAP / 8; ++c) {
-          if (c >= jc && 8 * c < n) {
-            f4 a, b;
+        for (int g = 0; g < kGroups; ++g) {
+          if (g >= jg && 32 * g < n) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              a[e] = R[JS].get(8 * c + e);
-              b[e] = R[JS].get(8 * c + 4 + e);
+            for (int c = 4 * g; c < min(4 * g + 4, CAP / 8); ++c) {
+              f4 a, b;
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                a[e] = R.get(JS, 8 * c + e);
+                b[e] = R.get(JS, 8 * c + 4 + e);
+              }
+              reinterpret_cast<f4 *>(dst)[2 * c] = a;
+              reinterpret_cast<f4 *>(dst)[2 * c + 1] = b;
             }
-            reinterpret_cast<f4 *>(st.prow)[2 * c] = a;
-            reinterpret_cast<f4 *>(st.prow)[2 * c + 1] = b;
           }
         }
-        st.prow[128] = T[JS][0];
-        st.prow[129] = T[JS][1];
+        dst[128] = T[JS][0];
+        dst[129] = T[JS][1];
       }
       wave_sync();
-      const float piv = st.prow[j];
-      const float rp = __builtin_amdgcn_rcpf(piv);
-      if (j < K) {
-        dmin = fminf(dmin, fabsf(piv));
-        dmax = fmaxf(dmax, fabsf(piv));
-      }
-      float fs[RS];
+      // A11 (identity rows past the block end), then A11 = L D L^T.
+      float a[4][4];
 #pragma unroll
-      for (int s = 0; s < RS; ++s) {
-        const int i = lane + 64 * s;
-        fs[s] = 0.f;
-        if (s >= JS) {
-          const float mij = st.prow[min(i, 127)];
-          fs[s] = (i > j && i < n) ? mij * rp : 0.f;
-          d[s] = (i == j) ? piv : d[s];
+      for (int t = 0; t < 4; ++t) {
+        const f4 r = *reinterpret_cast<const f4 *>(st.prow + t * kProw + j);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[t][u] = (t < bk) ? r[u] : (t == u ? 1.f : 0.f);
+      }
+      float D[4], rD[4], L[4][4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        float s_ = a[t][t];
+#pragma unroll
+        for (int u = 0; u < t; ++u) s_ -= L[t][u] * L[t][u] * D[u];
+        D[t] = s_;
+        rD[t] = __builtin_amdgcn_rcpf(s_);
+#pragma unroll
+        for (int r = t + 1; r < 4; ++r) {
+          float v = a[r][t];
+#pragma unroll
+          for (int u = 0; u < t; ++u) v -= L[r][u] * L[t][u] * D[u];
+          L[r][t] = v * rD[t];
         }
       }
 #pragma unroll
-      for (int c = 0; c < CAP / 8; ++c) {
-        if (c >= jc && 8 * c < n) {
-          const f4 pa = prow4[2 * c], pb = prow4[2 * c + 1];
+      for (int t = 0; t < 4; ++t)
+        if (t < bk && j + t < K) {
+          dmin = fminf(dmin, fabsf(D[t]));
+          dmax = fmaxf(dmax, fabsf(D[t]));
+        }
+      // Coefficients of the lane's rows.
+      float cf[RS][4];
 #pragma unroll
-          for (int s = JS; s < RS; ++s) {
-            if (s == 1 && JS == 0 && !two) continue;
+      for (int s = 0; s < RS; ++s) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              const int k = 8 * c + e;
-              R[s].set(k, fmaf(-fs[s], e < 4 ? pa[e] : pb[e - 4], R[s].get(k)));
+        for (int t = 0; t < 4; ++t) cf[s][t] = 0.f;
+        if (s < JS) continue;
+        const int i = lane + 64 * s;
+        const int m = (i < j || i >= n) ? 0 : min(i - j, bk);
+        float z[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          float v = st.prow[t * kProw + min(i, 127)];
+#pragma unroll
+          for (int u = 0; u < t; ++u) v -= L[t][u] * z[u];
+          z[t] = v;
+        }
+#pragma unroll
+        for (int t = 3; t >= 0; --t) {
+          float v = (t < m) ? z[t] * rD[t] : 0.f;
+#pragma unroll
+          for (int u = t + 1; u < 4; ++u) v -= L[u][t] * cf[s][u];
+          cf[s][t] = v;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) d[s] = (i == j + t && t < bk) ? D[t] : d[s];
+      }
+      // Rank-4 update, 8 columns (4 rows x 2 vectors per row) per load batch.
+      // Columns left of the block inside its first group belong to the lower
+      // triangle, which no later step reads; row set 1 (rows 64..) never
+      // needs its columns below 64.
+#pragma unroll
+      for (int g = 0; g < kGroups; ++g) {
+        if (g >= jg && 32 * g < n) {
+#pragma unroll
+          for (int c = 4 * g; c < min(4 * g + 4, CAP / 8); ++c) {
+            f4 pv[4][2];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              pv[t][0] = *reinterpret_cast<const f4 *>(st.prow + t * kProw + 8 * c);
+              pv[t][1] = *reinterpret_cast<const f4 *>(st.prow + t * kProw + 8 * c + 4);
+            }
+#pragma unroll
+            for (int s = JS; s < RS; ++s) {
+              if (s == 1 && (c < 8 || (JS == 0 && !two))) continue;
+#pragma unroll
+              for (int e = 0; e < 8; ++e) {
+                const int k = 8 * c + e;
+                float v = R.get(s, k);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) v = fmaf(-cf[s][t], pv[t][e >> 2][e & 3], v);
+                R.set(s, k, v);
+              }
             }
           }
         }
       }
-      const float t0 = st.prow[128], t1 = st.prow[129];
 #pragma unroll
-      for (int s = JS; s < RS; ++s) {
-        T[s][0] = fmaf(-fs[s], t0, T[s][0]);
-        T[s][1] = fmaf(-fs[s], t1, T[s][1]);
+      for (int t = 0; t < 4; ++t) {
+        const float t0 = st.prow[t * kProw + 128], t1 = st.prow[t * kProw + 129];
+#pragma unroll
+        for (int s = JS; s < RS; ++s) {
+          T[s][0] = fmaf(-cf[s][t], t0, T[s][0]);
+          T[s][1] = fmaf(-cf[s][t], t1, T[s][1]);
+        }
       }
-      wave_sync();  // every lane has read the pivot row before the next one is published
+      wave_sync();  // every lane has read the block rows before the next are published
     }
   }
   const bool need = (f.refine == 2) || (f.refine == 1 && !(dmin >= f.tau * dmax));
@@ -236,7 +323,7 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
       for (int s = 0; s < RS; ++s) {
         if (64 * s < k) {
           const bool above = lane + 64 * s < k;
-          const float u = R[s].get(k);
+          const float u = R.get(s, k);
           acc[s][0] = above ? fmaf(u, x0, acc[s][0]) : acc[s][0];
           acc[s][1] = above ? fmaf(u, x1, acc[s][1]) : acc[s][1];
         }
@@ -284,7 +371,7 @@ __device__ __forceinline__ void wide_eval32(const FrameDev &f, const WideJob &jb
                                             const WideStage &st, int lane, int w, int h, int W) {
   const float *Dw = D, *Dh = D + 1024, *lam = D + 2048;
   const int lo = lane & 15, hi = lane >> 4;
-  const int nch = (jb.K + 3) >> 2;
+  const int nch = (jb.K + 7) >> 3;  // pairs of 4-point chunks (staged points are zero past K)
   for (int v = 0; v < jb.nv; ++v) {
     f4 acc[2][2];
 #pragma unroll
@@ -292,19 +379,24 @@ __device__ __forceinline__ void wide_eval32(const FrameDev &f, const WideJob &jb
 #pragma unroll
       for (int qt = 0; qt < 2; ++qt) acc[pt][qt] = f4{0.f, 0.f, 0.f, 0.f};
     for (int ch = 0; ch < nch; ++ch) {
-      const WidePoint P = st.p[4 * ch + hi];
-      const float cv = v ? P.c1 : P.c0;
-      float ao[2], bo[2];
+      float ao[2][2], bo[2][2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        ao[t] = cv * Dw[(16 * t + lo) * 32 + P.x];  // A[p][i], p = 16 pt + lo
-        bo[t] = Dh[(16 * t + lo) * 32 + P.y];       // B[i][q], q = 16 qt + lo
+      for (int u = 0; u < 2; ++u) {
+        const WidePoint P = st.p[8 * ch + 4 * u + hi];
+        const float cv = v ? P.c1 : P.c0;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          ao[u][t] = cv * Dw[(16 * t + lo) * 32 + P.x];  // A[p][i], p = 16 pt + lo
+          bo[u][t] = Dh[(16 * t + lo) * 32 + P.y];       // B[i][q], q = 16 qt + lo
+        }
       }
 #pragma unroll
-      for (int pt = 0; pt < 2; ++pt)
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int qt = 0; qt < 2; ++qt)
-          acc[pt][qt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ao[pt], bo[qt], acc[pt][qt], 0, 0, 0);
+        for (int pt = 0; pt < 2; ++pt)
+#pragma unroll
+          for (int qt = 0; qt < 2; ++qt)
+            acc[pt][qt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ao[u][pt], bo[u][qt], acc[pt][qt], 0, 0, 0);
     }
     // acc[pt][qt][j] = V^T[p = 16 pt + 4 hi + j][q = 16 qt + lo].
     // S[q][x] = sum_p lam[q][p] V^T[p][q] Dw[p][x]
@@ -457,10 +549,14 @@ __device__ __forceinline__ void wide_eval16(const FrameDev &f, const WideJob &jb
   }
 }
 
-__global__ __launch_bounds__(kWideThreads) void k_wide(FrameDev f) {
+// One block per wave, WAVES waves per workgroup (the workgroup shares the
+// shape's tables in LDS).
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_wide(FrameDev f) {
   extern __shared__ __attribute__((aligned(16))) float tabs[];  // Hc | Dw | Dh | lam of the shape
-  __shared__ WideStage stage[kWideWaves];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  __shared__ WideStage stage[WAVES];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform, so is all that follows
   const int wg = blockIdx.x;
   int si = 0;
   while (si + 1 < f.nsegs && wg >= f.seg[si + 1].first_wg) ++si;
@@ -472,11 +568,11 @@ __global__ __launch_bounds__(kWideThreads) void k_wide(FrameDev f) {
     const int n4 = (S.jt_floats + 3072) >> 2;
     const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + S.fast);
     f4 *dst = reinterpret_cast<f4 *>(tabs);
-    for (int i = tid; i < n4; i += kWideThreads) dst[i] = src[i];
+    for (int i = tid; i < n4; i += 64 * WAVES) dst[i] = src[i];
   }
   __syncthreads();  // the only workgroup barrier: waves are independent from here on
 
-  const int k = (wg - sg.first_wg) * kWideWaves + wv;
+  const int k = (wg - sg.first_wg) * WAVES + wv;
   if (k >= sg.count) return;
   const int bx = sg.bx0 + k % sg.nx, by = sg.by0 + k / sg.nx;
   const int m = G.first + by * G.nbx + bx;
@@ -517,7 +613,12 @@ __global__ __launch_bounds__(kWideThreads) void k_wide(FrameDev f) {
 hipError_t launch_wide(const FrameDev &f, hipStream_t stream) {
   if (f.fast_wgs == 0) return hipSuccess;
   const size_t lds = sizeof(float) * (size_t)f.fast_lds;
-  hipLaunchKernelGGL(k_wide, dim3(f.fast_wgs), dim3(kWideThreads), lds, stream, f);
+  switch (f.ipw) {
+    case 1: hipLaunchKernelGGL(k_wide<1>, dim3(f.fast_wgs), dim3(64), lds, stream, f); break;
+    case 2: hipLaunchKernelGGL(k_wide<2>, dim3(f.fast_wgs), dim3(128), lds, stream, f); break;
+    case 4: hipLaunchKernelGGL(k_wide<4>, dim3(f.fast_wgs), dim3(256), lds, stream, f); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -257,3 +257,17 @@ def test_eval_dtypes_config2(dec):
         assert mx <= (FP32_TOL if ev == 0 else EVAL_TOL[ev])
         if ev in (0, 3):
             assert mx <= 0.5 and agree >= 0.999
+
+
+def test_autotune_keeps_results(dec):
+    """pdi_autotune picks a workgroup grouping for 32x32 blocks; every choice
+    decodes to bitwise the same planes.  Other block sizes have no choices."""
+    fr = synth.random_frame(300, 170, synth.YUV420, 32, (0.02, 0.1), seed=77)
+    ref, _ = gpu_decode(dec, fr)
+    d = dec.upload(fr)
+    ch = dec.autotune(d)
+    assert ch in (1, 2, 4)
+    got, _ = gpu_decode(dec, fr)
+    np.testing.assert_array_equal(got, ref)
+    d16 = dec.upload(synth.random_frame(100, 60, synth.YUV420, 16, (0.01, 0.1), seed=78))
+    assert dec.autotune(d16) == 0
