@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -41,8 +42,9 @@ using TuneKey = std::tuple<int, int, int, int, int, int, double, int>;  // Table
 // concurrently, so each stream gets its own.
 struct Workspace {
   int *status = nullptr;    // device status word
-  int *counters = nullptr;  // device counters [8]
+  int *counters = nullptr;  // device counters [kNumCounters]
   int *deferred = nullptr;  // device list of deferred mask blocks
+  int *binlist = nullptr;   // device queues of the wave-per-block path
   int deferred_cap = 0;
   float *slots = nullptr;   // global-memory bordered systems
   long long slot_floats = 0;
@@ -320,13 +322,13 @@ int get_workspace(pdi_ctx *c, hipStream_t stream, Workspace **out) {
   }
   Workspace w;
   int rc = dev_alloc(c, (void **)&w.status, sizeof(int) * 4, "status");
-  if (!rc) rc = dev_alloc(c, (void **)&w.counters, sizeof(int) * 8, "counters");
+  if (!rc) rc = dev_alloc(c, (void **)&w.counters, sizeof(int) * pdi::kNumCounters, "counters");
   if (rc) {
     dev_free(c, w.status, sizeof(int) * 4);
     return rc;
   }
   hipError_t e = hipMemset(w.status, 0, sizeof(int) * 4);
-  if (e == hipSuccess) e = hipMemset(w.counters, 0, sizeof(int) * 8);
+  if (e == hipSuccess) e = hipMemset(w.counters, 0, sizeof(int) * pdi::kNumCounters);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(c, e, "workspace init");
   *out = &c->ws.emplace(stream, w).first->second;
@@ -336,9 +338,11 @@ int get_workspace(pdi_ctx *c, hipStream_t stream, Workspace **out) {
 int ensure_workspace(pdi_ctx *c, Workspace *W, int n_items, int b, int nslots) {
   if (n_items > W->deferred_cap) {
     dev_free(c, W->deferred, sizeof(int) * (size_t)W->deferred_cap);
-    W->deferred = nullptr;
+    dev_free(c, W->binlist, sizeof(int) * (size_t)W->deferred_cap);
+    W->deferred = W->binlist = nullptr;
     W->deferred_cap = 0;
     int rc = dev_alloc(c, (void **)&W->deferred, sizeof(int) * (size_t)n_items, "deferred list");
+    if (!rc) rc = dev_alloc(c, (void **)&W->binlist, sizeof(int) * (size_t)n_items, "block queues");
     if (rc) return rc;
     W->deferred_cap = n_items;
   }
@@ -503,6 +507,7 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
     ipw = it != c->tune.end() ? it->second : pdi::kWideItemsDefault;
   }
   F.ipw = ipw;
+  int shape_count[pdi::kMaxShapes] = {0};
   const int dct_floats = fast ? 3 * 256 : 3 * 1024;
   F.nsegs = 0;
   F.fast_wgs = 0;
@@ -527,9 +532,31 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
       S.count = nx * ny;
       S.first_wg = F.fast_wgs;
       F.fast_wgs += (S.count + ipw - 1) / ipw;
+      shape_count[S.shape] += S.count;
       const pdi::ShapeDev &SH = ts->s[S.shape];
       if (SH.jt_floats + dct_floats > F.fast_lds) F.fast_lds = SH.jt_floats + dct_floats;
     }
+  }
+  if (wide) {
+    // One queue per block shape, the smallest first so that the few edge
+    // blocks start early; each queue's workgroups follow one another.
+    int order[pdi::kMaxShapes], nq = 0;
+    for (int sh = 0; sh < ts->nshapes; ++sh)
+      if (shape_count[sh] > 0) order[nq++] = sh;
+    std::sort(order, order + nq, [&](int a, int b) { return shape_count[a] < shape_count[b]; });
+    int base = 0, wgs = 0;
+    for (int i = 0; i < nq; ++i) {
+      pdi::QueueDev &Q = F.q[i];
+      Q.shape = order[i];
+      Q.count = shape_count[order[i]];
+      Q.base = base;
+      Q.first_wg = wgs;
+      base += Q.count;
+      wgs += (Q.count + ipw - 1) / ipw;
+      F.qof[order[i]] = i;
+    }
+    F.nq = nq;
+    F.fast_wgs = wgs;
   }
   rc = ensure_workspace(c, W, (int)nitems, block_size, fast ? F.fast_wgs : 0);
   if (rc) return rc;
@@ -541,6 +568,7 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
   F.tab32 = ts->tab32;
   F.tab64 = ts->tab64;
   F.deferred = W->deferred;
+  F.binlist = W->binlist;
   F.counters = W->counters;
   F.status = W->status;
   F.slots = W->slots;
@@ -573,7 +601,7 @@ int pdi_sync(pdi_ctx *c, void *stream) {
   if (e != hipSuccess) return hip_fail(c, e, "status read");
   if (st) {
     e = hipMemset(W.status, 0, sizeof(int));
-    if (e == hipSuccess) e = hipMemset(W.counters, 0, sizeof(int) * 8);
+    if (e == hipSuccess) e = hipMemset(W.counters, 0, sizeof(int) * pdi::kNumCounters);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(c, e, "status reset");
     if (st & pdi::kStatusMask) return set_err(c, PDI_EMASK, "device validation: bad mask positions");

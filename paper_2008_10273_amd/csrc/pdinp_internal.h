@@ -15,6 +15,11 @@ constexpr int kWaveItems = 4;      // blocks per wave in the wave-level path
 constexpr int kFastItemsPerWG = 16;  // blocks per workgroup of the wave-level path (b <= 16)
 constexpr int kWideItemsDefault = 2;  // blocks per workgroup of the wave-per-block path (1, 2 or 4)
 constexpr int kWideKMax = 103;       // largest K of the wave-per-block path
+constexpr int kBinSplitK = 64;       // wave-per-block queues hand out blocks with K >= this first
+// Device counters: [0], [1] deferred-list lengths, [2] finished workgroups of
+// the deferred pass, then per wave-per-block queue q: [kQueueCounters + 3q]
+// blocks with K >= kBinSplitK, [+1] the others, [+2] blocks handed out.
+constexpr int kQueueCounters = 8;
 // The FP32 table buffer is padded by this many floats so that the wave-level
 // path may read whole 16-byte vectors per thread past the last table.
 constexpr int kTabPadFloats = 6 * 256 * 4;
@@ -44,6 +49,14 @@ struct SegDev {
   int group, shape, bx0, nx, by0, count, first_wg;
 };
 constexpr int kMaxSegs = 4 * kMaxGroups;
+constexpr int kNumCounters = kQueueCounters + 3 * kMaxShapes;
+
+// The blocks of one shape for the wave-per-block path: binlist[base ..
+// base + count) holds them by point count (large K from the front, the rest
+// from the back); workgroups first_wg .. take them in that order.
+struct QueueDev {
+  int shape, count, base, first_wg;
+};
 
 // Per mask-plane group (Y; shared chroma; or Cb and Cr separately).
 struct GroupDev {
@@ -71,6 +84,9 @@ struct FrameDev {
   SegDev seg[kMaxSegs];
   int nsegs;
   int ipw;           // blocks per workgroup of the batched path
+  int nq;            // wave-per-block queues (one per block shape), smallest first
+  QueueDev q[kMaxShapes];
+  int qof[kMaxShapes];  // queue of each shape
   int fast_wgs;      // workgroups of the batched path (k_fast or k_wide)
   int fast_lds;      // its dynamic LDS (floats): largest table block
   int tab32_floats;  // size of the FP32 table buffer (floats)
@@ -82,7 +98,8 @@ struct FrameDev {
   const float *tab32;
   const double *tab64;
   int *deferred;   // list of mask blocks left to the general path
-  int *counters;   // [0] medium count, [1] large count, [2] finished workgroups
+  int *binlist;    // wave-per-block queues (n_items entries)
+  int *counters;   // kNumCounters device counters (layout above)
   int *status;     // device status word
   float *slots;    // global-memory systems for K > kLdsKMax, one slot per workgroup
   long long slot_floats;
@@ -90,7 +107,7 @@ struct FrameDev {
 
 // Launchers (pdinp_kernels.hip).  All asynchronous on `stream`.
 hipError_t launch_fast(const FrameDev &f, hipStream_t stream);
-hipError_t launch_wide(const FrameDev &f, hipStream_t stream);
+hipError_t launch_wide(const FrameDev &f, hipStream_t stream);  // binning kernel + k_wide
 hipError_t launch_plain_all(const FrameDev &f, hipStream_t stream);
 hipError_t launch_general_deferred(const FrameDev &f, hipStream_t stream);
 

@@ -310,15 +310,15 @@ __global__ __launch_bounds__(kGenThreads) void k_general_deferred(FrameDev f) {
     }
   }
   // Every workgroup has read both counts before it gets here; the last one
-  // to arrive clears them for the next decode (the kernel boundary orders
-  // these writes before any later kernel on the stream).
+  // to arrive clears every counter (these and the wave-per-block queues',
+  // whose kernels ran before this one) for the next decode; the kernel
+  // boundary orders these writes before any later kernel on the stream.
   __syncthreads();
   if (threadIdx.x == 0) {
     int done = __hip_atomic_fetch_add(&f.counters[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (done == (int)gridDim.x - 1) {
-      __hip_atomic_store(&f.counters[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&f.counters[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&f.counters[2], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int i = 0; i < kNumCounters; ++i)
+        __hip_atomic_store(&f.counters[i], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }

@@ -549,8 +549,49 @@ __device__ __forceinline__ void wide_eval16(const FrameDev &f, const WideJob &jb
   }
 }
 
+// Binning: every mask block goes to its shape's queue, K >= kBinSplitK from
+// the front and the rest from the back, so that the long solves are handed
+// out first; blocks the wave path does not take (K = 0, K = w*h, K > 103,
+// invalid counts) go to the general path's lists.
+__global__ __launch_bounds__(256) void k_bin(FrameDev f) {
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  int key = -1;  // 2 * queue + (K < kBinSplitK), or -1: not queued
+  if (m < f.n_items) {
+  int g = 0;
+  if (f.ngroups > 1 && m >= f.g[1].first) g = 1;
+  if (f.ngroups > 2 && m >= f.g[2].first) g = 2;
+  const GroupDev &G = f.g[g];
+  const int l = m - G.first, bx = l % G.nbx, by = l / G.nbx;
+  const int e = ((bx == G.nbx - 1) && (G.W % f.b) ? 1 : 0) + ((by == G.nby - 1) && (G.H % f.b) ? 2 : 0);
+  const int shape = G.shape[e];
+  const int w = f.s[shape].w, h = f.s[shape].h;
+  const int K = f.block_ptr[m + 1] - f.block_ptr[m];
+  if (K < 1 || K >= w * h || K > kWideKMax) push_deferred(f, m, K, w, h);
+  else key = 2 * f.qof[shape] + (K < kBinSplitK ? 1 : 0);
+  }
+  // One atomic per distinct queue and bin in the wave: the lanes of a key
+  // take consecutive slots after the leader's reservation.
+  unsigned long long todo = __ballot(key >= 0);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int k = __shfl(key, leader);
+    const unsigned long long mine = __ballot(key == k);
+    todo &= ~mine;
+    const int rank = __popcll(mine & ((1ull << (threadIdx.x & 63)) - 1ull));
+    int base = 0;
+    if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(&f.counters[kQueueCounters + 3 * (k >> 1) + (k & 1)], __popcll(mine));
+    base = __shfl(base, leader);
+    if (key == k) {
+      const QueueDev &Q = f.q[k >> 1];
+      const int idx = base + rank;
+      if (idx < Q.count) f.binlist[Q.base + ((k & 1) ? Q.count - 1 - idx : idx)] = m;
+      else atomicOr(f.status, kStatusSolve);  // counters were not cleared by the previous decode
+    }
+  }
+}
+
 // One block per wave, WAVES waves per workgroup (the workgroup shares the
-// shape's tables in LDS).
+// shape's tables in LDS); each wave takes the next block of its queue.
 template <int WAVES>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_wide(FrameDev f) {
   extern __shared__ __attribute__((aligned(16))) float tabs[];  // Hc | Dw | Dh | lam of the shape
@@ -558,11 +599,10 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform, so is all that follows
   const int wg = blockIdx.x;
-  int si = 0;
-  while (si + 1 < f.nsegs && wg >= f.seg[si + 1].first_wg) ++si;
-  const SegDev sg = f.seg[si];
-  const ShapeDev S = f.s[sg.shape];
-  const GroupDev &G = f.g[sg.group];
+  int qi = 0;
+  while (qi + 1 < f.nq && wg >= f.q[qi + 1].first_wg) ++qi;
+  const QueueDev Q = f.q[qi];
+  const ShapeDev S = f.s[Q.shape];
   const int w = S.w, h = S.h;
   {
     const int n4 = (S.jt_floats + 3072) >> 2;
@@ -572,10 +612,22 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2
   }
   __syncthreads();  // the only workgroup barrier: waves are independent from here on
 
-  const int k = (wg - sg.first_wg) * WAVES + wv;
-  if (k >= sg.count) return;
-  const int bx = sg.bx0 + k % sg.nx, by = sg.by0 + k / sg.nx;
-  const int m = G.first + by * G.nbx + bx;
+  // Queue position of this wave's block: workgroups start in index order, so
+  // the first ones take the large-K blocks at the front of the queue.
+  const int p = (wg - Q.first_wg) * WAVES + wv;
+  const int nl = f.counters[kQueueCounters + 3 * qi], ns = f.counters[kQueueCounters + 3 * qi + 1];
+  int m;
+  if (p >= Q.count || nl + ns > Q.count) return;
+  if (p < nl) m = f.binlist[Q.base + p];
+  else if (p - nl < ns) m = f.binlist[Q.base + Q.count - 1 - (p - nl)];
+  else return;
+  m = __builtin_amdgcn_readfirstlane(m);
+  if ((unsigned)m >= (unsigned)f.n_items) return;
+  int gi = 0;
+  if (f.ngroups > 1 && m >= f.g[1].first) gi = 1;
+  if (f.ngroups > 2 && m >= f.g[2].first) gi = 2;
+  const GroupDev &G = f.g[gi];
+  const int bl = m - G.first, bx = bl % G.nbx, by = bl / G.nbx;
   const int lo = f.block_ptr[m], hi = f.block_ptr[m + 1];
   WideJob jb;
   jb.K = hi - lo;
@@ -590,11 +642,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2
     jb.vb1 = f.shared ? (long long)f.block_ptr[f.n_items] + (lo - f.block_ptr[f.chroma_first]) : lo;
     jb.ob1 = G.out_off[1] + pix;
   }
-  const int K = jb.K;
-  if (K < 1 || K >= w * h || K > kWideKMax) {  // K = 0, K = w*h, large or invalid counts
-    if (lane == 0) push_deferred(f, m, K, w, h);
-    return;
-  }
+  const int K = jb.K;  // 1 <= K <= min(w*h - 1, kWideKMax): binned
   WideStage &st = stage[wv];
   const bool solved = wide_solve(f, jb, lane, w, h, tabs, st);
   if (!solved) {
@@ -611,7 +659,8 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2
 }
 
 hipError_t launch_wide(const FrameDev &f, hipStream_t stream) {
-  if (f.fast_wgs == 0) return hipSuccess;
+  if (f.n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bin, dim3((f.n_items + 255) / 256), dim3(256), 0, stream, f);
   const size_t lds = sizeof(float) * (size_t)f.fast_lds;
   switch (f.ipw) {
     case 1: hipLaunchKernelGGL(k_wide<1>, dim3(f.fast_wgs), dim3(64), lds, stream, f); break;
