@@ -338,11 +338,11 @@ int get_workspace(pdi_ctx *c, hipStream_t stream, Workspace **out) {
 int ensure_workspace(pdi_ctx *c, Workspace *W, int n_items, int b, int nslots) {
   if (n_items > W->deferred_cap) {
     dev_free(c, W->deferred, sizeof(int) * (size_t)W->deferred_cap);
-    dev_free(c, W->binlist, sizeof(int) * (size_t)W->deferred_cap);
+    dev_free(c, W->binlist, sizeof(int) * 2 * (size_t)W->deferred_cap);
     W->deferred = W->binlist = nullptr;
     W->deferred_cap = 0;
     int rc = dev_alloc(c, (void **)&W->deferred, sizeof(int) * (size_t)n_items, "deferred list");
-    if (!rc) rc = dev_alloc(c, (void **)&W->binlist, sizeof(int) * (size_t)n_items, "block queues");
+    if (!rc) rc = dev_alloc(c, (void **)&W->binlist, sizeof(int) * 2 * (size_t)n_items, "block queues");
     if (rc) return rc;
     W->deferred_cap = n_items;
   }

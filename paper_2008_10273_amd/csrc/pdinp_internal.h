@@ -15,10 +15,12 @@ constexpr int kWaveItems = 4;      // blocks per wave in the wave-level path
 constexpr int kFastItemsPerWG = 16;  // blocks per workgroup of the wave-level path (b <= 16)
 constexpr int kWideItemsDefault = 2;  // blocks per workgroup of the wave-per-block path (1, 2 or 4)
 constexpr int kWideKMax = 103;       // largest K of the wave-per-block path
-constexpr int kBinSplitK = 64;       // wave-per-block queues hand out blocks with K >= this first
+// Point-count bins of the wave-per-block queues, handed out largest first:
+// bin 0 K >= 84, bin 1 K >= 64, bin 2 K >= 42, bin 3 the rest.
+constexpr int kBinK0 = 84, kBinK1 = 64, kBinK2 = 42;
 // Device counters: [0], [1] deferred-list lengths, [2] finished workgroups of
-// the deferred pass, then per wave-per-block queue q: [kQueueCounters + 3q]
-// blocks with K >= kBinSplitK, [+1] the others, [+2] blocks handed out.
+// the deferred pass, then per wave-per-block queue q the lengths of its 4
+// bins at [kQueueCounters + 4q + bin].
 constexpr int kQueueCounters = 8;
 // The FP32 table buffer is padded by this many floats so that the wave-level
 // path may read whole 16-byte vectors per thread past the last table.
@@ -49,11 +51,12 @@ struct SegDev {
   int group, shape, bx0, nx, by0, count, first_wg;
 };
 constexpr int kMaxSegs = 4 * kMaxGroups;
-constexpr int kNumCounters = kQueueCounters + 3 * kMaxShapes;
+constexpr int kNumCounters = kQueueCounters + 4 * kMaxShapes;
 
-// The blocks of one shape for the wave-per-block path: binlist[base ..
-// base + count) holds them by point count (large K from the front, the rest
-// from the back); workgroups first_wg .. take them in that order.
+// The blocks of one shape for the wave-per-block path.  binlist[2 base ..
+// 2 base + 2 count) holds them by point count: bin 0 from the front of the
+// first half, bin 1 from its back, bins 2 and 3 likewise in the second half;
+// workgroups first_wg .. take them in bin order.
 struct QueueDev {
   int shape, count, base, first_wg;
 };
@@ -98,7 +101,7 @@ struct FrameDev {
   const float *tab32;
   const double *tab64;
   int *deferred;   // list of mask blocks left to the general path
-  int *binlist;    // wave-per-block queues (n_items entries)
+  int *binlist;    // wave-per-block queues (2 n_items entries)
   int *counters;   // kNumCounters device counters (layout above)
   int *status;     // device status word
   float *slots;    // global-memory systems for K > kLdsKMax, one slot per workgroup

@@ -549,13 +549,13 @@ __device__ __forceinline__ void wide_eval16(const FrameDev &f, const WideJob &jb
   }
 }
 
-// Binning: every mask block goes to its shape's queue, K >= kBinSplitK from
-// the front and the rest from the back, so that the long solves are handed
-// out first; blocks the wave path does not take (K = 0, K = w*h, K > 103,
-// invalid counts) go to the general path's lists.
+// Binning: every mask block goes to its shape's queue, into one of 4 bins by
+// point count, so that the long solves are handed out first; blocks the wave
+// path does not take (K = 0, K = w*h, K > 103, invalid counts) go to the
+// general path's lists.
 __global__ __launch_bounds__(256) void k_bin(FrameDev f) {
   const int m = blockIdx.x * 256 + threadIdx.x;
-  int key = -1;  // 2 * queue + (K < kBinSplitK), or -1: not queued
+  int key = -1;  // 4 * queue + bin, or -1: not queued
   if (m < f.n_items) {
   int g = 0;
   if (f.ngroups > 1 && m >= f.g[1].first) g = 1;
@@ -567,7 +567,7 @@ __global__ __launch_bounds__(256) void k_bin(FrameDev f) {
   const int w = f.s[shape].w, h = f.s[shape].h;
   const int K = f.block_ptr[m + 1] - f.block_ptr[m];
   if (K < 1 || K >= w * h || K > kWideKMax) push_deferred(f, m, K, w, h);
-  else key = 2 * f.qof[shape] + (K < kBinSplitK ? 1 : 0);
+  else key = 4 * f.qof[shape] + (K >= kBinK0 ? 0 : K >= kBinK1 ? 1 : K >= kBinK2 ? 2 : 3);
   }
   // One atomic per distinct queue and bin in the wave: the lanes of a key
   // take consecutive slots after the leader's reservation.
@@ -579,12 +579,13 @@ __global__ __launch_bounds__(256) void k_bin(FrameDev f) {
     todo &= ~mine;
     const int rank = __popcll(mine & ((1ull << (threadIdx.x & 63)) - 1ull));
     int base = 0;
-    if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(&f.counters[kQueueCounters + 3 * (k >> 1) + (k & 1)], __popcll(mine));
+    if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(&f.counters[kQueueCounters + k], __popcll(mine));
     base = __shfl(base, leader);
     if (key == k) {
-      const QueueDev &Q = f.q[k >> 1];
-      const int idx = base + rank;
-      if (idx < Q.count) f.binlist[Q.base + ((k & 1) ? Q.count - 1 - idx : idx)] = m;
+      const QueueDev &Q = f.q[k >> 2];
+      const int bin = k & 3, idx = base + rank;
+      const int half = 2 * Q.base + (bin >> 1) * Q.count;  // bins 0, 1 | bins 2, 3
+      if (idx < Q.count) f.binlist[half + ((bin & 1) ? Q.count - 1 - idx : idx)] = m;
       else atomicOr(f.status, kStatusSolve);  // counters were not cleared by the previous decode
     }
   }
@@ -615,11 +616,15 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2
   // Queue position of this wave's block: workgroups start in index order, so
   // the first ones take the large-K blocks at the front of the queue.
   const int p = (wg - Q.first_wg) * WAVES + wv;
-  const int nl = f.counters[kQueueCounters + 3 * qi], ns = f.counters[kQueueCounters + 3 * qi + 1];
+  const int *cnt = f.counters + kQueueCounters + 4 * qi;
+  const int n0 = cnt[0], n1 = cnt[1], n2 = cnt[2], n3 = cnt[3];
+  if (p >= Q.count || n0 + n1 > Q.count || n2 + n3 > Q.count) return;
+  const int *h0 = f.binlist + 2 * Q.base, *h1 = h0 + Q.count;
   int m;
-  if (p >= Q.count || nl + ns > Q.count) return;
-  if (p < nl) m = f.binlist[Q.base + p];
-  else if (p - nl < ns) m = f.binlist[Q.base + Q.count - 1 - (p - nl)];
+  if (p < n0) m = h0[p];
+  else if (p < n0 + n1) m = h0[Q.count - 1 - (p - n0)];
+  else if (p < n0 + n1 + n2) m = h1[p - n0 - n1];
+  else if (p < n0 + n1 + n2 + n3) m = h1[Q.count - 1 - (p - n0 - n1 - n2)];
   else return;
   m = __builtin_amdgcn_readfirstlane(m);
   if ((unsigned)m >= (unsigned)f.n_items) return;
