@@ -38,8 +38,8 @@ EVALS = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16x2": 3}
 # HBM bytes per launch of the decode kernel from rocprofv3 FETCH_SIZE +
 # WRITE_SIZE counters, scaled by the same counters read on a copy kernel of
 # known size (profiles/k_fast_fhd420_b16_hbm_counters.txt); only for the
-# kernel build the counters were taken on.
-TRAFFIC = {1: 15088948}
+# kernel build the counters were taken on (null after a kernel change).
+TRAFFIC = {}
 
 
 def algorithmic_bytes(fr) -> int:

@@ -89,6 +89,8 @@ typedef struct {
     int32_t validate;    /* 1: check masks/values on the device, report at pdi_sync */
     int32_t path;        /* PDI_PATH_*; default PDI_PATH_AUTO */
     double refine_tau;   /* auto-refine when min/max pivot < tau; default 1/64 */
+    int32_t out_int8;    /* 1: `out` receives int8 pixels clamp(rint(u), -128, 127)
+                            (round half to even) instead of FP32; default 0 */
 } pdi_params;
 
 /* Fill *p with the defaults. */
@@ -113,8 +115,9 @@ void pdi_destroy(pdi_ctx *ctx);
  *     values (aligned with the chroma part again when chroma_shared).
  *   block_size: 8, 16 or 32.
  *   params: NULL for the defaults.
- *   out: DEVICE float32 array of W*H (+ 2 * ceil(W/2)*ceil(H/2) for YUV420)
- *     elements, planes Y, Cb, Cr back to back, row-major.
+ *   out: DEVICE array of W*H (+ 2 * ceil(W/2)*ceil(H/2) for YUV420)
+ *     elements, planes Y, Cb, Cr back to back, row-major: float32, or int8
+ *     with params->out_int8.
  * The library keeps no reference to caller memory after the stream work
  * completes.  Host-side checks (geometry, params, mask block count) return
  * PDI_EINVAL synchronously; with validate=1 mask/value errors found on the
@@ -139,8 +142,9 @@ const char *pdi_last_error(pdi_ctx *ctx);
  * choices only change how blocks are grouped into workgroups, never a
  * block's arithmetic, so results are bitwise the same with any choice.
  * Synchronous (not capturable).  *choice (may be NULL) receives the blocks
- * per workgroup chosen, or 0 when the path has no choices (block sizes 8 and
- * 16, PDI_PATH_PLAIN), in which case the call is one decode + pdi_sync.
+ * per workgroup chosen (block size 32: 1, 2 or 4; block sizes 8 and 16: 8 to
+ * 16), or 0 with PDI_PATH_PLAIN, which has no choices (the call is then one
+ * decode + pdi_sync).
  * Returns the codes of decode_residual / pdi_sync. */
 int pdi_autotune(pdi_ctx *ctx, const pdi_frame *frame, const pdi_mask *mask, const float *values,
                  int block_size, const pdi_params *params, float *out, void *stream, int *choice);
@@ -207,17 +211,18 @@ int pdi_server_create(pdi_ctx *ctx, int nlanes, size_t hbm_budget_bytes, int max
                       pdi_server **out);
 /* Queue one frame.  mask->block_ptr / mask->pos and values are HOST arrays,
  * copied before the call returns (layouts as for decode_residual; n_values
- * is the length of values).  out_dev: caller-owned DEVICE float array of the
- * frame's output size that the decode writes (it must stay valid until the
- * request completes), or NULL to decode into a pooled server buffer.  out:
- * HOST float array of the output size that pdi_wait fills, or NULL.
+ * is the length of values).  out_dev: caller-owned DEVICE array of the
+ * frame's output size (float32, or int8 with params->out_int8) that the
+ * decode writes (it must stay valid until the request completes), or NULL
+ * to decode into a pooled server buffer.  out: HOST array of the same type
+ * and size that pdi_wait fills, or NULL.
  * With params->validate the mask and values are checked here (PDI_EMASK /
  * PDI_EVALUE, nothing queued).  Returns PDI_EINVAL, PDI_ENOMEM (the frame
  * alone exceeds the budget, or staging failed), PDI_EBUSY (queue full); on
  * PDI_OK *ticket identifies the request. */
 int pdi_submit(pdi_server *srv, const pdi_frame *frame, const pdi_mask *mask, const float *values,
-               int64_t n_values, int block_size, const pdi_params *params, float *out,
-               float *out_dev, int64_t *ticket);
+               int64_t n_values, int block_size, const pdi_params *params, void *out,
+               void *out_dev, int64_t *ticket);
 /* Non-blocking: *done = 1 once the request has completed; then
  * *latency_us = submit-to-completion time and the return value is the
  * request's status.  PDI_EINVAL for an unknown ticket. */

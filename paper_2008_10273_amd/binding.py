@@ -42,7 +42,7 @@ class pdi_mask(ctypes.Structure):
 class pdi_params(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("s", ctypes.c_double), ("eval_dtype", ctypes.c_int32),
                 ("refine", ctypes.c_int32), ("validate", ctypes.c_int32), ("path", ctypes.c_int32),
-                ("refine_tau", ctypes.c_double)]
+                ("refine_tau", ctypes.c_double), ("out_int8", ctypes.c_int32)]
 
 
 class PdiError(RuntimeError):
@@ -228,12 +228,14 @@ class Decoder:
         rc, nb, nel = pdi_frame_info(frame.width, frame.height, frame.fmt, frame.block_size,
                                      frame.chroma_shared)
         out = torch.empty(nel, dtype=torch.float32, device=dev)
-        return dict(frame=frame, block_ptr=bp, pos=pos_t, values=vals_t, out=out,
+        out_i8 = torch.empty(nel, dtype=torch.int8, device=dev)
+        return dict(frame=frame, block_ptr=bp, pos=pos_t, values=vals_t, out=out, out_i8=out_i8,
                     n_mask_blocks=int(frame.block_ptr.shape[0] - 1))
 
     def decode(self, d, params: Optional[pdi_params] = None, stream=None, out=None, check=True) -> int:
         fr = d["frame"]
-        out = d["out"] if out is None else out
+        if out is None:
+            out = d["out_i8"] if (params is not None and params.out_int8) else d["out"]
         s = stream.cuda_stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
         rc = decode_residual(self.ctx, fr.width, fr.height, fr.fmt, d["block_ptr"].data_ptr(),
                              d["pos"].data_ptr(), d["n_mask_blocks"], fr.chroma_shared,
@@ -334,7 +336,8 @@ class Server:
         pos = np.ascontiguousarray(frame.pos, np.uint16)
         vals = np.ascontiguousarray(frame.values, np.float32)
         rc, nb, nel = pdi_frame_info(frame.width, frame.height, frame.fmt, frame.block_size, frame.chroma_shared)
-        out = np.empty(nel, np.float32) if want_output else None
+        i8 = params is not None and params.out_int8
+        out = np.empty(nel, np.int8 if i8 else np.float32) if want_output else None
         fr = pdi_frame(frame.width, frame.height, frame.fmt)
         mk = pdi_mask(bp.ctypes.data, pos.ctypes.data if pos.size else None, int(bp.size - 1),
                       int(bool(frame.chroma_shared)))

@@ -20,6 +20,17 @@ __device__ __forceinline__ void push_deferred(const FrameDev &f, int m, int K, i
   }
 }
 
+// Store one decoded pixel: FP32, or int8 = clamp(rint(u), -128, 127) with
+// round-half-to-even when the frame asks for 8-bit output.
+__device__ __forceinline__ void store_px(const FrameDev &f, long long idx, float u) {
+  if (f.out_i8) {
+    const float q = fminf(fmaxf(__builtin_rintf(u), -128.f), 127.f);
+    reinterpret_cast<int8_t *>(f.out)[idx] = (int8_t)(int)q;
+  } else {
+    f.out[idx] = u;
+  }
+}
+
 // Make this lane's LDS writes visible to the other lanes of its wave (no
 // instruction beyond the wait the writes need).
 __device__ __forceinline__ void wave_sync() {

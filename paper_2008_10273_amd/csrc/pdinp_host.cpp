@@ -378,6 +378,7 @@ void pdi_default_params(pdi_params *p) {
   p->eval_dtype = PDI_EVAL_FP32;
   p->refine = 1;
   p->validate = 0;
+  p->out_int8 = 0;
   p->path = PDI_PATH_AUTO;
   p->refine_tau = 1.0 / 64.0;
 }
@@ -446,6 +447,7 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
   if (P.refine < 0 || P.refine > 2) return set_err(c, PDI_EINVAL, "bad refine");
   if (P.path != PDI_PATH_AUTO && P.path != PDI_PATH_PLAIN) return set_err(c, PDI_EINVAL, "bad path");
   if (!(P.refine_tau >= 0.0) || !(P.refine_tau <= 1.0)) return set_err(c, PDI_EINVAL, "bad refine_tau");
+  if (P.out_int8 != 0 && P.out_int8 != 1) return set_err(c, PDI_EINVAL, "bad out_int8");
   int shared = (frame->format == PDI_YUV420 && mask->chroma_shared) ? 1 : 0;
   long long nitems = mask_blocks_of(frame, block_size, shared);
   if (nitems != mask->n_mask_blocks)
@@ -473,6 +475,7 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
   F.refine = P.refine;
   F.tau = (float)P.refine_tau;
   F.eval = P.eval_dtype;
+  F.out_i8 = P.out_int8;
   PlaneGeom pg[3];
   planes_of(frame, pg);
   long long poff[3] = {0, 0, 0};
@@ -500,11 +503,11 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
   // 16 blocks per workgroup) or k_wide (b = 32, 4 blocks per workgroup).
   const bool fast = (P.path == PDI_PATH_AUTO && block_size <= 16);
   const bool wide = (P.path == PDI_PATH_AUTO && block_size == 32);
-  int ipw = pdi::kFastItemsPerWG;
-  if (!fast) {
+  int ipw = fast ? pdi::kFastItemsPerWG : pdi::kWideItemsDefault;
+  {
     auto it = c->tune.find(TuneKey{frame->width, frame->height, frame->format, block_size, shared, P.op, P.s,
                                    P.eval_dtype});
-    ipw = it != c->tune.end() ? it->second : pdi::kWideItemsDefault;
+    if (it != c->tune.end()) ipw = it->second;
   }
   F.ipw = ipw;
   int shape_count[pdi::kMaxShapes] = {0};
@@ -620,11 +623,17 @@ int pdi_autotune(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, const
   const int shared = (frame->format == PDI_YUV420 && mask->chroma_shared) ? 1 : 0;
   const TuneKey key{frame->width, frame->height, frame->format, block_size, shared, P.op, P.s, P.eval_dtype};
   if (choice) *choice = 0;
-  // Only the wave-per-block path (32 x 32 blocks) has launch choices.
-  if (!(P.path == PDI_PATH_AUTO && block_size == 32)) {
+  // Launch choices: blocks per workgroup of the batched path (k_fast: up to
+  // 16, fewer spread a frame more evenly over the compute units; k_wide: one
+  // block per wave).  The plain path has none.
+  if (P.path != PDI_PATH_AUTO) {
     int rc = decode_residual(c, frame, mask, values, block_size, params, out, stream);
     return rc ? rc : pdi_sync(c, stream);
   }
+  static const int fast_cands[] = {16, 14, 13, 12, 10, 8};
+  static const int wide_cands[] = {1, 2, 4};
+  const int *cands = block_size == 32 ? wide_cands : fast_cands;
+  const int ncand = block_size == 32 ? 3 : 6;
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipSetDevice(c->device);
@@ -634,10 +643,10 @@ int pdi_autotune(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, const
     if (e0) (void)hipEventDestroy(e0);
     return hip_fail(c, e, "autotune events");
   }
-  const int cands[3] = {1, 2, 4};
-  int best = pdi::kWideItemsDefault, rc = PDI_OK;
+  int best = cands[0], rc = PDI_OK;
   float best_ms = 3.0e38f;
-  for (int cand : cands) {
+  for (int ci = 0; ci < ncand; ++ci) {
+    const int cand = cands[ci];
     {
       std::lock_guard<std::mutex> lock(c->mu);
       c->tune[key] = cand;

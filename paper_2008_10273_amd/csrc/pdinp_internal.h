@@ -82,6 +82,7 @@ struct FrameDev {
   int refine;        // 0 off, 1 auto, 2 always
   float tau;         // auto-refine threshold on min/max pivot
   int eval;          // PDI_EVAL_*
+  int out_i8;        // 1: out holds int8 pixels, clamp(rint(u), -128, 127)
   GroupDev g[kMaxGroups];
   ShapeDev s[kMaxShapes];
   SegDev seg[kMaxSegs];
@@ -97,7 +98,7 @@ struct FrameDev {
   const int32_t *block_ptr;
   const uint16_t *pos;
   const float *values;
-  float *out;
+  float *out;      // FP32 planes, or int8 planes when out_i8
   const float *tab32;
   const double *tab64;
   int *deferred;   // list of mask blocks left to the general path

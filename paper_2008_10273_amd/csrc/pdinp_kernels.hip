@@ -122,14 +122,13 @@ __device__ void general_block(const FrameDev &f, int m, GenScratch<B> &sh, float
   const Item it = load_item(f, m);
   const int K = it.K, w = it.w, h = it.h, N = w * h;
   const ShapeDev S = f.s[it.shape];
-  float *out = f.out;
 
   if (tid == 0) sh.flag = 0;
   __syncthreads();
   if (K < 0 || K > N) {
     if (tid == 0) atomicOr(f.status, kStatusMask);
     for (int v = 0; v < it.nv; ++v)
-      for (int p = tid; p < N; p += kGenThreads) out[it.obase(v) + (p / w) * it.W + p % w] = 0.f;
+      for (int p = tid; p < N; p += kGenThreads) store_px(f, it.obase(v) + (p / w) * it.W + p % w, 0.f);
     return;
   }
   if (f.validate) {
@@ -144,20 +143,20 @@ __device__ void general_block(const FrameDev &f, int m, GenScratch<B> &sh, float
     __syncthreads();
     if (sh.flag) {
       for (int v = 0; v < it.nv; ++v)
-        for (int p = tid; p < N; p += kGenThreads) out[it.obase(v) + (p / w) * it.W + p % w] = 0.f;
+        for (int p = tid; p < N; p += kGenThreads) store_px(f, it.obase(v) + (p / w) * it.W + p % w, 0.f);
       return;
     }
   }
   if (K == 0) {
     for (int v = 0; v < it.nv; ++v)
-      for (int p = tid; p < N; p += kGenThreads) out[it.obase(v) + (p / w) * it.W + p % w] = 0.f;
+      for (int p = tid; p < N; p += kGenThreads) store_px(f, it.obase(v) + (p / w) * it.W + p % w, 0.f);
     return;
   }
   if (K == N) {  // every pixel known: u = r (the system is singular here)
     for (int v = 0; v < it.nv; ++v)
       for (int i = tid; i < K; i += kGenThreads) {
         int p = min((int)f.pos[it.base + i], N - 1);
-        out[it.obase(v) + (p / w) * it.W + p % w] = f.values[it.vbase(v) + i];
+        store_px(f, it.obase(v) + (p / w) * it.W + p % w, f.values[it.vbase(v) + i]);
       }
     return;
   }
@@ -268,11 +267,11 @@ __device__ void general_block(const FrameDev &f, int m, GenScratch<B> &sh, float
     }
     float u0 = acc0 + a_v[0];
     bad |= !isfinite(u0);
-    out[it.obase0 + (long long)yy * it.W + xx] = u0;
+    store_px(f, it.obase0 + (long long)yy * it.W + xx, u0);
     if (it.nv > 1) {
       float u1 = acc1 + a_v[1];
       bad |= !isfinite(u1);
-      out[it.obase1 + (long long)yy * it.W + xx] = u1;
+      store_px(f, it.obase1 + (long long)yy * it.W + xx, u1);
     }
   }
   if (bad) atomicOr(f.status, kStatusSolve);
@@ -623,7 +622,7 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int y = 4 * hi + j, x = lo;
-        if (x < w && y < h) f.out[o + (long long)y * W + x] = U[g][j] + a;
+        if (x < w && y < h) store_px(f, o + (long long)y * W + x, U[g][j] + a);
       }
     }
   }
@@ -706,7 +705,7 @@ __device__ __forceinline__ void fast_eval16(const FrameDev &f, const float *D, c
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int y = 4 * hi + j, x = lo;
-        if (x < w && y < h) f.out[o + (long long)y * W + x] = U[j] + av;
+        if (x < w && y < h) store_px(f, o + (long long)y * W + x, U[j] + av);
       }
     }
   }
@@ -741,9 +740,21 @@ void k_fast(FrameDev f) {
   const GroupDev &G = f.g[sg.group];
   const int w = S.w, h = S.h;
 
-  // Prologue: the shape's tables into LDS (16-byte loads, all in flight
-  // before the first store); the workgroup's 16 blocks (geometry from the
-  // segment, counts from block_ptr) into LDS records.
+  // Prologue: the workgroup's blocks (geometry from the segment, counts from
+  // block_ptr: these loads are issued first) and the shape's tables into LDS
+  // (16-byte loads, all in flight before the first store).
+  const int kk = (wg - sg.first_wg) * f.ipw + tid;
+  const bool has = tid < f.ipw && kk < sg.count;
+  int im = 0, ilo = 0, ihi = 0, ibx = 0, iby = 0;
+  long long icr = 0;
+  if (has) {
+    ibx = sg.bx0 + kk % sg.nx;
+    iby = sg.by0 + kk / sg.nx;
+    im = G.first + iby * G.nbx + ibx;
+    ilo = f.block_ptr[im];
+    ihi = f.block_ptr[im + 1];
+    if (G.nv > 1 && f.shared) icr = (long long)f.block_ptr[f.n_items] - f.block_ptr[f.chroma_first];
+  }
   {
     const int n4 = (S.jt_floats + 768) >> 2;
     const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + S.fast);
@@ -764,21 +775,18 @@ void k_fast(FrameDev f) {
     r.cls = 4;
     r.m = r.K = r.base = r.nv = r.pad_ = 0;
     r.vb0 = r.vb1 = r.ob0 = r.ob1 = 0;
-    const int k = (wg - sg.first_wg) * kFastItems + tid;
-    if (k < sg.count) {
-      const int bx = sg.bx0 + k % sg.nx, by = sg.by0 + k / sg.nx;
-      const int m = G.first + by * G.nbx + bx;
-      const int lo = f.block_ptr[m], hi = f.block_ptr[m + 1];
-      r.m = m;
-      r.K = hi - lo;
-      r.base = lo;
+    if (has) {
+      r.m = im;
+      r.K = ihi - ilo;
+      r.base = ilo;
       r.nv = G.nv;
       r.cls = fast_class(r.K, w * h);
-      const long long pix = (long long)(by * f.b) * G.W + bx * f.b;
-      r.vb0 = lo;
+      const long long pix = (long long)(iby * f.b) * G.W + ibx * f.b;
+      r.vb0 = ilo;
       r.ob0 = G.out_off[0] + pix;
       if (G.nv > 1) {
-        r.vb1 = f.shared ? (long long)f.block_ptr[f.n_items] + (lo - f.block_ptr[f.chroma_first]) : lo;
+        // a shared chroma mask: the Cr run follows every other value
+        r.vb1 = f.shared ? icr + ilo : ilo;
         r.ob1 = G.out_off[1] + pix;
       }
     }

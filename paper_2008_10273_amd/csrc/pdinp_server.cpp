@@ -40,14 +40,15 @@ struct Request {
   int32_t chroma_shared = 0;
   int32_t n_mask_blocks = 0;
   int64_t out_elems = 0;
+  size_t out_elem = 4;  // bytes per output pixel (4, or 1 with out_int8)
   // block_ptr at 0, pos at off_pos, values at off_val of the input buffer
   size_t off_pos = 0, off_val = 0, in_used = 0, in_bytes = 0, out_bytes = 0;
   void *h_in = nullptr;       // pinned staging of the input buffer
-  float *h_out = nullptr;     // pinned staging of the result
-  float *user_out = nullptr;  // host destination (may be null), written by pdi_wait
-  float *user_dev = nullptr;  // caller-owned device destination (may be null)
+  void *h_out = nullptr;      // pinned staging of the result
+  void *user_out = nullptr;   // host destination (may be null), written by pdi_wait
+  void *user_dev = nullptr;   // caller-owned device destination (may be null)
   void *d_in = nullptr;
-  float *d_out = nullptr;     // user_dev or a pooled buffer of out_bytes
+  void *d_out = nullptr;      // user_dev or a pooled buffer of out_bytes
   int lane = -1;
   hipEvent_t done_ev = nullptr;
   Clock::time_point t_submit;
@@ -122,7 +123,7 @@ void *hpool_get(pdi_server *S, size_t bytes) {
   return p;
 }
 
-size_t out_floats_bytes(const Request *r) { return bucket(sizeof(float) * (size_t)r->out_elems); }
+size_t out_floats_bytes(const Request *r) { return bucket(r->out_elem * (size_t)r->out_elems); }
 
 void release_host(pdi_server *S, Request *r) {
   if (r->h_in) S->hpool[r->in_bytes].push_back(r->h_in);
@@ -137,7 +138,7 @@ void release_host(pdi_server *S, Request *r) {
 // copy and a completion event, all asynchronous on the lane's stream.
 int launch_request(pdi_server *S, Request *r) {
   r->d_in = pool_get(S, r->in_bytes);
-  r->d_out = r->user_dev ? r->user_dev : (float *)pool_get(S, r->out_bytes);
+  r->d_out = r->user_dev ? r->user_dev : pool_get(S, r->out_bytes);
   if (!r->d_in || !r->d_out) return PDI_ENOMEM;
   hipStream_t st = S->lanes[r->lane];
   if (hipMemcpyAsync(r->d_in, r->h_in, r->in_used, hipMemcpyHostToDevice, st) != hipSuccess) return PDI_EHIP;
@@ -148,9 +149,9 @@ int launch_request(pdi_server *S, Request *r) {
   mk.n_mask_blocks = r->n_mask_blocks;
   mk.chroma_shared = r->chroma_shared;
   const int rc = decode_residual(S->ctx, &r->frame, &mk, (const float *)(base + r->off_val), r->block_size,
-                                 &r->params, r->d_out, st);
+                                 &r->params, (float *)r->d_out, st);
   if (rc != PDI_OK) return rc;
-  if (r->user_out && hipMemcpyAsync(r->h_out, r->d_out, sizeof(float) * (size_t)r->out_elems,
+  if (r->user_out && hipMemcpyAsync(r->h_out, r->d_out, r->out_elem * (size_t)r->out_elems,
                                     hipMemcpyDeviceToHost, st) != hipSuccess)
     return PDI_EHIP;
   return hipEventRecord(r->done_ev, st) == hipSuccess ? PDI_OK : PDI_EHIP;
@@ -259,7 +260,7 @@ int pdi_server_create(pdi_ctx *ctx, int nlanes, size_t hbm_budget_bytes, int max
 }
 
 int pdi_submit(pdi_server *S, const pdi_frame *frame, const pdi_mask *mask, const float *values,
-               int64_t n_values, int block_size, const pdi_params *params, float *out, float *out_dev,
+               int64_t n_values, int block_size, const pdi_params *params, void *out, void *out_dev,
                int64_t *ticket) {
   if (!S || !frame || !mask || !mask->block_ptr || !values || !ticket || n_values < 0) return PDI_EINVAL;
   int32_t nb = 0;
@@ -289,6 +290,7 @@ int pdi_submit(pdi_server *S, const pdi_frame *frame, const pdi_mask *mask, cons
   r->chroma_shared = mask->chroma_shared;
   r->n_mask_blocks = nb;
   r->out_elems = nel;
+  r->out_elem = P.out_int8 ? 1 : 4;
   r->user_out = out;
   r->user_dev = out_dev;
   r->off_pos = align256(sizeof(int32_t) * (size_t)(nb + 1));
@@ -306,7 +308,7 @@ int pdi_submit(pdi_server *S, const pdi_frame *frame, const pdi_mask *mask, cons
     return PDI_EBUSY;
   }
   r->h_in = hpool_get(S, r->in_bytes);
-  if (out) r->h_out = (float *)hpool_get(S, out_floats_bytes(r));
+  if (out) r->h_out = hpool_get(S, out_floats_bytes(r));
   if (!r->h_in || (out && !r->h_out) || hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess) {
     release_host(S, r);
     delete r;
@@ -347,11 +349,11 @@ int pdi_wait(pdi_server *S, int64_t ticket, double *latency_us) {
   if (latency_us) *latency_us = r->latency_us;
   const int st = r->status;
   S->all.erase(it);
-  float *h_out = r->h_out;
+  void *h_out = r->h_out;
   r->h_out = nullptr;
   lk.unlock();
   if (st == PDI_OK && r->user_out && h_out)
-    std::memcpy(r->user_out, h_out, sizeof(float) * (size_t)r->out_elems);
+    std::memcpy(r->user_out, h_out, r->out_elem * (size_t)r->out_elems);
   lk.lock();
   if (h_out) S->hpool[out_floats_bytes(r)].push_back(h_out);
   lk.unlock();

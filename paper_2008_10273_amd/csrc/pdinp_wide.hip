@@ -433,7 +433,7 @@ __device__ __forceinline__ void wide_eval32(const FrameDev &f, const WideJob &jb
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int y = 16 * yt + 4 * hi + r, x = 16 * xt + lo;
-          if (x < w && y < h) f.out[ob + (long long)y * W + x] = u4[r] + av;
+          if (x < w && y < h) store_px(f, ob + (long long)y * W + x, u4[r] + av);
         }
       }
   }
@@ -543,7 +543,7 @@ __device__ __forceinline__ void wide_eval16(const FrameDev &f, const WideJob &jb
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int y = 16 * yt + 4 * hi + r, x = 16 * xt + lo;
-          if (x < w && y < h) f.out[ob + (long long)y * W + x] = u4[r] + av;
+          if (x < w && y < h) store_px(f, ob + (long long)y * W + x, u4[r] + av);
         }
       }
   }

@@ -33,6 +33,7 @@ def test_default_params():
     p = binding.default_params()
     assert p.op == 0 and p.s == 1.0 and p.eval_dtype == 0 and p.refine == 1
     assert p.path == 0 and abs(p.refine_tau - 1 / 64) < 1e-15
+    assert p.out_int8 == 0
 
 
 @pytest.mark.parametrize("w,h,fmt,b,shared,nb,nel", [

@@ -203,7 +203,7 @@ def test_host_errors(dec):
     d["n_mask_blocks"] = 255
     assert dec.decode(d, check=False) == binding.PDI_EINVAL
     d["n_mask_blocks"] = 256
-    for bad in (dict(eval_dtype=9), dict(s=-1.0), dict(refine=5), dict(path=4)):
+    for bad in (dict(eval_dtype=9), dict(s=-1.0), dict(refine=5), dict(path=4), dict(out_int8=2)):
         assert dec.decode(d, binding.default_params(**bad), check=False) == binding.PDI_EINVAL
     assert dec.decode(d, check=False) == 0
     assert dec.sync() == 0
@@ -260,8 +260,9 @@ def test_eval_dtypes_config2(dec):
 
 
 def test_autotune_keeps_results(dec):
-    """pdi_autotune picks a workgroup grouping for 32x32 blocks; every choice
-    decodes to bitwise the same planes.  Other block sizes have no choices."""
+    """pdi_autotune picks a workgroup grouping; every choice decodes to
+    bitwise the same planes.  The plain path has no choices."""
+    from paper_2008_10273_amd import binding
     fr = synth.random_frame(300, 170, synth.YUV420, 32, (0.02, 0.1), seed=77)
     ref, _ = gpu_decode(dec, fr)
     d = dec.upload(fr)
@@ -269,5 +270,31 @@ def test_autotune_keeps_results(dec):
     assert ch in (1, 2, 4)
     got, _ = gpu_decode(dec, fr)
     np.testing.assert_array_equal(got, ref)
-    d16 = dec.upload(synth.random_frame(100, 60, synth.YUV420, 16, (0.01, 0.1), seed=78))
-    assert dec.autotune(d16) == 0
+    fr16 = synth.random_frame(300, 170, synth.YUV420, 16, (0.01, 0.12), seed=78)
+    ref16, _ = gpu_decode(dec, fr16)
+    assert dec.autotune(dec.upload(fr16)) in (16, 14, 13, 12, 10, 8)
+    got16, _ = gpu_decode(dec, fr16)
+    np.testing.assert_array_equal(got16, ref16)
+    assert dec.autotune(dec.upload(fr16), binding.default_params(path=1)) == 0
+
+
+@pytest.mark.parametrize("case", ["cfg0", "ragged420", "b8", "b32", "edge_counts"])
+@pytest.mark.parametrize("path", [0, 1])
+def test_int8_output(dec, case, path):
+    """out_int8: the planes as clamp(rint(u), -128, 127) with round half to
+    even, exactly the 8-bit rounding of the FP32 result of the same path, and
+    the acceptance bar against the oracle."""
+    from paper_2008_10273_amd import binding
+    fr = {"cfg0": lambda: synth.config_frame(0),
+          "ragged420": lambda: synth.random_frame(70, 37, synth.YUV420, 16, (0.01, 0.12), seed=2606),
+          "b8": lambda: synth.random_frame(100, 67, synth.YUV420, 8, (0.02, 0.3), seed=3),
+          "b32": lambda: synth.random_frame(150, 90, synth.YUV420, 32, (0.02, 0.1), seed=32),
+          "edge_counts": lambda: _custom_frame(77, 55, 16, lambda k, n: [0, 1, n, n - 1, 40][k % 5], seed=9)}[case]()
+    got32, _ = gpu_decode(dec, fr, path=path)
+    d = dec.upload(fr)
+    dec.decode(d, binding.default_params(out_int8=1, path=path))
+    assert dec.sync() == 0
+    got8 = d["out_i8"].cpu().numpy().astype(np.float64)
+    np.testing.assert_array_equal(got8, _q8(got32))
+    ref = oracle.decode_flat(fr)
+    assert float(np.mean(got8 == _q8(ref))) >= 0.999
