@@ -209,6 +209,27 @@ def bench_frame(args, torch, binding, synth):
                      note="8 different frames of this workload in flight on several streams")
         log(f"overlapped on {args.nstreams} streams: {mfps:.1f} frames/s")
 
+    batched = None
+    if extra:
+        ds = [d] + [dec.upload(f) for f in extra]
+        for _ in range(5):
+            dec.decode_batch(ds, params, stream=stream)
+        torch.cuda.synchronize()
+        bsteps = max(10, args.steps // len(ds))
+        tm = StreamTimer(torch, stream)
+        tm.start()
+        for _ in range(bsteps):
+            dec.decode_batch(ds, params, stream=stream)
+        bsecs = tm.stop()
+        assert dec.sync(stream) == 0
+        bfps = len(ds) * bsteps / bsecs
+        ab8 = sum(algorithmic_bytes(x) for x in [fr] + extra)
+        batched = dict(value=bfps, unit="frames/s", frames_per_launch=len(ds), launches=bsteps,
+                       ms_per_launch=1e3 * bsecs / bsteps,
+                       achieved_GBs=ab8 / (bsecs / bsteps) / 1e9,
+                       note="decode_residual_batch: 8 different frames of this workload per launch")
+        log(f"batched ({len(ds)} frames per launch): {bfps:.1f} frames/s")
+
     plain = None
     if not args.no_plain:
         pp = binding.default_params(eval_dtype=EVALS[args.eval], path=binding.PDI_PATH_PLAIN)
@@ -239,7 +260,7 @@ def bench_frame(args, torch, binding, synth):
                        "blocks_per_workgroup": tune or None},
                latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "mean": float(lat.mean())},
-               error_vs_oracle=err, plain_path=plain, overlapped=multi,
+               error_vs_oracle=err, plain_path=plain, overlapped=multi, batched=batched,
                roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC.get(args.config),
                          "kernel": "k_fast" if cfg["block_size"] <= 16 else "k_plain_all + k_general_deferred",

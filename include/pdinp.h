@@ -128,6 +128,18 @@ int decode_residual(pdi_ctx *ctx, const pdi_frame *frame, const pdi_mask *mask,
                     const float *values, int block_size, const pdi_params *params,
                     float *out, void *stream);
 
+/* Decode n (1..PDI_MAX_BATCH) frames of one geometry in one launch of each
+ * kernel: masks[k] (chroma sharing equal for all k), values[k] and outs[k]
+ * describe frame k exactly as for decode_residual (DEVICE pointers, caller
+ * owned); the host arrays masks, values and outs are read during the call
+ * only.  More blocks per launch keep more waves in flight, so a batch is
+ * the throughput form of decode_residual; each frame's result is the same
+ * as when decoded alone.  Errors as for decode_residual. */
+#define PDI_MAX_BATCH 8
+int decode_residual_batch(pdi_ctx *ctx, int n, const pdi_frame *frame, const pdi_mask *masks,
+                          const float *const *values, int block_size, const pdi_params *params,
+                          float *const *outs, void *stream);
+
 /* Wait for `stream`, then read and clear the device status word.
  * Returns PDI_OK, PDI_EMASK, PDI_EVALUE, PDI_ESOLVE or PDI_EHIP. */
 int pdi_sync(pdi_ctx *ctx, void *stream);
@@ -171,12 +183,13 @@ int pdi_validate_host(const pdi_frame *frame, int block_size, const int32_t *blo
                       const uint16_t *pos, int32_t n_mask_blocks, int32_t chroma_shared,
                       const float *values);
 
-/* ---- Frame sequences as one HIP graph (per-frame decode, captured) ----
+/* ---- Frame sequences as one HIP graph (batched decodes, captured) ----
  * The decodes of n frames of ONE geometry (frame, block_size, params, chroma
- * sharing) are recorded once into a HIP graph, frame k on internal stream
- * k % nstreams, the streams forked from and joined back to the first one, so
- * that independent frames overlap on the GPU; pdi_seq_launch replays all n
- * decodes with one graph launch.  masks[k], values[k] and outs[k] are DEVICE
+ * sharing) are recorded once into a HIP graph as decode_residual_batch calls
+ * over consecutive frames (at most PDI_MAX_BATCH per call, about n / nstreams),
+ * batch b on internal stream b % nstreams, the streams forked from and
+ * joined back to the first one, so that independent batches overlap on the
+ * GPU; pdi_seq_launch replays all n decodes with one graph launch.  masks[k], values[k] and outs[k] are DEVICE
  * pointers (caller-owned) read / written by every replay: update their
  * contents between replays, not their addresses.  pdi_seq_create runs one
  * eager decode per internal stream first (allocations and errors happen

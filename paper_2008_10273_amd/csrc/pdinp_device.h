@@ -8,26 +8,28 @@ namespace pdi {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-// Hand a block to the general path: blocks whose bordered system fits in LDS
-// are listed from the front of the deferred list, larger ones from the back.
-__device__ __forceinline__ void push_deferred(const FrameDev &f, int m, int K, int w, int h) {
+// Hand block m of frame fi to the general path: blocks whose bordered system
+// fits in LDS are listed from the front of the deferred list, larger ones from
+// the back.
+__device__ __forceinline__ void push_deferred(const FrameDev &f, int fi, int m, int K, int w, int h) {
+  const int e = (fi << kDeferFrameShift) | m;
   if (K > kLdsKMax && K < w * h) {
     int idx = atomicAdd(&f.counters[1], 1);
-    f.deferred[f.n_items - 1 - idx] = m;
+    f.deferred[f.n_items * f.nframes - 1 - idx] = e;
   } else {
     int idx = atomicAdd(&f.counters[0], 1);
-    f.deferred[idx] = m;
+    f.deferred[idx] = e;
   }
 }
 
 // Store one decoded pixel: FP32, or int8 = clamp(rint(u), -128, 127) with
 // round-half-to-even when the frame asks for 8-bit output.
-__device__ __forceinline__ void store_px(const FrameDev &f, long long idx, float u) {
+__device__ __forceinline__ void store_px(const FrameDev &f, int fi, long long idx, float u) {
   if (f.out_i8) {
     const float q = fminf(fmaxf(__builtin_rintf(u), -128.f), 127.f);
-    reinterpret_cast<int8_t *>(f.out)[idx] = (int8_t)(int)q;
+    reinterpret_cast<int8_t *>(f.fp[fi].out)[idx] = (int8_t)(int)q;
   } else {
-    f.out[idx] = u;
+    f.fp[fi].out[idx] = u;
   }
 }
 

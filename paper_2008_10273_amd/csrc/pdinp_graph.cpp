@@ -1,7 +1,8 @@
 // Graph-captured decode of a frame sequence (pdi_seq_*): the decodes of n
-// frames of one geometry are recorded once into a HIP graph, spread over
-// several streams joined by events so that independent frames overlap on
-// the GPU, and the graph is then replayed with one launch.
+// frames of one geometry are recorded once into a HIP graph, as batched
+// decodes of up to PDI_MAX_BATCH frames spread over several streams joined
+// by events (independent batches overlap on the GPU), and the graph is then
+// replayed with one launch.
 #include "../../include/pdinp.h"
 
 #include <hip/hip_runtime.h>
@@ -51,11 +52,15 @@ int pdi_seq_create(pdi_ctx *ctx, int n, const pdi_frame *frame, const pdi_mask *
     pdi_seq_destroy(q);
     return PDI_EHIP;
   }
-  // Eager decodes first: tables and per-stream workspaces are allocated
-  // outside the capture, and errors surface here.
+  // Batches: consecutive frames, at most PDI_MAX_BATCH, spread evenly.
+  const int per_stream = (n + nstreams - 1) / nstreams;
+  const int bsize = per_stream < PDI_MAX_BATCH ? per_stream : PDI_MAX_BATCH;
+  // Eager decodes of the largest batch on every stream first: tables and
+  // per-stream workspaces are allocated outside the capture, and errors
+  // surface here.
   for (int i = 0; i < nstreams && rc == PDI_OK; ++i) {
-    const int k = i % n;
-    rc = decode_residual(ctx, frame, &masks[k], values[k], block_size, params, outs[k], q->streams[i]);
+    const int cnt = bsize < n ? bsize : n;
+    rc = decode_residual_batch(ctx, cnt, frame, masks, values, block_size, params, outs, q->streams[i]);
     if (rc == PDI_OK) rc = pdi_sync(ctx, q->streams[i]);
   }
   if (rc != PDI_OK) {
@@ -67,9 +72,11 @@ int pdi_seq_create(pdi_ctx *ctx, int n, const pdi_frame *frame, const pdi_mask *
   if (e == hipSuccess) {
     e = hipEventRecord(q->events[0], origin);
     for (int i = 1; i < nstreams && e == hipSuccess; ++i) e = hipStreamWaitEvent(q->streams[i], q->events[0], 0);
-    for (int k = 0; k < n && e == hipSuccess && rc == PDI_OK; ++k)
-      rc = decode_residual(ctx, frame, &masks[k], values[k], block_size, params, outs[k],
-                           q->streams[k % nstreams]);
+    for (int k0 = 0, b = 0; k0 < n && e == hipSuccess && rc == PDI_OK; k0 += bsize, ++b) {
+      const int cnt = n - k0 < bsize ? n - k0 : bsize;
+      rc = decode_residual_batch(ctx, cnt, frame, &masks[k0], &values[k0], block_size, params, &outs[k0],
+                                 q->streams[b % nstreams]);
+    }
     for (int i = 1; i < nstreams && e == hipSuccess; ++i) {
       e = hipEventRecord(q->events[nstreams + i], q->streams[i]);
       if (e == hipSuccess) e = hipStreamWaitEvent(origin, q->events[nstreams + i], 0);

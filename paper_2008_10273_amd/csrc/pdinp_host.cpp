@@ -431,10 +431,14 @@ int pdi_frame_info(const pdi_frame *frame, int block_size, int chroma_shared,
   return PDI_OK;
 }
 
-int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, const float *values,
-                    int block_size, const pdi_params *params, float *out, void *stream) {
+// Decode n frames of one geometry (one launch per kernel for all of them).
+static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask *masks,
+                       const float *const *values, int block_size, const pdi_params *params,
+                       float *const *outs, void *stream) {
   if (!c) return PDI_EINVAL;
-  if (!frame || !mask || !out) return set_err(c, PDI_EINVAL, "null frame, mask or out");
+  if (n < 1 || n > pdi::kMaxBatch) return set_err(c, PDI_EINVAL, "batch of %d frames (1..%d)", n, pdi::kMaxBatch);
+  if (!frame || !masks || !values || !outs) return set_err(c, PDI_EINVAL, "null frame, mask, values or out");
+  const pdi_mask *mask = &masks[0];
   if (check_geometry(frame, block_size))
     return set_err(c, PDI_EINVAL, "bad geometry %dx%d format %d block %d", frame->width,
                    frame->height, frame->format, block_size);
@@ -450,10 +454,16 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
   if (P.out_int8 != 0 && P.out_int8 != 1) return set_err(c, PDI_EINVAL, "bad out_int8");
   int shared = (frame->format == PDI_YUV420 && mask->chroma_shared) ? 1 : 0;
   long long nitems = mask_blocks_of(frame, block_size, shared);
-  if (nitems != mask->n_mask_blocks)
-    return set_err(c, PDI_EINVAL, "n_mask_blocks %d, geometry needs %lld", mask->n_mask_blocks, nitems);
-  if (!mask->block_ptr || (!mask->pos) || !values)
-    return set_err(c, PDI_EINVAL, "null block_ptr, pos or values");
+  if (nitems > pdi::kDeferItemMask) return set_err(c, PDI_EINVAL, "%lld mask blocks (at most %d)", nitems, pdi::kDeferItemMask);
+  for (int k = 0; k < n; ++k) {
+    const pdi_mask &mk = masks[k];
+    const int sh = (frame->format == PDI_YUV420 && mk.chroma_shared) ? 1 : 0;
+    if (sh != shared) return set_err(c, PDI_EINVAL, "frame %d: chroma sharing differs within the batch", k);
+    if (nitems != mk.n_mask_blocks)
+      return set_err(c, PDI_EINVAL, "n_mask_blocks %d, geometry needs %lld", mk.n_mask_blocks, nitems);
+    if (!mk.block_ptr || !mk.pos || !values[k] || !outs[k])
+      return set_err(c, PDI_EINVAL, "frame %d: null block_ptr, pos, values or out", k);
+  }
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   std::lock_guard<std::mutex> lock(c->mu);
@@ -561,13 +571,17 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
     F.nq = nq;
     F.fast_wgs = wgs;
   }
-  rc = ensure_workspace(c, W, (int)nitems, block_size, fast ? F.fast_wgs : 0);
+  rc = ensure_workspace(c, W, (int)nitems * n, block_size, fast ? F.fast_wgs : 0);
   if (rc) return rc;
   F.tab32_floats = ts->tab32_floats;
-  F.block_ptr = mask->block_ptr;
-  F.pos = mask->pos;
-  F.values = values;
-  F.out = out;
+  F.nframes = n;
+  F.tail_in_wg = (n == 1) ? 1 : 0;
+  for (int k = 0; k < n; ++k) {
+    F.fp[k].block_ptr = masks[k].block_ptr;
+    F.fp[k].pos = masks[k].pos;
+    F.fp[k].values = values[k];
+    F.fp[k].out = outs[k];
+  }
   F.tab32 = ts->tab32;
   F.tab64 = ts->tab64;
   F.deferred = W->deferred;
@@ -578,7 +592,10 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
   F.slot_floats = W->slot_floats;
 
   if (fast) {
-    e = pdi::launch_fast(F, s);  // one launch: the workgroups also decode their leftover blocks
+    // A single frame: one launch, the workgroups also decode their leftover
+    // blocks.  A batch: leftover blocks go to the deferred pass.
+    e = pdi::launch_fast(F, s);
+    if (e == hipSuccess && n > 1) e = pdi::launch_general_deferred(F, s);
   } else if (wide) {
     e = pdi::launch_wide(F, s);  // leftover blocks go to the deferred list
     if (e == hipSuccess) e = pdi::launch_general_deferred(F, s);
@@ -588,6 +605,18 @@ int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, co
   }
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   return PDI_OK;
+}
+
+int decode_residual(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, const float *values,
+                    int block_size, const pdi_params *params, float *out, void *stream) {
+  if (c && (!mask || !out)) return set_err(c, PDI_EINVAL, "null frame, mask or out");
+  return decode_impl(c, 1, frame, mask, &values, block_size, params, &out, stream);
+}
+
+int decode_residual_batch(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask *masks,
+                          const float *const *values, int block_size, const pdi_params *params,
+                          float *const *outs, void *stream) {
+  return decode_impl(c, n, frame, masks, values, block_size, params, outs, stream);
 }
 
 int pdi_sync(pdi_ctx *c, void *stream) {

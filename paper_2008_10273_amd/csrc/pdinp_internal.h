@@ -19,9 +19,13 @@ constexpr int kWideKMax = 103;       // largest K of the wave-per-block path
 // bin 0 K >= 84, bin 1 K >= 64, bin 2 K >= 42, bin 3 the rest.
 constexpr int kBinK0 = 84, kBinK1 = 64, kBinK2 = 42;
 // Device counters: [0], [1] deferred-list lengths, [2] finished workgroups of
-// the deferred pass, then per wave-per-block queue q the lengths of its 4
-// bins at [kQueueCounters + 4q + bin].
+// the deferred pass, then per frame fi of the launch and wave-per-block queue
+// q the lengths of its 4 bins at [kQueueCounters + 4 (fi kMaxShapes + q) + bin].
 constexpr int kQueueCounters = 8;
+constexpr int kMaxBatch = 8;  // frames of one geometry per launch (decode_residual_batch)
+// Deferred-list entries hold (frame << kDeferFrameShift) | block.
+constexpr int kDeferFrameShift = 24;
+constexpr int kDeferItemMask = (1 << kDeferFrameShift) - 1;
 // The FP32 table buffer is padded by this many floats so that the wave-level
 // path may read whole 16-byte vectors per thread past the last table.
 constexpr int kTabPadFloats = 6 * 256 * 4;
@@ -51,7 +55,7 @@ struct SegDev {
   int group, shape, bx0, nx, by0, count, first_wg;
 };
 constexpr int kMaxSegs = 4 * kMaxGroups;
-constexpr int kNumCounters = kQueueCounters + 4 * kMaxShapes;
+constexpr int kNumCounters = kQueueCounters + 4 * kMaxShapes * kMaxBatch;
 
 // The blocks of one shape for the wave-per-block path.  binlist[2 base ..
 // 2 base + 2 count) holds them by point count: bin 0 from the front of the
@@ -69,6 +73,14 @@ struct GroupDev {
   int vplane[2];        // value planes (0 = Y, 1 = Cb, 2 = Cr)
   long long out_off[2]; // output offset of each value plane (floats)
   int shape[4];         // shape ids: full, right edge, bottom edge, corner
+};
+
+// Caller buffers of one frame of a launch.
+struct FramePtrs {
+  const int32_t *block_ptr;
+  const uint16_t *pos;
+  const float *values;
+  float *out;  // FP32 planes, or int8 planes when out_i8
 };
 
 struct FrameDev {
@@ -94,15 +106,15 @@ struct FrameDev {
   int fast_wgs;      // workgroups of the batched path (k_fast or k_wide)
   int fast_lds;      // its dynamic LDS (floats): largest table block
   int tab32_floats;  // size of the FP32 table buffer (floats)
-  // buffers
-  const int32_t *block_ptr;
-  const uint16_t *pos;
-  const float *values;
-  float *out;      // FP32 planes, or int8 planes when out_i8
+  // buffers: frame fi of the launch (blockIdx.y in the batched kernels)
+  int nframes;
+  int tail_in_wg;  // k_fast decodes its leftover blocks itself (else: deferred list)
+  FramePtrs fp[kMaxBatch];
   const float *tab32;
   const double *tab64;
-  int *deferred;   // list of mask blocks left to the general path
-  int *binlist;    // wave-per-block queues (2 n_items entries)
+  int *deferred;   // mask blocks left to the general path, as (fi << 24) | m
+                   // (n_items * nframes entries)
+  int *binlist;    // wave-per-block queues (2 n_items entries per frame)
   int *counters;   // kNumCounters device counters (layout above)
   int *status;     // device status word
   float *slots;    // global-memory systems for K > kLdsKMax, one slot per workgroup

@@ -32,7 +32,7 @@ struct Item {
   __device__ __forceinline__ long long obase(int v) const { return v ? obase1 : obase0; }
 };
 
-__device__ __forceinline__ Item load_item(const FrameDev &f, int m) {
+__device__ __forceinline__ Item load_item(const FrameDev &f, const int32_t *bp, int m) {
   Item it;
   int g = 0;
   if (f.ngroups > 1 && m >= f.g[1].first) g = 1;
@@ -47,7 +47,7 @@ __device__ __forceinline__ Item load_item(const FrameDev &f, int m) {
   it.h = min(b, G.H - it.y0);
   int e = ((bx == G.nbx - 1) && (G.W % b) ? 1 : 0) + ((by == G.nby - 1) && (G.H % b) ? 2 : 0);
   it.shape = G.shape[e];
-  int lo = f.block_ptr[m], hi = f.block_ptr[m + 1];
+  int lo = bp[m], hi = bp[m + 1];
   it.K = hi - lo;
   it.base = lo;
   it.nv = G.nv;
@@ -57,7 +57,7 @@ __device__ __forceinline__ Item load_item(const FrameDev &f, int m) {
   it.obase0 = G.out_off[0] + pix;
   if (G.nv > 1) {
     // a shared chroma mask: the Cr run follows every other value
-    it.vbase1 = f.shared ? (long long)f.block_ptr[f.n_items] + (lo - f.block_ptr[f.chroma_first]) : lo;
+    it.vbase1 = f.shared ? (long long)bp[f.n_items] + (lo - bp[f.chroma_first]) : lo;
     it.obase1 = G.out_off[1] + pix;
   } else {
     it.vbase1 = it.vbase0;
@@ -117,9 +117,13 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 // Decode one block with a whole workgroup.  M points at LDS (K <= kLdsKMax)
 // or at a global slot (ld = row stride).
 template <int B>
-__device__ void general_block(const FrameDev &f, int m, GenScratch<B> &sh, float *M) {
+__device__ void general_block(const FrameDev &f, int fi, int m, GenScratch<B> &sh, float *M) {
   const int tid = threadIdx.x;
-  const Item it = load_item(f, m);
+  fi = __builtin_amdgcn_readfirstlane(fi);
+  const FramePtrs fp = f.fp[fi];
+  const Item it = load_item(f, fp.block_ptr, m);
+  const uint16_t *pos = fp.pos;
+  const float *values = fp.values;
   const int K = it.K, w = it.w, h = it.h, N = w * h;
   const ShapeDev S = f.s[it.shape];
 
@@ -128,42 +132,42 @@ __device__ void general_block(const FrameDev &f, int m, GenScratch<B> &sh, float
   if (K < 0 || K > N) {
     if (tid == 0) atomicOr(f.status, kStatusMask);
     for (int v = 0; v < it.nv; ++v)
-      for (int p = tid; p < N; p += kGenThreads) store_px(f, it.obase(v) + (p / w) * it.W + p % w, 0.f);
+      for (int p = tid; p < N; p += kGenThreads) store_px(f, fi, it.obase(v) + (p / w) * it.W + p % w, 0.f);
     return;
   }
   if (f.validate) {
     int bad = 0;
     for (int i = tid; i < K; i += kGenThreads) {
-      int p = f.pos[it.base + i];
-      if (p >= N || (i > 0 && f.pos[it.base + i - 1] >= p)) bad |= kStatusMask;
+      int p = pos[it.base + i];
+      if (p >= N || (i > 0 && pos[it.base + i - 1] >= p)) bad |= kStatusMask;
       for (int v = 0; v < it.nv; ++v)
-        if (!isfinite(f.values[it.vbase(v) + i])) bad |= kStatusValue;
+        if (!isfinite(values[it.vbase(v) + i])) bad |= kStatusValue;
     }
     if (bad) { atomicOr(f.status, bad); atomicOr(&sh.flag, 1); }
     __syncthreads();
     if (sh.flag) {
       for (int v = 0; v < it.nv; ++v)
-        for (int p = tid; p < N; p += kGenThreads) store_px(f, it.obase(v) + (p / w) * it.W + p % w, 0.f);
+        for (int p = tid; p < N; p += kGenThreads) store_px(f, fi, it.obase(v) + (p / w) * it.W + p % w, 0.f);
       return;
     }
   }
   if (K == 0) {
     for (int v = 0; v < it.nv; ++v)
-      for (int p = tid; p < N; p += kGenThreads) store_px(f, it.obase(v) + (p / w) * it.W + p % w, 0.f);
+      for (int p = tid; p < N; p += kGenThreads) store_px(f, fi, it.obase(v) + (p / w) * it.W + p % w, 0.f);
     return;
   }
   if (K == N) {  // every pixel known: u = r (the system is singular here)
     for (int v = 0; v < it.nv; ++v)
       for (int i = tid; i < K; i += kGenThreads) {
-        int p = min((int)f.pos[it.base + i], N - 1);
-        store_px(f, it.obase(v) + (p / w) * it.W + p % w, f.values[it.vbase(v) + i]);
+        int p = min((int)pos[it.base + i], N - 1);
+        store_px(f, fi, it.obase(v) + (p / w) * it.W + p % w, values[it.vbase(v) + i]);
       }
     return;
   }
 
   for (int i = tid; i < (w + 1) * (h + 1); i += kGenThreads) sh.tab[i] = f.tab32[S.hc32 + i];
   for (int i = tid; i < K; i += kGenThreads) {
-    int p = min((int)f.pos[it.base + i], N - 1);
+    int p = min((int)pos[it.base + i], N - 1);
     sh.px[i] = (short)(p % w);
     sh.py[i] = (short)(p / w);
   }
@@ -177,7 +181,7 @@ __device__ void general_block(const FrameDev &f, int m, GenScratch<B> &sh, float
       float v;
       if (k < K) v = (i < K) ? green_tab(sh.tab, w, h, sh.px[i], sh.py[i], sh.px[k], sh.py[k]) : 1.f;
       else if (k == K) v = (i < K) ? 1.f : 0.f;
-      else v = (i < K) ? f.values[it.vbase(k - n) + i] : 0.f;
+      else v = (i < K) ? values[it.vbase(k - n) + i] : 0.f;
       M[(long long)i * ld + k] = v;
     }
 
@@ -219,7 +223,7 @@ __device__ void general_block(const FrameDev &f, int m, GenScratch<B> &sh, float
   __syncthreads();
   dmin = fminf(fminf(sh.redf[0][0], sh.redf[0][1]), fminf(sh.redf[0][2], sh.redf[0][3]));
   dmax = fmaxf(fmaxf(sh.redf[1][0], sh.redf[1][1]), fmaxf(sh.redf[1][2], sh.redf[1][3]));
-  float a_v[2] = {sh.rho[0], it.nv > 1 ? sh.rho[1] : 0.f};
+  float a0 = sh.rho[0], a1 = it.nv > 1 ? sh.rho[1] : 0.f;  // a of each value set
   const bool refine = (f.refine == 2) || (f.refine == 1 && !(dmin >= f.tau * dmax));
 
   if (refine) {
@@ -236,8 +240,8 @@ __device__ void general_block(const FrameDev &f, int m, GenScratch<B> &sh, float
         for (int k = 0; k < K; ++k)
           acc += green_tab(tab64, w, h, (int)sh.px[i], (int)sh.py[i], (int)sh.px[k], (int)sh.py[k]) *
                  (double)sh.c[v][k];
-        double r = (double)f.values[it.vbase(v) + i];
-        sh.rho[i] = (float)(r - (double)a_v[v] - acc);
+        double r = (double)values[it.vbase(v) + i];
+        sh.rho[i] = (float)(r - (double)(v ? a1 : a0) - acc);
       }
       if (tid == 0) sh.rho[K] = (float)(-cs);
       // Replay the elimination on rho, then divide by the pivots.
@@ -250,7 +254,8 @@ __device__ void general_block(const FrameDev &f, int m, GenScratch<B> &sh, float
       }
       __syncthreads();
       for (int i = tid; i < K; i += kGenThreads) sh.c[v][i] += sh.rho[i] / M[(long long)i * ld + i];
-      a_v[v] += sh.rho[K] / M[(long long)K * ld + K];
+      const float da = sh.rho[K] / M[(long long)K * ld + K];
+      if (v) a1 += da; else a0 += da;
     }
     __syncthreads();
   }
@@ -265,13 +270,13 @@ __device__ void general_block(const FrameDev &f, int m, GenScratch<B> &sh, float
       acc0 = fmaf(sh.c[0][i], g, acc0);
       if (it.nv > 1) acc1 = fmaf(sh.c[1][i], g, acc1);
     }
-    float u0 = acc0 + a_v[0];
+    float u0 = acc0 + a0;
     bad |= !isfinite(u0);
-    store_px(f, it.obase0 + (long long)yy * it.W + xx, u0);
+    store_px(f, fi, it.obase0 + (long long)yy * it.W + xx, u0);
     if (it.nv > 1) {
-      float u1 = acc1 + a_v[1];
+      float u1 = acc1 + a1;
       bad |= !isfinite(u1);
-      store_px(f, it.obase1 + (long long)yy * it.W + xx, u1);
+      store_px(f, fi, it.obase1 + (long long)yy * it.W + xx, u1);
     }
   }
   if (bad) atomicOr(f.status, kStatusSolve);
@@ -281,14 +286,14 @@ __device__ void general_block(const FrameDev &f, int m, GenScratch<B> &sh, float
 // system does not fit in LDS go to the large list.
 __global__ __launch_bounds__(kGenThreads) void k_plain_all(FrameDev f) {
   __shared__ GenShared sh;
-  const int m = blockIdx.x;
+  const int m = blockIdx.x, fi = blockIdx.y;
   if (m >= f.n_items) return;
-  const Item it = load_item(f, m);
+  const Item it = load_item(f, f.fp[fi].block_ptr, m);
   if (it.K > kLdsKMax && it.K < it.w * it.h) {
-    if (threadIdx.x == 0) push_deferred(f, m, it.K, it.w, it.h);
+    if (threadIdx.x == 0) push_deferred(f, fi, m, it.K, it.w, it.h);
     return;
   }
-  general_block<32>(f, m, sh.g, sh.M);
+  general_block<32>(f, fi, m, sh.g, sh.M);
 }
 
 // Persistent pass over the deferred lists; the last workgroup clears the
@@ -297,15 +302,18 @@ __global__ __launch_bounds__(kGenThreads) void k_general_deferred(FrameDev f) {
   __shared__ GenShared sh;
   const int nmed = f.counters[0];
   const int nlarge = f.counters[1];
+  const int cap = f.n_items * f.nframes;
   for (int idx = blockIdx.x; idx < nmed; idx += gridDim.x) {
     __syncthreads();
-    general_block<32>(f, f.deferred[idx], sh.g, sh.M);
+    const int e = f.deferred[idx];
+    general_block<32>(f, e >> kDeferFrameShift, e & kDeferItemMask, sh.g, sh.M);
   }
   if (blockIdx.x < kDeferredGrid) {
     float *slot = f.slots + (long long)blockIdx.x * f.slot_floats;
     for (int idx = blockIdx.x; idx < nlarge; idx += kDeferredGrid) {
       __syncthreads();
-      general_block<32>(f, f.deferred[f.n_items - 1 - idx], sh.g, slot);
+      const int e = f.deferred[cap - 1 - idx];
+      general_block<32>(f, e >> kDeferFrameShift, e & kDeferItemMask, sh.g, slot);
     }
   }
   // Every workgroup has read both counts before it gets here; the last one
@@ -418,15 +426,16 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *it
     T[s][0] = T[s][1] = 0.f;
     if (i < K) {
       const int base = items[slot].base;
-      int p = f.pos[base + i];
+      int p = f.fp[blockIdx.y].pos[base + i];
       if (f.validate) {
-        if (p >= N || (i > 0 && (int)f.pos[base + i - 1] >= p)) bad |= kStatusMask;
+        if (p >= N || (i > 0 && (int)f.fp[blockIdx.y].pos[base + i - 1] >= p)) bad |= kStatusMask;
       }
       p = min(p, N - 1);
       xr[s] = p % w;
       yr[s] = p / w;
-      T[s][0] = f.values[items[slot].vb0 + i];
-      if (items[slot].nv > 1) T[s][1] = f.values[items[slot].vb1 + i];
+      const float *vals = f.fp[blockIdx.y].values;
+      T[s][0] = vals[items[slot].vb0 + i];
+      if (items[slot].nv > 1) T[s][1] = vals[items[slot].vb1 + i];
       if (f.validate && !(isfinite(T[s][0]) && isfinite(T[s][1]))) bad |= kStatusValue;
     }
   }
@@ -622,7 +631,7 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int y = 4 * hi + j, x = lo;
-        if (x < w && y < h) store_px(f, o + (long long)y * W + x, U[g][j] + a);
+        if (x < w && y < h) store_px(f, blockIdx.y, o + (long long)y * W + x, U[g][j] + a);
       }
     }
   }
@@ -705,7 +714,7 @@ __device__ __forceinline__ void fast_eval16(const FrameDev &f, const float *D, c
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int y = 4 * hi + j, x = lo;
-        if (x < w && y < h) store_px(f, o + (long long)y * W + x, U[j] + av);
+        if (x < w && y < h) store_px(f, blockIdx.y, o + (long long)y * W + x, U[j] + av);
       }
     }
   }
@@ -751,9 +760,10 @@ void k_fast(FrameDev f) {
     ibx = sg.bx0 + kk % sg.nx;
     iby = sg.by0 + kk / sg.nx;
     im = G.first + iby * G.nbx + ibx;
-    ilo = f.block_ptr[im];
-    ihi = f.block_ptr[im + 1];
-    if (G.nv > 1 && f.shared) icr = (long long)f.block_ptr[f.n_items] - f.block_ptr[f.chroma_first];
+    const int32_t *bp = f.fp[blockIdx.y].block_ptr;
+    ilo = bp[im];
+    ihi = bp[im + 1];
+    if (G.nv > 1 && f.shared) icr = (long long)bp[f.n_items] - bp[f.chroma_first];
   }
   {
     const int n4 = (S.jt_floats + 768) >> 2;
@@ -791,7 +801,10 @@ void k_fast(FrameDev f) {
       }
     }
     items[tid] = r;
-    defer[tid] = (r.cls == 3) ? 1 : 0;
+    // Blocks the waves do not take: decoded by this workgroup at its end
+    // (single-frame launches) or handed to the deferred pass (batches).
+    defer[tid] = (r.cls == 3 && f.tail_in_wg) ? 1 : 0;
+    if (r.cls == 3 && !f.tail_in_wg) push_deferred(f, blockIdx.y, r.m, r.K, w, h);
   }
   __syncthreads();
   // Bin by size class so that every wave solves blocks of one class.
@@ -823,7 +836,10 @@ void k_fast(FrameDev f) {
     if (Kw <= 15) solved = fast_solve<16>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
     else if (Kw <= 23) solved = fast_solve<24>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
     else solved = fast_solve<32>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
-    if (ok && !solved && t == 0) defer[slot] = 1;
+    if (ok && !solved && t == 0) {
+      if (f.tail_in_wg) defer[slot] = 1;
+      else push_deferred(f, blockIdx.y, items[slot].m, items[slot].K, w, h);
+    }
     const bool eval = ok && solved;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -846,12 +862,13 @@ void k_fast(FrameDev f) {
   // or whose pivots asked for FP64 refinement: the whole workgroup runs the
   // general algorithm on them, one at a time, with the bordered system in
   // this workgroup's global slot.
+  if (!f.tail_in_wg) return;
   __syncthreads();
   float *slot_mem = f.slots + (long long)blockIdx.x * f.slot_floats;
   for (int j = 0; j < kFastItems; ++j) {
     if (defer[j]) {
       __syncthreads();
-      general_block<16>(f, items[j].m, gs, slot_mem);
+      general_block<16>(f, 0, items[j].m, gs, slot_mem);
     }
   }
 }
@@ -861,13 +878,13 @@ void k_fast(FrameDev f) {
 hipError_t launch_fast(const FrameDev &f, hipStream_t stream) {
   if (f.fast_wgs == 0) return hipSuccess;
   const size_t lds = sizeof(float) * (size_t)f.fast_lds;
-  hipLaunchKernelGGL(k_fast, dim3(f.fast_wgs), dim3(kFastThreads), lds, stream, f);
+  hipLaunchKernelGGL(k_fast, dim3(f.fast_wgs, f.nframes), dim3(kFastThreads), lds, stream, f);
   return hipGetLastError();
 }
 
 hipError_t launch_plain_all(const FrameDev &f, hipStream_t stream) {
   if (f.n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plain_all, dim3(f.n_items), dim3(kGenThreads), 0, stream, f);
+  hipLaunchKernelGGL(k_plain_all, dim3(f.n_items, f.nframes), dim3(kGenThreads), 0, stream, f);
   return hipGetLastError();
 }
 

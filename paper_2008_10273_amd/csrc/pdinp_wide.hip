@@ -101,14 +101,16 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
     xr[s] = yr[s] = ywr[s] = 0;
     T[s][0] = T[s][1] = 0.f;
     if (i < K) {
-      int p = f.pos[jb.base + i];
-      if (f.validate && (p >= N || (i > 0 && (int)f.pos[jb.base + i - 1] >= p))) bad |= kStatusMask;
+      const uint16_t *pos = f.fp[blockIdx.y].pos;
+      int p = pos[jb.base + i];
+      if (f.validate && (p >= N || (i > 0 && (int)pos[jb.base + i - 1] >= p))) bad |= kStatusMask;
       p = min(p, N - 1);
       xr[s] = p % w;
       yr[s] = p / w;
       ywr[s] = yr[s] * W1;
-      T[s][0] = f.values[jb.vb0 + i];
-      if (jb.nv > 1) T[s][1] = f.values[jb.vb1 + i];
+      const float *vals = f.fp[blockIdx.y].values;
+      T[s][0] = vals[jb.vb0 + i];
+      if (jb.nv > 1) T[s][1] = vals[jb.vb1 + i];
       if (f.validate && !(isfinite(T[s][0]) && isfinite(T[s][1]))) bad |= kStatusValue;
     }
     if (i < kWideCap2) st.xy[i] = (i < K) ? (xr[s] | (ywr[s] << 16)) : 0;
@@ -433,7 +435,7 @@ __device__ __forceinline__ void wide_eval32(const FrameDev &f, const WideJob &jb
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int y = 16 * yt + 4 * hi + r, x = 16 * xt + lo;
-          if (x < w && y < h) store_px(f, ob + (long long)y * W + x, u4[r] + av);
+          if (x < w && y < h) store_px(f, blockIdx.y, ob + (long long)y * W + x, u4[r] + av);
         }
       }
   }
@@ -543,7 +545,7 @@ __device__ __forceinline__ void wide_eval16(const FrameDev &f, const WideJob &jb
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int y = 16 * yt + 4 * hi + r, x = 16 * xt + lo;
-          if (x < w && y < h) store_px(f, ob + (long long)y * W + x, u4[r] + av);
+          if (x < w && y < h) store_px(f, blockIdx.y, ob + (long long)y * W + x, u4[r] + av);
         }
       }
   }
@@ -554,7 +556,10 @@ __device__ __forceinline__ void wide_eval16(const FrameDev &f, const WideJob &jb
 // path does not take (K = 0, K = w*h, K > 103, invalid counts) go to the
 // general path's lists.
 __global__ __launch_bounds__(256) void k_bin(FrameDev f) {
-  const int m = blockIdx.x * 256 + threadIdx.x;
+  const int m = blockIdx.x * 256 + threadIdx.x, fi = blockIdx.y;
+  const int32_t *bp = f.fp[fi].block_ptr;
+  int *cnt = f.counters + kQueueCounters + 4 * kMaxShapes * fi;
+  int *list = f.binlist + 2 * f.n_items * fi;
   int key = -1;  // 4 * queue + bin, or -1: not queued
   if (m < f.n_items) {
   int g = 0;
@@ -565,8 +570,8 @@ __global__ __launch_bounds__(256) void k_bin(FrameDev f) {
   const int e = ((bx == G.nbx - 1) && (G.W % f.b) ? 1 : 0) + ((by == G.nby - 1) && (G.H % f.b) ? 2 : 0);
   const int shape = G.shape[e];
   const int w = f.s[shape].w, h = f.s[shape].h;
-  const int K = f.block_ptr[m + 1] - f.block_ptr[m];
-  if (K < 1 || K >= w * h || K > kWideKMax) push_deferred(f, m, K, w, h);
+  const int K = bp[m + 1] - bp[m];
+  if (K < 1 || K >= w * h || K > kWideKMax) push_deferred(f, fi, m, K, w, h);
   else key = 4 * f.qof[shape] + (K >= kBinK0 ? 0 : K >= kBinK1 ? 1 : K >= kBinK2 ? 2 : 3);
   }
   // One atomic per distinct queue and bin in the wave: the lanes of a key
@@ -579,13 +584,13 @@ __global__ __launch_bounds__(256) void k_bin(FrameDev f) {
     todo &= ~mine;
     const int rank = __popcll(mine & ((1ull << (threadIdx.x & 63)) - 1ull));
     int base = 0;
-    if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(&f.counters[kQueueCounters + k], __popcll(mine));
+    if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(&cnt[k], __popcll(mine));
     base = __shfl(base, leader);
     if (key == k) {
       const QueueDev &Q = f.q[k >> 2];
       const int bin = k & 3, idx = base + rank;
       const int half = 2 * Q.base + (bin >> 1) * Q.count;  // bins 0, 1 | bins 2, 3
-      if (idx < Q.count) f.binlist[half + ((bin & 1) ? Q.count - 1 - idx : idx)] = m;
+      if (idx < Q.count) list[half + ((bin & 1) ? Q.count - 1 - idx : idx)] = m;
       else atomicOr(f.status, kStatusSolve);  // counters were not cleared by the previous decode
     }
   }
@@ -616,10 +621,12 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2
   // Queue position of this wave's block: workgroups start in index order, so
   // the first ones take the large-K blocks at the front of the queue.
   const int p = (wg - Q.first_wg) * WAVES + wv;
-  const int *cnt = f.counters + kQueueCounters + 4 * qi;
+  const int fi = blockIdx.y;
+  const int32_t *bp = f.fp[fi].block_ptr;
+  const int *cnt = f.counters + kQueueCounters + 4 * (kMaxShapes * fi + qi);
   const int n0 = cnt[0], n1 = cnt[1], n2 = cnt[2], n3 = cnt[3];
   if (p >= Q.count || n0 + n1 > Q.count || n2 + n3 > Q.count) return;
-  const int *h0 = f.binlist + 2 * Q.base, *h1 = h0 + Q.count;
+  const int *h0 = f.binlist + 2 * f.n_items * fi + 2 * Q.base, *h1 = h0 + Q.count;
   int m;
   if (p < n0) m = h0[p];
   else if (p < n0 + n1) m = h0[Q.count - 1 - (p - n0)];
@@ -633,7 +640,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2
   if (f.ngroups > 2 && m >= f.g[2].first) gi = 2;
   const GroupDev &G = f.g[gi];
   const int bl = m - G.first, bx = bl % G.nbx, by = bl / G.nbx;
-  const int lo = f.block_ptr[m], hi = f.block_ptr[m + 1];
+  const int lo = bp[m], hi = bp[m + 1];
   WideJob jb;
   jb.K = hi - lo;
   jb.base = lo;
@@ -644,14 +651,14 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2
   jb.vb1 = jb.vb0;
   jb.ob1 = jb.ob0;
   if (G.nv > 1) {
-    jb.vb1 = f.shared ? (long long)f.block_ptr[f.n_items] + (lo - f.block_ptr[f.chroma_first]) : lo;
+    jb.vb1 = f.shared ? (long long)bp[f.n_items] + (lo - bp[f.chroma_first]) : lo;
     jb.ob1 = G.out_off[1] + pix;
   }
   const int K = jb.K;  // 1 <= K <= min(w*h - 1, kWideKMax): binned
   WideStage &st = stage[wv];
   const bool solved = wide_solve(f, jb, lane, w, h, tabs, st);
   if (!solved) {
-    if (lane == 0) push_deferred(f, m, K, w, h);
+    if (lane == 0) push_deferred(f, fi, m, K, w, h);
     return;
   }
   const float *D = tabs + S.jt_floats;
@@ -665,12 +672,12 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2
 
 hipError_t launch_wide(const FrameDev &f, hipStream_t stream) {
   if (f.n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bin, dim3((f.n_items + 255) / 256), dim3(256), 0, stream, f);
+  hipLaunchKernelGGL(k_bin, dim3((f.n_items + 255) / 256, f.nframes), dim3(256), 0, stream, f);
   const size_t lds = sizeof(float) * (size_t)f.fast_lds;
   switch (f.ipw) {
-    case 1: hipLaunchKernelGGL(k_wide<1>, dim3(f.fast_wgs), dim3(64), lds, stream, f); break;
-    case 2: hipLaunchKernelGGL(k_wide<2>, dim3(f.fast_wgs), dim3(128), lds, stream, f); break;
-    case 4: hipLaunchKernelGGL(k_wide<4>, dim3(f.fast_wgs), dim3(256), lds, stream, f); break;
+    case 1: hipLaunchKernelGGL(k_wide<1>, dim3(f.fast_wgs, f.nframes), dim3(64), lds, stream, f); break;
+    case 2: hipLaunchKernelGGL(k_wide<2>, dim3(f.fast_wgs, f.nframes), dim3(128), lds, stream, f); break;
+    case 4: hipLaunchKernelGGL(k_wide<4>, dim3(f.fast_wgs, f.nframes), dim3(256), lds, stream, f); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

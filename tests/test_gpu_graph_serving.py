@@ -158,3 +158,44 @@ def test_serving_budget_admission_and_busy(dec):
     rc, _, _ = srv.submit(bad, binding.default_params(validate=1))
     assert rc == binding.PDI_EMASK
     srv.close()
+
+
+@pytest.mark.parametrize("b,path,i8", [(16, 0, 0), (32, 0, 0), (8, 0, 0), (16, 1, 0), (32, 1, 0), (16, 0, 1)])
+def test_batch_equals_single(dec, b, path, i8):
+    """decode_residual_batch over 1..8 frames equals decoding each frame alone,
+    bitwise, including blocks left to the general path (K = 0, K = w*h,
+    large K) in every frame of the batch."""
+    from paper_2008_10273_amd import binding
+    print(f"case batch b={b} path={path} int8={i8}", flush=True)
+    params = binding.default_params(path=path, out_int8=i8)
+    frames = [synth.random_frame(260, 150, synth.YUV420, b, (0.01, 0.12), seed=600 + k) for k in range(7)]
+    # a frame with degenerate and large point counts
+    W, H = 260, 150
+    rng = np.random.default_rng(5)
+    ms, fs = [], []
+    for (pw, ph) in synth.plane_dims(W, H, synth.YUV420)[:2]:
+        m = rng.uniform(size=(ph, pw)) < 0.08
+        m[:b, :b] = False                      # K = 0
+        m[:b, b:2 * b] = True                  # K = w*h
+        m[b:2 * b, :b] = rng.uniform(size=(b, b)) < 0.6   # large K
+        ms.append(m)
+        fs.append(rng.uniform(-64, 64, (ph, pw)))
+    fs.append(rng.uniform(-64, 64, fs[1].shape))
+    frames.append(synth.pack_dense(W, H, synth.YUV420, b, ms, fs))
+    key = "out_i8" if i8 else "out"
+    alone = []
+    for fr in frames:
+        d = dec.upload(fr)
+        dec.decode(d, params)
+        assert dec.sync() == 0
+        alone.append(d[key].cpu().numpy())
+    for n in (1, 3, 8):
+        ds = [dec.upload(fr) for fr in frames[-n:]]
+        for d in ds:
+            d[key].zero_()
+        dec.decode_batch(ds, params)
+        assert dec.sync() == 0
+        for d, ref in zip(ds, alone[-n:]):
+            np.testing.assert_array_equal(d[key].cpu().numpy(), ref)
+    ds = [dec.upload(frames[0]) for _ in range(9)]
+    assert dec.decode_batch(ds, params, check=False) == binding.PDI_EINVAL
