@@ -2,13 +2,15 @@
 """Residual-decode benchmark on one MI355X.
 
 Workloads (synthetic, seeded; the recipe is in paper_2008_10273_amd/synth.py):
-  --config 1 (default): one 1920x1080 4:2:0 residual frame, 16x16 blocks,
+  --config 1 (default): 1920x1080 4:2:0 residual frames, 16x16 blocks,
       per-block mask density U[1%, 10%] (3-26 points per full block), values
       = smooth sum of 4 random sinusoids + N(0, 2) noise, clipped to
-      [-64, 64].  One step = one decode_residual call over that frame: every
-      block assembled, solved and evaluated on the GPU, inputs resident in HBM.
-  --config 0 / 2: the 256x256 grey case / the same 1080p frame with 32x32
-      blocks and density U[2%, 10%].
+      [-64, 64].  One step = one decode_residual_batch call over --batch (8)
+      different frames: every block assembled, solved and evaluated on the
+      GPU, inputs resident in HBM.  Single-frame throughput and latency are
+      reported beside it.
+  --config 0 / 2: the 256x256 grey case / 1080p frames with 32x32 blocks and
+      density U[2%, 10%].
   --config 3: 64 consecutive 1080p frames decoded as one HIP-graph replay
       (pdi_seq, frames spread over --nstreams streams); one step = one replay.
   --config 4: serving mix, 16 client streams (6x 854x480, 6x 1280x720,
@@ -37,9 +39,9 @@ HBM_PEAK_GBS = 8000.0
 EVALS = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16x2": 3}
 # HBM bytes per launch of the decode kernel from rocprofv3 FETCH_SIZE +
 # WRITE_SIZE counters, scaled by the same counters read on a copy kernel of
-# known size (profiles/k_fast_fhd420_b16_hbm_counters.txt); only for the
-# kernel build the counters were taken on (null after a kernel change).
-TRAFFIC = {}
+# known size (profiles/*_hbm_counters.txt); only for the kernel build the
+# counters were taken on (null after a kernel change).
+TRAFFIC = {(1, 8): 112142541, (2, 8): 114913690}  # (config, frames per step): bytes per launch
 
 
 def algorithmic_bytes(fr) -> int:
@@ -185,50 +187,55 @@ def overlapped(torch, dec, ds, params, nstreams, steps):
 
 
 def bench_frame(args, torch, binding, synth):
-    fr = generate([("cfg", args.config, 0)], 1)[0]
-    extra = generate([("cfg", args.config, k) for k in range(1, 8)], args.workers) if args.config != 0 else []
+    """One step = one decode_residual_batch call over `--batch` different
+    frames of the workload (decode_residual for --batch 1)."""
+    B = args.batch
+    frames = generate([("cfg", args.config, k) for k in range(B)], args.workers if B > 1 else 1)
+    fr = frames[0]
     cfg = synth.CONFIGS[args.config]
     dec = binding.Decoder(0)
-    d = dec.upload(fr)
+    ds = [dec.upload(f) for f in frames]
+    d = ds[0]
     stream = torch.cuda.Stream()
     params = binding.default_params(eval_dtype=EVALS[args.eval])
     tune = dec.autotune(d, params, stream=stream)  # launch choice for this geometry (0: none to make)
-    log(f"config {args.config} ({cfg['name']}), eval {args.eval}, {args.steps} steps, autotune choice {tune}")
-    secs, wall = time_decodes(torch, dec, d, params, stream, args.steps, args.warmup)
+    log(f"config {args.config} ({cfg['name']}), eval {args.eval}, {B} frames per step, {args.steps} steps, "
+        f"autotune choice {tune}")
+
+    def step():
+        if B == 1:
+            dec.decode(d, params, stream=stream)
+        else:
+            dec.decode_batch(ds, params, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    tm = StreamTimer(torch, stream)
+    t0 = time.perf_counter()
+    tm.start()
+    for _ in range(args.steps):
+        step()
+    secs = tm.stop()
+    wall = time.perf_counter() - t0
     assert dec.sync(stream) == 0, binding.pdi_last_error(dec.ctx)
-    fps = args.steps / secs
-    lat = latencies(torch, dec, d, params, stream, args.latency_iters)
+    fps = B * args.steps / secs
     got = d["out"].cpu().numpy().astype(np.float64)
-    log(f"decode: {fps:.1f} frames/s, {1e3 * secs / args.steps:.4f} ms/frame")
+    log(f"decode: {fps:.1f} frames/s, {1e3 * secs / args.steps:.4f} ms per step of {B} frames")
+
+    # single frames: throughput and latency of one frame decoded alone
+    s_secs, _ = time_decodes(torch, dec, d, params, stream, args.steps, max(5, args.warmup // 4))
+    lat = latencies(torch, dec, d, params, stream, args.latency_iters)
+    single = dict(value=args.steps / s_secs, unit="frames/s", ms_per_frame=1e3 * s_secs / args.steps)
+    log(f"single frame: {single['value']:.1f} frames/s, p50 {np.percentile(lat, 50):.4f} ms, "
+        f"p99 {np.percentile(lat, 99):.4f} ms")
 
     multi = None
-    if extra:
-        ds = [d] + [dec.upload(f) for f in extra]
+    if len(ds) > 1:
         mfps = overlapped(torch, dec, ds, params, args.nstreams, args.steps)
         multi = dict(value=mfps, unit="frames/s", streams=args.nstreams, frames=len(ds),
-                     note="8 different frames of this workload in flight on several streams")
+                     note="single-frame decodes of these frames in flight on several streams")
         log(f"overlapped on {args.nstreams} streams: {mfps:.1f} frames/s")
-
-    batched = None
-    if extra:
-        ds = [d] + [dec.upload(f) for f in extra]
-        for _ in range(5):
-            dec.decode_batch(ds, params, stream=stream)
-        torch.cuda.synchronize()
-        bsteps = max(10, args.steps // len(ds))
-        tm = StreamTimer(torch, stream)
-        tm.start()
-        for _ in range(bsteps):
-            dec.decode_batch(ds, params, stream=stream)
-        bsecs = tm.stop()
-        assert dec.sync(stream) == 0
-        bfps = len(ds) * bsteps / bsecs
-        ab8 = sum(algorithmic_bytes(x) for x in [fr] + extra)
-        batched = dict(value=bfps, unit="frames/s", frames_per_launch=len(ds), launches=bsteps,
-                       ms_per_launch=1e3 * bsecs / bsteps,
-                       achieved_GBs=ab8 / (bsecs / bsteps) / 1e9,
-                       note="decode_residual_batch: 8 different frames of this workload per launch")
-        log(f"batched ({len(ds)} frames per launch): {bfps:.1f} frames/s")
 
     plain = None
     if not args.no_plain:
@@ -236,7 +243,7 @@ def bench_frame(args, torch, binding, synth):
         psteps = max(10, args.steps // 10)
         ps, _ = time_decodes(torch, dec, d, pp, stream, psteps, 5)
         plain = dict(value=psteps / ps, unit="frames/s", ms_per_step=1e3 * ps / psteps,
-                     path="one workgroup per block, FP32 LDS Gauss-Jordan, direct VALU evaluation")
+                     path="one workgroup per block, FP32 LDS Gauss-Jordan, direct VALU evaluation, single frames")
         log(f"plain path: {plain['value']:.1f} frames/s")
 
     err = cpu = None
@@ -245,27 +252,29 @@ def bench_frame(args, torch, binding, synth):
         err = error_vs(got, ref)
         log(f"oracle: {cpu['value']:.2f} frames/s on {cpu['cores']} cores; max|err| {err['max_abs']:.3e}")
 
-    ab = algorithmic_bytes(fr)
-    t_dec = secs / args.steps
-    achieved = ab / t_dec / 1e9
+    ab = sum(algorithmic_bytes(f) for f in frames)
+    t_step = secs / args.steps
+    achieved = ab / t_step / 1e9
     copy_gbs = copy_bandwidth(torch, stream=stream)
     log(f"copy kernel: {copy_gbs:.0f} GB/s")
+    kern = "k_fast" if cfg["block_size"] <= 16 else "k_wide"
     rec = dict(metric=METRIC, value=fps, unit="frames/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
-               ms_per_step=1e3 * t_dec, higher_is_better=True, scaling="weak", vs_baseline=None,
+               ms_per_step=1e3 * t_step, higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="f32" if args.eval == "fp32" else f"f32 solve, {args.eval} eval", data="synthetic",
                config={"workload": cfg["name"], "width": cfg["width"], "height": cfg["height"],
                        "format": "4:2:0" if cfg["fmt"] == 1 else "gray", "block_size": cfg["block_size"],
-                       "density": list(cfg["density"]), "frames_per_step": 1,
+                       "density": list(cfg["density"]), "frames_per_step": B,
                        "mask_blocks": fr.n_mask_blocks, "mask_points": int(fr.pos.size),
                        "blocks_per_workgroup": tune or None},
                latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                           "mean": float(lat.mean())},
-               error_vs_oracle=err, plain_path=plain, overlapped=multi, batched=batched,
+                           "mean": float(lat.mean()), "of": "one frame decoded alone"},
+               single_frame=single, error_vs_oracle=err, plain_path=plain, overlapped=multi,
                roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC.get(args.config),
-                         "kernel": "k_fast" if cfg["block_size"] <= 16 else "k_plain_all + k_general_deferred",
-                         "algorithmic_bytes_per_launch": ab, "measured_copy_GBs": copy_gbs,
-                         "frac_of_measured_copy": achieved / copy_gbs},
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": TRAFFIC.get((args.config, B)),
+                         "kernel": kern + (" (+ deferred pass)" if B > 1 or cfg["block_size"] > 16 else ""),
+                         "algorithmic_bytes_per_launch": ab, "launch_ms": 1e3 * t_step,
+                         "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs},
                cpu_baseline=cpu, wall_s=wall)
     dec.close()
     return rec
@@ -439,6 +448,7 @@ def main():
     ap.add_argument("--eval", default="fp32", choices=sorted(EVALS))
     ap.add_argument("--latency-iters", type=int, default=300)
     ap.add_argument("--nstreams", type=int, default=4, help="streams for overlapped / sequence decodes")
+    ap.add_argument("--batch", type=int, default=8, help="frames per decode_residual_batch step (1 to 8)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1), help="frame generator processes")
     ap.add_argument("--lanes", type=int, default=4, help="serving: GPU streams of the request loop")
     ap.add_argument("--budget-mb", type=int, default=2048, help="serving: HBM budget of admitted frames")
