@@ -212,9 +212,12 @@ void pdi_seq_destroy(pdi_seq *q);
  * frame's HOST mask and values into pinned staging and queues it; the worker
  * admits queued frames in arrival order whenever a lane is free and the
  * device bytes of the running frames stay within hbm_budget_bytes (0 = no
- * cap), copies them to the device, decodes them with decode_residual on the
- * lane's stream (frames on different lanes overlap on the GPU) and copies the
- * result back.  A frame's result does not depend on what else is in flight.
+ * cap): the oldest queued frame, joined by queued frames of the same
+ * geometry and params (up to PDI_MAX_BATCH), is copied to the device and
+ * decoded by one decode_residual_batch launch on the lane's stream (frames on
+ * different lanes overlap on the GPU), and the results are copied back.  A
+ * frame's result does not depend on what it is batched with or on what else
+ * is in flight.
  * The context must outlive the server.  Created on the current HIP device. */
 typedef struct pdi_server pdi_server;
 /* max_queue: frames waiting for admission before pdi_submit answers

@@ -103,7 +103,7 @@ struct FrameDev {
   int nq;            // wave-per-block queues (one per block shape), smallest first
   QueueDev q[kMaxShapes];
   int qof[kMaxShapes];  // queue of each shape
-  int fast_wgs;      // workgroups of the batched path (k_fast or k_wide)
+  int fast_wgs;      // workgroups per frame of the batched path (k_fast or k_wide)
   int fast_lds;      // its dynamic LDS (floats): largest table block
   int tab32_floats;  // size of the FP32 table buffer (floats)
   // buffers: frame fi of the launch (blockIdx.y in the batched kernels)

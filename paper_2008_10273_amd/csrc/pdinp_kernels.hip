@@ -321,13 +321,13 @@ __global__ __launch_bounds__(kGenThreads) void k_general_deferred(FrameDev f) {
   // whose kernels ran before this one) for the next decode; the kernel
   // boundary orders these writes before any later kernel on the stream.
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int done = __hip_atomic_fetch_add(&f.counters[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (done == (int)gridDim.x - 1) {
-      for (int i = 0; i < kNumCounters; ++i)
-        __hip_atomic_store(&f.counters[i], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  if (threadIdx.x == 0)
+    sh.g.flag = __hip_atomic_fetch_add(&f.counters[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                (int)gridDim.x - 1;
+  __syncthreads();
+  if (sh.g.flag)
+    for (int i = threadIdx.x; i < kNumCounters; i += kGenThreads)
+      __hip_atomic_store(&f.counters[i], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // -------------------------------------------------------- wave-level path

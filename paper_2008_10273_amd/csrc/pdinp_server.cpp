@@ -5,9 +5,10 @@
 // arrives while others run is admitted as soon as a lane and enough of the
 // HBM budget are free, without waiting for the running ones to finish.
 //
-// Every request is decoded by the same decode_residual call as a frame
-// decoded on its own, and nothing in that call depends on what else is in
-// flight, so a frame's result is the same alone and in the mix.
+// Queued frames of one geometry and parameters are admitted together, up to
+// PDI_MAX_BATCH at a time, and decoded by one decode_residual_batch launch;
+// a frame's result does not depend on what it is batched with or on what
+// else is in flight, so it is the same alone and in the mix.
 #include "../../include/pdinp.h"
 
 #include <hip/hip_runtime.h>
@@ -50,11 +51,17 @@ struct Request {
   void *d_in = nullptr;
   void *d_out = nullptr;      // user_dev or a pooled buffer of out_bytes
   int lane = -1;
-  hipEvent_t done_ev = nullptr;
   Clock::time_point t_submit;
   double latency_us = 0.0;
   int status = PDI_OK;
   bool finished = false;
+};
+
+// Frames admitted together: one batched decode on one lane.
+struct Group {
+  std::vector<Request *> reqs;
+  int lane = -1;
+  hipEvent_t ev = nullptr;
 };
 
 }  // namespace
@@ -66,12 +73,14 @@ struct pdi_server {
   size_t in_use = 0;     // device bytes of running requests
   size_t allocated = 0;  // device bytes held (running requests + pool)
   int max_queue = 0;
+  int max_batch = PDI_MAX_BATCH;
   std::vector<hipStream_t> lanes;
   std::vector<int> lane_busy;
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Request *> queue;     // waiting for admission, arrival order
-  std::vector<Request *> running;  // admitted, on the GPU
+  std::vector<Group *> running;    // admitted, on the GPU
+  std::vector<hipEvent_t> ev_pool; // completion events not in use
   std::map<int64_t, Request *> all;
   std::map<size_t, std::vector<void *>> pool;   // free device buffers by size
   std::map<size_t, std::vector<void *>> hpool;  // free pinned host buffers by size
@@ -130,35 +139,60 @@ void release_host(pdi_server *S, Request *r) {
   if (r->h_out) S->hpool[out_floats_bytes(r)].push_back(r->h_out);
   r->h_in = nullptr;
   r->h_out = nullptr;
-  if (r->done_ev) (void)hipEventDestroy(r->done_ev);
-  r->done_ev = nullptr;
 }
 
-// Start an admitted request on its lane (lock held): H2D copy, decode, D2H
-// copy and a completion event, all asynchronous on the lane's stream.
-int launch_request(pdi_server *S, Request *r) {
-  r->d_in = pool_get(S, r->in_bytes);
-  r->d_out = r->user_dev ? r->user_dev : pool_get(S, r->out_bytes);
-  if (!r->d_in || !r->d_out) return PDI_ENOMEM;
-  hipStream_t st = S->lanes[r->lane];
-  if (hipMemcpyAsync(r->d_in, r->h_in, r->in_used, hipMemcpyHostToDevice, st) != hipSuccess) return PDI_EHIP;
-  char *base = (char *)r->d_in;
-  pdi_mask mk;
-  mk.block_ptr = (const int32_t *)base;
-  mk.pos = (const uint16_t *)(base + r->off_pos);
-  mk.n_mask_blocks = r->n_mask_blocks;
-  mk.chroma_shared = r->chroma_shared;
-  const int rc = decode_residual(S->ctx, &r->frame, &mk, (const float *)(base + r->off_val), r->block_size,
-                                 &r->params, (float *)r->d_out, st);
+// Can b join a batched decode with a (same geometry, block size and params)?
+bool same_kind(const Request *a, const Request *b) {
+  const pdi_params &p = a->params, &q = b->params;
+  return a->frame.width == b->frame.width && a->frame.height == b->frame.height &&
+         a->frame.format == b->frame.format && a->block_size == b->block_size &&
+         a->chroma_shared == b->chroma_shared && p.op == q.op && p.s == q.s && p.eval_dtype == q.eval_dtype &&
+         p.refine == q.refine && p.validate == q.validate && p.path == q.path && p.refine_tau == q.refine_tau &&
+         p.out_int8 == q.out_int8;
+}
+
+// Start an admitted group on its lane (lock held): H2D copies, one batched
+// decode, D2H copies and a completion event, all asynchronous on the lane's
+// stream.
+int launch_group(pdi_server *S, Group *g) {
+  const int n = (int)g->reqs.size();
+  hipStream_t st = S->lanes[g->lane];
+  pdi_mask mk[PDI_MAX_BATCH];
+  const float *vals[PDI_MAX_BATCH];
+  float *outs[PDI_MAX_BATCH];
+  for (int k = 0; k < n; ++k) {
+    Request *r = g->reqs[k];
+    r->d_in = pool_get(S, r->in_bytes);
+    r->d_out = r->user_dev ? r->user_dev : pool_get(S, r->out_bytes);
+    if (!r->d_in || !r->d_out) return PDI_ENOMEM;
+    if (hipMemcpyAsync(r->d_in, r->h_in, r->in_used, hipMemcpyHostToDevice, st) != hipSuccess) return PDI_EHIP;
+    char *base = (char *)r->d_in;
+    mk[k].block_ptr = (const int32_t *)base;
+    mk[k].pos = (const uint16_t *)(base + r->off_pos);
+    mk[k].n_mask_blocks = r->n_mask_blocks;
+    mk[k].chroma_shared = r->chroma_shared;
+    vals[k] = (const float *)(base + r->off_val);
+    outs[k] = (float *)r->d_out;
+  }
+  const Request *r0 = g->reqs[0];
+  const int rc = decode_residual_batch(S->ctx, n, &r0->frame, mk, vals, r0->block_size, &r0->params, outs, st);
   if (rc != PDI_OK) return rc;
-  if (r->user_out && hipMemcpyAsync(r->h_out, r->d_out, r->out_elem * (size_t)r->out_elems,
-                                    hipMemcpyDeviceToHost, st) != hipSuccess)
-    return PDI_EHIP;
-  return hipEventRecord(r->done_ev, st) == hipSuccess ? PDI_OK : PDI_EHIP;
+  for (Request *r : g->reqs)
+    if (r->user_out && hipMemcpyAsync(r->h_out, r->d_out, r->out_elem * (size_t)r->out_elems,
+                                      hipMemcpyDeviceToHost, st) != hipSuccess)
+      return PDI_EHIP;
+  if (S->ev_pool.empty()) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return PDI_EHIP;
+    S->ev_pool.push_back(e);
+  }
+  g->ev = S->ev_pool.back();
+  S->ev_pool.pop_back();
+  return hipEventRecord(g->ev, st) == hipSuccess ? PDI_OK : PDI_EHIP;
 }
 
-// Complete a request (lock held): return its device buffers, free its lane
-// and its share of the budget.  A host result stays in its pinned staging
+// Complete a request (lock held): return its device buffers and its share of
+// the budget.  A host result stays in its pinned staging
 // buffer until pdi_wait copies it out.
 void finish_request(pdi_server *S, Request *r, int status) {
   r->status = status;
@@ -166,12 +200,9 @@ void finish_request(pdi_server *S, Request *r, int status) {
   if (r->d_out && !r->user_dev) S->pool[r->out_bytes].push_back(r->d_out);
   r->d_in = nullptr;
   r->d_out = nullptr;
-  if (r->lane >= 0) S->lane_busy[r->lane] = 0;
   S->in_use -= dev_bytes(r);
   if (r->h_in) S->hpool[r->in_bytes].push_back(r->h_in);
   r->h_in = nullptr;
-  if (r->done_ev) (void)hipEventDestroy(r->done_ev);
-  r->done_ev = nullptr;
   r->latency_us = std::chrono::duration<double, std::micro>(Clock::now() - r->t_submit).count();
   r->finished = true;
 }
@@ -182,18 +213,24 @@ void worker_loop(pdi_server *S) {
   while (true) {
     bool progressed = false;
     for (size_t i = 0; i < S->running.size();) {
-      Request *r = S->running[i];
-      const hipError_t q = hipEventQuery(r->done_ev);
+      Group *g = S->running[i];
+      const hipError_t q = hipEventQuery(g->ev);
       if (q == hipErrorNotReady) {
         ++i;
         continue;
       }
-      const int st = q == hipSuccess ? pdi_sync(S->ctx, S->lanes[r->lane]) : PDI_EHIP;
-      finish_request(S, r, st);
+      // The lane holds no later work, so this returns at once; the status
+      // word covers the whole batch.
+      const int st = q == hipSuccess ? pdi_sync(S->ctx, S->lanes[g->lane]) : PDI_EHIP;
+      for (Request *r : g->reqs) finish_request(S, r, st);
+      S->lane_busy[g->lane] = 0;
+      S->ev_pool.push_back(g->ev);
+      delete g;
       S->running.erase(S->running.begin() + (long)i);
       progressed = true;
     }
-    // Admission in arrival order while a lane and the budget allow.
+    // Admission in arrival order while a lane and the budget allow: the
+    // oldest frame, joined by queued frames of the same kind.
     while (!S->queue.empty() && !S->hold) {
       Request *r = S->queue.front();
       int lane = -1;
@@ -204,16 +241,32 @@ void worker_loop(pdi_server *S) {
         }
       if (lane < 0) break;
       if (S->budget && S->in_use + dev_bytes(r) > S->budget) break;
+      Group *g = new Group();
+      g->lane = lane;
+      g->reqs.push_back(r);
       S->queue.pop_front();
-      r->lane = lane;
-      S->lane_busy[lane] = 1;
       S->in_use += dev_bytes(r);
-      const int rc = launch_request(S, r);
+      for (size_t k = 0; k < S->queue.size() && (int)g->reqs.size() < S->max_batch;) {
+        Request *c = S->queue[k];
+        if (same_kind(r, c) && (!S->budget || S->in_use + dev_bytes(c) <= S->budget)) {
+          g->reqs.push_back(c);
+          S->in_use += dev_bytes(c);
+          S->queue.erase(S->queue.begin() + (long)k);
+        } else {
+          ++k;
+        }
+      }
+      for (Request *c : g->reqs) c->lane = lane;
+      S->lane_busy[lane] = 1;
+      const int rc = launch_group(S, g);
       if (rc != PDI_OK) {
         (void)hipStreamSynchronize(S->lanes[lane]);  // buffers go back to the pool
-        finish_request(S, r, rc);
+        for (Request *c : g->reqs) finish_request(S, c, rc);
+        S->lane_busy[lane] = 0;
+        if (g->ev) S->ev_pool.push_back(g->ev);
+        delete g;
       } else {
-        S->running.push_back(r);
+        S->running.push_back(g);
       }
       progressed = true;
     }
@@ -309,7 +362,7 @@ int pdi_submit(pdi_server *S, const pdi_frame *frame, const pdi_mask *mask, cons
   }
   r->h_in = hpool_get(S, r->in_bytes);
   if (out) r->h_out = hpool_get(S, out_floats_bytes(r));
-  if (!r->h_in || (out && !r->h_out) || hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess) {
+  if (!r->h_in || (out && !r->h_out)) {
     release_host(S, r);
     delete r;
     return PDI_ENOMEM;
@@ -366,7 +419,11 @@ int pdi_server_stats(pdi_server *S, int64_t *queued, int64_t *running, size_t *b
   if (!S) return PDI_EINVAL;
   std::lock_guard<std::mutex> lk(S->mu);
   if (queued) *queued = (int64_t)S->queue.size();
-  if (running) *running = (int64_t)S->running.size();
+  if (running) {
+    int64_t n = 0;
+    for (const Group *g : S->running) n += (int64_t)g->reqs.size();
+    *running = n;
+  }
   if (bytes_in_use) *bytes_in_use = S->in_use;
   if (bytes_allocated) *bytes_allocated = S->allocated;
   return PDI_OK;
@@ -397,6 +454,7 @@ void pdi_server_destroy(pdi_server *S) {
     delete kv.second;
   }
   pool_release_all(S);
+  for (hipEvent_t e : S->ev_pool) (void)hipEventDestroy(e);
   for (auto &kv : S->hpool)
     for (void *p : kv.second) (void)hipHostFree(p);
   for (hipStream_t s : S->lanes) (void)hipStreamDestroy(s);

