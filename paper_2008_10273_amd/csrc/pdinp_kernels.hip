@@ -332,27 +332,6 @@ __global__ __launch_bounds__(kGenThreads) void k_general_deferred(FrameDev f) {
 
 // -------------------------------------------------------- wave-level path
 
-// Broadcast lane `src` of every 16-lane row (DPP row_newbcast).  `src` must
-// fold to a constant after unrolling.  Callers whose consumers are VOP2 ALU
-// instructions pass the result through pin_v(): row_newbcast folded into
-// other VOP2 instructions gave wrong results on gfx950, so every broadcast
-// stays a standalone v_mov_b32_dpp (tests/test_isa.py checks the ISA).
-__device__ __forceinline__ int bcast_i(int x, int src) {
-#define PDI_NB(n) case n: return __builtin_amdgcn_mov_dpp(x, 0x150 + n, 0xF, 0xF, true);
-  switch (src & 15) {
-    PDI_NB(0) PDI_NB(1) PDI_NB(2) PDI_NB(3) PDI_NB(4) PDI_NB(5) PDI_NB(6) PDI_NB(7)
-    PDI_NB(8) PDI_NB(9) PDI_NB(10) PDI_NB(11) PDI_NB(12) PDI_NB(13) PDI_NB(14) PDI_NB(15)
-  }
-#undef PDI_NB
-  return x;
-}
-// Empty statement that takes and "returns" v: the value is materialised in a
-// VGPR here, so its producer cannot be merged into its consumers.
-__device__ __forceinline__ void pin_v(int &v) { asm volatile("" : "+v"(v)); }
-__device__ __forceinline__ float bcast_f(float x, int src) {
-  return __builtin_bit_cast(float, bcast_i(__builtin_bit_cast(int, x), src));
-}
-
 // The 64-bit value v of lane `src` (uniform result).
 __device__ __forceinline__ long long lane_i64(long long v, int src) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)v, src);

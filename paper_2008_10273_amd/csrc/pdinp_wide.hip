@@ -2,65 +2,31 @@
 // points (Sec. 2.2 of the paper, per block: assemble G_K, solve the bordered
 // system [G_K 1; 1^T 0][c; a] = [r; 0], evaluate u = sum_i c_i G(., x_i) + a).
 //
-// One 64-lane wave per block.  Lane i holds row i of the bordered system in
-// VGPRs, and row i + 64 as well when K + 1 > 64.  The elimination runs in
-// LDL^T order without pivoting: the leading K x K block is SPD and the last
-// pivot is -1^T G_K^-1 1 != 0.  Every trailing submatrix of the symmetric
-// bordered matrix is symmetric, so the multiplier of row i at step j,
-// M[i][j] / M[j][j], is read from the pivot row (element i), which its owner
-// lane publishes in LDS; the other lanes read it whole as broadcast vector
-// loads.  A back substitution over the upper triangle left in the rows then
-// gives (c, a).  The evaluation uses the DCT-II factorisation of G (Eq. 4)
-// on 2 x 2 tiles of 16 x 16 matrix-core products.
+// One 64-lane wave per block.  The bordered matrix (n = K + 1 rows, padded
+// with identity rows to a multiple of 16) is held as its upper triangle of
+// 16 x 16 tiles in the matrix-core accumulator layout: lane l, register r
+// holds row 4(l/16) + r, column l%16 of the tile.  Block LDL^T without
+// pivoting (the leading K x K block is SPD and the last pivot is
+// -1^T G_K^-1 1 != 0): per diagonal tile p the lanes factor A_pp = L D L^T
+// row by row (16-lane rows, broadcasts within a row) and keep D and L^-1;
+// W = L^-1 A_pj for the tiles right of it, A_ij -= W_pi^T D^-1 W_pj for the
+// trailing tiles, and the right-hand sides alike, are matrix-core products.
+// A back substitution over the tiles gives (c, a).  The evaluation uses the
+// DCT-II factorisation of G (Eq. 4) on 2 x 2 tiles of 16 x 16 products.
 #include "pdinp_device.h"
 
 #include <hip/hip_runtime.h>
 
 namespace pdi {
 
-typedef float V32 __attribute__((ext_vector_type(32)));
-typedef float V8 __attribute__((ext_vector_type(8)));
-
-constexpr int kWideCap2 = kWideKMax + 1;       // n <= 104: rows i and i + 64 per lane
-constexpr int kWideStagePts = 112;             // evaluation points staged (multiple of 16)
-constexpr int kGroups = (kWideCap2 + 31) / 32; // 32-column groups of a row
-constexpr int kProw = 132;                     // stride of a published row (floats, 16-byte multiple)
-static_assert(kWideCap2 == 104, "row storage below holds 104 columns");
-
-// The lane's rows of the bordered system in VGPRs: row i (columns 0..103)
-// and row i + 64, of which only columns 64..103 are kept: its columns below
-// 64 lie in the lower triangle, which the elimination never reads.  Indices
-// are compile-time constants after unrolling.
-struct WRow {
-  V32 q0, q1, q2;
-  V8 t0;
-  __device__ __forceinline__ float get(int k) const {
-    return k < 32 ? q0[k] : k < 64 ? q1[k - 32] : k < 96 ? q2[k - 64] : t0[k - 96];
-  }
-  __device__ __forceinline__ void set(int k, float v) {
-    if (k < 32) q0[k] = v;
-    else if (k < 64) q1[k - 32] = v;
-    else if (k < 96) q2[k - 64] = v;
-    else t0[k - 96] = v;
-  }
-};
-struct WRowHi {
-  V32 q2;
-  V8 t0;
-  __device__ __forceinline__ float get(int k) const { return k < 64 ? 0.f : k < 96 ? q2[k - 64] : t0[k - 96]; }
-  __device__ __forceinline__ void set(int k, float v) {
-    if (k >= 64 && k < 96) q2[k - 64] = v;
-    else if (k >= 96) t0[k - 96] = v;
-  }
-};
-struct WRows {
-  WRow r0;
-  WRowHi r1;
-  __device__ __forceinline__ float get(int s, int k) const { return s ? r1.get(k) : r0.get(k); }
-  __device__ __forceinline__ void set(int s, int k, float v) {
-    if (s) r1.set(k, v); else r0.set(k, v);
-  }
-};
+constexpr int kWideStagePts = 112;  // points staged (multiple of 16, > kWideKMax)
+constexpr int kTileN = 7;           // 16 x 16 tiles per side: n = K + 1 <= 104 <= 112
+constexpr int kTb = 20;             // row stride of the per-wave tile buffer (floats)
+static_assert(16 * kTileN == kWideStagePts && kWideKMax + 1 <= kWideStagePts, "tile cover");
+// Index of tile (i, j), i <= j, in the packed upper triangle.
+__host__ __device__ constexpr int tix(int i, int j) { return i * kTileN - i * (i - 1) / 2 + (j - i); }
+constexpr int kNumTiles = tix(kTileN - 1, kTileN - 1) + 1;
+typedef int i4 __attribute__((ext_vector_type(4)));
 
 struct WidePoint {
   int x, y;
@@ -69,9 +35,11 @@ struct WidePoint {
 
 // Per-wave LDS.
 struct alignas(16) WideStage {
-  float prow[4 * 132];  // published block rows (stride kProw): columns 0..103, values at 128, 129
-  int xy[kWideCap2];    // mask points: x | (y * (w + 1)) << 16
-  WidePoint p[kWideStagePts];
+  float tb[16 * kTb];                // rows of a diagonal tile
+  float dv[kWideStagePts];           // reciprocal pivots
+  float rv[2][kWideStagePts];        // right-hand sides
+  int xy[kWideStagePts];             // points as table byte offsets: 4x | (4 y (w + 1)) << 16
+  WidePoint p[kWideStagePts];        // points and coefficients for the evaluation
   float a[2];
 };
 
@@ -80,8 +48,24 @@ struct WideJob {
   long long vb0, vb1, ob0, ob1;
 };
 
-__device__ __forceinline__ float lane_f(float v, int l) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+// c + X^T Y for 16 x 16 tiles X, Y in accumulator layout: the k-th product
+// of the chain takes register r of both operands, so lane l supplies
+// A[l%16][l/16] = X[4(l/16) + r][l%16] and B[l/16][l%16] = Y[4(l/16) + r][l%16].
+__device__ __forceinline__ f4 mma_tn(const f4 &x, const f4 &y, f4 c) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[r], y[r], c, 0, 0, 0);
+  return c;
+}
+
+// Row broadcast kept as a standalone move (see bcast_i).
+__device__ __forceinline__ float bcast_pin(float x, int src) {
+  int v = bcast_i(__builtin_bit_cast(int, x), src);
+  pin_v(v);
+  return __builtin_bit_cast(float, v);
+}
+
+__device__ __forceinline__ float tab_at(const float *Hc, int byte_off) {
+  return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(Hc) + byte_off);
 }
 
 // Assemble, factor and solve the bordered system of one block; stage (x, y,
@@ -89,275 +73,199 @@ __device__ __forceinline__ float lane_f(float v, int l) {
 // call for FP64 refinement (the general path refines).
 __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb, int lane, int w, int h,
                                            const float *Hc, WideStage &st) {
-  constexpr int RS = 2, CAP = kWideCap2;
   const int K = jb.K, n = K + 1, N = w * h, W1 = w + 1;
-  const bool two = n > 64;  // row set 1 (rows 64..) in use; otherwise its work is skipped
-  int xr[RS], yr[RS], ywr[RS];
-  float T[RS][2];
+  const int NT = (n + 15) >> 4;
+  const int lo = lane & 15, hi = lane >> 4;
+
+  // Points (as table byte offsets) and right-hand sides into LDS.
   int bad = 0;
 #pragma unroll
-  for (int s = 0; s < RS; ++s) {
+  for (int s = 0; s < 2; ++s) {
     const int i = lane + 64 * s;
-    xr[s] = yr[s] = ywr[s] = 0;
-    T[s][0] = T[s][1] = 0.f;
+    int x = 0, y = 0;
+    float v0 = 0.f, v1 = 0.f;
     if (i < K) {
       const uint16_t *pos = f.fp[blockIdx.y].pos;
       int p = pos[jb.base + i];
       if (f.validate && (p >= N || (i > 0 && (int)pos[jb.base + i - 1] >= p))) bad |= kStatusMask;
       p = min(p, N - 1);
-      xr[s] = p % w;
-      yr[s] = p / w;
-      ywr[s] = yr[s] * W1;
+      x = p % w;
+      y = p / w;
       const float *vals = f.fp[blockIdx.y].values;
-      T[s][0] = vals[jb.vb0 + i];
-      if (jb.nv > 1) T[s][1] = vals[jb.vb1 + i];
-      if (f.validate && !(isfinite(T[s][0]) && isfinite(T[s][1]))) bad |= kStatusValue;
+      v0 = vals[jb.vb0 + i];
+      if (jb.nv > 1) v1 = vals[jb.vb1 + i];
+      if (f.validate && !(isfinite(v0) && isfinite(v1))) bad |= kStatusValue;
     }
-    if (i < kWideCap2) st.xy[i] = (i < K) ? (xr[s] | (ywr[s] << 16)) : 0;
+    if (i < kWideStagePts) {
+      st.xy[i] = (4 * x) | ((4 * y * W1) << 16);
+      st.p[i] = WidePoint{x, y, 0.f, 0.f};
+      st.rv[0][i] = v0;
+      st.rv[1][i] = v1;
+    }
   }
   if (bad) atomicOr(f.status, bad);
   wave_sync();
 
-  // Assembly: row i = [G(x_i, x_k) for k < K | 1 | 0...] for i < K, the border
-  // row [1 ... 1 | 0] for i = K, zero rows past K.  G is the sum of four
-  // quarter-scaled compact-table entries: (|dx|, |dy|) and the reflections
-  // x_i + x_k + 1, y_i + y_k + 1 folded into [0, w] and [0, h].
-  WRows R;
-  const int xcr = 2 * w - 1, ycr = (2 * h - 1) * W1;
+  // Assembly of the tiles (ti <= tj): entry (i, k) is G(x_i, x_k) for i, k
+  // < K, 1 in the border row and column, 0 at (K, K), identity past K.  G is
+  // the sum of four quarter-scaled compact-table entries: (|dx|, |dy|) and
+  // the reflections x_i + x_k + 1, y_i + y_k + 1 folded into [0, w], [0, h].
+  f4 T[kNumTiles], R[kTileN];
+  const int xcr = 4 * (2 * w - 1), ycr = 4 * (2 * h - 1) * W1, W4 = 4 * W1;
 #pragma unroll
-  for (int c = 0; c < CAP / 8; ++c) {
-    if (8 * c < n) {
-      const f4 pa = *reinterpret_cast<const f4 *>(&st.xy[8 * c]);
-      const f4 pb = *reinterpret_cast<const f4 *>(&st.xy[8 * c + 4]);
-      float g[RS][8];
+  for (int ti = 0; ti < kTileN; ++ti) {
+    if (ti < NT) {
+      const i4 rowp = *reinterpret_cast<const i4 *>(&st.xy[16 * ti + 4 * hi]);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int pk = __builtin_bit_cast(int, e < 4 ? pa[e] : pb[e - 4]);
-        const int xk = pk & 0xffff, ykw = pk >> 16;
+      for (int tj = ti; tj < kTileN; ++tj) {
+        if (tj < NT) {
+          const int k = 16 * tj + lo, ck = st.xy[k];
+          const int xk = ck & 0xffff, yk = ck >> 16;
+          f4 t;
 #pragma unroll
-        for (int s = 0; s < RS; ++s) {
-          g[s][e] = 0.f;
-          if (s == 1 && (c < 8 || !two)) continue;  // row set 1 needs columns >= 64 only
-          const int dyw = (int)__usad((unsigned)ywr[s], (unsigned)ykw, 0u);
-          const int syw = min(ywr[s] + ykw + W1, ycr - ywr[s] - ykw);
-          const int dx = (int)__usad((unsigned)xr[s], (unsigned)xk, 0u);
-          const int sx = min(xr[s] + xk + 1, xcr - xr[s] - xk);
-          g[s][e] = (Hc[dyw + dx] + Hc[dyw + sx]) + (Hc[syw + dx] + Hc[syw + sx]);
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * ti + 4 * hi + r, ci = rowp[r];
+            const int xi = ci & 0xffff, yi = ci >> 16;
+            const int dy = (int)__usad((unsigned)yi, (unsigned)yk, 0u);
+            const int sy = min(yi + yk + W4, ycr - yi - yk);
+            const int dx = (int)__usad((unsigned)xi, (unsigned)xk, 0u);
+            const int sx = min(xi + xk + 4, xcr - xi - xk);
+            const float g = (tab_at(Hc, dy + dx) + tab_at(Hc, dy + sx)) + (tab_at(Hc, sy + dx) + tab_at(Hc, sy + sx));
+            const bool one = (i == K && k < K) || (k == K && i < K) || (i == k && i > K);
+            t[r] = (i < K && k < K) ? g : (one ? 1.f : 0.f);
+          }
+          T[tix(ti, tj)] = t;
         }
       }
-#pragma unroll
-      for (int s = 0; s < RS; ++s) {
-        const int i = lane + 64 * s;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int k = 8 * c + e;
-          const float inner = (i < K) ? g[s][e] : (i == K ? 1.f : 0.f);  // columns k < K
-          const float outer = (k == K && i < K) ? 1.f : 0.f;              // columns k >= K
-          R.set(s, k, k < K ? inner : outer);
-        }
-      }
+      const f4 rv = *reinterpret_cast<const f4 *>(&st.rv[lo & 1][16 * ti + 4 * hi]);
+      R[ti] = lo < 2 ? rv : f4{0.f, 0.f, 0.f, 0.f};
     }
   }
 
-  // Forward elimination in blocks of 4 pivots (rows j .. j+3; fewer at the
-  // end).  The 4 owner lanes publish their rows from the block's 32-column
-  // group on, with the value columns.  Every lane factors the 4 x 4 diagonal
-  // block A11 = L D L^T (the same arithmetic in every lane) and, with p_i =
-  // the block rows' column i (= row i's columns j..j+3, by symmetry), solves
-  // A11 c_i = p_i; a row inside the block uses only the pivots before it.
-  // Then row i -= sum_t c_i[t] * (block row t): a rank-4 update that leaves
-  // the Schur complement below the block and the U rows of the block.
-  float d[RS];
+  // Forward elimination, one diagonal tile p at a time.
+  f4 ident;
 #pragma unroll
-  for (int s = 0; s < RS; ++s) d[s] = 1.f;
+  for (int r = 0; r < 4; ++r) ident[r] = (lo == 4 * hi + r) ? 1.f : 0.f;
   float dmin = 3.0e38f, dmax = 0.f;
 #pragma unroll
-  for (int JS = 0; JS < RS; ++JS) {
-    const int jend = min(n, 64 * JS + 64);
-    for (int j = 64 * JS; j < jend; j += 4) {
-      const int bk = min(4, n - j), jl = j & 63, jg = j >> 5;
-      const int tw = lane - jl;  // this lane's row position in the block
-      if (tw >= 0 && tw < 4) {   // rows past n are zero rows: they publish zeros
-        float *dst = st.prow + tw * kProw;
+  for (int p = 0; p < kTileN; ++p) {
+    if (p < NT) {
+      // Row lo of A_pp in every lane.
+      float e[16];
+      {
+        const f4 t = T[tix(p, p)];
 #pragma unroll
-        for (int g = 0; g < kGroups; ++g) {
-          if (g >= jg && 32 * g < n) {
+        for (int r = 0; r < 4; ++r) st.tb[(4 * hi + r) * kTb + lo] = t[r];
+        wave_sync();
 #pragma unroll
-            for (int c = 4 * g; c < min(4 * g + 4, CAP / 8); ++c) {
-              f4 a, b;
+        for (int c = 0; c < 4; ++c) {
+          const f4 v = *reinterpret_cast<const f4 *>(st.tb + lo * kTb + 4 * c);
 #pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                a[e] = R.get(JS, 8 * c + e);
-                b[e] = R.get(JS, 8 * c + 4 + e);
-              }
-              reinterpret_cast<f4 *>(dst)[2 * c] = a;
-              reinterpret_cast<f4 *>(dst)[2 * c + 1] = b;
-            }
-          }
+          for (int u = 0; u < 4; ++u) e[4 * c + u] = v[u];
         }
-        dst[128] = T[JS][0];
-        dst[129] = T[JS][1];
+        wave_sync();  // read before the next tile is written
       }
-      wave_sync();
-      // A11 (identity rows past the block end), then A11 = L D L^T.
-      float a[4][4];
+      // Row reduction of [A_pp | I] without pivoting: lane lo keeps row lo of
+      // the reduced A_pp and columns 4 hi .. 4 hi + 3 of row lo of L^-1; the
+      // multiplier of row lo at step j is its own entry j over the pivot.
+      f4 lv, ds;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const f4 r = *reinterpret_cast<const f4 *>(st.prow + t * kProw + j);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) a[t][u] = (t < bk) ? r[u] : (t == u ? 1.f : 0.f);
-      }
-      float D[4], rD[4], L[4][4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        float s_ = a[t][t];
-#pragma unroll
-        for (int u = 0; u < t; ++u) s_ -= L[t][u] * L[t][u] * D[u];
-        D[t] = s_;
-        rD[t] = __builtin_amdgcn_rcpf(s_);
-#pragma unroll
-        for (int r = t + 1; r < 4; ++r) {
-          float v = a[r][t];
-#pragma unroll
-          for (int u = 0; u < t; ++u) v -= L[r][u] * L[t][u] * D[u];
-          L[r][t] = v * rD[t];
-        }
+      for (int c = 0; c < 4; ++c) {
+        lv[c] = (lo == 4 * hi + c) ? 1.f : 0.f;
+        ds[c] = 1.f;
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (t < bk && j + t < K) {
-          dmin = fminf(dmin, fabsf(D[t]));
-          dmax = fmaxf(dmax, fabsf(D[t]));
+      for (int j = 0; j < 16; ++j) {
+        const float dj = bcast_pin(e[j], j);
+        const float rj = __builtin_amdgcn_rcpf(dj);
+        if (16 * p + j < K) {
+          dmin = fminf(dmin, fabsf(dj));
+          dmax = fmaxf(dmax, fabsf(dj));
         }
-      // Coefficients of the lane's rows.
-      float cf[RS][4];
+        if (hi == (j >> 2)) ds[j & 3] = rj;
+        const float fm = (lo > j) ? e[j] * rj : 0.f;
 #pragma unroll
-      for (int s = 0; s < RS; ++s) {
+        for (int k = j + 1; k < 16; ++k) e[k] = fmaf(-fm, bcast_pin(e[k], j), e[k]);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) cf[s][t] = 0.f;
-        if (s < JS) continue;
-        const int i = lane + 64 * s;
-        const int m = (i < j || i >= n) ? 0 : min(i - j, bk);
-        float z[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          float v = st.prow[t * kProw + min(i, 127)];
-#pragma unroll
-          for (int u = 0; u < t; ++u) v -= L[t][u] * z[u];
-          z[t] = v;
-        }
-#pragma unroll
-        for (int t = 3; t >= 0; --t) {
-          float v = (t < m) ? z[t] * rD[t] : 0.f;
-#pragma unroll
-          for (int u = t + 1; u < 4; ++u) v -= L[u][t] * cf[s][u];
-          cf[s][t] = v;
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) d[s] = (i == j + t && t < bk) ? D[t] : d[s];
+        for (int c = 0; c < 4; ++c) lv[c] = fmaf(-fm, bcast_pin(lv[c], j), lv[c]);
       }
-      // Rank-4 update, 8 columns (4 rows x 2 vectors per row) per load batch.
-      // Columns left of the block inside its first group belong to the lower
-      // triangle, which no later step reads; row set 1 (rows 64..) never
-      // needs its columns below 64.
+      // lv is (L^-1)^T in accumulator layout.  Keep L^-1 itself (for the back
+      // substitution) in place of A_pp, and the reciprocal pivots in LDS.
+      T[tix(p, p)] = mma_tn(lv, ident, f4{0.f, 0.f, 0.f, 0.f});
+      if (lo == 0) *reinterpret_cast<f4 *>(&st.dv[16 * p + 4 * hi]) = ds;
+      // W_pj = L^-1 A_pj for the trailing updates; W_pj^T kept for the back
+      // substitution.
+      f4 Wp[kTileN];
 #pragma unroll
-      for (int g = 0; g < kGroups; ++g) {
-        if (g >= jg && 32 * g < n) {
-#pragma unroll
-          for (int c = 4 * g; c < min(4 * g + 4, CAP / 8); ++c) {
-            f4 pv[4][2];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              pv[t][0] = *reinterpret_cast<const f4 *>(st.prow + t * kProw + 8 * c);
-              pv[t][1] = *reinterpret_cast<const f4 *>(st.prow + t * kProw + 8 * c + 4);
-            }
-#pragma unroll
-            for (int s = JS; s < RS; ++s) {
-              if (s == 1 && (c < 8 || (JS == 0 && !two))) continue;
-#pragma unroll
-              for (int e = 0; e < 8; ++e) {
-                const int k = 8 * c + e;
-                float v = R.get(s, k);
-#pragma unroll
-                for (int t = 0; t < 4; ++t) v = fmaf(-cf[s][t], pv[t][e >> 2][e & 3], v);
-                R.set(s, k, v);
-              }
-            }
-          }
+      for (int j = p + 1; j < kTileN; ++j) {
+        if (j < NT) {
+          const f4 a = T[tix(p, j)];
+          Wp[j] = mma_tn(lv, a, f4{0.f, 0.f, 0.f, 0.f});
+          T[tix(p, j)] = mma_tn(a, lv, f4{0.f, 0.f, 0.f, 0.f});
         }
       }
+      R[p] = mma_tn(lv, R[p], f4{0.f, 0.f, 0.f, 0.f});
+      // A_ij -= W_pi^T D^-1 W_pj, r_i -= W_pi^T D^-1 r_p.
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const float t0 = st.prow[t * kProw + 128], t1 = st.prow[t * kProw + 129];
+      for (int i = p + 1; i < kTileN; ++i) {
+        if (i < NT) {
+          f4 x;
 #pragma unroll
-        for (int s = JS; s < RS; ++s) {
-          T[s][0] = fmaf(-cf[s][t], t0, T[s][0]);
-          T[s][1] = fmaf(-cf[s][t], t1, T[s][1]);
+          for (int r = 0; r < 4; ++r) x[r] = -ds[r] * Wp[i][r];
+#pragma unroll
+          for (int j = i; j < kTileN; ++j)
+            if (j < NT) T[tix(i, j)] = mma_tn(x, Wp[j], T[tix(i, j)]);
+          R[i] = mma_tn(x, R[p], R[i]);
         }
       }
-      wave_sync();  // every lane has read the block rows before the next are published
     }
   }
   const bool need = (f.refine == 2) || (f.refine == 1 && !(dmin >= f.tau * dmax));
-  if (need) return false;
+  if (__ballot(need)) return false;
+  wave_sync();  // reciprocal pivots written
 
-  // Back substitution: x_k = (y_k - sum_{j > k} U[k][j] x_j) / U[k][k],
-  // accumulated into the rows above k as each x_k is broadcast.
-  float rd[RS], acc[RS][2];
+  // Back substitution: x_p = L_p^-T D_p^-1 (r_p - sum_{j > p} W_pj x_j).
 #pragma unroll
-  for (int s = 0; s < RS; ++s) {
-    rd[s] = __builtin_amdgcn_rcpf(d[s]);
-    acc[s][0] = acc[s][1] = 0.f;
-  }
+  for (int p = kTileN - 1; p >= 0; --p) {
+    if (p < NT) {
+      f4 y = R[p];
 #pragma unroll
-  for (int k = CAP - 1; k >= 0; --k) {
-    if (k < n) {
-      const int ks = k >> 6, kl = k & 63;
-      float t0 = 0.f, t1 = 0.f;
+      for (int j = p + 1; j < kTileN; ++j) {
+        if (j < NT) {
+          f4 wt = T[tix(p, j)];
 #pragma unroll
-      for (int s = 0; s < RS; ++s)
-        if (s == ks) {
-          t0 = (T[s][0] - acc[s][0]) * rd[s];
-          t1 = (T[s][1] - acc[s][1]) * rd[s];
+          for (int r = 0; r < 4; ++r) wt[r] = -wt[r];
+          y = mma_tn(wt, R[j], y);
         }
-      const float x0 = lane_f(t0, kl), x1 = lane_f(t1, kl);
+      }
+      const f4 dv = *reinterpret_cast<const f4 *>(&st.dv[16 * p + 4 * hi]);
 #pragma unroll
-      for (int s = 0; s < RS; ++s) {
-        if (64 * s < k) {
-          const bool above = lane + 64 * s < k;
-          const float u = R.get(s, k);
-          acc[s][0] = above ? fmaf(u, x0, acc[s][0]) : acc[s][0];
-          acc[s][1] = above ? fmaf(u, x1, acc[s][1]) : acc[s][1];
+      for (int r = 0; r < 4; ++r) y[r] *= dv[r];
+      R[p] = mma_tn(T[tix(p, p)], y, f4{0.f, 0.f, 0.f, 0.f});
+    }
+  }
+
+  // Stage the coefficients (column lo of the solution tiles, lo < 2) and
+  // a = x_K; staged points past K keep c = 0.
+  bool fin = true;
+#pragma unroll
+  for (int p = 0; p < kTileN; ++p) {
+    if (p < NT) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int idx = 16 * p + 4 * hi + r;
+        const float v = R[p][r];
+        if (lo < 2) {
+          if (idx < K) {
+            if (lo == 0) st.p[idx].c0 = v;
+            else st.p[idx].c1 = v;
+          }
+          if (idx == K) st.a[lo] = v;
+          if (idx <= K) fin &= isfinite(v);
         }
       }
     }
   }
-
-  // Stage the K points with their coefficients (zeros up to the next multiple
-  // of 16) and a = x_K.
-  bool fin = true;
-  float aK0 = 0.f, aK1 = 0.f;
-#pragma unroll
-  for (int s = 0; s < RS; ++s) {
-    const int i = lane + 64 * s;
-    const float c0 = (T[s][0] - acc[s][0]) * rd[s];
-    const float c1 = (T[s][1] - acc[s][1]) * rd[s];
-    if (i < kWideStagePts) {
-      WidePoint P;
-      P.x = i < K ? xr[s] : 0;
-      P.y = i < K ? yr[s] : 0;
-      P.c0 = i < K ? c0 : 0.f;
-      P.c1 = i < K ? c1 : 0.f;
-      st.p[i] = P;
-    }
-    if (i <= K) fin &= isfinite(c0) && isfinite(c1);
-    if ((K >> 6) == s) {
-      aK0 = c0;
-      aK1 = c1;
-    }
-  }
-  st.a[0] = lane_f(aK0, K & 63);
-  st.a[1] = lane_f(aK1, K & 63);
   if (__ballot(!fin)) {
     if (lane == 0) atomicOr(f.status, kStatusSolve);
   }

@@ -118,6 +118,19 @@ def test_b32_point_counts(dec, path):
     check(dec, fr, path=path)
 
 
+@pytest.mark.parametrize("case", ["counts", "config2"])
+def test_b32_wave_solve_unrefined(dec, case):
+    """refine = 0: every 32x32 block with K <= 103 keeps the FP32 solve of
+    the wave-per-block path (none is handed to the FP64 pass), so this
+    checks that solve itself."""
+    if case == "counts":
+        ks = [63, 64, 65, 102, 103, 1, 2, 31, 32, 33, 47, 48, 49, 79, 80, 81, 95, 96, 97, 15, 16, 17]
+        fr = _custom_frame(32 * 6 + 7, 32 * 3 + 20, 32, lambda k, n: min(n - 1, ks[k % len(ks)]), seed=9)
+    else:
+        fr = synth.config_frame(2, keep_fields=False)
+    check(dec, fr, refine=0)
+
+
 @pytest.mark.parametrize("refine", [0, 1, 2])
 def test_refine_modes(dec, refine):
     fr = synth.random_frame(96, 64, synth.YUV420, 16, (0.01, 0.12), seed=11)

@@ -13,7 +13,10 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SRC = os.path.join(ROOT, "paper_2008_10273_amd", "csrc", "pdinp_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2008_10273_amd", "csrc")
+# Sources with the per-file flags the build passes.
+SOURCES = [("pdinp_kernels.hip", []),
+           ("pdinp_wide.hip", ["-mllvm", "-pragma-unroll-threshold=1000000"])]
 
 
 @pytest.fixture(scope="module")
@@ -21,12 +24,16 @@ def isa(tmp_path_factory):
     hipcc = "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else shutil.which("hipcc")
     if not hipcc:
         pytest.skip("hipcc not available")
-    out = tmp_path_factory.mktemp("isa") / "k.s"
-    subprocess.check_call([hipcc, "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature",
-                           "-Xclang", "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"),
-                           "--cuda-device-only", "-S", SRC, "-o", str(out)],
-                          stderr=subprocess.DEVNULL)
-    return out.read_text()
+    d = tmp_path_factory.mktemp("isa")
+    text = []
+    for name, extra in SOURCES:
+        out = d / (name + ".s")
+        subprocess.check_call([hipcc, "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature",
+                               "-Xclang", "-packed-fp32-ops", *extra, "-I", os.path.join(ROOT, "include"),
+                               "--cuda-device-only", "-S", os.path.join(CSRC, name), "-o", str(out)],
+                              stderr=subprocess.DEVNULL)
+        text.append(out.read_text())
+    return "\n".join(text)
 
 
 def test_newbcast_only_in_standalone_moves(isa):
