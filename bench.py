@@ -198,9 +198,12 @@ def bench_frame(args, torch, binding, synth):
     d = ds[0]
     stream = torch.cuda.Stream()
     params = binding.default_params(eval_dtype=EVALS[args.eval])
-    tune = dec.autotune(d, params, stream=stream)  # launch choice for this geometry (0: none to make)
+    # launch choices for this geometry (0: none to make), one for single-frame
+    # decodes and one for launches of B frames
+    tune = dec.autotune(d, params, stream=stream)
+    tune_b = dec.autotune_batch(ds, params, stream=stream) if B > 1 else tune
     log(f"config {args.config} ({cfg['name']}), eval {args.eval}, {B} frames per step, {args.steps} steps, "
-        f"autotune choice {tune}")
+        f"autotune choice {tune_b} ({B} frames), {tune} (single frame)")
 
     def step():
         if B == 1:
@@ -265,7 +268,7 @@ def bench_frame(args, torch, binding, synth):
                        "format": "4:2:0" if cfg["fmt"] == 1 else "gray", "block_size": cfg["block_size"],
                        "density": list(cfg["density"]), "frames_per_step": B,
                        "mask_blocks": fr.n_mask_blocks, "mask_points": int(fr.pos.size),
-                       "blocks_per_workgroup": tune or None},
+                       "blocks_per_workgroup": tune_b or None, "blocks_per_workgroup_single": tune or None},
                latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "mean": float(lat.mean()), "of": "one frame decoded alone"},
                single_frame=single, error_vs_oracle=err, plain_path=plain, overlapped=multi,

@@ -150,7 +150,7 @@ const char *pdi_last_error(pdi_ctx *ctx);
 /* Measure the launch choices of the batched path for this frame geometry,
  * operator and evaluation dtype on the given inputs (device pointers, as for
  * decode_residual; `out` is overwritten) and keep the fastest in the context
- * for later decode_residual calls with the same geometry and params.  The
+ * for later single-frame decode_residual calls with the same geometry and params.  The
  * choices only change how blocks are grouped into workgroups, never a
  * block's arithmetic, so results are bitwise the same with any choice.
  * Synchronous (not capturable).  *choice (may be NULL) receives the blocks
@@ -160,6 +160,17 @@ const char *pdi_last_error(pdi_ctx *ctx);
  * Returns the codes of decode_residual / pdi_sync. */
 int pdi_autotune(pdi_ctx *ctx, const pdi_frame *frame, const pdi_mask *mask, const float *values,
                  int block_size, const pdi_params *params, float *out, void *stream, int *choice);
+
+/* pdi_autotune for decode_residual_batch launches of n (1..PDI_MAX_BATCH)
+ * frames: the candidates are timed on the given batch (arguments as for
+ * decode_residual_batch; outs[k] are overwritten) and the fastest is kept
+ * for later batches of n frames with the same geometry and params.  A
+ * choice is kept per n: a launch of 8 frames has 8 times the workgroups of
+ * one and may prefer other groupings.  pdi_autotune is this call with n = 1.
+ * Synchronous; *choice and return codes as for pdi_autotune. */
+int pdi_autotune_batch(pdi_ctx *ctx, int n, const pdi_frame *frame, const pdi_mask *masks,
+                       const float *const *values, int block_size, const pdi_params *params,
+                       float *const *outs, void *stream, int *choice);
 
 /* Host helper: number of mask blocks, value count and output size of a
  * frame geometry (for sizing buffers).  Pointers may be NULL. */

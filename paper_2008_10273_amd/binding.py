@@ -25,7 +25,7 @@ ERROR_NAMES = {0: "PDI_OK", -1: "PDI_EINVAL", -2: "PDI_EMASK", -3: "PDI_ENOMEM",
 
 EXPORTS = ["pdi_default_params", "pdi_create", "pdi_destroy", "decode_residual", "decode_residual_batch",
            "pdi_sync",
-           "pdi_last_error", "pdi_frame_info", "pdi_pack_dense", "pdi_validate_host", "pdi_autotune",
+           "pdi_last_error", "pdi_frame_info", "pdi_pack_dense", "pdi_validate_host", "pdi_autotune", "pdi_autotune_batch",
            "pdi_seq_create", "pdi_seq_launch", "pdi_seq_sync", "pdi_seq_destroy",
            "pdi_server_create", "pdi_submit", "pdi_poll", "pdi_wait", "pdi_server_stats",
            "pdi_server_hold", "pdi_server_destroy"]
@@ -90,6 +90,10 @@ def lib() -> ctypes.CDLL:
         L.pdi_autotune.argtypes = [P, ctypes.POINTER(pdi_frame), ctypes.POINTER(pdi_mask), P, i32,
                                    ctypes.POINTER(pdi_params), P, P, ctypes.POINTER(ctypes.c_int)]
         L.pdi_autotune.restype = i32
+        L.pdi_autotune_batch.argtypes = [P, i32, ctypes.POINTER(pdi_frame), ctypes.POINTER(pdi_mask),
+                                         ctypes.POINTER(ctypes.c_void_p), i32, ctypes.POINTER(pdi_params),
+                                         ctypes.POINTER(ctypes.c_void_p), P, ctypes.POINTER(ctypes.c_int)]
+        L.pdi_autotune_batch.restype = i32
         PP = ctypes.POINTER(ctypes.c_void_p)
         L.pdi_seq_create.argtypes = [P, i32, ctypes.POINTER(pdi_frame), ctypes.POINTER(pdi_mask), PP, i32,
                                      ctypes.POINTER(pdi_params), PP, i32, PP]
@@ -274,6 +278,31 @@ class Decoder:
         if check and rc != PDI_OK:
             raise PdiError(rc, pdi_last_error(self.ctx))
         return rc
+
+    def autotune_batch(self, ds, params: Optional[pdi_params] = None, stream=None) -> int:
+        """pdi_autotune_batch over uploaded frames of one geometry (the
+        launch decode_batch makes); returns the launch choice."""
+        n = len(ds)
+        f0 = ds[0]["frame"]
+        fr = pdi_frame(f0.width, f0.height, f0.fmt)
+        masks = (pdi_mask * n)()
+        vals = (ctypes.c_void_p * n)()
+        outs = (ctypes.c_void_p * n)()
+        i8 = params is not None and params.out_int8
+        for k, d in enumerate(ds):
+            f = d["frame"]
+            masks[k] = pdi_mask(d["block_ptr"].data_ptr(), d["pos"].data_ptr(), d["n_mask_blocks"],
+                                int(bool(f.chroma_shared)))
+            vals[k] = d["values"].data_ptr()
+            outs[k] = (d["out_i8"] if i8 else d["out"]).data_ptr()
+        s = stream.cuda_stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
+        ch = ctypes.c_int()
+        rc = lib().pdi_autotune_batch(self.ctx, n, ctypes.byref(fr), masks, vals, f0.block_size,
+                                      ctypes.byref(params) if params is not None else None, outs, s,
+                                      ctypes.byref(ch))
+        if rc != PDI_OK:
+            raise PdiError(rc, pdi_last_error(self.ctx))
+        return ch.value
 
     def autotune(self, d, params: Optional[pdi_params] = None, stream=None) -> int:
         """pdi_autotune on an uploaded frame; returns the launch choice."""

@@ -291,6 +291,30 @@ def test_autotune_keeps_results(dec):
     assert dec.autotune(dec.upload(fr16), binding.default_params(path=1)) == 0
 
 
+@pytest.mark.parametrize("b", [16, 32])
+def test_autotune_batch_keeps_results(dec, b):
+    """pdi_autotune_batch times the launch of n frames and keeps its choice
+    for launches of n frames only; batched results stay bitwise those of
+    the frames decoded alone, before and after tuning."""
+    from paper_2008_10273_amd import binding
+    frames = [synth.random_frame(300, 170, synth.YUV420, b, (0.01, 0.1), seed=90 + k) for k in range(3)]
+    alone = []
+    for fr in frames:
+        got, _ = gpu_decode(dec, fr)
+        alone.append(got)
+    ds = [dec.upload(fr) for fr in frames]
+    ch = dec.autotune_batch(ds)
+    assert ch in ((1, 2, 4) if b == 32 else (16, 14, 13, 12, 10, 8))
+    for d in ds:
+        d["out"].fill_(float("nan"))
+    dec.decode_batch(ds)
+    assert dec.sync() == 0
+    for d, ref in zip(ds, alone):
+        np.testing.assert_array_equal(d["out"].cpu().numpy().astype(np.float64), ref)
+    with pytest.raises(binding.PdiError):
+        dec.autotune_batch(ds * 3)  # 9 frames: more than one launch takes
+
+
 @pytest.mark.parametrize("case", ["cfg0", "ragged420", "b8", "b32", "edge_counts"])
 @pytest.mark.parametrize("path", [0, 1])
 def test_int8_output(dec, case, path):
