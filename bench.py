@@ -41,7 +41,7 @@ EVALS = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16x2": 3}
 # WRITE_SIZE counters, scaled by the same counters read on a copy kernel of
 # known size (profiles/*_hbm_counters.txt); only for the kernel build the
 # counters were taken on (null after a kernel change).
-TRAFFIC = {(1, 8): 112142541, (2, 8): 114913690}  # (config, frames per step): bytes per launch
+TRAFFIC = {(1, 8): 112142541}  # (config, frames per step): bytes per launch
 
 
 def algorithmic_bytes(fr) -> int:

@@ -203,9 +203,9 @@ void build_shape_tables(int w, int h, int op, double s, std::vector<double> &lam
 }
 
 // Orthonormal DCT-II matrix of size n, rows = frequency, cols = position,
-// zero padded to ld x ld.
-void dct_padded(int n, int ld, float *out) {
-  for (int p = 0; p < ld; ++p)
+// zero padded to m x m, row stride ld >= m.
+void dct_padded(int n, int m, int ld, float *out) {
+  for (int p = 0; p < m; ++p)
     for (int x = 0; x < ld; ++x) {
       double v = 0.0;
       if (p < n && x < n) v = std::sqrt((p == 0 ? 1.0 : 2.0) / n) * std::cos(kPi * p * (x + 0.5) / n);
@@ -264,7 +264,7 @@ int get_tables(pdi_ctx *c, const pdi_frame *f, int b, int shared, const pdi_para
       const int W1 = w + 1;
       S.fast = (int)t32.size();
       S.jt_floats = (h * h * W1 + 3) & ~3;
-      t32.resize(t32.size() + S.jt_floats + 768, 0.f);
+      t32.resize(t32.size() + S.jt_floats + 3 * pdi::kDct16Floats, 0.f);
       float *J = &t32[S.fast];
       for (int y = 0; y < h; ++y)
         for (int y2 = 0; y2 < h; ++y2) {
@@ -275,23 +275,25 @@ int get_tables(pdi_ctx *c, const pdi_frame *f, int b, int shared, const pdi_para
             J[(y * h + y2) * W1 + a] = (float)(hc[(size_t)dy * W1 + a] + hc[(size_t)sy * W1 + a]);
         }
       float *D = J + S.jt_floats;
-      dct_padded(w, 16, D);
-      dct_padded(h, 16, D + 256);
+      dct_padded(w, 16, pdi::kDct16Ld, D);
+      dct_padded(h, 16, pdi::kDct16Ld, D + pdi::kDct16Floats);
       for (int q = 0; q < h; ++q)
-        for (int p = 0; p < w; ++p) D[512 + q * 16 + p] = (float)lam[(size_t)q * w + p];
+        for (int p = 0; p < w; ++p)
+          D[2 * pdi::kDct16Floats + q * pdi::kDct16Ld + p] = (float)lam[(size_t)q * w + p];
     } else {
-      // Compact table, then Dw, Dh and lam zero-padded to 32 x 32.
+      // Compact table, then Dw, Dh and lam zero-padded to 32 x 32 (row stride 33).
       const int W1 = w + 1;
       S.fast = (int)t32.size();
       S.jt_floats = (W1 * (h + 1) + 3) & ~3;
-      t32.resize(t32.size() + S.jt_floats + 3 * 1024, 0.f);
+      t32.resize(t32.size() + S.jt_floats + 3 * pdi::kDct32Floats, 0.f);
       float *Hq = &t32[S.fast];
       for (size_t i = 0; i < hc.size(); ++i) Hq[i] = (float)hc[i];
       float *D = Hq + S.jt_floats;
-      dct_padded(w, 32, D);
-      dct_padded(h, 32, D + 1024);
+      dct_padded(w, 32, pdi::kDct32Ld, D);
+      dct_padded(h, 32, pdi::kDct32Ld, D + pdi::kDct32Floats);
       for (int q = 0; q < h; ++q)
-        for (int p = 0; p < w; ++p) D[2048 + q * 32 + p] = (float)lam[(size_t)q * w + p];
+        for (int p = 0; p < w; ++p)
+          D[2 * pdi::kDct32Floats + q * pdi::kDct32Ld + p] = (float)lam[(size_t)q * w + p];
     }
   }
   ts.tab32_floats = (int)t32.size();
@@ -522,7 +524,7 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
   }
   F.ipw = ipw;
   int shape_count[pdi::kMaxShapes] = {0};
-  const int dct_floats = fast ? 3 * 256 : 3 * 1024;
+  const int dct_floats = fast ? 3 * pdi::kDct16Floats : 3 * pdi::kDct32Floats;
   F.nsegs = 0;
   F.fast_wgs = 0;
   F.fast_lds = 0;

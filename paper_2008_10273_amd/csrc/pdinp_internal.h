@@ -26,6 +26,13 @@ constexpr int kMaxBatch = 8;  // frames of one geometry per launch (decode_resid
 // Deferred-list entries hold (frame << kDeferFrameShift) | block.
 constexpr int kDeferFrameShift = 24;
 constexpr int kDeferItemMask = (1 << kDeferFrameShift) - 1;
+// Zero-padded DCT-II matrices Dw, Dh and eigenvalues lam of a block shape,
+// n x n (n = 16 for b <= 16, 32 for b = 32) with row stride n + 1, so that
+// the evaluation's column gathers (16 lanes, 16 rows, one column) fall into
+// 16 different LDS banks.
+constexpr int kDct16Ld = 17, kDct16Floats = 16 * kDct16Ld;
+constexpr int kDct32Ld = 33, kDct32Floats = 32 * kDct32Ld;
+static_assert(kDct16Floats % 4 == 0 && kDct32Floats % 4 == 0, "16-byte copies");
 // The FP32 table buffer is padded by this many floats so that the wave-level
 // path may read whole 16-byte vectors per thread past the last table.
 constexpr int kTabPadFloats = 6 * 256 * 4;
@@ -43,9 +50,10 @@ struct ShapeDev {
   int fast;       // block of the batched paths: for b <= 16 the row-pair table
                   // J[(y*h + y')*(w+1) + alpha] (jt_floats floats), then the
                   // zero-padded 16x16 DCT-II matrices Dw[p][x], Dh[q][y] and the
-                  // eigenvalues lam[q][p] (256 floats each); for b = 32 the
-                  // compact table (jt_floats floats) and the same three
-                  // matrices zero-padded to 32x32 (1024 floats each)
+                  // eigenvalues lam[q][p] (kDct16Floats floats each, row
+                  // stride kDct16Ld); for b = 32 the compact table
+                  // (jt_floats floats) and the same three matrices padded to
+                  // 32x32 (kDct32Floats floats each, row stride kDct32Ld)
   int jt_floats;  // size of the first table rounded up to a multiple of 4
 };
 

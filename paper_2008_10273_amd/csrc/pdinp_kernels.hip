@@ -353,8 +353,9 @@ constexpr int kFastThreads = 256;
 constexpr int kFastWaves = kFastThreads / 64;
 constexpr int kFastItems = kFastWaves * kWaveItems;  // blocks per workgroup
 // 16-byte table loads per thread: J (16*16*17 floats at most, rounded to 4)
-// plus the DCT matrices and eigenvalues (768 floats) of a b <= 16 shape.
-constexpr int kTabVec = ((16 * 16 * 17 + 3) / 4 + 768 / 4 + kFastThreads - 1) / kFastThreads;
+// plus the DCT matrices and eigenvalues (3 kDct16Floats) of a b <= 16 shape.
+constexpr int kTabVec = ((16 * 16 * 17 + 3) / 4 + 3 * kDct16Floats / 4 + kFastThreads - 1) / kFastThreads;
+static_assert(kTabVec * kFastThreads * 4 <= kTabPadFloats, "table reads stay inside the padded buffer");
 
 // A block of the workgroup, as staged by the prologue.
 struct FastItem {
@@ -558,15 +559,15 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
                                           int lane, unsigned okmask, int nvw, int w, int h,
                                           int W, long long ob0, long long ob1) {
   constexpr int nch = R / 4;  // staged rows K..R-1 hold zero coefficients
-  const float *Dw = D, *Dh = D + 256, *lam = D + 512;
+  const float *Dw = D, *Dh = D + kDct16Floats, *lam = D + 2 * kDct16Floats;
   const int lo = lane & 15, hi = lane >> 4;
   float lam4[4], dwb[4], dha[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int pq = 4 * hi + j;
-    lam4[j] = lam[lo * 16 + pq];  // lam[q][p], q = lo, p = 4 hi + j
-    dwb[j] = Dw[pq * 16 + lo];    // Dw[p][x], p = 4 hi + j, x = lo
-    dha[j] = Dh[pq * 16 + lo];    // Dh[q][y], q = 4 hi + j, y = lo
+    lam4[j] = lam[lo * kDct16Ld + pq];  // lam[q][p], q = lo, p = 4 hi + j
+    dwb[j] = Dw[pq * kDct16Ld + lo];    // Dw[p][x], p = 4 hi + j, x = lo
+    dha[j] = Dh[pq * kDct16Ld + lo];    // Dh[q][y], q = 4 hi + j, y = lo
   }
   for (int v = 0; v < nvw; ++v) {
     f4 acc[kWaveItems];
@@ -578,8 +579,8 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
 #pragma unroll
       for (int g = 0; g < kWaveItems; ++g) {
         const FastPoint P = st.p[g][ch * 4 + hi];
-        aop[g] = (v ? P.c1 : P.c0) * Dw[lo * 16 + P.x];  // A[p][i], p = lo
-        bop[g] = Dh[lo * 16 + P.y];                      // B[i][q], q = lo
+        aop[g] = (v ? P.c1 : P.c0) * Dw[lo * kDct16Ld + P.x];  // A[p][i], p = lo
+        bop[g] = Dh[lo * kDct16Ld + P.y];                      // B[i][q], q = lo
       }
 #pragma unroll
       for (int g = 0; g < kWaveItems; ++g)
@@ -655,15 +656,15 @@ __device__ __forceinline__ void fast_eval16(const FrameDev &f, const float *D, c
                                             int lane, unsigned okmask, int nvw, int w, int h,
                                             int W, long long ob0, long long ob1) {
   constexpr int nch = (R + 15) / 16;
-  const float *Dw = D, *Dh = D + 256, *lam = D + 512;
+  const float *Dw = D, *Dh = D + kDct16Floats, *lam = D + 2 * kDct16Floats;
   const int lo = lane & 15, hi = lane >> 4;
   float lam4[4], dwb[4], dha[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int pq = 4 * hi + j;
-    lam4[j] = lam[lo * 16 + pq];
-    dwb[j] = Dw[pq * 16 + lo];
-    dha[j] = Dh[pq * 16 + lo];
+    lam4[j] = lam[lo * kDct16Ld + pq];
+    dwb[j] = Dw[pq * kDct16Ld + lo];
+    dha[j] = Dh[pq * kDct16Ld + lo];
   }
   for (int v = 0; v < nvw; ++v) {
 #pragma unroll 1
@@ -676,8 +677,8 @@ __device__ __forceinline__ void fast_eval16(const FrameDev &f, const float *D, c
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const FastPoint P = st.p[g][ch * 16 + 4 * hi + e];
-          a[e] = (v ? P.c1 : P.c0) * Dw[lo * 16 + P.x];  // A[p = lo][i]
-          b[e] = Dh[lo * 16 + P.y];                      // B[i][q = lo]
+          a[e] = (v ? P.c1 : P.c0) * Dw[lo * kDct16Ld + P.x];  // A[p = lo][i]
+          b[e] = Dh[lo * kDct16Ld + P.y];                      // B[i][q = lo]
         }
         acc = mma16<EV>(acc, a, b);
       }
@@ -745,7 +746,7 @@ void k_fast(FrameDev f) {
     if (G.nv > 1 && f.shared) icr = (long long)bp[f.n_items] - bp[f.chroma_first];
   }
   {
-    const int n4 = (S.jt_floats + 768) >> 2;
+    const int n4 = (S.jt_floats + 3 * kDct16Floats) >> 2;
     const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + S.fast);
     f4 *dst = reinterpret_cast<f4 *>(tabs);
     f4 buf[kTabVec];

@@ -276,10 +276,11 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
 // u = Dh^T (lam .* (Dw[:,X] diag(c) Dh[:,Y]^T)^T) Dw + a over the 32 x 32
 // block as 2 x 2 tiles of FP32 16x16x4 MFMA chains (lane l supplies
 // A[l%16][l/16] and B[l/16][l%16]; the result D[4(l/16)+r][l%16] is register
-// r).  D holds Dw[p][x], Dh[q][y] and lam[q][p], 32 x 32 each, zero-padded.
+// r).  D holds Dw[p][x], Dh[q][y] and lam[q][p], 32 x 32 each, zero-padded,
+// row stride kDct32Ld.
 __device__ __forceinline__ void wide_eval32(const FrameDev &f, const WideJob &jb, const float *D,
                                             const WideStage &st, int lane, int w, int h, int W) {
-  const float *Dw = D, *Dh = D + 1024, *lam = D + 2048;
+  const float *Dw = D, *Dh = D + kDct32Floats, *lam = D + 2 * kDct32Floats;
   const int lo = lane & 15, hi = lane >> 4;
   const int nch = (jb.K + 7) >> 3;  // pairs of 4-point chunks (staged points are zero past K)
   for (int v = 0; v < jb.nv; ++v) {
@@ -296,8 +297,8 @@ __device__ __forceinline__ void wide_eval32(const FrameDev &f, const WideJob &jb
         const float cv = v ? P.c1 : P.c0;
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          ao[u][t] = cv * Dw[(16 * t + lo) * 32 + P.x];  // A[p][i], p = 16 pt + lo
-          bo[u][t] = Dh[(16 * t + lo) * 32 + P.y];       // B[i][q], q = 16 qt + lo
+          ao[u][t] = cv * Dw[(16 * t + lo) * kDct32Ld + P.x];  // A[p][i], p = 16 pt + lo
+          bo[u][t] = Dh[(16 * t + lo) * kDct32Ld + P.y];       // B[i][q], q = 16 qt + lo
         }
       }
 #pragma unroll
@@ -321,8 +322,8 @@ __device__ __forceinline__ void wide_eval32(const FrameDev &f, const WideJob &jb
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int p = 16 * pt + 4 * hi + j;
-            const float a = acc[pt][qt][j] * lam[(16 * qt + lo) * 32 + p];
-            s4 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Dw[p * 32 + 16 * xt + lo], s4, 0, 0, 0);
+            const float a = acc[pt][qt][j] * lam[(16 * qt + lo) * kDct32Ld + p];
+            s4 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Dw[p * kDct32Ld + 16 * xt + lo], s4, 0, 0, 0);
           }
         S[qt][xt] = s4;  // S[q = 16 qt + 4 hi + r][x = 16 xt + lo]
       }
@@ -338,7 +339,7 @@ __device__ __forceinline__ void wide_eval32(const FrameDev &f, const WideJob &jb
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int q = 16 * qt + 4 * hi + j;
-            u4 = __builtin_amdgcn_mfma_f32_16x16x4f32(Dh[q * 32 + 16 * yt + lo], S[qt][xt][j], u4, 0, 0, 0);
+            u4 = __builtin_amdgcn_mfma_f32_16x16x4f32(Dh[q * kDct32Ld + 16 * yt + lo], S[qt][xt][j], u4, 0, 0, 0);
           }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -386,7 +387,7 @@ __device__ __forceinline__ f4 wmma16(f4 acc, const float a[4], const float b[4])
 template <int EV>
 __device__ __forceinline__ void wide_eval16(const FrameDev &f, const WideJob &jb, const float *D,
                                             const WideStage &st, int lane, int w, int h, int W) {
-  const float *Dw = D, *Dh = D + 1024, *lam = D + 2048;
+  const float *Dw = D, *Dh = D + kDct32Floats, *lam = D + 2 * kDct32Floats;
   const int lo = lane & 15, hi = lane >> 4;
   const int nch = (jb.K + 15) >> 4;
   for (int v = 0; v < jb.nv; ++v) {
@@ -403,8 +404,8 @@ __device__ __forceinline__ void wide_eval16(const FrameDev &f, const WideJob &jb
         const float cv = v ? P.c1 : P.c0;
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          ao[t][e] = cv * Dw[(16 * t + lo) * 32 + P.x];
-          bo[t][e] = Dh[(16 * t + lo) * 32 + P.y];
+          ao[t][e] = cv * Dw[(16 * t + lo) * kDct32Ld + P.x];
+          bo[t][e] = Dh[(16 * t + lo) * kDct32Ld + P.y];
         }
       }
 #pragma unroll
@@ -425,8 +426,8 @@ __device__ __forceinline__ void wide_eval16(const FrameDev &f, const WideJob &jb
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int p = 16 * pt + 4 * hi + e;
-            a[e] = acc[pt][qt][e] * lam[(16 * qt + lo) * 32 + p];
-            b[e] = Dw[p * 32 + 16 * xt + lo];
+            a[e] = acc[pt][qt][e] * lam[(16 * qt + lo) * kDct32Ld + p];
+            b[e] = Dw[p * kDct32Ld + 16 * xt + lo];
           }
           s4 = wmma16<EV>(s4, a, b);
         }
@@ -445,7 +446,7 @@ __device__ __forceinline__ void wide_eval16(const FrameDev &f, const WideJob &jb
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int q = 16 * qt + 4 * hi + e;
-            a[e] = Dh[q * 32 + 16 * yt + lo];
+            a[e] = Dh[q * kDct32Ld + 16 * yt + lo];
             b[e] = S[qt][xt][e];
           }
           u4 = wmma16<EV>(u4, a, b);
@@ -519,7 +520,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2
   const ShapeDev S = f.s[Q.shape];
   const int w = S.w, h = S.h;
   {
-    const int n4 = (S.jt_floats + 3072) >> 2;
+    const int n4 = (S.jt_floats + 3 * kDct32Floats) >> 2;
     const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + S.fast);
     f4 *dst = reinterpret_cast<f4 *>(tabs);
     for (int i = tid; i < n4; i += 64 * WAVES) dst[i] = src[i];
