@@ -68,7 +68,7 @@ typedef struct {
 
 /* Packed mask (CSR over blocks).  Mask blocks are ordered: the Y blocks, then
  * the chroma blocks once (chroma_shared != 0: one mask for Cb and Cr, as in
- * Sec. 2.4 of the paper) or the Cb blocks then the Cr blocks; raster order
+ * Sec. 2.3 of the paper) or the Cb blocks then the Cr blocks; raster order
  * inside each plane.  block_ptr[n_mask_blocks + 1] are int32 offsets into
  * pos; pos[] holds in-block pixel indices y*w + x (w = width of that block),
  * strictly ascending inside a block.  K = 0 is allowed (the block decodes to

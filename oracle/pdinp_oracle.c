@@ -15,7 +15,7 @@
  *        M (u - f) - (I - M) A u = 0,
  *      on a w x h block treated as an independent image with reflecting
  *      (mirrored) boundary conditions (Sec. 2.2, last paragraph), with the
- *      harmonic operator A = -L (Sec. 2.1 and Sec. 2.4), L the 5-point
+ *      harmonic operator A = -L (Sec. 2.1 and Sec. 2.3), L the 5-point
  *      Laplacian, or its square A = L^2 (s = 2).  The mask rows fix u = f,
  *      so the unknowns solve A_UU u_U = -A_UK f_K, an SPD banded system,
  *      solved here by banded Cholesky.
@@ -321,7 +321,7 @@ int orc_block_green(int w, int h, int op, double s, int K, const uint16_t *pos,
 }
 
 /* ------------------------------------------------------------------ */
-/* Whole frame: blocks independent (Sec. 2.2), planes per Sec. 2.4.   */
+/* Whole frame: blocks independent (Sec. 2.2), planes per Sec. 2.3.   */
 /* ------------------------------------------------------------------ */
 
 typedef struct {

@@ -15,7 +15,7 @@ images in Sec. 2.3 and Fig. 3 of the paper):
   per-frame peak ``A_f`` for sequences);
 * mask per block: density ``d ~ U[lo, hi]`` (or fixed), ``K = max(1,
   floor(d w h + 1/2))`` points drawn as a uniform K-subset of the w*h pixels;
-* in 4:2:0 frames both chroma planes share one mask (Sec. 2.4 of the paper:
+* in 4:2:0 frames both chroma planes share one mask (Sec. 2.3 of the paper:
   one mask for both chroma channels), each with its own values.
 
 Packed layout (identical to the C-ABI contract):
