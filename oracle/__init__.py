@@ -8,7 +8,9 @@ block_size, chroma_shared, block_ptr, pos, values``).
 
 The C source ``pdinp_oracle.c`` holds two independent routes from the paper
 (Sec. 2.1-2.2): the plain definition, Eq. (1) solved per block, and the
-Green's-function route, Eqs. (2)-(4).  Both are pinned by ``tests/`` against
+Green's-function route, Eqs. (2)-(4); and the decoder of stored, dead-zone
+quantised coefficients (Sec. 2.2 last paragraph, Sec. 2.3), Eq. (2) summed
+directly.  Both are pinned by ``tests/`` against
 facts the paper and the mathematics fix (closed forms, brute-force solves,
 textbook routines).
 """
@@ -63,6 +65,10 @@ def _lib():
             L.orc_block_green.restype = i
             L.orc_decode.argtypes = [i, i, i, i, P, P, P, i, i, i, d, P, i]
             L.orc_decode.restype = i
+            L.orc_dequant.argtypes = [i, d, d]
+            L.orc_dequant.restype = d
+            L.orc_decode_coef.argtypes = [i, i, i, i, P, P, P, i, P, P, d, i, d, P, i]
+            L.orc_decode_coef.restype = i
             _lib_handle = L
     return _lib_handle
 
@@ -159,3 +165,47 @@ def decode(frame, method: int = DIRECT, op: int = 0, s: float = 1.0,
 def decode_flat(frame, **kw) -> np.ndarray:
     """Like :func:`decode` but returns the concatenated planes (C-ABI layout)."""
     return np.concatenate([p.ravel() for p in decode(frame, **kw)])
+
+
+def dequant(q, step: float, rho: float) -> np.ndarray:
+    """Dead-zone reconstruction of stored codes (Sec. 2.3): 0 stays 0, else
+    sign(q) (|q| + rho) step."""
+    q = np.asarray(q)
+    L = _lib()
+    return np.array([L.orc_dequant(int(v), float(step), float(rho)) for v in q.ravel()]).reshape(q.shape)
+
+
+def decode_coef(frame, coef, consts, steps, rho: float, op: int = 0, s: float = 1.0,
+                nthreads: int = 0) -> List[np.ndarray]:
+    """Decode a frame from stored coefficients (Sec. 2.2, last paragraph):
+    per block u = sum_i c_i G(., x_i) + a with c_i the dequantised codes
+    (laid out like ``frame.values``) and a from ``consts`` (one per block of
+    each plane: Y, then Cb, then Cr, raster order).  ``steps``: quantiser step
+    per plane.  Returns one float64 (H, W) array per plane."""
+    dims = plane_dims(frame.width, frame.height, frame.fmt)
+    out = np.zeros(sum(W * H for W, H in dims))
+    bp = np.ascontiguousarray(frame.block_ptr, dtype=np.int32)
+    pos = np.ascontiguousarray(frame.pos, dtype=np.uint16)
+    q = np.ascontiguousarray(coef, dtype=np.int8)
+    cs = np.ascontiguousarray(consts, dtype=np.float32)
+    st = np.zeros(3)
+    st[:len(steps)] = steps
+    if pos.size == 0:
+        pos = np.zeros(1, np.uint16)
+    if q.size == 0:
+        q = np.zeros(1, np.int8)
+    rc = _lib().orc_decode_coef(frame.width, frame.height, frame.fmt, frame.block_size,
+                                _ptr(bp), _ptr(pos), _ptr(q), int(bool(frame.chroma_shared)),
+                                _ptr(cs), _ptr(st), float(rho), int(op), float(s), _ptr(out), int(nthreads))
+    if rc != 0:
+        raise ValueError("orc_decode_coef failed")
+    planes, o = [], 0
+    for W, H in dims:
+        planes.append(out[o:o + W * H].reshape(H, W))
+        o += W * H
+    return planes
+
+
+def decode_coef_flat(frame, coef, consts, steps, rho: float, **kw) -> np.ndarray:
+    """Like :func:`decode_coef` but returns the concatenated planes."""
+    return np.concatenate([p.ravel() for p in decode_coef(frame, coef, consts, steps, rho, **kw)])

@@ -441,3 +441,131 @@ int orc_decode(int width, int height, int fmt, int b, const int32_t *block_ptr,
     free(items);
     return err ? -1 : 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* (3) The decoder of stored coefficients: when the encoder keeps c   */
+/*     and a of every block (Sec. 2.2, last paragraph), the decoder   */
+/*     only evaluates Eq. (2).  The coefficients are stored as codes  */
+/*     in [-127, 127] of a uniform quantiser with a dead zone around  */
+/*     zero, so that zero comes back as zero (Sec. 2.3).              */
+/* ------------------------------------------------------------------ */
+
+/* Reconstruction of one code: 0 for q = 0, else sign(q) (|q| + rho) step.
+ * rho in [0, 1) places the value inside the quantiser interval (0: its
+ * edge nearer zero, 0.5: its middle); step is the plane's step. */
+double orc_dequant(int q, double step, double rho)
+{
+    if (q == 0) return 0.0;
+    return (q > 0 ? 1.0 : -1.0) * ((double)abs(q) + rho) * step;
+}
+
+/* Decode every block of a frame from stored coefficients.  Geometry, mask
+ * layout and chroma sharing as for orc_decode; coef[] is laid out like the
+ * values of orc_decode (one code per mask point and value plane); consts[]
+ * holds a for every block of every plane: the Y blocks, then Cb, then Cr,
+ * raster order.  steps[plane] is the quantiser step of the plane.  Per
+ * block, u_k = sum_i c_i G(x_k, x_i) + a over all pixels k (Eq. 2), G
+ * from the table of orc_green_table, summed directly.  K = 0 gives u = a.
+ * Returns 0, or -1 on a position outside its block. */
+int orc_decode_coef(int width, int height, int fmt, int b, const int32_t *block_ptr,
+                    const uint16_t *pos, const int8_t *coef, int chroma_shared,
+                    const float *consts, const double *steps, double rho,
+                    int op, double s, double *out, int nthreads)
+{
+    int PW[3], PH[3], NB[3], np_, g, ngroups, mp[3], vp[3][2], nv[3];
+    long long poff[3], cbase[3], nnz;
+    int nitems = 0, cap, chroma_first = -1, m = 0, err = 0, it, k;
+    int nshape = 0, shw[16], shh[16];
+    double *shtab[16];
+    orc_item *items;
+    int *pblock;
+    if (fmt == 0) { np_ = 1; PW[0] = width; PH[0] = height; }
+    else { np_ = 3; PW[0] = width; PH[0] = height;
+           PW[1] = PW[2] = (width + 1) / 2; PH[1] = PH[2] = (height + 1) / 2; }
+    poff[0] = 0;
+    cbase[0] = 0;
+    for (g = 0; g < np_; g++) NB[g] = ((PW[g] + b - 1) / b) * ((PH[g] + b - 1) / b);
+    for (g = 1; g < np_; g++) {
+        poff[g] = poff[g - 1] + (long long)PW[g - 1] * PH[g - 1];
+        cbase[g] = cbase[g - 1] + NB[g - 1];
+    }
+    if (fmt == 0) { ngroups = 1; mp[0] = 0; vp[0][0] = 0; nv[0] = 1; }
+    else if (chroma_shared) { ngroups = 2; mp[0] = 0; vp[0][0] = 0; nv[0] = 1;
+                              mp[1] = 1; vp[1][0] = 1; vp[1][1] = 2; nv[1] = 2; }
+    else { ngroups = 3; for (g = 0; g < 3; g++) { mp[g] = g; vp[g][0] = g; nv[g] = 1; } }
+    cap = 0;
+    for (g = 0; g < ngroups; g++) cap += NB[mp[g]];
+    items = (orc_item *)malloc(sizeof(orc_item) * (size_t)cap);
+    pblock = (int *)malloc(sizeof(int) * (size_t)cap);  /* block index inside its plane */
+    for (g = 0; g < ngroups; g++) {
+        int W = PW[mp[g]], H = PH[mp[g]], bx, by;
+        if (mp[g] == 1) chroma_first = m;
+        for (by = 0; by < (H + b - 1) / b; by++)
+            for (bx = 0; bx < (W + b - 1) / b; bx++) {
+                orc_item *I = &items[nitems];
+                pblock[nitems++] = by * ((W + b - 1) / b) + bx;
+                I->m = m; I->x0 = bx * b; I->y0 = by * b;
+                I->w = W - I->x0 < b ? W - I->x0 : b;
+                I->h = H - I->y0 < b ? H - I->y0 : b;
+                I->pw = W; I->nplanes = nv[g];
+                for (k = 0; k < nv[g]; k++) I->plane[k] = vp[g][k];
+                m++;
+            }
+    }
+    nnz = block_ptr[m];
+    for (it = 0; it < nitems; it++) {
+        orc_item *I = &items[it];
+        for (k = 0; k < I->nplanes; k++) {
+            if (I->plane[k] == 2 && chroma_shared)
+                I->vbase[k] = nnz + (block_ptr[I->m] - block_ptr[chroma_first]);
+            else
+                I->vbase[k] = block_ptr[I->m];
+        }
+        for (k = 0; k < nshape; k++)
+            if (shw[k] == I->w && shh[k] == I->h) break;
+        if (k == nshape && nshape < 16) {
+            double *lam = (double *)malloc(sizeof(double) * (size_t)I->w * I->h);
+            shw[nshape] = I->w; shh[nshape] = I->h;
+            shtab[nshape] = (double *)malloc(sizeof(double) * (size_t)(I->w + 1) * (I->h + 1));
+            orc_eigenvalues(I->w, I->h, op, s, lam);
+            orc_green_table(I->w, I->h, lam, shtab[nshape]);
+            free(lam);
+            nshape++;
+        }
+    }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16) reduction(|:err)
+#endif
+    for (it = 0; it < nitems; it++) {
+        orc_item *I = &items[it];
+        int K = block_ptr[I->m + 1] - block_ptr[I->m];
+        const uint16_t *ps = pos + block_ptr[I->m];
+        const double *tab = 0;
+        int t, i, j, kk;
+        for (kk = 0; kk < nshape; kk++)
+            if (shw[kk] == I->w && shh[kk] == I->h) tab = shtab[kk];
+        if (tab == 0) { err |= 1; continue; }
+        for (i = 0; i < K; i++)
+            if (ps[i] >= I->w * I->h) err |= 1;
+        if (err) continue;
+        for (kk = 0; kk < I->nplanes; kk++) {
+            int pl = I->plane[kk];
+            double a = (double)consts[cbase[pl] + pblock[it]];
+            double *dst = out + poff[pl];
+            for (t = 0; t < I->h; t++)
+                for (j = 0; j < I->w; j++) {
+                    double acc = 0.0;
+                    for (i = 0; i < K; i++) {
+                        double c = orc_dequant(coef[I->vbase[kk] + i], steps[pl], rho);
+                        acc += c * orc_green(I->w, I->h, tab, j, t, ps[i] % I->w, ps[i] / I->w);
+                    }
+                    dst[(long long)(I->y0 + t) * I->pw + I->x0 + j] = acc + a;
+                }
+        }
+    }
+    for (it = 0; it < nshape; it++) free(shtab[it]);
+    free(items);
+    free(pblock);
+    return err ? -1 : 0;
+}

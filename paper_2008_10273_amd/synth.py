@@ -255,6 +255,11 @@ CONFIGS: Dict[int, dict] = {
             block_size=16, density=(0.01, 0.10), frames=64, amp_range=(5.0, 64.0)),
 }
 
+# Coefficient-input workload: the paper's 8x8 residual blocks (Sec. 2.3) on a
+# 1080p 4:2:0 frame, masks drawn as for config 1; see coef_inputs.
+COEF_CONFIG = dict(name="fhd420_b8_coef_d1-10", width=1920, height=1080, fmt=YUV420,
+                   block_size=8, density=(0.01, 0.10), steps=(0.25, 0.25, 0.25), rho=0.5)
+
 # Serving mix: (width, height, count) per resolution class, 4:2:0, b16.
 SERVING_MIX = [(854, 480, 6), (1280, 720, 6), (1920, 1080, 4)]
 
@@ -299,3 +304,33 @@ def random_frame(width: int, height: int, fmt: int, block_size: int,
     """A small seeded frame for parity tests (any geometry)."""
     return make_frame(width, height, fmt, block_size, density, (SEED_ROOT, 99, seed, 0),
                       chroma_shared=chroma_shared)
+
+
+def plane_block_counts(width: int, height: int, fmt: int, block_size: int) -> List[int]:
+    """Number of blocks of every plane (edge blocks included)."""
+    return [((W + block_size - 1) // block_size) * ((H + block_size - 1) // block_size)
+            for W, H in plane_dims(width, height, fmt)]
+
+
+def coef_inputs(frame: Frame, seed) -> Tuple[np.ndarray, np.ndarray]:
+    """Stored-coefficient inputs for ``frame``'s mask: int8 codes laid out like
+    ``frame.values`` and one FP32 constant per block of every plane (Y, then
+    Cb, then Cr, raster order).  Codes are rounded draws clipped to
+    [-127, 127] with Laplace(0, 3) (mostly small, about 15 % zero: the shape a
+    dead-zone quantiser leaves); constants are U[-64, 64].  Random numbers
+    only."""
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_ROOT, 5] + list(np.atleast_1d(seed))))
+    q = np.clip(np.rint(rng.laplace(0.0, 3.0, frame.values.size)), -127, 127).astype(np.int8)
+    nb = sum(plane_block_counts(frame.width, frame.height, frame.fmt, frame.block_size))
+    consts = rng.uniform(-64.0, 64.0, nb).astype(np.float32)
+    return q, consts
+
+
+def coef_frame(frame: int = 0) -> Tuple[Frame, np.ndarray, np.ndarray]:
+    """Frame ``frame`` of the coefficient-input workload: (mask frame, codes,
+    constants)."""
+    c = COEF_CONFIG
+    fr = make_frame(c["width"], c["height"], c["fmt"], c["block_size"], c["density"],
+                    (SEED_ROOT, 5, 0, frame), keep_fields=False)
+    q, consts = coef_inputs(fr, (0, frame))
+    return fr, q, consts

@@ -315,3 +315,115 @@ def test_planted_mistake_is_caught():
     lam_bad = lam.copy()
     lam_bad[1] *= 1.01
     assert np.abs(C.T @ np.diag(lam_bad) @ C - P).max() > 1e-4
+
+
+# ------------------------------------------------- stored coefficients
+
+def test_dequant_codes():
+    """Dead-zone reconstruction (Sec. 2.3): hand-computed values; catches a
+    lost offset, a wrong sign for negative codes or a zero that comes back
+    non-zero."""
+    cases = [(0, 0.5, 0.5, 0.0), (3, 0.5, 0.5, 1.75), (-2, 0.5, 0.5, -1.25), (1, 2.0, 0.0, 2.0),
+             (-127, 1.0, 0.25, -127.25), (127, 0.125, 0.0, 15.875), (0, 7.0, 0.9, 0.0)]
+    for q, step, rho, want in cases:
+        assert oracle.dequant([q], step, rho)[0] == want, (q, step, rho)
+
+
+def _coef_identity(w, h, pos, c, a, u):
+    """u solves A u = M c - mean_k(M c) with mean(u) = a, A = -L built by
+    Kronecker products (no Green's table, no DCT); these fix u uniquely."""
+    A = brute.neg_laplacian(w, h)
+    mc = np.zeros(w * h)
+    mc[np.asarray(pos, dtype=np.int64)] = c
+    np.testing.assert_allclose(A @ u.ravel(), mc - mc.mean(), atol=1e-9 * max(1.0, np.abs(c).sum()))
+    assert abs(u.mean() - a) <= 1e-10 * max(1.0, abs(a) + np.abs(u).max())
+
+
+@pytest.mark.parametrize("fmt,shared", [(synth.GRAY, True), (synth.YUV420, True), (synth.YUV420, False)])
+def test_coef_decode_solves_operator_equation(fmt, shared):
+    """Every block of a frame decoded from codes satisfies A u = M c -
+    mean(M c) and mean(u) = a (Eq. 2 with G the pseudo-inverse of A and the
+    constant its null space), for ragged edge blocks, K = 0, K = w*h, shared
+    and separate chroma masks; catches a wrong Green's weight or sign, a
+    code read from the wrong run, a constant of the wrong block or plane."""
+    W, H, b = 21, 13, 8
+    # one empty and one full block in the Y plane
+    rng = _rng(4)
+    ms, fs = [], []
+    dims = synth.plane_dims(W, H, fmt)
+    for k, (pw, ph) in enumerate(dims):
+        m = rng.uniform(size=(ph, pw)) < 0.3
+        if k == 0:
+            m[:8, :8] = False
+            m[:8, 8:16] = True
+        ms.append(m)
+        fs.append(rng.uniform(-64, 64, (ph, pw)))
+    if fmt == synth.YUV420 and shared:
+        ms = ms[:2]
+    fr = synth.pack_dense(W, H, fmt, b, ms, fs)
+    q, consts = synth.coef_inputs(fr, 7)
+    steps = (0.5, 0.25, 0.75)
+    rho = 0.5
+    planes = oracle.decode_coef(fr, q, consts, steps, rho)
+    # walk the documented layout independently of the oracle
+    bp = fr.block_ptr
+    groups = [[0]] if fmt == synth.GRAY else ([[0], [1, 2]] if fr.chroma_shared else [[0], [1], [2]])
+    cbase = np.concatenate([[0], np.cumsum(synth.plane_block_counts(W, H, fmt, b))])
+    m = 0
+    chroma_first = None
+    runs = []
+    for gp in groups:
+        pw, ph = dims[gp[0]]
+        if gp[0] == 1:
+            chroma_first = m
+        for k, (x0, y0, w, h) in enumerate(synth.block_grid(pw, ph, b)):
+            runs.append((gp, k, x0, y0, w, h, m))
+            m += 1
+    nnz = bp[m]
+    checked = 0
+    for gp, k, x0, y0, w, h, mb in runs:
+        lo, hi = bp[mb], bp[mb + 1]
+        pos = fr.pos[lo:hi]
+        for pl in gp:
+            vb = nnz + (lo - bp[chroma_first]) if (pl == 2 and fr.chroma_shared) else lo
+            codes = q[vb:vb + (hi - lo)].astype(np.float64)
+            c = np.where(codes == 0, 0.0, np.sign(codes) * (np.abs(codes) + rho) * steps[pl])
+            a = float(consts[cbase[pl] + k])
+            u = planes[pl][y0:y0 + h, x0:x0 + w]
+            _coef_identity(w, h, pos, c, a, u)
+            checked += 1
+    assert checked == sum(synth.plane_block_counts(W, H, fmt, b))
+
+
+def test_coef_zero_codes_give_constant():
+    """All codes zero: every block is its constant."""
+    fr = synth.random_frame(24, 16, synth.YUV420, 8, (0.1, 0.4), seed=5)
+    q = np.zeros(fr.values.size, np.int8)
+    consts = np.arange(sum(synth.plane_block_counts(24, 16, synth.YUV420, 8)), dtype=np.float32) - 7.0
+    planes = oracle.decode_coef(fr, q, consts, (1.0, 1.0, 1.0), 0.5)
+    k = 0
+    for pl, (pw, ph) in enumerate(synth.plane_dims(24, 16, synth.YUV420)):
+        for (x0, y0, w, h) in synth.block_grid(pw, ph, 8):
+            assert np.all(planes[pl][y0:y0 + h, x0:x0 + w] == consts[k])
+            k += 1
+
+
+def test_coef_round_trip_of_the_solve():
+    """Coefficients taken from the plain definition (c = A u at the mask
+    points of the Eq. (1) solution, a = its mean), stored with a fine step,
+    decode back to that solution within the quantisation bound: the stored
+    form is the same inpainting (Sec. 2.2, last paragraph)."""
+    w = h = 8
+    rng = _rng(12)
+    pos = np.sort(rng.choice(w * h, 9, replace=False))
+    r = rng.uniform(-64, 64, pos.size)
+    u = brute.solve_eq1(w, h, pos, r, brute.operator(w, h, 1))
+    c = (brute.neg_laplacian(w, h) @ u.ravel())[pos]
+    step = np.abs(c).max() / 120.0
+    qc = np.rint(c / step).astype(np.int8)
+    fr = synth.pack_dense(w, h, synth.GRAY, 8, [np.isin(np.arange(w * h), pos).reshape(h, w)],
+                          [u.reshape(h, w)])
+    got = oracle.decode_coef(fr, qc, np.array([u.mean()], np.float32), (step,), 0.0)[0]
+    G = np.linalg.pinv(brute.neg_laplacian(w, h))
+    bound = 0.5 * step * np.abs(G).max() * pos.size + 1e-4
+    assert np.abs(got - u.reshape(h, w)).max() <= bound
