@@ -140,6 +140,46 @@ int decode_residual_batch(pdi_ctx *ctx, int n, const pdi_frame *frame, const pdi
                           const float *const *values, int block_size, const pdi_params *params,
                           float *const *outs, void *stream);
 
+/* ---- Decoding stored coefficients (the paper's decoder split) ----
+ * When the encoder keeps each block's Green's-function coefficients c and
+ * constant a (Sec. 2.2, last paragraph), the decoder only evaluates Eq. 2,
+ * u = sum_i c_i G(., x_i) + a over the block (here through Eq. 4 as for
+ * decode_residual), with no system to solve.  The coefficients are stored
+ * as codes q in [-127, 127] of a uniform quantiser with a dead zone around
+ * zero (Sec. 2.3); a code is reconstructed as 0 for q = 0, else as
+ * sign(q) (|q| + rho) step[plane]. */
+typedef struct {
+    float step[3]; /* quantiser step of the Y, Cb, Cr planes (GRAY: step[0]); finite, >= 0 */
+    float rho;     /* reconstruction offset inside the quantiser interval, [0, 1) */
+} pdi_coef_params;
+
+/* Decode one frame from stored coefficients.  frame, mask, block_size and
+ * out as for decode_residual (DEVICE pointers, caller owned); qp is a HOST
+ * pointer read during the call.
+ *   coef:   int8 codes laid out exactly like decode_residual's values (one
+ *           per mask point and value plane: Y, then the chroma runs).
+ *   consts: FP32 constant a of EVERY block of every plane: the Y blocks,
+ *           then Cb, then Cr, raster order inside each plane
+ *           (ceil(W/b) * ceil(H/b) per plane, edge blocks included).
+ * A block with K = 0 becomes its constant; K = w*h is allowed.  params: op,
+ * s, eval_dtype, validate and out_int8 apply as for decode_residual; refine
+ * and path do not (no solve).  With validate = 1 a code of -128 or a
+ * non-finite constant is reported as PDI_EVALUE and bad positions as
+ * PDI_EMASK at pdi_sync.  Returns PDI_EINVAL for a NULL pointer, a bad step
+ * (non-finite or negative) or rho outside [0, 1); otherwise as
+ * decode_residual. */
+int decode_coefficients(pdi_ctx *ctx, const pdi_frame *frame, const pdi_mask *mask,
+                        const int8_t *coef, const float *consts, const pdi_coef_params *qp,
+                        int block_size, const pdi_params *params, float *out, void *stream);
+
+/* decode_coefficients for n (1..PDI_MAX_BATCH) frames of one geometry in one
+ * launch of each kernel (coefs[k], consts[k], outs[k] as for frame k alone;
+ * the host arrays are read during the call only). */
+int decode_coefficients_batch(pdi_ctx *ctx, int n, const pdi_frame *frame, const pdi_mask *masks,
+                              const int8_t *const *coefs, const float *const *consts,
+                              const pdi_coef_params *qp, int block_size, const pdi_params *params,
+                              float *const *outs, void *stream);
+
 /* Wait for `stream`, then read and clear the device status word.
  * Returns PDI_OK, PDI_EMASK, PDI_EVALUE, PDI_ESOLVE or PDI_EHIP. */
 int pdi_sync(pdi_ctx *ctx, void *stream);

@@ -24,7 +24,7 @@ ERROR_NAMES = {0: "PDI_OK", -1: "PDI_EINVAL", -2: "PDI_EMASK", -3: "PDI_ENOMEM",
                -5: "PDI_EBUSY", -6: "PDI_EVALUE", -7: "PDI_ESOLVE"}
 
 EXPORTS = ["pdi_default_params", "pdi_create", "pdi_destroy", "decode_residual", "decode_residual_batch",
-           "pdi_sync",
+           "decode_coefficients", "decode_coefficients_batch", "pdi_sync",
            "pdi_last_error", "pdi_frame_info", "pdi_pack_dense", "pdi_validate_host", "pdi_autotune", "pdi_autotune_batch",
            "pdi_seq_create", "pdi_seq_launch", "pdi_seq_sync", "pdi_seq_destroy",
            "pdi_server_create", "pdi_submit", "pdi_poll", "pdi_wait", "pdi_server_stats",
@@ -44,6 +44,19 @@ class pdi_params(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("s", ctypes.c_double), ("eval_dtype", ctypes.c_int32),
                 ("refine", ctypes.c_int32), ("validate", ctypes.c_int32), ("path", ctypes.c_int32),
                 ("refine_tau", ctypes.c_double), ("out_int8", ctypes.c_int32)]
+
+
+class pdi_coef_params(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_float * 3), ("rho", ctypes.c_float)]
+
+
+def coef_params(steps, rho: float) -> pdi_coef_params:
+    q = pdi_coef_params()
+    st = list(steps) + [0.0] * (3 - len(steps))
+    for k in range(3):
+        q.step[k] = float(st[k])
+    q.rho = float(rho)
+    return q
 
 
 class PdiError(RuntimeError):
@@ -76,6 +89,14 @@ def lib() -> ctypes.CDLL:
                                             ctypes.POINTER(ctypes.c_void_p), i32, ctypes.POINTER(pdi_params),
                                             ctypes.POINTER(ctypes.c_void_p), P]
         L.decode_residual_batch.restype = i32
+        VP = ctypes.POINTER(ctypes.c_void_p)
+        L.decode_coefficients.argtypes = [P, ctypes.POINTER(pdi_frame), ctypes.POINTER(pdi_mask), P, P,
+                                          ctypes.POINTER(pdi_coef_params), i32, ctypes.POINTER(pdi_params), P, P]
+        L.decode_coefficients.restype = i32
+        L.decode_coefficients_batch.argtypes = [P, i32, ctypes.POINTER(pdi_frame), ctypes.POINTER(pdi_mask), VP,
+                                                VP, ctypes.POINTER(pdi_coef_params), i32,
+                                                ctypes.POINTER(pdi_params), VP, P]
+        L.decode_coefficients_batch.restype = i32
         L.pdi_sync.argtypes = [P, P]
         L.pdi_sync.restype = i32
         L.pdi_last_error.argtypes = [P]
@@ -240,6 +261,61 @@ class Decoder:
         out_i8 = torch.empty(nel, dtype=torch.int8, device=dev)
         return dict(frame=frame, block_ptr=bp, pos=pos_t, values=vals_t, out=out, out_i8=out_i8,
                     n_mask_blocks=int(frame.block_ptr.shape[0] - 1))
+
+    def upload_coef(self, frame, coef, consts):
+        """upload() plus stored-coefficient inputs: int8 codes (laid out like
+        the values) and one FP32 constant per block of every plane."""
+        import numpy as np
+        torch = self.torch
+        dev = torch.device("cuda", self.device)
+        d = self.upload(frame)
+        q = np.ascontiguousarray(coef, np.int8)
+        d["coef"] = torch.from_numpy(q if q.size else np.zeros(1, np.int8)).to(dev)
+        cs = np.ascontiguousarray(consts, np.float32)
+        d["consts"] = torch.from_numpy(cs if cs.size else np.zeros(1, np.float32)).to(dev)
+        return d
+
+    def decode_coef(self, d, qp: pdi_coef_params, params: Optional[pdi_params] = None, stream=None,
+                    check=True) -> int:
+        """decode_coefficients on a frame from upload_coef."""
+        fr = d["frame"]
+        out = d["out_i8"] if (params is not None and params.out_int8) else d["out"]
+        s = stream.cuda_stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
+        f = pdi_frame(fr.width, fr.height, fr.fmt)
+        mk = pdi_mask(d["block_ptr"].data_ptr(), d["pos"].data_ptr(), d["n_mask_blocks"], int(bool(fr.chroma_shared)))
+        rc = lib().decode_coefficients(self.ctx, ctypes.byref(f), ctypes.byref(mk), d["coef"].data_ptr(),
+                                       d["consts"].data_ptr(), ctypes.byref(qp) if qp is not None else None,
+                                       fr.block_size, ctypes.byref(params) if params is not None else None,
+                                       out.data_ptr(), s)
+        if check and rc != PDI_OK:
+            raise PdiError(rc, pdi_last_error(self.ctx))
+        return rc
+
+    def decode_coef_batch(self, ds, qp: pdi_coef_params, params: Optional[pdi_params] = None, stream=None,
+                          check=True) -> int:
+        """decode_coefficients_batch over frames from upload_coef (one geometry)."""
+        n = len(ds)
+        f0 = ds[0]["frame"]
+        fr = pdi_frame(f0.width, f0.height, f0.fmt)
+        masks = (pdi_mask * n)()
+        qs = (ctypes.c_void_p * n)()
+        cs = (ctypes.c_void_p * n)()
+        outs = (ctypes.c_void_p * n)()
+        i8 = params is not None and params.out_int8
+        for k, d in enumerate(ds):
+            f = d["frame"]
+            masks[k] = pdi_mask(d["block_ptr"].data_ptr(), d["pos"].data_ptr(), d["n_mask_blocks"],
+                                int(bool(f.chroma_shared)))
+            qs[k] = d["coef"].data_ptr()
+            cs[k] = d["consts"].data_ptr()
+            outs[k] = (d["out_i8"] if i8 else d["out"]).data_ptr()
+        s = stream.cuda_stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
+        rc = lib().decode_coefficients_batch(self.ctx, n, ctypes.byref(fr), masks, qs, cs,
+                                             ctypes.byref(qp) if qp is not None else None, f0.block_size,
+                                             ctypes.byref(params) if params is not None else None, outs, s)
+        if check and rc != PDI_OK:
+            raise PdiError(rc, pdi_last_error(self.ctx))
+        return rc
 
     def decode(self, d, params: Optional[pdi_params] = None, stream=None, out=None, check=True) -> int:
         fr = d["frame"]

@@ -33,6 +33,13 @@ __device__ __forceinline__ void store_px(const FrameDev &f, int fi, long long id
   }
 }
 
+// Reconstruction of a stored code (dead-zone quantiser, Sec. 2.3 of the
+// paper): 0 stays 0, else sign(q) (|q| + rho) step.
+__device__ __forceinline__ float coef_value(int q, float step, float rho) {
+  const float m = ((float)abs(q) + rho) * step;
+  return q == 0 ? 0.f : (q > 0 ? m : -m);
+}
+
 // Make this lane's LDS writes visible to the other lanes of its wave (no
 // instruction beyond the wait the writes need).
 __device__ __forceinline__ void wave_sync() {

@@ -434,13 +434,24 @@ int pdi_frame_info(const pdi_frame *frame, int block_size, int chroma_shared,
   return PDI_OK;
 }
 
-// Decode n frames of one geometry (one launch per kernel for all of them).
+// Decode n frames of one geometry (one launch per kernel for all of them):
+// residual decodes (values, qp == nullptr) or stored-coefficient decodes
+// (coefs + consts, qp != nullptr).
 static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask *masks,
                        const float *const *values, int block_size, const pdi_params *params,
-                       float *const *outs, void *stream) {
+                       float *const *outs, void *stream, const int8_t *const *coefs = nullptr,
+                       const float *const *consts = nullptr, const pdi_coef_params *qp = nullptr) {
   if (!c) return PDI_EINVAL;
+  const bool coef = qp != nullptr;
   if (n < 1 || n > pdi::kMaxBatch) return set_err(c, PDI_EINVAL, "batch of %d frames (1..%d)", n, pdi::kMaxBatch);
-  if (!frame || !masks || !values || !outs) return set_err(c, PDI_EINVAL, "null frame, mask, values or out");
+  if (!frame || !masks || !outs || (coef ? (!coefs || !consts) : !values))
+    return set_err(c, PDI_EINVAL, coef ? "null frame, mask, coefficients, constants or out"
+                                       : "null frame, mask, values or out");
+  if (coef) {
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(qp->step[k]) || qp->step[k] < 0.f) return set_err(c, PDI_EINVAL, "bad quantiser step");
+    if (!(qp->rho >= 0.f) || !(qp->rho < 1.f)) return set_err(c, PDI_EINVAL, "rho must be in [0, 1)");
+  }
   const pdi_mask *mask = &masks[0];
   if (check_geometry(frame, block_size))
     return set_err(c, PDI_EINVAL, "bad geometry %dx%d format %d block %d", frame->width,
@@ -464,8 +475,9 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
     if (sh != shared) return set_err(c, PDI_EINVAL, "frame %d: chroma sharing differs within the batch", k);
     if (nitems != mk.n_mask_blocks)
       return set_err(c, PDI_EINVAL, "n_mask_blocks %d, geometry needs %lld", mk.n_mask_blocks, nitems);
-    if (!mk.block_ptr || !mk.pos || !values[k] || !outs[k])
-      return set_err(c, PDI_EINVAL, "frame %d: null block_ptr, pos, values or out", k);
+    if (!mk.block_ptr || !mk.pos || !outs[k] || (coef ? (!coefs[k] || !consts[k]) : !values[k]))
+      return set_err(c, PDI_EINVAL, "frame %d: null block_ptr, pos, %s or out", k,
+                     coef ? "coefficients, constants" : "values");
   }
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
@@ -489,10 +501,19 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
   F.tau = (float)P.refine_tau;
   F.eval = P.eval_dtype;
   F.out_i8 = P.out_int8;
+  F.coef = coef ? 1 : 0;
+  if (coef) {
+    for (int k = 0; k < 3; ++k) F.qstep[k] = qp->step[k];
+    F.qrho = qp->rho;
+  }
   PlaneGeom pg[3];
   planes_of(frame, pg);
   long long poff[3] = {0, 0, 0};
-  for (int i = 1; i < 3; ++i) poff[i] = poff[i - 1] + (long long)pg[i - 1].W * pg[i - 1].H;
+  int pbo[3] = {0, 0, 0};  // first block of each plane in consts[]
+  for (int i = 1; i < 3; ++i) {
+    poff[i] = poff[i - 1] + (long long)pg[i - 1].W * pg[i - 1].H;
+    pbo[i] = pbo[i - 1] + ((pg[i - 1].W + block_size - 1) / block_size) * ((pg[i - 1].H + block_size - 1) / block_size);
+  }
   int mp[3], vp[3][2], nv[3];
   F.ngroups = groups_of(frame, shared, mp, vp, nv);
   int first = 0;
@@ -505,7 +526,11 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
     G.nbx = (G.W + block_size - 1) / block_size;
     G.nby = (G.H + block_size - 1) / block_size;
     G.nv = nv[g];
-    for (int k = 0; k < nv[g]; ++k) { G.vplane[k] = vp[g][k]; G.out_off[k] = poff[vp[g][k]]; }
+    for (int k = 0; k < nv[g]; ++k) {
+      G.vplane[k] = vp[g][k];
+      G.out_off[k] = poff[vp[g][k]];
+      G.cbase[k] = pbo[vp[g][k]];
+    }
     for (int k = 0; k < 4; ++k) G.shape[k] = ts->group_shape[g][k];
     if (mp[g] == 1) F.chroma_first = first;
     first += G.nbx * G.nby;
@@ -514,10 +539,11 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
   for (int k = 0; k < ts->nshapes; ++k) F.s[k] = ts->s[k];
   // Shape-homogeneous runs of blocks for the batched paths: k_fast (b <= 16,
   // 16 blocks per workgroup) or k_wide (b = 32, 4 blocks per workgroup).
-  const bool fast = (P.path == PDI_PATH_AUTO && block_size <= 16);
-  const bool wide = (P.path == PDI_PATH_AUTO && block_size == 32);
+  // Stored-coefficient decodes always take the batched paths (no solve).
+  const bool fast = ((coef || P.path == PDI_PATH_AUTO) && block_size <= 16);
+  const bool wide = ((coef || P.path == PDI_PATH_AUTO) && block_size == 32);
   int ipw = fast ? pdi::kFastItemsPerWG : pdi::kWideItemsDefault;
-  {
+  if (!coef) {
     auto it = c->tune.find(TuneKey{frame->width, frame->height, frame->format, block_size, shared, P.op, P.s,
                                    P.eval_dtype, n});
     if (it != c->tune.end()) ipw = it->second;
@@ -550,7 +576,8 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
       F.fast_wgs += (S.count + ipw - 1) / ipw;
       shape_count[S.shape] += S.count;
       const pdi::ShapeDev &SH = ts->s[S.shape];
-      if (SH.jt_floats + dct_floats > F.fast_lds) F.fast_lds = SH.jt_floats + dct_floats;
+      const int need = (coef ? 0 : SH.jt_floats) + dct_floats;  // coef: the matrices only
+      if (need > F.fast_lds) F.fast_lds = need;
     }
   }
   if (wide) {
@@ -578,12 +605,14 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
   if (rc) return rc;
   F.tab32_floats = ts->tab32_floats;
   F.nframes = n;
-  F.tail_in_wg = (n == 1) ? 1 : 0;
+  F.tail_in_wg = (n == 1 && !coef) ? 1 : 0;
   for (int k = 0; k < n; ++k) {
     F.fp[k].block_ptr = masks[k].block_ptr;
     F.fp[k].pos = masks[k].pos;
-    F.fp[k].values = values[k];
+    F.fp[k].values = coef ? nullptr : values[k];
     F.fp[k].out = outs[k];
+    F.fp[k].coef = coef ? coefs[k] : nullptr;
+    F.fp[k].consts = coef ? consts[k] : nullptr;
   }
   F.tab32 = ts->tab32;
   F.tab64 = ts->tab64;
@@ -594,7 +623,11 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
   F.slots = W->slots;
   F.slot_floats = W->slot_floats;
 
-  if (fast) {
+  if (coef) {
+    // Batched kernels, then the blocks with more points than they stage.
+    e = fast ? pdi::launch_fast(F, s) : pdi::launch_wide(F, s);
+    if (e == hipSuccess) e = pdi::launch_coef_general(F, s);
+  } else if (fast) {
     // A single frame: one launch, the workgroups also decode their leftover
     // blocks.  A batch: leftover blocks go to the deferred pass.
     e = pdi::launch_fast(F, s);
@@ -620,6 +653,21 @@ int decode_residual_batch(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_m
                           const float *const *values, int block_size, const pdi_params *params,
                           float *const *outs, void *stream) {
   return decode_impl(c, n, frame, masks, values, block_size, params, outs, stream);
+}
+
+int decode_coefficients(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, const int8_t *coef,
+                        const float *consts, const pdi_coef_params *qp, int block_size,
+                        const pdi_params *params, float *out, void *stream) {
+  if (c && (!mask || !out || !qp)) return set_err(c, PDI_EINVAL, "null mask, quantiser params or out");
+  return decode_impl(c, 1, frame, mask, nullptr, block_size, params, &out, stream, &coef, &consts, qp);
+}
+
+int decode_coefficients_batch(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask *masks,
+                              const int8_t *const *coefs, const float *const *consts,
+                              const pdi_coef_params *qp, int block_size, const pdi_params *params,
+                              float *const *outs, void *stream) {
+  if (c && !qp) return set_err(c, PDI_EINVAL, "null quantiser params");
+  return decode_impl(c, n, frame, masks, nullptr, block_size, params, outs, stream, coefs, consts, qp);
 }
 
 int pdi_sync(pdi_ctx *c, void *stream) {

@@ -81,6 +81,9 @@ struct GroupDev {
   int vplane[2];        // value planes (0 = Y, 1 = Cb, 2 = Cr)
   long long out_off[2]; // output offset of each value plane (floats)
   int shape[4];         // shape ids: full, right edge, bottom edge, corner
+  int cbase[2];         // stored-coefficient decodes: index in consts[] of the
+                        // first block of each value plane (block l of the
+                        // group is at cbase[v] + l)
 };
 
 // Caller buffers of one frame of a launch.
@@ -89,6 +92,8 @@ struct FramePtrs {
   const uint16_t *pos;
   const float *values;
   float *out;  // FP32 planes, or int8 planes when out_i8
+  const int8_t *coef;    // stored-coefficient decodes: codes, laid out like values
+  const float *consts;   // and the constant of every block of every plane
 };
 
 struct FrameDev {
@@ -103,6 +108,9 @@ struct FrameDev {
   float tau;         // auto-refine threshold on min/max pivot
   int eval;          // PDI_EVAL_*
   int out_i8;        // 1: out holds int8 pixels, clamp(rint(u), -128, 127)
+  int coef;          // 1: stored coefficients (codes + constants), no solve
+  float qstep[3];    // quantiser step per plane (coef)
+  float qrho;        // reconstruction offset (coef)
   GroupDev g[kMaxGroups];
   ShapeDev s[kMaxShapes];
   SegDev seg[kMaxSegs];
@@ -134,5 +142,6 @@ hipError_t launch_fast(const FrameDev &f, hipStream_t stream);
 hipError_t launch_wide(const FrameDev &f, hipStream_t stream);  // binning kernel + k_wide
 hipError_t launch_plain_all(const FrameDev &f, hipStream_t stream);
 hipError_t launch_general_deferred(const FrameDev &f, hipStream_t stream);
+hipError_t launch_coef_general(const FrameDev &f, hipStream_t stream);  // coef: the deferred blocks
 
 }  // namespace pdi

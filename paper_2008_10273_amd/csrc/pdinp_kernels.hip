@@ -26,7 +26,7 @@ namespace pdi {
 // ------------------------------------------------------------------ items
 
 struct Item {
-  int K, base, w, h, x0, y0, shape, nv, W;
+  int K, base, w, h, x0, y0, shape, nv, W, g, l;  // g: group, l: block index in its plane
   long long vbase0, vbase1, obase0, obase1;
   __device__ __forceinline__ long long vbase(int v) const { return v ? vbase1 : vbase0; }
   __device__ __forceinline__ long long obase(int v) const { return v ? obase1 : obase0; }
@@ -40,6 +40,8 @@ __device__ __forceinline__ Item load_item(const FrameDev &f, const int32_t *bp, 
   const GroupDev &G = f.g[g];
   const int b = f.b;
   int l = m - G.first;
+  it.g = g;
+  it.l = l;
   int bx = l % G.nbx, by = l / G.nbx;
   it.x0 = bx * b;
   it.y0 = by * b;
@@ -376,10 +378,53 @@ struct FastStage {
 };
 
 // Size class of a block for the wave-level path: 0, 1, 2 -> R = 16, 24, 32
-// rows; 3 -> not taken (general path).
+// rows (staged points); 3 -> not taken (general path).  Stored-coefficient
+// decodes (COEF) take K = 0 (u = a) and K = w*h as well.
+template <bool COEF>
 __device__ __forceinline__ int fast_class(int K, int N) {
-  if (K < 1 || K >= N || K > kFastKMax) return 3;
+  if (COEF ? (K < 0 || K > N || K > kFastKMax) : (K < 1 || K >= N || K > kFastKMax)) return 3;
   return K <= 15 ? 0 : (K <= 23 ? 1 : 2);
+}
+
+// Stored-coefficient decodes: stage (x, y, c) of the wave's 4 blocks (codes
+// dequantised, zeros up to R) and their constants, in place of the solve.
+template <int R>
+__device__ __forceinline__ void fast_coef_stage(const FrameDev &f, const FastItem *items, int slot, bool ok,
+                                                int t, int gi, int w, int h, const GroupDev &G,
+                                                FastStage &st) {
+  constexpr int NS = (R + 15) / 16;
+  const FramePtrs fp = f.fp[blockIdx.y];
+  const int K = ok ? items[slot].K : 0, N = w * h, nv = ok ? items[slot].nv : 0;
+  const int pl0 = G.vplane[0], pl1 = G.vplane[nv > 1 ? 1 : 0];
+  int bad = 0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = t + 16 * s;
+    FastPoint P{0, 0, 0.f, 0.f};
+    if (i < K) {
+      const int base = items[slot].base;
+      int p = fp.pos[base + i];
+      if (f.validate && (p >= N || (i > 0 && (int)fp.pos[base + i - 1] >= p))) bad |= kStatusMask;
+      p = min(p, N - 1);
+      P.x = p % w;
+      P.y = p / w;
+      const int q0 = fp.coef[items[slot].vb0 + i];
+      const int q1 = nv > 1 ? (int)fp.coef[items[slot].vb1 + i] : 0;
+      if (f.validate && (q0 == -128 || q1 == -128)) bad |= kStatusValue;
+      P.c0 = coef_value(q0, f.qstep[pl0], f.qrho);
+      P.c1 = coef_value(q1, f.qstep[pl1], f.qrho);
+    }
+    st.p[gi][i] = P;  // zeros past K up to 16 NS: 16-point chunks may read up to row 31
+  }
+  if (t < 2) {
+    float a = 0.f;
+    if (t < nv) {
+      a = fp.consts[G.cbase[t] + (items[slot].m - G.first)];
+      if (f.validate && !isfinite(a)) bad |= kStatusValue;
+    }
+    st.a[gi][t] = a;
+  }
+  if (bad) atomicOr(f.status, bad);
 }
 
 // Solve the bordered systems of the wave's 4 blocks (R = 16, 24 or 32 rows
@@ -712,6 +757,7 @@ __device__ __forceinline__ void fast_eval_any(const FrameDev &f, const float *D,
   }
 }
 
+template <bool COEF>
 __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(3, 8)))
 void k_fast(FrameDev f) {
   extern __shared__ __attribute__((aligned(16))) float tabs[];  // J, Dw, Dh, lam of the workgroup's shape
@@ -745,7 +791,12 @@ void k_fast(FrameDev f) {
     ihi = bp[im + 1];
     if (G.nv > 1 && f.shared) icr = (long long)bp[f.n_items] - bp[f.chroma_first];
   }
-  {
+  if constexpr (COEF) {  // the evaluation's matrices only
+    const int n4 = (3 * kDct16Floats) >> 2;
+    const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + S.fast + S.jt_floats);
+    f4 *dst = reinterpret_cast<f4 *>(tabs);
+    for (int i = tid; i < n4; i += kFastThreads) dst[i] = src[i];
+  } else {
     const int n4 = (S.jt_floats + 3 * kDct16Floats) >> 2;
     const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + S.fast);
     f4 *dst = reinterpret_cast<f4 *>(tabs);
@@ -770,7 +821,7 @@ void k_fast(FrameDev f) {
       r.K = ihi - ilo;
       r.base = ilo;
       r.nv = G.nv;
-      r.cls = fast_class(r.K, w * h);
+      r.cls = fast_class<COEF>(r.K, w * h);
       const long long pix = (long long)(iby * f.b) * G.W + ibx * f.b;
       r.vb0 = ilo;
       r.ob0 = G.out_off[0] + pix;
@@ -810,12 +861,18 @@ void k_fast(FrameDev f) {
   }
   const int Kw = __builtin_amdgcn_readfirstlane(kw);
   const int NVw = __builtin_amdgcn_readfirstlane(nvw);
-  if (Kw > 0) {
+  if (COEF || Kw > 0) {
     FastStage &st = stage[wv];
-    bool solved;
-    if (Kw <= 15) solved = fast_solve<16>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
-    else if (Kw <= 23) solved = fast_solve<24>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
-    else solved = fast_solve<32>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
+    bool solved = true;
+    if constexpr (COEF) {
+      if (Kw <= 15) fast_coef_stage<16>(f, items, slot, ok, t, gi, w, h, G, st);
+      else if (Kw <= 23) fast_coef_stage<24>(f, items, slot, ok, t, gi, w, h, G, st);
+      else fast_coef_stage<32>(f, items, slot, ok, t, gi, w, h, G, st);
+    } else {
+      if (Kw <= 15) solved = fast_solve<16>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
+      else if (Kw <= 23) solved = fast_solve<24>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
+      else solved = fast_solve<32>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
+    }
     if (ok && !solved && t == 0) {
       if (f.tail_in_wg) defer[slot] = 1;
       else push_deferred(f, blockIdx.y, items[slot].m, items[slot].K, w, h);
@@ -831,7 +888,7 @@ void k_fast(FrameDev f) {
     for (int g = 0; g < kWaveItems; ++g) okmask |= ((em >> (16 * g)) & 1ull) ? (1u << g) : 0u;
     const long long ob0 = items[slot].ob0, ob1 = items[slot].ob1;
     if (okmask) {
-      const float *D = tabs + S.jt_floats;
+      const float *D = tabs + (COEF ? 0 : S.jt_floats);
       if (Kw <= 15) fast_eval_any<16>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
       else if (Kw <= 23) fast_eval_any<24>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
       else fast_eval_any<32>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
@@ -842,15 +899,107 @@ void k_fast(FrameDev f) {
   // or whose pivots asked for FP64 refinement: the whole workgroup runs the
   // general algorithm on them, one at a time, with the bordered system in
   // this workgroup's global slot.
-  if (!f.tail_in_wg) return;
-  __syncthreads();
-  float *slot_mem = f.slots + (long long)blockIdx.x * f.slot_floats;
-  for (int j = 0; j < kFastItems; ++j) {
-    if (defer[j]) {
-      __syncthreads();
-      general_block<16>(f, 0, items[j].m, gs, slot_mem);
+  if constexpr (!COEF) {
+    if (!f.tail_in_wg) return;
+    __syncthreads();
+    float *slot_mem = f.slots + (long long)blockIdx.x * f.slot_floats;
+    for (int j = 0; j < kFastItems; ++j) {
+      if (defer[j]) {
+        __syncthreads();
+        general_block<16>(f, 0, items[j].m, gs, slot_mem);
+      }
     }
   }
+}
+
+// ------------------------------------------- stored coefficients, general
+
+// One stored-coefficient block with a whole workgroup: u = sum_i c_i
+// G(., x_i) + a at every pixel (Eq. 2 summed directly, FP32), the points
+// staged in LDS 256 at a time, G from the compact table in LDS.  For the
+// blocks the batched kernels leave (more points than they stage).
+__device__ void coef_block(const FrameDev &f, int fi, int m, FastPoint *pts, float *tab) {
+  const int tid = threadIdx.x;
+  fi = __builtin_amdgcn_readfirstlane(fi);
+  const FramePtrs fp = f.fp[fi];
+  const Item it = load_item(f, fp.block_ptr, m);
+  const GroupDev &G = f.g[it.g];
+  const int K = it.K, w = it.w, h = it.h, N = w * h;
+  const ShapeDev S = f.s[it.shape];
+  __syncthreads();  // the previous block's readers are done
+  for (int i = tid; i < (w + 1) * (h + 1); i += kGenThreads) tab[i] = f.tab32[S.hc32 + i];
+  int bad = (K < 0 || K > N) ? kStatusMask : 0;
+  const int Kc = (K < 0 || K > N) ? 0 : K;
+  const int pl0 = G.vplane[0], pl1 = G.vplane[it.nv > 1 ? 1 : 0];
+  float acc[4][2];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = 0.f;
+  for (int k0 = 0; k0 < Kc; k0 += kGenThreads) {
+    const int i = k0 + tid;
+    FastPoint P{0, 0, 0.f, 0.f};
+    if (i < Kc) {
+      int p = fp.pos[it.base + i];
+      if (f.validate && (p >= N || (i > 0 && (int)fp.pos[it.base + i - 1] >= p))) bad |= kStatusMask;
+      p = min(p, N - 1);
+      P.x = p % w;
+      P.y = p / w;
+      const int q0 = fp.coef[it.vbase0 + i];
+      const int q1 = it.nv > 1 ? (int)fp.coef[it.vbase1 + i] : 0;
+      if (f.validate && (q0 == -128 || q1 == -128)) bad |= kStatusValue;
+      P.c0 = coef_value(q0, f.qstep[pl0], f.qrho);
+      P.c1 = coef_value(q1, f.qstep[pl1], f.qrho);
+    }
+    __syncthreads();  // the previous chunk is consumed
+    pts[tid] = P;
+    __syncthreads();
+    const int nk = min(kGenThreads, Kc - k0);
+    for (int k = 0; k < nk; ++k) {
+      const FastPoint Q = pts[k];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int px = tid + j * kGenThreads;
+        if (px < N) {
+          const float g = green_tab(tab, w, h, px % w, px / w, Q.x, Q.y);
+          acc[j][0] = fmaf(Q.c0, g, acc[j][0]);
+          acc[j][1] = fmaf(Q.c1, g, acc[j][1]);
+        }
+      }
+    }
+  }
+  if (Kc == 0) __syncthreads();  // the table is in LDS (no chunk loop ran)
+  for (int v = 0; v < it.nv; ++v) {
+    const float a = fp.consts[G.cbase[v] + it.l];
+    if (f.validate && !isfinite(a)) bad |= kStatusValue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int px = tid + j * kGenThreads;
+      if (px < N) store_px(f, fi, it.obase(v) + (px / w) * it.W + px % w, (v ? acc[j][1] : acc[j][0]) + a);
+    }
+  }
+  if (bad) atomicOr(f.status, bad);
+}
+
+// Persistent pass over both deferred lists of a stored-coefficient decode;
+// the last workgroup clears the counters as in k_general_deferred.
+__global__ __launch_bounds__(kGenThreads) void k_coef_general(FrameDev f) {
+  __shared__ FastPoint pts[kGenThreads];
+  __shared__ float tab[33 * 33];
+  __shared__ int last;
+  const int nmed = f.counters[0];
+  const int nlarge = f.counters[1];
+  const int cap = f.n_items * f.nframes;
+  for (int idx = blockIdx.x; idx < nmed + nlarge; idx += gridDim.x) {
+    const int e = idx < nmed ? f.deferred[idx] : f.deferred[cap - 1 - (idx - nmed)];
+    coef_block(f, e >> kDeferFrameShift, e & kDeferItemMask, pts, tab);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    last = __hip_atomic_fetch_add(&f.counters[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+           (int)gridDim.x - 1;
+  __syncthreads();
+  if (last)
+    for (int i = threadIdx.x; i < kNumCounters; i += kGenThreads)
+      __hip_atomic_store(&f.counters[i], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -858,7 +1007,8 @@ void k_fast(FrameDev f) {
 hipError_t launch_fast(const FrameDev &f, hipStream_t stream) {
   if (f.fast_wgs == 0) return hipSuccess;
   const size_t lds = sizeof(float) * (size_t)f.fast_lds;
-  hipLaunchKernelGGL(k_fast, dim3(f.fast_wgs, f.nframes), dim3(kFastThreads), lds, stream, f);
+  if (f.coef) hipLaunchKernelGGL(k_fast<true>, dim3(f.fast_wgs, f.nframes), dim3(kFastThreads), lds, stream, f);
+  else hipLaunchKernelGGL(k_fast<false>, dim3(f.fast_wgs, f.nframes), dim3(kFastThreads), lds, stream, f);
   return hipGetLastError();
 }
 
@@ -870,6 +1020,11 @@ hipError_t launch_plain_all(const FrameDev &f, hipStream_t stream) {
 
 hipError_t launch_general_deferred(const FrameDev &f, hipStream_t stream) {
   hipLaunchKernelGGL(k_general_deferred, dim3(kGeneralGrid), dim3(kGenThreads), 0, stream, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef_general(const FrameDev &f, hipStream_t stream) {
+  hipLaunchKernelGGL(k_coef_general, dim3(kGeneralGrid), dim3(kGenThreads), 0, stream, f);
   return hipGetLastError();
 }
 

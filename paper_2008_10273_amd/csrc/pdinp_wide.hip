@@ -46,7 +46,46 @@ struct alignas(16) WideStage {
 struct WideJob {
   int K, base, nv;
   long long vb0, vb1, ob0, ob1;
+  int pl0, pl1;     // value planes (stored-coefficient decodes)
+  int cidx0, cidx1; // indices of the block's constants
 };
+
+// Stored-coefficient decodes: stage (x, y, c) of the block's points (codes
+// dequantised; zeros past K) and its constants, in place of the solve.
+__device__ __forceinline__ void wide_coef_stage(const FrameDev &f, const WideJob &jb, int lane, int w, int h,
+                                                WideStage &st) {
+  const FramePtrs fp = f.fp[blockIdx.y];
+  const int K = jb.K, N = w * h;
+  int bad = 0;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int i = lane + 64 * s;
+    WidePoint P{0, 0, 0.f, 0.f};
+    if (i < K) {
+      int p = fp.pos[jb.base + i];
+      if (f.validate && (p >= N || (i > 0 && (int)fp.pos[jb.base + i - 1] >= p))) bad |= kStatusMask;
+      p = min(p, N - 1);
+      P.x = p % w;
+      P.y = p / w;
+      const int q0 = fp.coef[jb.vb0 + i];
+      const int q1 = jb.nv > 1 ? (int)fp.coef[jb.vb1 + i] : 0;
+      if (f.validate && (q0 == -128 || q1 == -128)) bad |= kStatusValue;
+      P.c0 = coef_value(q0, f.qstep[jb.pl0], f.qrho);
+      P.c1 = coef_value(q1, f.qstep[jb.pl1], f.qrho);
+    }
+    if (i < kWideStagePts) st.p[i] = P;
+  }
+  if (lane < 2) {
+    float a = 0.f;
+    if (lane < jb.nv) {
+      a = fp.consts[lane ? jb.cidx1 : jb.cidx0];
+      if (f.validate && !isfinite(a)) bad |= kStatusValue;
+    }
+    st.a[lane] = a;
+  }
+  if (bad) atomicOr(f.status, bad);
+  wave_sync();
+}
 
 // c + X^T Y for 16 x 16 tiles X, Y in accumulator layout: the k-th product
 // of the chain takes register r of both operands, so lane l supplies
@@ -464,6 +503,7 @@ __device__ __forceinline__ void wide_eval16(const FrameDev &f, const WideJob &jb
 // point count, so that the long solves are handed out first; blocks the wave
 // path does not take (K = 0, K = w*h, K > 103, invalid counts) go to the
 // general path's lists.
+template <bool COEF>
 __global__ __launch_bounds__(256) void k_bin(FrameDev f) {
   const int m = blockIdx.x * 256 + threadIdx.x, fi = blockIdx.y;
   const int32_t *bp = f.fp[fi].block_ptr;
@@ -480,7 +520,8 @@ __global__ __launch_bounds__(256) void k_bin(FrameDev f) {
   const int shape = G.shape[e];
   const int w = f.s[shape].w, h = f.s[shape].h;
   const int K = bp[m + 1] - bp[m];
-  if (K < 1 || K >= w * h || K > kWideKMax) push_deferred(f, fi, m, K, w, h);
+  const bool take = COEF ? (K >= 0 && K <= w * h && K <= kWideKMax) : (K >= 1 && K < w * h && K <= kWideKMax);
+  if (!take) push_deferred(f, fi, m, K, w, h);
   else key = 4 * f.qof[shape] + (K >= kBinK0 ? 0 : K >= kBinK1 ? 1 : K >= kBinK2 ? 2 : 3);
   }
   // One atomic per distinct queue and bin in the wave: the lanes of a key
@@ -507,8 +548,8 @@ __global__ __launch_bounds__(256) void k_bin(FrameDev f) {
 
 // One block per wave, WAVES waves per workgroup (the workgroup shares the
 // shape's tables in LDS); each wave takes the next block of its queue.
-template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_wide(FrameDev f) {
+template <int WAVES, bool COEF>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, COEF ? 3 : 2))) void k_wide(FrameDev f) {
   extern __shared__ __attribute__((aligned(16))) float tabs[];  // Hc | Dw | Dh | lam of the shape
   __shared__ WideStage stage[WAVES];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -519,9 +560,9 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2
   const QueueDev Q = f.q[qi];
   const ShapeDev S = f.s[Q.shape];
   const int w = S.w, h = S.h;
-  {
-    const int n4 = (S.jt_floats + 3 * kDct32Floats) >> 2;
-    const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + S.fast);
+  {  // stored-coefficient decodes need the evaluation's matrices only
+    const int n4 = ((COEF ? 0 : S.jt_floats) + 3 * kDct32Floats) >> 2;
+    const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + S.fast + (COEF ? S.jt_floats : 0));
     f4 *dst = reinterpret_cast<f4 *>(tabs);
     for (int i = tid; i < n4; i += 64 * WAVES) dst[i] = src[i];
   }
@@ -563,14 +604,22 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2
     jb.vb1 = f.shared ? (long long)bp[f.n_items] + (lo - bp[f.chroma_first]) : lo;
     jb.ob1 = G.out_off[1] + pix;
   }
-  const int K = jb.K;  // 1 <= K <= min(w*h - 1, kWideKMax): binned
+  const int K = jb.K;  // binned: 1 <= K <= min(w*h - 1, kWideKMax) (COEF: 0 <= K <= ..)
   WideStage &st = stage[wv];
-  const bool solved = wide_solve(f, jb, lane, w, h, tabs, st);
-  if (!solved) {
-    if (lane == 0) push_deferred(f, fi, m, K, w, h);
-    return;
+  if constexpr (COEF) {
+    jb.pl0 = G.vplane[0];
+    jb.pl1 = G.vplane[G.nv > 1 ? 1 : 0];
+    jb.cidx0 = G.cbase[0] + bl;
+    jb.cidx1 = G.cbase[1] + bl;
+    wide_coef_stage(f, jb, lane, w, h, st);
+  } else {
+    const bool solved = wide_solve(f, jb, lane, w, h, tabs, st);
+    if (!solved) {
+      if (lane == 0) push_deferred(f, fi, m, K, w, h);
+      return;
+    }
   }
-  const float *D = tabs + S.jt_floats;
+  const float *D = tabs + (COEF ? 0 : S.jt_floats);
   switch (f.eval) {
     case 1: wide_eval16<1>(f, jb, D, st, lane, w, h, G.W); break;
     case 2: wide_eval16<2>(f, jb, D, st, lane, w, h, G.W); break;
@@ -581,13 +630,24 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2
 
 hipError_t launch_wide(const FrameDev &f, hipStream_t stream) {
   if (f.n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bin, dim3((f.n_items + 255) / 256, f.nframes), dim3(256), 0, stream, f);
+  const dim3 bgrid((f.n_items + 255) / 256, f.nframes), grid(f.fast_wgs, f.nframes);
   const size_t lds = sizeof(float) * (size_t)f.fast_lds;
-  switch (f.ipw) {
-    case 1: hipLaunchKernelGGL(k_wide<1>, dim3(f.fast_wgs, f.nframes), dim3(64), lds, stream, f); break;
-    case 2: hipLaunchKernelGGL(k_wide<2>, dim3(f.fast_wgs, f.nframes), dim3(128), lds, stream, f); break;
-    case 4: hipLaunchKernelGGL(k_wide<4>, dim3(f.fast_wgs, f.nframes), dim3(256), lds, stream, f); break;
-    default: return hipErrorInvalidValue;
+  if (f.coef) {
+    hipLaunchKernelGGL(k_bin<true>, bgrid, dim3(256), 0, stream, f);
+    switch (f.ipw) {
+      case 1: hipLaunchKernelGGL((k_wide<1, true>), grid, dim3(64), lds, stream, f); break;
+      case 2: hipLaunchKernelGGL((k_wide<2, true>), grid, dim3(128), lds, stream, f); break;
+      case 4: hipLaunchKernelGGL((k_wide<4, true>), grid, dim3(256), lds, stream, f); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    hipLaunchKernelGGL(k_bin<false>, bgrid, dim3(256), 0, stream, f);
+    switch (f.ipw) {
+      case 1: hipLaunchKernelGGL((k_wide<1, false>), grid, dim3(64), lds, stream, f); break;
+      case 2: hipLaunchKernelGGL((k_wide<2, false>), grid, dim3(128), lds, stream, f); break;
+      case 4: hipLaunchKernelGGL((k_wide<4, false>), grid, dim3(256), lds, stream, f); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }

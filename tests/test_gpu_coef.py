@@ -1,0 +1,190 @@
+"""Parity of the stored-coefficient decoder (decode_coefficients, through
+the C ABI) with the FP64 oracle's coefficient decoder.
+
+Bars as for the residual decoder: every pixel within FP32_TOL (FP32
+evaluation; the same derivation: relative rounding of the FP32 sums ~ 2^-24
+times the number of terms, times values of at most ~10^2 -> < 10^-3,
+rounded up to 10^-2), within 0.5 grey levels, and identical 8-bit rounding
+on at least 99.9 % of the pixels; reduced-precision evaluations within the
+bounds EVAL_TOL derived below.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_10273_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-2
+# Reduced-precision operands: relative rounding 2^-11 (FP16) and 2^-8 (BF16)
+# of the operands, values of at most ~50 -> 0.025 and 0.2, rounded up; split
+# BF16 carries ~16 bits and meets the FP32 bound.
+EVAL_TOL = {1: 0.05, 2: 0.25, 3: FP32_TOL}
+STEPS = (0.25, 0.5, 0.375)
+RHO = 0.5
+
+
+@pytest.fixture(scope="module")
+def dec():
+    from paper_2008_10273_amd import binding
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = binding.Decoder(0)
+    yield d
+    d.close()
+
+
+def _q8(x):
+    return np.clip(np.rint(x), -128, 127)
+
+
+def _dense_frame(W, H, fmt, b, counts_fn, seed, shared=True):
+    """Frame whose block k of every mask plane gets counts_fn(k, w*h) points."""
+    rng = np.random.default_rng(seed)
+    dims = synth.plane_dims(W, H, fmt)
+    nm = 1 if fmt == synth.GRAY else (2 if shared else 3)
+    ms, fs = [], []
+    for p in range(nm):
+        pw, ph = dims[p]
+        m = np.zeros((ph, pw), bool)
+        for k, (x0, y0, w, h) in enumerate(synth.block_grid(pw, ph, b)):
+            K = counts_fn(k, w * h)
+            idx = rng.choice(w * h, K, replace=False)
+            m[y0 + idx // w, x0 + idx % w] = True
+        ms.append(m)
+    for pw, ph in dims:
+        fs.append(np.zeros((ph, pw)))
+    return synth.pack_dense(W, H, fmt, b, ms, fs)
+
+
+CASES = {
+    "b8_420": lambda: synth.random_frame(100, 67, synth.YUV420, 8, (0.02, 0.3), seed=41),
+    "b16_420": lambda: synth.random_frame(150, 90, synth.YUV420, 16, (0.01, 0.12), seed=42),
+    "b16_separate": lambda: synth.random_frame(90, 52, synth.YUV420, 16, (0.01, 0.12), seed=43,
+                                               chroma_shared=False),
+    "b32_420": lambda: synth.random_frame(150, 90, synth.YUV420, 32, (0.02, 0.1), seed=44),
+    "b8_gray_ragged": lambda: synth.random_frame(37, 21, synth.GRAY, 8, (0.05, 0.5), seed=45),
+    # every K class: 0, 1, the staged limits (31 / 103), beyond them, w*h
+    "b16_counts": lambda: _dense_frame(16 * 5 + 9, 16 * 3 + 5, synth.YUV420, 16,
+                                       lambda k, n: min(n, [0, 1, 15, 16, 31, 32, 60, n, n - 1, 200][k % 10]), 46),
+    "b32_counts": lambda: _dense_frame(32 * 4 + 11, 32 * 2 + 7, synth.YUV420, 32,
+                                       lambda k, n: min(n, [0, 1, 63, 64, 103, 104, 300, n, n - 1][k % 9]), 47),
+}
+
+
+def _decode(dec, fr, q, consts, **kw):
+    from paper_2008_10273_amd import binding
+    d = dec.upload_coef(fr, q, consts)
+    params = binding.default_params(**kw)
+    dec.decode_coef(d, binding.coef_params(STEPS, RHO), params)
+    rc = dec.sync()
+    assert rc == 0, binding.pdi_last_error(dec.ctx)
+    key = "out_i8" if kw.get("out_int8") else "out"
+    return d[key].cpu().numpy().astype(np.float64)
+
+
+def _check(got, ref, tol):
+    err = np.abs(got - ref)
+    agree = float(np.mean(_q8(got) == _q8(ref)))
+    print(f"  max|err|={err.max():.3e} round-agree={agree * 100:.4f}%", flush=True)
+    assert np.all(np.isfinite(got))
+    assert err.max() <= tol
+    return err.max(), agree
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_coef_parity(dec, case):
+    fr = CASES[case]()
+    q, consts = synth.coef_inputs(fr, 3)
+    print(f"case coef {case} {fr.width}x{fr.height} b={fr.block_size}", flush=True)
+    got = _decode(dec, fr, q, consts)
+    ref = oracle.decode_coef_flat(fr, q, consts, STEPS, RHO)
+    mx, agree = _check(got, ref, FP32_TOL)
+    assert mx <= 0.5 and agree >= 0.999
+
+
+@pytest.mark.parametrize("ev", [1, 2, 3])
+@pytest.mark.parametrize("case", ["b8_420", "b32_420"])
+def test_coef_eval_dtypes(dec, case, ev):
+    fr = CASES[case]()
+    q, consts = synth.coef_inputs(fr, 4)
+    print(f"case coef {case} eval {ev}", flush=True)
+    got = _decode(dec, fr, q, consts, eval_dtype=ev)
+    ref = oracle.decode_coef_flat(fr, q, consts, STEPS, RHO)
+    mx, agree = _check(got, ref, EVAL_TOL[ev])
+    if ev == 3:
+        assert mx <= 0.5 and agree >= 0.999
+
+
+@pytest.mark.parametrize("case", ["b8_420", "b16_counts", "b32_counts"])
+def test_coef_int8_output(dec, case):
+    """out_int8 is exactly the 8-bit rounding of the same path's FP32 result."""
+    fr = CASES[case]()
+    q, consts = synth.coef_inputs(fr, 5)
+    f32 = _decode(dec, fr, q, consts)
+    i8 = _decode(dec, fr, q, consts, out_int8=1)
+    np.testing.assert_array_equal(i8, _q8(f32))
+
+
+def test_coef_full_frame(dec):
+    """The 1080p 4:2:0 workload with the paper's 8x8 blocks."""
+    fr, q, consts = synth.coef_frame(0)
+    c = synth.COEF_CONFIG
+    print("case coef full frame", flush=True)
+    from paper_2008_10273_amd import binding
+    d = dec.upload_coef(fr, q, consts)
+    dec.decode_coef(d, binding.coef_params(c["steps"], c["rho"]))
+    assert dec.sync() == 0
+    got = d["out"].cpu().numpy().astype(np.float64)
+    ref = oracle.decode_coef_flat(fr, q, consts, c["steps"], c["rho"])
+    mx, agree = _check(got, ref, FP32_TOL)
+    assert mx <= 0.5 and agree >= 0.999
+
+
+@pytest.mark.parametrize("b", [8, 32])
+def test_coef_batch_equals_single(dec, b):
+    """decode_coefficients_batch gives every frame bitwise its single decode."""
+    from paper_2008_10273_amd import binding
+    qp = binding.coef_params(STEPS, RHO)
+    frames = [synth.random_frame(120, 70, synth.YUV420, b, (0.02, 0.2), seed=60 + k) for k in range(3)]
+    if b == 32:  # blocks beyond the staged limit and full blocks in the batch too
+        frames.append(_dense_frame(120, 70, synth.YUV420, 32, lambda k, n: min(n, [0, 5, 104, n][k % 4]), 61))
+    alone, ds = [], []
+    for k, fr in enumerate(frames):
+        q, consts = synth.coef_inputs(fr, 10 + k)
+        alone.append(_decode(dec, fr, q, consts))
+        ds.append(dec.upload_coef(fr, q, consts))
+    for d in ds:
+        d["out"].fill_(float("nan"))
+    dec.decode_coef_batch(ds, qp)
+    assert dec.sync() == 0
+    for d, ref in zip(ds, alone):
+        np.testing.assert_array_equal(d["out"].cpu().numpy().astype(np.float64), ref)
+
+
+def test_coef_validation(dec):
+    """Device checks (validate = 1) and host argument errors."""
+    from paper_2008_10273_amd import binding
+    fr = CASES["b16_420"]()
+    q, consts = synth.coef_inputs(fr, 6)
+    qp = binding.coef_params(STEPS, RHO)
+    params = binding.default_params(validate=1)
+    bad_q = q.copy()
+    bad_q[len(bad_q) // 2] = -128
+    d = dec.upload_coef(fr, bad_q, consts)
+    dec.decode_coef(d, qp, params)
+    assert dec.sync() == binding.PDI_EVALUE
+    bad_c = consts.copy()
+    bad_c[3] = np.nan
+    d = dec.upload_coef(fr, q, bad_c)
+    dec.decode_coef(d, qp, params)
+    assert dec.sync() == binding.PDI_EVALUE
+    d = dec.upload_coef(fr, q, consts)
+    dec.decode_coef(d, qp, params)
+    assert dec.sync() == 0
+    for bad in (binding.coef_params(STEPS, 1.0), binding.coef_params((-1.0, 1.0, 1.0), 0.5),
+                binding.coef_params((np.inf, 1.0, 1.0), 0.5)):
+        assert dec.decode_coef(d, bad, check=False) == binding.PDI_EINVAL
+    assert dec.decode_coef(d, None, check=False) == binding.PDI_EINVAL
