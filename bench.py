@@ -17,6 +17,9 @@ Workloads (synthetic, seeded; the recipe is in paper_2008_10273_amd/synth.py):
       4x 1920x1080, 4:2:0, b16) with Poisson arrivals at 25 frames/s each,
       through the pdi_server request loop; latency counts from submission
       (host data) to completion on the device.
+  --config 5: the paper's decoder split - 1080p 4:2:0 frames with 8x8 blocks
+      (masks as config 1) decoded from stored int8 codes and block constants
+      by decode_coefficients_batch over --batch frames (no solve).
 
 Prints one JSON line with the metric, latency percentiles, the error against
 the FP64 oracle, a roofline record of the decode and the oracle timed on the
@@ -41,7 +44,7 @@ EVALS = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16x2": 3}
 # WRITE_SIZE counters, scaled by the same counters read on a copy kernel of
 # known size (profiles/*_hbm_counters.txt); only for the kernel build the
 # counters were taken on (null after a kernel change).
-TRAFFIC = {(1, 8): 112142541}  # (config, frames per step): bytes per launch
+TRAFFIC = {}  # (config, frames per step): bytes per launch
 
 
 def algorithmic_bytes(fr) -> int:
@@ -55,6 +58,8 @@ def _gen(job):
     kind, a, b = job
     if kind == "cfg":
         return synth.config_frame(a, frame=b, keep_fields=False)
+    if kind == "coef":
+        return synth.coef_frame(b)
     return synth.serving_frame(a, b)
 
 
@@ -283,6 +288,95 @@ def bench_frame(args, torch, binding, synth):
     return rec
 
 
+def coef_bytes(fr, q, consts) -> int:
+    """Bytes a stored-coefficient decode must move: packed mask, int8 codes
+    and block constants in, FP32 planes out."""
+    return int(4 * fr.block_ptr.size + 2 * fr.pos.size + q.size + 4 * consts.size + 4 * fr.out_size)
+
+
+def bench_coef(args, torch, binding, synth):
+    """Config 5: the paper's decoder split - 1080p 4:2:0 frames with 8x8
+    blocks decoded from stored codes and constants (decode_coefficients).
+    One step = one decode_coefficients_batch call over --batch frames."""
+    B = args.batch
+    c = synth.COEF_CONFIG
+    items = generate([("coef", 5, k) for k in range(B)], args.workers if B > 1 else 1)
+    dec = binding.Decoder(0)
+    ds = [dec.upload_coef(fr, q, cs) for fr, q, cs in items]
+    d = ds[0]
+    fr, q0, c0 = items[0]
+    stream = torch.cuda.Stream()
+    params = binding.default_params(eval_dtype=EVALS[args.eval])
+    qp = binding.coef_params(c["steps"], c["rho"])
+    log(f"config 5 ({c['name']}), eval {args.eval}, {B} frames per step, {args.steps} steps")
+
+    def step():
+        if B == 1:
+            dec.decode_coef(d, qp, params, stream=stream)
+        else:
+            dec.decode_coef_batch(ds, qp, params, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    tm = StreamTimer(torch, stream)
+    t0 = time.perf_counter()
+    tm.start()
+    for _ in range(args.steps):
+        step()
+    secs = tm.stop()
+    wall = time.perf_counter() - t0
+    assert dec.sync(stream) == 0, binding.pdi_last_error(dec.ctx)
+    fps = B * args.steps / secs
+    got = d["out"].cpu().numpy().astype(np.float64)
+    log(f"decode: {fps:.1f} frames/s, {1e3 * secs / args.steps:.4f} ms per step of {B} frames")
+    lat = []
+    for _ in range(args.latency_iters):
+        tm.start()
+        dec.decode_coef(d, qp, params, stream=stream)
+        lat.append(1e3 * tm.stop())
+    lat = np.array(lat)
+    log(f"single frame: p50 {np.percentile(lat, 50):.4f} ms, p99 {np.percentile(lat, 99):.4f} ms")
+    err = cpu = None
+    if not args.no_cpu:
+        import oracle
+        cores = host_cores()
+        oracle.decode_coef(fr, q0, c0, c["steps"], c["rho"], nthreads=cores)
+        n, tc0 = 0, time.perf_counter()
+        while n < 3 or time.perf_counter() - tc0 < 5.0:
+            ref = oracle.decode_coef_flat(fr, q0, c0, c["steps"], c["rho"], nthreads=cores)
+            n += 1
+        dt = time.perf_counter() - tc0
+        cpu = dict(value=n / dt, unit="frames/s", cores=cores, kind="oracle",
+                   sample=f"{n} decodes of the benchmark frame (FP64 oracle, Eq. 2 summed directly, "
+                          f"OpenMP over blocks), {dt:.1f} s", cpu_model=cpu_model(), nproc=os.cpu_count())
+        err = error_vs(got, ref)
+        log(f"oracle: {cpu['value']:.2f} frames/s on {cores} cores; max|err| {err['max_abs']:.3e}")
+    ab = sum(coef_bytes(*it) for it in items)
+    t_step = secs / args.steps
+    achieved = ab / t_step / 1e9
+    copy_gbs = copy_bandwidth(torch, stream=stream)
+    rec = dict(metric="1080p residual frames/s decoded from stored coefficients (8x8 blocks)", value=fps,
+               unit="frames/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=1e3 * t_step,
+               higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f32" if args.eval == "fp32" else f"{args.eval} eval", data="synthetic",
+               config={"workload": c["name"], "width": c["width"], "height": c["height"], "format": "4:2:0",
+                       "block_size": c["block_size"], "density": list(c["density"]), "frames_per_step": B,
+                       "mask_blocks": fr.n_mask_blocks, "mask_points": int(fr.pos.size),
+                       "quantiser_steps": list(c["steps"]), "rho": c["rho"]},
+               latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "mean": float(lat.mean()), "of": "one frame decoded alone"},
+               error_vs_oracle=err,
+               roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC.get((5, B)),
+                         "kernel": "k_fast (coefficient mode) + k_coef_general",
+                         "algorithmic_bytes_per_launch": ab, "launch_ms": 1e3 * t_step,
+                         "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs},
+               cpu_baseline=cpu, wall_s=wall)
+    dec.close()
+    return rec
+
+
 def bench_sequence(args, torch, binding, synth):
     cfg = synth.CONFIGS[3]
     n = cfg["frames"]
@@ -447,7 +541,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2, 3, 4])
+    ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2, 3, 4, 5])
     ap.add_argument("--eval", default="fp32", choices=sorted(EVALS))
     ap.add_argument("--latency-iters", type=int, default=300)
     ap.add_argument("--nstreams", type=int, default=4, help="streams for overlapped / sequence decodes")
@@ -467,7 +561,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this decoder runs on one GPU; --gpus {args.gpus} is not supported "
-              "(blocks and frames shard across GPUs with no exchange step, see DESIGN.md)", file=sys.stderr)
+              "(blocks and frames shard across GPUs with no exchange step)", file=sys.stderr)
         sys.exit(2)
     if args.steps is None:
         args.steps = {3: 30}.get(args.config, 500)
@@ -486,6 +580,8 @@ def main():
         rec = bench_frame(args, torch, binding, synth)
     elif args.config == 3:
         rec = bench_sequence(args, torch, binding, synth)
+    elif args.config == 5:
+        rec = bench_coef(args, torch, binding, synth)
     else:
         rec = bench_serving(args, torch, binding, synth)
     assert torch.cuda.is_available()
