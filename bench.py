@@ -42,9 +42,11 @@ HBM_PEAK_GBS = 8000.0
 EVALS = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16x2": 3}
 # HBM bytes per launch of the decode kernel from rocprofv3 FETCH_SIZE +
 # WRITE_SIZE counters, scaled by the same counters read on a copy kernel of
-# known size (profiles/*_hbm_counters.txt); only for the kernel build the
-# counters were taken on (null after a kernel change).
-TRAFFIC = {}  # (config, frames per step): bytes per launch
+# known size (profiles/*_hbm_counters.txt); only for the kernel build and
+# launch shape the counters were taken on (null after a kernel change, or
+# when the autotuned launch choice differs).
+# (config, frames per step, launch choice): bytes per launch
+TRAFFIC = {(1, 8, 16): 111724485, (2, 8, 2): 116325032}
 
 
 def algorithmic_bytes(fr) -> int:
@@ -279,7 +281,7 @@ def bench_frame(args, torch, binding, synth):
                single_frame=single, error_vs_oracle=err, plain_path=plain, overlapped=multi,
                roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": TRAFFIC.get((args.config, B)),
+                         "traffic": TRAFFIC.get((args.config, B, tune_b)),
                          "kernel": kern + (" (+ deferred pass)" if B > 1 or cfg["block_size"] > 16 else ""),
                          "algorithmic_bytes_per_launch": ab, "launch_ms": 1e3 * t_step,
                          "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs},
@@ -368,7 +370,7 @@ def bench_coef(args, torch, binding, synth):
                            "mean": float(lat.mean()), "of": "one frame decoded alone"},
                error_vs_oracle=err,
                roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC.get((5, B)),
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC.get((5, B, 0)),
                          "kernel": "k_fast (coefficient mode) + k_coef_general",
                          "algorithmic_bytes_per_launch": ab, "launch_ms": 1e3 * t_step,
                          "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs},
