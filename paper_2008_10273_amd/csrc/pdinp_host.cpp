@@ -259,11 +259,12 @@ int get_tables(pdi_ctx *c, const pdi_frame *f, int b, int shared, const pdi_para
     S.hc64 = (int)t64.size();
     for (double v : hc) t64.push_back(v);
     if (b <= 16) {
-      // Row-pair table: J[(y*h + y')*(w+1) + a] = Hc(a,|y-y'|)/4 + Hc(a, refl(y+y'+1))/4,
+      // Row-pair table: J[y*jrow + y'*(w+1) + a] = Hc(a,|y-y'|)/4 + Hc(a, refl(y+y'+1))/4,
       // so that G(x, x') = J[..][|x-x'|] + J[..][refl(x+x'+1)].
       const int W1 = w + 1;
       S.fast = (int)t32.size();
-      S.jt_floats = (h * h * W1 + 3) & ~3;
+      const int JR = pdi::jrow(w, h);
+      S.jt_floats = (h * JR + 3) & ~3;
       t32.resize(t32.size() + S.jt_floats + 3 * pdi::kDct16Floats, 0.f);
       float *J = &t32[S.fast];
       for (int y = 0; y < h; ++y)
@@ -272,7 +273,7 @@ int get_tables(pdi_ctx *c, const pdi_frame *f, int b, int shared, const pdi_para
           int sy = y + y2 + 1;
           if (sy > h) sy = 2 * h - sy;
           for (int a = 0; a <= w; ++a)
-            J[(y * h + y2) * W1 + a] = (float)(hc[(size_t)dy * W1 + a] + hc[(size_t)sy * W1 + a]);
+            J[y * JR + y2 * W1 + a] = (float)(hc[(size_t)dy * W1 + a] + hc[(size_t)sy * W1 + a]);
         }
       float *D = J + S.jt_floats;
       dct_padded(w, 16, pdi::kDct16Ld, D);

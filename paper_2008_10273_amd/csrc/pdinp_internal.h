@@ -31,6 +31,10 @@ constexpr int kDeferItemMask = (1 << kDeferFrameShift) - 1;
 // the evaluation's column gathers (16 lanes, 16 rows, one column) fall into
 // 16 different LDS banks.
 constexpr int kDct16Ld = 17, kDct16Floats = 16 * kDct16Ld;
+// Row-pair table of a w x h shape (b <= 16): the block of row y holds h rows
+// of w + 1 floats plus one pad float, so that lanes whose points differ in y
+// read from different LDS banks (h (w + 1) = 272 alone is 16 mod 64).
+__host__ __device__ constexpr int jrow(int w, int h) { return h * (w + 1) + 1; }
 constexpr int kDct32Ld = 33, kDct32Floats = 32 * kDct32Ld;
 static_assert(kDct16Floats % 4 == 0 && kDct32Floats % 4 == 0, "16-byte copies");
 // The FP32 table buffer is padded by this many floats so that the wave-level
@@ -48,7 +52,7 @@ struct ShapeDev {
   int hc32;       // FP32 compact Green table, (w+1)*(h+1), quarter-scaled (floats)
   int hc64;       // same in FP64 (doubles)
   int fast;       // block of the batched paths: for b <= 16 the row-pair table
-                  // J[(y*h + y')*(w+1) + alpha] (jt_floats floats), then the
+                  // J[y*jrow(w,h) + y'*(w+1) + alpha] (jt_floats floats), then the
                   // zero-padded 16x16 DCT-II matrices Dw[p][x], Dh[q][y] and the
                   // eigenvalues lam[q][p] (kDct16Floats floats each, row
                   // stride kDct16Ld); for b = 32 the compact table

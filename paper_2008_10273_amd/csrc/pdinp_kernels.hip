@@ -354,9 +354,9 @@ __device__ __forceinline__ float row_max(float v) {
 constexpr int kFastThreads = 256;
 constexpr int kFastWaves = kFastThreads / 64;
 constexpr int kFastItems = kFastWaves * kWaveItems;  // blocks per workgroup
-// 16-byte table loads per thread: J (16*16*17 floats at most, rounded to 4)
+// 16-byte table loads per thread: J (16 jrow(16, 16) floats at most, rounded to 4)
 // plus the DCT matrices and eigenvalues (3 kDct16Floats) of a b <= 16 shape.
-constexpr int kTabVec = ((16 * 16 * 17 + 3) / 4 + 3 * kDct16Floats / 4 + kFastThreads - 1) / kFastThreads;
+constexpr int kTabVec = ((16 * jrow(16, 16) + 3) / 4 + 3 * kDct16Floats / 4 + kFastThreads - 1) / kFastThreads;
 static_assert(kTabVec * kFastThreads * 4 <= kTabPadFloats, "table reads stay inside the padded buffer");
 
 // A block of the workgroup, as staged by the prologue.
@@ -468,14 +468,18 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *it
 
   // Assembly of row i of [G_K 1; 1^T 0] (identity on padding rows):
   // G(x_i, x_k) = J[y_i, y_k][|x_i - x_k|] + J[y_i, y_k][refl(x_i + x_k + 1)].
-  int yrow[NS], ycol[NS], xi1[NS], xcr[NS];
+  // Indices are kept as byte offsets, so that |x_i - x_k| plus the row base
+  // is one v_sad_u32 and no shift is needed per entry.
+  int x4[NS], yrow[NS], ycol[NS], xi1[NS], xcr[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    yrow[s] = yr[s] * h * W1;
-    ycol[s] = yr[s] * W1;
-    xi1[s] = xr[s] + 1;
-    xcr[s] = 2 * w - 1 - xr[s];
+    x4[s] = 4 * xr[s];
+    yrow[s] = 4 * yr[s] * jrow(w, h);
+    ycol[s] = 4 * yr[s] * W1;
+    xi1[s] = 4 * (xr[s] + 1);
+    xcr[s] = 4 * (2 * w - 1 - xr[s]);
   }
+  const char *Jb = reinterpret_cast<const char *>(J);
   // The table lookups are unconditional (every index is in range) so that
   // they issue back to back; the border and padding pattern is applied by
   // selects afterwards.
@@ -487,17 +491,17 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *it
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
       const int k = k0 + kk;
-      int xk = bcast_i(xr[k >> 4], k & 15);
+      int xk = bcast_i(x4[k >> 4], k & 15);
       int yk = bcast_i(ycol[k >> 4], k & 15);
       pin_v(xk);
       pin_v(yk);
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int base = yrow[s] + yk;
-        const int a1 = (int)__usad((unsigned)xr[s], (unsigned)xk, (unsigned)base);
+        const int a1 = (int)__usad((unsigned)x4[s], (unsigned)xk, (unsigned)base);
         const int a2 = base + min(xi1[s] + xk, xcr[s] - xk);
-        g1[s][kk] = J[a1];
-        g2[s][kk] = J[a2];
+        g1[s][kk] = *reinterpret_cast<const float *>(Jb + a1);
+        g2[s][kk] = *reinterpret_cast<const float *>(Jb + a2);
       }
     }
     // Empty statements that take every looked-up value: the compiler keeps
