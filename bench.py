@@ -46,7 +46,7 @@ EVALS = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16x2": 3}
 # launch shape the counters were taken on (null after a kernel change, or
 # when the autotuned launch choice differs).
 # (config, frames per step, launch choice): bytes per launch
-TRAFFIC = {(2, 8, 2): 116325032}
+TRAFFIC = {}
 
 
 def algorithmic_bytes(fr) -> int:

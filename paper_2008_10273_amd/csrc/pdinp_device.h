@@ -22,14 +22,28 @@ __device__ __forceinline__ void push_deferred(const FrameDev &f, int fi, int m, 
   }
 }
 
-// Store one decoded pixel: FP32, or int8 = clamp(rint(u), -128, 127) with
-// round-half-to-even when the frame asks for 8-bit output.
-__device__ __forceinline__ void store_px(const FrameDev &f, int fi, long long idx, float u) {
-  if (f.out_i8) {
+// Output planes of one frame of a launch: FP32, or int8 = clamp(rint(u),
+// -128, 127) with round-half-to-even when the frame asks for 8-bit output.
+// Taken once per wave, so that the pixel stores need no reload of the
+// frame's pointer; element offsets fit in 32 bits (the host limits a
+// plane to 2^30 pixels).
+struct PlaneOut {
+  float *f32;   // FP32 planes, or null
+  int8_t *i8;   // int8 planes, or null
+};
+__device__ __forceinline__ PlaneOut plane_out(const FrameDev &f, int fi) {
+  float *o = f.fp[fi].out;
+  PlaneOut po;
+  po.f32 = f.out_i8 ? nullptr : o;
+  po.i8 = f.out_i8 ? reinterpret_cast<int8_t *>(o) : nullptr;
+  return po;
+}
+__device__ __forceinline__ void store_px(const PlaneOut &po, unsigned idx, float u) {
+  if (po.i8) {
     const float q = fminf(fmaxf(__builtin_rintf(u), -128.f), 127.f);
-    reinterpret_cast<int8_t *>(f.fp[fi].out)[idx] = (int8_t)(int)q;
+    po.i8[idx] = (int8_t)(int)q;
   } else {
-    f.fp[fi].out[idx] = u;
+    po.f32[idx] = u;
   }
 }
 

@@ -128,13 +128,14 @@ __device__ void general_block(const FrameDev &f, int fi, int m, GenScratch<B> &s
   const float *values = fp.values;
   const int K = it.K, w = it.w, h = it.h, N = w * h;
   const ShapeDev S = f.s[it.shape];
+  const PlaneOut po = plane_out(f, fi);
 
   if (tid == 0) sh.flag = 0;
   __syncthreads();
   if (K < 0 || K > N) {
     if (tid == 0) atomicOr(f.status, kStatusMask);
     for (int v = 0; v < it.nv; ++v)
-      for (int p = tid; p < N; p += kGenThreads) store_px(f, fi, it.obase(v) + (p / w) * it.W + p % w, 0.f);
+      for (int p = tid; p < N; p += kGenThreads) store_px(po, (unsigned)(it.obase(v) + (p / w) * it.W + p % w), 0.f);
     return;
   }
   if (f.validate) {
@@ -149,20 +150,20 @@ __device__ void general_block(const FrameDev &f, int fi, int m, GenScratch<B> &s
     __syncthreads();
     if (sh.flag) {
       for (int v = 0; v < it.nv; ++v)
-        for (int p = tid; p < N; p += kGenThreads) store_px(f, fi, it.obase(v) + (p / w) * it.W + p % w, 0.f);
+        for (int p = tid; p < N; p += kGenThreads) store_px(po, (unsigned)(it.obase(v) + (p / w) * it.W + p % w), 0.f);
       return;
     }
   }
   if (K == 0) {
     for (int v = 0; v < it.nv; ++v)
-      for (int p = tid; p < N; p += kGenThreads) store_px(f, fi, it.obase(v) + (p / w) * it.W + p % w, 0.f);
+      for (int p = tid; p < N; p += kGenThreads) store_px(po, (unsigned)(it.obase(v) + (p / w) * it.W + p % w), 0.f);
     return;
   }
   if (K == N) {  // every pixel known: u = r (the system is singular here)
     for (int v = 0; v < it.nv; ++v)
       for (int i = tid; i < K; i += kGenThreads) {
         int p = min((int)pos[it.base + i], N - 1);
-        store_px(f, fi, it.obase(v) + (p / w) * it.W + p % w, values[it.vbase(v) + i]);
+        store_px(po, (unsigned)(it.obase(v) + (p / w) * it.W + p % w), values[it.vbase(v) + i]);
       }
     return;
   }
@@ -274,11 +275,11 @@ __device__ void general_block(const FrameDev &f, int fi, int m, GenScratch<B> &s
     }
     float u0 = acc0 + a0;
     bad |= !isfinite(u0);
-    store_px(f, fi, it.obase0 + (long long)yy * it.W + xx, u0);
+    store_px(po, (unsigned)(it.obase0 + (long long)yy * it.W + xx), u0);
     if (it.nv > 1) {
       float u1 = acc1 + a1;
       bad |= !isfinite(u1);
-      store_px(f, fi, it.obase1 + (long long)yy * it.W + xx, u1);
+      store_px(po, (unsigned)(it.obase1 + (long long)yy * it.W + xx), u1);
     }
   }
   if (bad) atomicOr(f.status, kStatusSolve);
@@ -608,6 +609,7 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
                                           int lane, unsigned okmask, int nvw, int w, int h,
                                           int W, long long ob0, long long ob1) {
   constexpr int nch = R / 4;  // staged rows K..R-1 hold zero coefficients
+  const PlaneOut po = plane_out(f, blockIdx.y);
   const float *Dw = D, *Dh = D + kDct16Floats, *lam = D + 2 * kDct16Floats;
   const int lo = lane & 15, hi = lane >> 4;
   float lam4[4], dwb[4], dha[4];
@@ -660,7 +662,7 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int y = 4 * hi + j, x = lo;
-        if (x < w && y < h) store_px(f, blockIdx.y, o + (long long)y * W + x, U[g][j] + a);
+        if (x < w && y < h) store_px(po, (unsigned)(o + (long long)y * W + x), U[g][j] + a);
       }
     }
   }
@@ -705,6 +707,7 @@ __device__ __forceinline__ void fast_eval16(const FrameDev &f, const float *D, c
                                             int lane, unsigned okmask, int nvw, int w, int h,
                                             int W, long long ob0, long long ob1) {
   constexpr int nch = (R + 15) / 16;
+  const PlaneOut po = plane_out(f, blockIdx.y);
   const float *Dw = D, *Dh = D + kDct16Floats, *lam = D + 2 * kDct16Floats;
   const int lo = lane & 15, hi = lane >> 4;
   float lam4[4], dwb[4], dha[4];
@@ -743,7 +746,7 @@ __device__ __forceinline__ void fast_eval16(const FrameDev &f, const float *D, c
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int y = 4 * hi + j, x = lo;
-        if (x < w && y < h) store_px(f, blockIdx.y, o + (long long)y * W + x, U[j] + av);
+        if (x < w && y < h) store_px(po, (unsigned)(o + (long long)y * W + x), U[j] + av);
       }
     }
   }
@@ -930,6 +933,7 @@ __device__ void coef_block(const FrameDev &f, int fi, int m, FastPoint *pts, flo
   const GroupDev &G = f.g[it.g];
   const int K = it.K, w = it.w, h = it.h, N = w * h;
   const ShapeDev S = f.s[it.shape];
+  const PlaneOut po = plane_out(f, fi);
   __syncthreads();  // the previous block's readers are done
   for (int i = tid; i < (w + 1) * (h + 1); i += kGenThreads) tab[i] = f.tab32[S.hc32 + i];
   int bad = (K < 0 || K > N) ? kStatusMask : 0;
@@ -977,7 +981,7 @@ __device__ void coef_block(const FrameDev &f, int fi, int m, FastPoint *pts, flo
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int px = tid + j * kGenThreads;
-      if (px < N) store_px(f, fi, it.obase(v) + (px / w) * it.W + px % w, (v ? acc[j][1] : acc[j][0]) + a);
+      if (px < N) store_px(po, (unsigned)(it.obase(v) + (px / w) * it.W + px % w), (v ? acc[j][1] : acc[j][0]) + a);
     }
   }
   if (bad) atomicOr(f.status, bad);

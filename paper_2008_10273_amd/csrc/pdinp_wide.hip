@@ -232,17 +232,10 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
       // substitution) in place of A_pp, and the reciprocal pivots in LDS.
       T[tix(p, p)] = mma_tn(lv, ident, f4{0.f, 0.f, 0.f, 0.f});
       if (lo == 0) *reinterpret_cast<f4 *>(&st.dv[16 * p + 4 * hi]) = ds;
-      // W_pj = L^-1 A_pj for the trailing updates; W_pj^T kept for the back
-      // substitution.
-      f4 Wp[kTileN];
+      // W_pj = L^-1 A_pj in place of A_pj for the trailing updates.
 #pragma unroll
-      for (int j = p + 1; j < kTileN; ++j) {
-        if (j < NT) {
-          const f4 a = T[tix(p, j)];
-          Wp[j] = mma_tn(lv, a, f4{0.f, 0.f, 0.f, 0.f});
-          T[tix(p, j)] = mma_tn(a, lv, f4{0.f, 0.f, 0.f, 0.f});
-        }
-      }
+      for (int j = p + 1; j < kTileN; ++j)
+        if (j < NT) T[tix(p, j)] = mma_tn(lv, T[tix(p, j)], f4{0.f, 0.f, 0.f, 0.f});
       R[p] = mma_tn(lv, R[p], f4{0.f, 0.f, 0.f, 0.f});
       // A_ij -= W_pi^T D^-1 W_pj, r_i -= W_pi^T D^-1 r_p.
 #pragma unroll
@@ -250,13 +243,17 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
         if (i < NT) {
           f4 x;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) x[r] = -ds[r] * Wp[i][r];
+          for (int r = 0; r < 4; ++r) x[r] = -ds[r] * T[tix(p, i)][r];
 #pragma unroll
           for (int j = i; j < kTileN; ++j)
-            if (j < NT) T[tix(i, j)] = mma_tn(x, Wp[j], T[tix(i, j)]);
+            if (j < NT) T[tix(i, j)] = mma_tn(x, T[tix(p, j)], T[tix(i, j)]);
           R[i] = mma_tn(x, R[p], R[i]);
         }
       }
+      // W_pj^T (= W_pj^T I) kept for the back substitution.
+#pragma unroll
+      for (int j = p + 1; j < kTileN; ++j)
+        if (j < NT) T[tix(p, j)] = mma_tn(T[tix(p, j)], ident, f4{0.f, 0.f, 0.f, 0.f});
     }
   }
   const bool need = (f.refine == 2) || (f.refine == 1 && !(dmin >= f.tau * dmax));
@@ -321,7 +318,8 @@ __device__ __forceinline__ void wide_eval32(const FrameDev &f, const WideJob &jb
                                             const WideStage &st, int lane, int w, int h, int W) {
   const float *Dw = D, *Dh = D + kDct32Floats, *lam = D + 2 * kDct32Floats;
   const int lo = lane & 15, hi = lane >> 4;
-  const int nch = (jb.K + 7) >> 3;  // pairs of 4-point chunks (staged points are zero past K)
+  const int nch = (jb.K + 7) >> 3;
+  const PlaneOut po = plane_out(f, blockIdx.y);  // pairs of 4-point chunks (staged points are zero past K)
   for (int v = 0; v < jb.nv; ++v) {
     f4 acc[2][2];
 #pragma unroll
@@ -383,7 +381,7 @@ __device__ __forceinline__ void wide_eval32(const FrameDev &f, const WideJob &jb
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int y = 16 * yt + 4 * hi + r, x = 16 * xt + lo;
-          if (x < w && y < h) store_px(f, blockIdx.y, ob + (long long)y * W + x, u4[r] + av);
+          if (x < w && y < h) store_px(po, (unsigned)(ob + (long long)y * W + x), u4[r] + av);
         }
       }
   }
@@ -429,6 +427,7 @@ __device__ __forceinline__ void wide_eval16(const FrameDev &f, const WideJob &jb
   const float *Dw = D, *Dh = D + kDct32Floats, *lam = D + 2 * kDct32Floats;
   const int lo = lane & 15, hi = lane >> 4;
   const int nch = (jb.K + 15) >> 4;
+  const PlaneOut po = plane_out(f, blockIdx.y);
   for (int v = 0; v < jb.nv; ++v) {
     f4 acc[2][2];
 #pragma unroll
@@ -493,7 +492,7 @@ __device__ __forceinline__ void wide_eval16(const FrameDev &f, const WideJob &jb
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int y = 16 * yt + 4 * hi + r, x = 16 * xt + lo;
-          if (x < w && y < h) store_px(f, blockIdx.y, ob + (long long)y * W + x, u4[r] + av);
+          if (x < w && y < h) store_px(po, (unsigned)(ob + (long long)y * W + x), u4[r] + av);
         }
       }
   }
