@@ -668,6 +668,64 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
   }
 }
 
+// The FP32 evaluation for blocks of at most 8 x 8 pixels: the wave's 4
+// blocks share one 16 x 16 tile, block g in quadrant (g / 2, g % 2) of V
+// (its p rows, its q columns), with the DCT matrices block-diagonal and lam
+// repeated in every quadrant.  A point product of block g only reaches its
+// quadrant and both transforms act quadrant by quadrant, so one tile does
+// the work of four (fast_eval spends a zero-padded tile per block).  Lane
+// l, register r then holds pixel (y = 4 (l/16) + r, x = l%16) of the tile:
+// block 2 (x / 8) + y / 8, pixel (x % 8, y % 8).
+template <int R>
+__device__ __forceinline__ void fast_eval8(const FrameDev &f, const float *D, const FastStage &st,
+                                           int lane, unsigned okmask, int nvw, int w, int h,
+                                           int W, long long ob0, long long ob1) {
+  constexpr int nch = R / 4;  // staged rows K..R-1 hold zero coefficients
+  const PlaneOut po = plane_out(f, blockIdx.y);
+  const float *Dw = D, *Dh = D + kDct16Floats, *lam = D + 2 * kDct16Floats;
+  const int lo = lane & 15, hi = lane >> 4, l8 = lo & 7, half = lo >> 3;
+  float lam4[4], dwb[4], dha[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int pq = 4 * hi + j;
+    lam4[j] = lam[l8 * kDct16Ld + (pq & 7)];                            // lam[q % 8][p % 8], q = lo, p = pq
+    dwb[j] = (pq >> 3) == half ? Dw[(pq & 7) * kDct16Ld + l8] : 0.f;  // block-diagonal Dw[p][x], x = lo
+    dha[j] = (pq >> 3) == half ? Dh[(pq & 7) * kDct16Ld + l8] : 0.f;  // block-diagonal Dh[q][y], y = lo
+  }
+  const int b = 2 * half + (hi >> 1);  // block of this lane's pixels
+  const int y0 = 4 * (hi & 1);         // their first row inside the block
+  for (int v = 0; v < nvw; ++v) {
+    f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int ch = 0; ch < nch; ++ch) {
+#pragma unroll
+      for (int g = 0; g < kWaveItems; ++g) {
+        const FastPoint P = st.p[g][ch * 4 + hi];
+        const float aop = half == (g >> 1) ? (v ? P.c1 : P.c0) * Dw[l8 * kDct16Ld + P.x] : 0.f;  // A[p][i]
+        const float bop = half == (g & 1) ? Dh[l8 * kDct16Ld + P.y] : 0.f;                      // B[i][q]
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
+      }
+    }
+    f4 Sx = f4{0.f, 0.f, 0.f, 0.f}, U = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Sx = __builtin_amdgcn_mfma_f32_16x16x4f32(acc[j] * lam4[j], dwb[j], Sx, 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) U = __builtin_amdgcn_mfma_f32_16x16x4f32(dha[j], Sx[j], U, 0, 0, 0);
+    long long ob[kWaveItems];
+#pragma unroll
+    for (int g = 0; g < kWaveItems; ++g) ob[g] = lane_i64(v ? ob1 : ob0, 16 * g);
+    const long long o = b == 0 ? ob[0] : b == 1 ? ob[1] : b == 2 ? ob[2] : ob[3];
+    if ((okmask >> b) & 1u) {
+      const float a = st.a[b][v];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int y = y0 + r, x = l8;
+        if (x < w && y < h) store_px(po, (unsigned)(o + (long long)y * W + x), U[r] + a);
+      }
+    }
+  }
+}
+
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef __bf16 b4 __attribute__((ext_vector_type(4)));
 
@@ -760,7 +818,10 @@ __device__ __forceinline__ void fast_eval_any(const FrameDev &f, const float *D,
     case 1: fast_eval16<R, 1>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1); break;
     case 2: fast_eval16<R, 2>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1); break;
     case 3: fast_eval16<R, 3>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1); break;
-    default: fast_eval<R>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1); break;
+    default:
+      if (f.b == 8) fast_eval8<R>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1);
+      else fast_eval<R>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1);
+      break;
   }
 }
 
