@@ -121,6 +121,7 @@ struct FrameDev {
   int nsegs;
   int ipw;           // blocks per workgroup of the batched path
   int nq;            // wave-per-block queues (one per block shape), smallest first
+                     // (0: no queue counters to clear after the decode)
   QueueDev q[kMaxShapes];
   int qof[kMaxShapes];  // queue of each shape
   int fast_wgs;      // workgroups per frame of the batched path (k_fast or k_wide)

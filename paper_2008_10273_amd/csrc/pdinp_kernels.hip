@@ -306,6 +306,9 @@ __global__ __launch_bounds__(kGenThreads) void k_general_deferred(FrameDev f) {
   const int nmed = f.counters[0];
   const int nlarge = f.counters[1];
   const int cap = f.n_items * f.nframes;
+  // Nothing deferred and no queue counters in use: every counter is still
+  // zero, so there is nothing to decode or clear.
+  if (nmed + nlarge == 0 && f.nq == 0) return;
   for (int idx = blockIdx.x; idx < nmed; idx += gridDim.x) {
     __syncthreads();
     const int e = f.deferred[idx];
@@ -1057,6 +1060,7 @@ __global__ __launch_bounds__(kGenThreads) void k_coef_general(FrameDev f) {
   const int nmed = f.counters[0];
   const int nlarge = f.counters[1];
   const int cap = f.n_items * f.nframes;
+  if (nmed + nlarge == 0 && f.nq == 0) return;  // as in k_general_deferred
   for (int idx = blockIdx.x; idx < nmed + nlarge; idx += gridDim.x) {
     const int e = idx < nmed ? f.deferred[idx] : f.deferred[cap - 1 - (idx - nmed)];
     coef_block(f, e >> kDeferFrameShift, e & kDeferItemMask, pts, tab);
