@@ -209,3 +209,42 @@ def decode_coef(frame, coef, consts, steps, rho: float, op: int = 0, s: float = 
 def decode_coef_flat(frame, coef, consts, steps, rho: float, **kw) -> np.ndarray:
     """Like :func:`decode_coef` but returns the concatenated planes."""
     return np.concatenate([p.ravel() for p in decode_coef(frame, coef, consts, steps, rho, **kw)])
+
+
+def homogeneous_inpaint(mask, f) -> np.ndarray:
+    """Global homogeneous diffusion inpainting (Sec. 2.1, Eq. (1) with
+    A = -L on the whole image, reflecting boundaries): u = f at the mask
+    pixels and (A u)_i = 0 at every other pixel.  Solved exactly in FP64:
+    the unknowns satisfy A_UU u_U = -A_UK f_K, a sparse SPD system when the
+    mask is not empty, factorised by a sparse LU (scipy's SuperLU).  An empty
+    mask leaves the system singular (constants); u = 0 is returned then.
+    mask: (H, W) bool; f: (H, W) values (read at the mask pixels only)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    m = np.asarray(mask, dtype=bool)
+    H, W = m.shape
+    fv = np.asarray(f, dtype=np.float64).ravel()
+    N = W * H
+    if not m.any():
+        return np.zeros((H, W))
+    # -L of the W x H grid: degree minus adjacency over the 4-neighbourhood
+    # inside the image (a mirrored neighbour equals the pixel itself and adds
+    # nothing).
+    idx = np.arange(N).reshape(H, W)
+    rows, cols = [], []
+    rows.append(idx[:, :-1].ravel()); cols.append(idx[:, 1:].ravel())
+    rows.append(idx[:-1, :].ravel()); cols.append(idx[1:, :].ravel())
+    r = np.concatenate(rows); c = np.concatenate(cols)
+    adj = sp.coo_matrix((np.ones(r.size), (r, c)), shape=(N, N))
+    adj = (adj + adj.T).tocsr()
+    deg = np.asarray(adj.sum(axis=1)).ravel()
+    A = (sp.diags(deg) - adj).tocsr()
+    K = m.ravel()
+    U = ~K
+    u = np.zeros(N)
+    u[K] = fv[K]
+    if U.any():
+        A_UU = A[U][:, U].tocsc()
+        rhs = -(A[U][:, K] @ fv[K])
+        u[U] = spla.spsolve(A_UU, rhs)
+    return u.reshape(H, W)

@@ -334,3 +334,21 @@ def coef_frame(frame: int = 0) -> Tuple[Frame, np.ndarray, np.ndarray]:
                     (SEED_ROOT, 5, 0, frame), keep_fields=False)
     q, consts = coef_inputs(fr, (0, frame))
     return fr, q, consts
+
+
+# Intra-frame workload for global homogeneous diffusion inpainting (Sec. 2.1):
+# one 1920x1080 plane, a uniform random mask of 4 % of the pixels, values
+# from the residual field recipe.
+INTRA_CONFIG = dict(name="fhd_gray_intra_d4", width=1920, height=1080, density=0.04)
+
+
+def intra_frame(width: int, height: int, density: float, seed) -> Tuple[np.ndarray, np.ndarray]:
+    """(mask, f): a (height, width) bool mask with each pixel known with
+    probability ``density`` (at least one pixel), and a float32 plane drawn
+    like a residual field (f is only read at the mask).  Random numbers only."""
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_ROOT, 6] + list(np.atleast_1d(seed))))
+    m = rng.uniform(size=(height, width)) < density
+    if not m.any():
+        m[rng.integers(height), rng.integers(width)] = True
+    f = _field(rng, width, height, 20.0)
+    return m, f.astype(np.float32)

@@ -427,3 +427,50 @@ def test_coef_round_trip_of_the_solve():
     G = np.linalg.pinv(brute.neg_laplacian(w, h))
     bound = 0.5 * step * np.abs(G).max() * pos.size + 1e-4
     assert np.abs(got - u.reshape(h, w)).max() <= bound
+
+
+# ------------------------------------- global homogeneous diffusion inpainting
+
+@pytest.mark.parametrize("W,H,d", [(7, 5, 0.3), (12, 9, 0.1), (16, 11, 0.05), (23, 14, 0.2)])
+def test_homogeneous_equals_block_route(W, H, d):
+    """Eq. (1) on the whole image is Eq. (1) on one W x H block: the sparse
+    solve equals the banded-Cholesky route of the per-block oracle."""
+    rng = _rng(W * 100 + H)
+    m = rng.uniform(size=(H, W)) < d
+    m[rng.integers(H), rng.integers(W)] = True
+    f = rng.uniform(-64, 64, (H, W))
+    pos = np.flatnonzero(m.ravel())
+    ref = oracle.block_direct(W, H, pos, f.ravel()[pos])
+    got = oracle.homogeneous_inpaint(m, f)
+    np.testing.assert_allclose(got, ref, atol=1e-9)
+
+
+def test_homogeneous_row_is_linear_interpolation():
+    """One image row: linear interpolation between known pixels, constant
+    continuation past the outermost ones (reflecting boundary)."""
+    m = np.zeros((1, 12), bool)
+    m[0, [2, 7, 9]] = True
+    f = np.zeros((1, 12))
+    f[0, [2, 7, 9]] = [4.0, -6.0, 10.0]
+    u = oracle.homogeneous_inpaint(m, f)[0]
+    want = np.array([4, 4, 4, 2, 0, -2, -4, -6, 2, 10, 10, 10], float)
+    np.testing.assert_allclose(u, want, atol=1e-12)
+
+
+def test_homogeneous_invariants():
+    """Interpolation at the mask, A u = 0 off the mask (A = -L by Kronecker
+    products), maximum principle, one known pixel gives a constant, an empty
+    mask gives 0 (reading)."""
+    rng = _rng(77)
+    H, W = 19, 26
+    m = rng.uniform(size=(H, W)) < 0.06
+    f = rng.uniform(-64, 64, (H, W))
+    u = oracle.homogeneous_inpaint(m, f)
+    assert np.all(u[m] == f[m])
+    Au = brute.neg_laplacian(W, H) @ u.ravel()
+    assert np.abs(Au[~m.ravel()]).max() < 1e-9
+    assert u.min() >= f[m].min() - 1e-9 and u.max() <= f[m].max() + 1e-9
+    one = np.zeros((H, W), bool)
+    one[3, 4] = True
+    np.testing.assert_allclose(oracle.homogeneous_inpaint(one, f), f[3, 4], atol=1e-9)
+    assert np.all(oracle.homogeneous_inpaint(np.zeros((H, W), bool), f) == 0)
