@@ -180,6 +180,36 @@ int decode_coefficients_batch(pdi_ctx *ctx, int n, const pdi_frame *frame, const
                               const pdi_coef_params *qp, int block_size, const pdi_params *params,
                               float *const *outs, void *stream);
 
+/* ---- Global homogeneous diffusion inpainting (intra prediction) ----
+ * The codec's intra frames are predicted by Eq. 1 of Sec. 2.1 on the whole
+ * plane with A = -L (5-point Laplacian, reflecting boundaries): u = f at
+ * the mask pixels and (A u)_i = 0 elsewhere.  Solved coarse to fine with
+ * conjugate gradients as in the paper: a pyramid of masks and values by
+ * 2x2 restriction (a coarse pixel is known when one of its children is,
+ * with their mean value), CG on the coarsest level, each finer level
+ * started from the coarser solution. */
+typedef struct {
+    double tol;       /* stop a level when |r|_2 <= tol |b|_2 (b: right-hand side of the
+                         unknowns' system); in (0, 1), default 1e-6 */
+    int32_t max_iter; /* CG iterations per level at most, in [1, 65536]; default 4000 */
+    int32_t check;    /* iterations between convergence tests (host read-backs); default 16 */
+} pdi_cg_params;
+
+void pdi_default_cg_params(pdi_cg_params *p);
+
+/* mask: uint8 W*H (non-zero = known), f: float W*H (read at the mask
+ * pixels only), u: float W*H output; row-major DEVICE buffers, caller
+ * owned.  cp: HOST pointer or NULL for the defaults.  *iterations (HOST,
+ * may be NULL) receives the CG iterations of the finest level.
+ * Synchronous on `stream` (the convergence tests read back one residual
+ * norm every cp->check iterations); the first call for a plane size
+ * allocates its pyramid.  An empty mask gives u = 0 (the system is then
+ * singular).  Returns PDI_EINVAL for NULL pointers, a size outside
+ * [1, 2^30] pixels or bad parameters, PDI_ESOLVE when the finest level does
+ * not reach tol within max_iter, PDI_ENOMEM / PDI_EHIP as elsewhere. */
+int inpaint_homogeneous(pdi_ctx *ctx, int width, int height, const uint8_t *mask, const float *f,
+                        const pdi_cg_params *cp, float *u, void *stream, int32_t *iterations);
+
 /* Wait for `stream`, then read and clear the device status word.
  * Returns PDI_OK, PDI_EMASK, PDI_EVALUE, PDI_ESOLVE or PDI_EHIP. */
 int pdi_sync(pdi_ctx *ctx, void *stream);

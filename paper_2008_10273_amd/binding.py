@@ -25,6 +25,7 @@ ERROR_NAMES = {0: "PDI_OK", -1: "PDI_EINVAL", -2: "PDI_EMASK", -3: "PDI_ENOMEM",
 
 EXPORTS = ["pdi_default_params", "pdi_create", "pdi_destroy", "decode_residual", "decode_residual_batch",
            "decode_coefficients", "decode_coefficients_batch", "pdi_sync",
+           "pdi_default_cg_params", "inpaint_homogeneous",
            "pdi_last_error", "pdi_frame_info", "pdi_pack_dense", "pdi_validate_host", "pdi_autotune", "pdi_autotune_batch",
            "pdi_seq_create", "pdi_seq_launch", "pdi_seq_sync", "pdi_seq_destroy",
            "pdi_server_create", "pdi_submit", "pdi_poll", "pdi_wait", "pdi_server_stats",
@@ -57,6 +58,18 @@ def coef_params(steps, rho: float) -> pdi_coef_params:
         q.step[k] = float(st[k])
     q.rho = float(rho)
     return q
+
+
+class pdi_cg_params(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("check", ctypes.c_int32)]
+
+
+def cg_params(**kw) -> pdi_cg_params:
+    p = pdi_cg_params()
+    lib().pdi_default_cg_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
 
 
 class PdiError(RuntimeError):
@@ -97,6 +110,11 @@ def lib() -> ctypes.CDLL:
                                                 VP, ctypes.POINTER(pdi_coef_params), i32,
                                                 ctypes.POINTER(pdi_params), VP, P]
         L.decode_coefficients_batch.restype = i32
+        L.pdi_default_cg_params.argtypes = [ctypes.POINTER(pdi_cg_params)]
+        L.pdi_default_cg_params.restype = None
+        L.inpaint_homogeneous.argtypes = [P, i32, i32, P, P, ctypes.POINTER(pdi_cg_params), P, P,
+                                          ctypes.POINTER(ctypes.c_int32)]
+        L.inpaint_homogeneous.restype = i32
         L.pdi_sync.argtypes = [P, P]
         L.pdi_sync.restype = i32
         L.pdi_last_error.argtypes = [P]
@@ -316,6 +334,29 @@ class Decoder:
         if check and rc != PDI_OK:
             raise PdiError(rc, pdi_last_error(self.ctx))
         return rc
+
+    def inpaint(self, mask, f, cp: Optional[pdi_cg_params] = None, stream=None, check=True, u=None):
+        """inpaint_homogeneous on a (H, W) mask (bool) and values; returns
+        (rc, u device tensor, finest-level iterations).  mask / f may be numpy
+        arrays (copied to the device) or device tensors (uint8 / float32)."""
+        import numpy as np
+        torch = self.torch
+        dev = torch.device("cuda", self.device)
+        if not torch.is_tensor(mask):
+            mask = torch.from_numpy(np.ascontiguousarray(mask, dtype=np.uint8)).to(dev)
+        if not torch.is_tensor(f):
+            f = torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).to(dev)
+        H, W = mask.shape
+        if u is None:
+            u = torch.empty((H, W), dtype=torch.float32, device=dev)
+        s = stream.cuda_stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
+        its = ctypes.c_int32()
+        rc = lib().inpaint_homogeneous(self.ctx, W, H, mask.data_ptr(), f.data_ptr(),
+                                       ctypes.byref(cp) if cp is not None else None, u.data_ptr(), s,
+                                       ctypes.byref(its))
+        if check and rc != PDI_OK:
+            raise PdiError(rc, pdi_last_error(self.ctx))
+        return rc, u, its.value
 
     def decode(self, d, params: Optional[pdi_params] = None, stream=None, out=None, check=True) -> int:
         fr = d["frame"]

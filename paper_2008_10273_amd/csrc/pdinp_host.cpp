@@ -52,6 +52,36 @@ struct Workspace {
   int slot_count = 0;
 };
 
+// Buffers of global homogeneous diffusion inpainting for one plane size:
+// the pyramid (levels 1.. : mask, values, solution; level 0 reads the
+// caller's mask and values and solves into the caller's output), the CG
+// vectors of the finest level (reused by the coarser ones) and the FP64
+// scalars RR[0..max_iter], PQ[0..max_iter], BB (kHdSlots slots each).
+struct DiffWork {
+  static constexpr int kMaxLevels = 12;
+  int levels = 0;
+  int w[kMaxLevels] = {0}, h[kMaxLevels] = {0};
+  uint8_t *m[kMaxLevels] = {nullptr};
+  float *f[kMaxLevels] = {nullptr}, *u[kMaxLevels] = {nullptr};
+  float *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+  double *sc = nullptr;
+  int sc_cap = 0;     // doubles in sc
+  double *host = nullptr;  // pinned: the slots of RR[i] and BB, read back for the convergence test
+};
+
+static void free_diff(DiffWork &d) {
+  for (int l = 1; l < d.levels; ++l) {
+    if (d.m[l]) (void)hipFree(d.m[l]);
+    if (d.f[l]) (void)hipFree(d.f[l]);
+    if (d.u[l]) (void)hipFree(d.u[l]);
+  }
+  for (float *p : {d.r, d.p0, d.p1, d.q})
+    if (p) (void)hipFree(p);
+  if (d.sc) (void)hipFree(d.sc);
+  if (d.host) (void)hipHostFree(d.host);
+  d = DiffWork();
+}
+
 struct pdi_ctx {
   int device = 0;
   size_t budget = 0;
@@ -61,6 +91,7 @@ struct pdi_ctx {
   std::map<TableKey, TableSet> tables;
   std::map<hipStream_t, Workspace> ws;
   std::map<TuneKey, int> tune;  // blocks per workgroup of the wave-per-block path
+  std::map<std::pair<int, int>, DiffWork> diff;  // per plane size (W, H)
 };
 
 namespace {
@@ -416,6 +447,7 @@ void pdi_destroy(pdi_ctx *c) {
     (void)hipFree(kv.second.deferred);
     (void)hipFree(kv.second.slots);
   }
+  for (auto &kv : c->diff) free_diff(kv.second);
   delete c;
 }
 
@@ -861,3 +893,119 @@ int pdi_pack_dense(const pdi_frame *frame, const uint8_t *m, const float *f, int
 }
 
 }  // extern "C"
+
+// ----------------------------------------------- homogeneous diffusion
+
+void pdi_default_cg_params(pdi_cg_params *p) {
+  if (!p) return;
+  p->tol = 1e-6;
+  p->max_iter = 4000;
+  p->check = 16;
+}
+
+int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, const float *f,
+                        const pdi_cg_params *cp, float *u, void *stream, int32_t *iterations) {
+  if (!c) return PDI_EINVAL;
+  if (iterations) *iterations = 0;
+  if (!mask || !f || !u) return set_err(c, PDI_EINVAL, "null mask, values or output");
+  if (width <= 0 || height <= 0 || (long long)width * height > (1LL << 30))
+    return set_err(c, PDI_EINVAL, "bad plane size %dx%d", width, height);
+  pdi_cg_params P;
+  pdi_default_cg_params(&P);
+  if (cp) P = *cp;
+  if (!(P.tol > 0.0) || !(P.tol < 1.0)) return set_err(c, PDI_EINVAL, "tol must be in (0, 1)");
+  if (P.max_iter < 1 || P.max_iter > (1 << 16)) return set_err(c, PDI_EINVAL, "max_iter must be in [1, 65536]");
+  if (P.check < 1) return set_err(c, PDI_EINVAL, "bad check");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  std::lock_guard<std::mutex> lock(c->mu);
+  hipStream_t s = (hipStream_t)stream;
+  DiffWork &D = c->diff[{width, height}];
+  int rc = PDI_OK;
+  if (D.levels == 0) {
+    // Pyramid: halve (rounding up) while both sides stay >= 64 pixels.
+    D.w[0] = width;
+    D.h[0] = height;
+    D.levels = 1;
+    while (D.levels < DiffWork::kMaxLevels && D.w[D.levels - 1] >= 128 && D.h[D.levels - 1] >= 128) {
+      D.w[D.levels] = (D.w[D.levels - 1] + 1) / 2;
+      D.h[D.levels] = (D.h[D.levels - 1] + 1) / 2;
+      ++D.levels;
+    }
+    const size_t n0 = (size_t)width * height;
+    for (int l = 1; l < D.levels && !rc; ++l) {
+      const size_t n = (size_t)D.w[l] * D.h[l];
+      rc = dev_alloc(c, (void **)&D.m[l], n, "diffusion pyramid");
+      if (!rc) rc = dev_alloc(c, (void **)&D.f[l], sizeof(float) * n, "diffusion pyramid");
+      if (!rc) rc = dev_alloc(c, (void **)&D.u[l], sizeof(float) * n, "diffusion pyramid");
+    }
+    if (!rc) rc = dev_alloc(c, (void **)&D.r, sizeof(float) * n0, "diffusion vectors");
+    if (!rc) rc = dev_alloc(c, (void **)&D.p0, sizeof(float) * n0, "diffusion vectors");
+    if (!rc) rc = dev_alloc(c, (void **)&D.p1, sizeof(float) * n0, "diffusion vectors");
+    if (!rc) rc = dev_alloc(c, (void **)&D.q, sizeof(float) * n0, "diffusion vectors");
+    if (!rc && hipHostMalloc((void **)&D.host, 2 * pdi::kHdSlots * sizeof(double)) != hipSuccess)
+      rc = set_err(c, PDI_ENOMEM, "pinned host word");
+    if (rc) {
+      free_diff(D);
+      c->diff.erase({width, height});
+      return rc;
+    }
+  }
+  const int need = (2 * (P.max_iter + 1) + 1) * pdi::kHdSlots;
+  if (D.sc_cap < need) {
+    if (D.sc) (void)hipFree(D.sc);
+    D.sc = nullptr;
+    D.sc_cap = 0;
+    rc = dev_alloc(c, (void **)&D.sc, sizeof(double) * (size_t)need, "diffusion scalars");
+    if (rc) return rc;
+    D.sc_cap = need;
+  }
+  D.m[0] = const_cast<uint8_t *>(mask);
+  D.f[0] = const_cast<float *>(f);
+  D.u[0] = u;
+  double *RR = D.sc, *PQ = D.sc + (P.max_iter + 1) * pdi::kHdSlots, *BB = D.sc + 2 * (P.max_iter + 1) * pdi::kHdSlots;
+  for (int l = 1; l < D.levels && e == hipSuccess; ++l)
+    e = pdi::hd_restrict(D.m[l - 1], D.f[l - 1], D.w[l - 1], D.h[l - 1], D.m[l], D.f[l], D.w[l], D.h[l], s);
+  bool converged = true;
+  int its0 = 0;
+  for (int l = D.levels - 1; l >= 0 && e == hipSuccess; --l) {
+    const int W = D.w[l], H = D.h[l];
+    e = pdi::hd_init(D.m[l], D.f[l], W, H, l + 1 < D.levels ? D.u[l + 1] : nullptr, l + 1 < D.levels ? D.w[l + 1] : 0,
+                     D.u[l], s);
+    if (e == hipSuccess) e = pdi::hd_zero(D.sc, need, s);
+    if (e == hipSuccess) e = pdi::hd_residual(D.m[l], D.f[l], D.u[l], W, H, D.r, RR, BB, s);
+    // CG; the residual norm is read back every P.check iterations.
+    int it = 0;
+    bool done = false;
+    while (e == hipSuccess) {
+      const size_t sb = sizeof(double) * pdi::kHdSlots;
+      e = hipMemcpyAsync(D.host, RR + (size_t)it * pdi::kHdSlots, sb, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(D.host + pdi::kHdSlots, BB, sb, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) break;
+      double rr = 0.0, bb = 0.0;
+      for (int k = 0; k < pdi::kHdSlots; ++k) {
+        rr += D.host[k];
+        bb += D.host[pdi::kHdSlots + k];
+      }
+      if (!(rr == rr)) break;  // NaN: not converging
+      if (rr <= P.tol * P.tol * bb) {
+        done = true;
+        break;
+      }
+      if (it >= P.max_iter) break;
+      const int stop = std::min(P.max_iter, it + P.check);
+      for (; it < stop && e == hipSuccess; ++it)
+        e = pdi::hd_iterate(D.m[l], W, H, RR, PQ, it, D.u[l], D.r, (it & 1) ? D.p1 : D.p0, (it & 1) ? D.p0 : D.p1,
+                            D.q, s);
+    }
+    if (l == 0) {
+      its0 = it;
+      converged = done;
+    }
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "diffusion inpainting");
+  if (iterations) *iterations = its0;
+  if (!converged) return set_err(c, PDI_ESOLVE, "CG did not reach tol %g within %d iterations", P.tol, P.max_iter);
+  return PDI_OK;
+}

@@ -149,4 +149,18 @@ hipError_t launch_plain_all(const FrameDev &f, hipStream_t stream);
 hipError_t launch_general_deferred(const FrameDev &f, hipStream_t stream);
 hipError_t launch_coef_general(const FrameDev &f, hipStream_t stream);  // coef: the deferred blocks
 
+// Global homogeneous diffusion inpainting (pdinp_diffusion.hip); all
+// asynchronous on the stream.  Scalars (RR per iteration, PQ per iteration,
+// BB) are kHdSlots doubles each, summed by their readers.
+constexpr int kHdSlots = 64;
+hipError_t hd_restrict(const uint8_t *mf, const float *ff, int Wf, int Hf, uint8_t *mc, float *fc, int Wc, int Hc,
+                       hipStream_t s);
+hipError_t hd_init(const uint8_t *m, const float *f, int W, int H, const float *uc, int Wc, float *u, hipStream_t s);
+hipError_t hd_residual(const uint8_t *m, const float *f, const float *u, int W, int H, float *r, double *rr,
+                       double *bb, hipStream_t s);
+// One CG iteration: k_hd_apply (pnew, q, PQ[it]) then k_hd_update (u, r, RR[it + 1]).
+hipError_t hd_iterate(const uint8_t *m, int W, int H, const double *RR, const double *PQ, int it, float *u, float *r,
+                      const float *pold, float *pnew, float *q, hipStream_t s);
+hipError_t hd_zero(double *a, int n, hipStream_t s);
+
 }  // namespace pdi
