@@ -49,7 +49,7 @@ EVALS = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16x2": 3}
 # launch shape the counters were taken on (null after a kernel change, or
 # when the autotuned launch choice differs).
 # (config, frames per step, launch choice): bytes per launch
-TRAFFIC = {}
+TRAFFIC = {(1, 8, 16): 111678052, (2, 8, 2): 116327924}
 
 
 def algorithmic_bytes(fr) -> int:
