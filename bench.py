@@ -50,6 +50,8 @@ EVALS = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16x2": 3}
 # when the autotuned launch choice differs).
 # (config, frames per step, launch choice): bytes per launch
 TRAFFIC = {(1, 8, 16): 111678052, (2, 8, 2): 116327924}
+# HBM bytes of one finest-level k_hd_cg iteration of config 6 (same counters)
+TRAFFIC_HD_ITER = 85364345
 
 
 def algorithmic_bytes(fr) -> int:
@@ -427,10 +429,12 @@ def bench_intra(args, torch, binding, synth):
                           f"{dt:.1f} s; planes/s scaled by the pixel ratio (the 1080p factorisation does not fit)",
                    cpu_model=cpu_model(), nproc=os.cpu_count())
         log(f"oracle: {cpu['value']:.3f} 1080p planes/s (scaled from {cw}x{ch})")
-    # bytes of the finest level's CG: per iteration the stencil kernel reads
-    # mask, r, p and writes p, q (17 B/px), the update reads p, q, u, r and
-    # writes u, r (24 B/px); coarser levels and convergence checks are in the time
-    ab = its * 41 * W * H
+    # bytes of the finest level's CG: per iteration k_hd_cg reads the mask
+    # (1 B) and writes p, r', w', s' (16 B) at every pixel, and reads u, p,
+    # r, w, s and writes u (24 B) at the unknowns; coarser levels and the
+    # convergence checks are in the time
+    nfree = int((~m).sum())
+    ab = its * (17 * W * H + 24 * nfree)
     achieved = ab / (secs / args.steps) / 1e9
     rec = dict(metric="1080p intra planes/s by global homogeneous diffusion inpainting (tol 1e-6)", value=pps,
                unit="planes/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=1e3 * secs / args.steps,
@@ -440,8 +444,8 @@ def bench_intra(args, torch, binding, synth):
                        "cg_iterations_finest": its},
                properties={"exact_at_mask": exact_at_mask, "min": float(g.min()), "max": float(g.max())},
                roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                         "kernel": "k_hd_apply + k_hd_update, finest level (whole solve timed)",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": its * TRAFFIC_HD_ITER,
+                         "kernel": "k_hd_cg, finest level (whole solve timed)",
                          "algorithmic_bytes_per_launch": ab, "launch_ms": 1e3 * secs / args.steps},
                cpu_baseline=cpu, wall_s=wall)
     dec.close()

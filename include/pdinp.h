@@ -189,10 +189,15 @@ int decode_coefficients_batch(pdi_ctx *ctx, int n, const pdi_frame *frame, const
  * with their mean value), CG on the coarsest level, each finer level
  * started from the coarser solution. */
 typedef struct {
-    double tol;       /* stop a level when |r|_2 <= tol |b|_2 (b: right-hand side of the
+    double tol;       /* stop the finest level when |r|_2 <= tol |b|_2 (b: right-hand side of the
                          unknowns' system); in (0, 1), default 1e-6 */
     int32_t max_iter; /* CG iterations per level at most, in [1, 65536]; default 4000 */
-    int32_t check;    /* iterations between convergence tests (host read-backs); default 16 */
+    int32_t check;    /* iterations queued between host read-backs, in [1, 1024]; default 16.
+                         Convergence is tested on the device before every iteration and
+                         the iterations queued past it do nothing, so a level stops at the
+                         first iteration that meets tol whatever check is */
+    double coarse_tol; /* the same test on the coarser levels, which only supply the
+                          finest level's start; in [tol, 1), default 1e-3 */
 } pdi_cg_params;
 
 void pdi_default_cg_params(pdi_cg_params *p);
@@ -201,9 +206,9 @@ void pdi_default_cg_params(pdi_cg_params *p);
  * pixels only), u: float W*H output; row-major DEVICE buffers, caller
  * owned.  cp: HOST pointer or NULL for the defaults.  *iterations (HOST,
  * may be NULL) receives the CG iterations of the finest level.
- * Synchronous on `stream` (the convergence tests read back one residual
- * norm every cp->check iterations); the first call for a plane size
- * allocates its pyramid.  An empty mask gives u = 0 (the system is then
+ * Synchronous on `stream` (the residual norms are read back every
+ * cp->check iterations); the first call for a plane size allocates its
+ * pyramid.  An empty mask gives u = 0 (the system is then
  * singular).  Returns PDI_EINVAL for NULL pointers, a size outside
  * [1, 2^30] pixels or bad parameters, PDI_ESOLVE when the finest level does
  * not reach tol within max_iter, PDI_ENOMEM / PDI_EHIP as elsewhere. */

@@ -61,7 +61,8 @@ def coef_params(steps, rho: float) -> pdi_coef_params:
 
 
 class pdi_cg_params(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("check", ctypes.c_int32)]
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("check", ctypes.c_int32),
+                ("coarse_tol", ctypes.c_double)]
 
 
 def cg_params(**kw) -> pdi_cg_params:

@@ -55,7 +55,7 @@ __device__ __forceinline__ void wg_add2(double v, double w, double *dst0, double
 
 // Kernels run on 64 x 16 pixel tiles: thread (tx, ty) of tile (bx, by)
 // owns pixel (64 bx + tx, 16 by + ty).  The per-level kernels take one tile
-// per workgroup (a 2D grid); the per-iteration kernels are persistent (at
+// per workgroup (a 2D grid); the per-iteration kernel is persistent (at
 // most kHdWgs workgroups, each looping over tiles) so that the scalars are
 // read and the partial sums added once per workgroup, not once per tile.
 constexpr int kTx = 64, kTy = 16;
@@ -122,74 +122,157 @@ __global__ __launch_bounds__(kHdThreads) void k_hd_residual(const uint8_t *m, co
   wg_add2(sr, sb, rr, bb);
 }
 
-// One half of CG iteration it: p = r + beta p_old (beta = RR[it] / RR[it-1],
-// 0 for it = 0), formed once per pixel of a tile and its one-pixel halo in
-// LDS (0 on the mask and outside the plane); q = A_UU p from LDS;
-// PQ[it] += p . q.  RR and PQ hold kHdSlots slots per iteration.
-__global__ __launch_bounds__(kHdThreads) void k_hd_apply(const uint8_t *m, const float *r, const float *pold,
-                                                         int W, int H, const double *RR, int it, float *pnew,
-                                                         float *q, double *PQ) {
-  __shared__ float ps[kTy + 2][kTx + 2];
+// w = A_UU r (r is zero on the mask) and DEL[0] += w . r: the start of the
+// single-reduction CG recurrences below (one 2D tile per workgroup, the
+// neighbours read from global memory: once per level).
+__global__ __launch_bounds__(kHdThreads) void k_hd_aw(const uint8_t *m, const float *r, int W, int H, float *w,
+                                                      double *del) {
+  const int x = blockIdx.x * kTx + (threadIdx.x & (kTx - 1)), y = blockIdx.y * kTy + threadIdx.x / kTx;
+  double sd = 0.0;
+  if (x < W && y < H) {
+    const int i = y * W + x;
+    float wi = 0.f;
+    if (!m[i]) {
+      const float ri = r[i];
+      float nsum = 0.f, deg = 0.f;
+      if (x > 0) { nsum += r[i - 1]; deg += 1.f; }
+      if (x + 1 < W) { nsum += r[i + 1]; deg += 1.f; }
+      if (y > 0) { nsum += r[i - W]; deg += 1.f; }
+      if (y + 1 < H) { nsum += r[i + W]; deg += 1.f; }
+      wi = deg * ri - nsum;
+      sd = (double)wi * ri;
+    }
+    w[i] = wi;
+  }
+  wg_add2(sd, 0.0, del, nullptr);
+}
+
+// Tile t of the persistent kernel's k-th pass for workgroup b of G.  Each
+// XCD (workgroups are dealt to the 8 XCDs in turn) takes one contiguous
+// eighth of the tiles in raster order, so the halo lines a tile shares with
+// its neighbours are mostly fetched by the same L2.  Every tile is taken
+// exactly once whatever the dispatch order; G < 8 falls back to a stride.
+struct TileWalk {
+  int t, end, step;
+  __device__ TileWalk(int ntiles) {
+    const int G = gridDim.x, b = blockIdx.x;
+    if (G < 8) {
+      t = b;
+      end = ntiles;
+      step = G;
+    } else {
+      const int k = b & 7, nk = (G - k + 7) >> 3;  // workgroups on this XCD
+      t = (int)((long long)ntiles * k / 8) + (b >> 3);
+      end = (int)((long long)ntiles * (k + 1) / 8);
+      step = nk;
+    }
+  }
+};
+
+// One CG iteration in the single-reduction form (Chronopoulos and Gear):
+// with w = A r and s = A p carried as vectors, both dot products of an
+// iteration come from the same pass, so an iteration is one launch.
+//   beta = g_i / g_{i-1}, alpha = g_i / (d_i - beta g_i / alpha_{i-1})
+//   (beta = 0, alpha = g_0 / d_0 for i = 0), with g_i = r.r, d_i = w.r;
+//   p = r + beta p, s = w + beta s, u += alpha p, r' = r - alpha s,
+//   w' = A r', and GAM[i+1] += r'.r', DEL[i+1] += w'.r'.
+// r', formed once per pixel of a tile and its one-pixel halo in LDS, feeds
+// the stencil; r, w and s are read at the halo, so they are double-buffered
+// (ri, wi, si in, ro, wo, so out); u and p are updated in place.  All
+// vectors are zero on the mask.  Workgroup 0 records alpha in ALPHA[i].
+// Once g_i <= tol2 |b|^2 (BB) every workgroup returns at once, leaving
+// GAM[i+1] = 0, so the launches queued after convergence do nothing.
+__global__ __launch_bounds__(kHdThreads) void k_hd_cg(const uint8_t *m, int W, int H, double *GAM, double *DEL,
+                                                      double *ALPHA, const double *BB, double tol2, int it, float *u, float *p,
+                                                      const float *ri, const float *wi, const float *si, float *ro,
+                                                      float *wo, float *so) {
+  __shared__ float rs[kTy + 2][kTx + 2];
   const int tx = threadIdx.x & (kTx - 1), ty = threadIdx.x / kTx;
   const int ntx = (W + kTx - 1) / kTx, ntiles = ntx * ((H + kTy - 1) / kTy);
-  float beta = 0.f;
-  if (it) {
-    const double prev = slot_sum(RR + (it - 1) * kHdSlots);
-    if (prev > 0.0) beta = (float)(slot_sum(RR + it * kHdSlots) / prev);  // 0 once converged exactly
+  float alpha = 0.f, beta = 0.f;
+  {
+    const double g = slot_sum(GAM + it * kHdSlots), d = slot_sum(DEL + it * kHdSlots);
+    if (g <= tol2 * slot_sum(BB)) return;  // converged (uniform over the grid)
+    double a = 0.0, bt = 0.0;
+    if (it == 0) {
+      if (d > 0.0) a = g / d;
+    } else {
+      const double gp = slot_sum(GAM + (it - 1) * kHdSlots), ap = ALPHA[it - 1];
+      if (gp > 0.0 && ap > 0.0) {
+        bt = g / gp;
+        const double den = d - bt * g / ap;
+        if (den > 0.0) a = g / den;
+      }
+    }
+    alpha = (float)a;
+    beta = (float)bt;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ALPHA[it] = a;  // 0 once converged exactly: the iterate stays put
   }
-  double s = 0.0;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int x0 = (t % ntx) * kTx, y0 = (t / ntx) * kTy;
+  const bool first = it == 0;
+  double sg = 0.0, sd = 0.0;
+  for (TileWalk tw(ntiles); tw.t < tw.end; tw.t += tw.step) {
+    const int x0 = (tw.t % ntx) * kTx, y0 = (tw.t / ntx) * kTy;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool in = x < W && y < H;
+    const int i = y * W + x;
+    bool free_px = false;
     __syncthreads();  // the previous tile's LDS reads are done
-    for (int k = threadIdx.x; k < (kTy + 2) * (kTx + 2); k += kHdThreads) {
-      const int ly = k / (kTx + 2), lx = k - ly * (kTx + 2);
+    // own pixel: coalesced rows of 64
+    float rn = 0.f;
+    if (in) {
+      free_px = !m[i];
+      float pn = 0.f, sn = 0.f;
+      if (free_px) {
+        const float rv = ri[i], wv = wi[i];
+        pn = first ? rv : fmaf(beta, p[i], rv);
+        sn = first ? wv : fmaf(beta, si[i], wv);
+        rn = fmaf(-alpha, sn, rv);
+        u[i] = fmaf(alpha, pn, u[i]);
+      }
+      p[i] = pn;
+      so[i] = sn;
+      ro[i] = rn;
+    }
+    rs[ty + 1][tx + 1] = rn;
+    // halo: 64 above, 64 below, 18 left, 18 right (same arithmetic as the
+    // owning tile, so both see the same r')
+    if (threadIdx.x < 2 * kTx + 2 * (kTy + 2)) {
+      int lx, ly;
+      const int h = threadIdx.x;
+      if (h < kTx) { lx = h + 1; ly = 0; }
+      else if (h < 2 * kTx) { lx = h - kTx + 1; ly = kTy + 1; }
+      else if (h < 2 * kTx + kTy + 2) { lx = 0; ly = h - 2 * kTx; }
+      else { lx = kTx + 1; ly = h - 2 * kTx - (kTy + 2); }
       const int gx = x0 + lx - 1, gy = y0 + ly - 1;
       float v = 0.f;
       if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
         const int j = gy * W + gx;
-        if (!m[j]) v = r[j] + beta * pold[j];
+        if (!m[j]) {
+          const float rv = ri[j], wv = wi[j];
+          const float sn = first ? wv : fmaf(beta, si[j], wv);
+          v = fmaf(-alpha, sn, rv);
+        }
       }
-      ps[ly][lx] = v;
+      rs[ly][lx] = v;
     }
     __syncthreads();
-    const int x = x0 + tx, y = y0 + ty;
-    if (x < W && y < H) {
-      const int i = y * W + x;
-      const float pi = ps[ty + 1][tx + 1];
-      float qi = 0.f;
-      if (!m[i]) {
-        // neighbours inside the plane; a masked neighbour holds p = 0
+    if (in) {
+      float wn = 0.f;
+      if (free_px) {
+        // neighbours inside the plane; a masked neighbour holds r' = 0
         float nsum = 0.f, deg = 0.f;
-        if (x > 0) { nsum += ps[ty + 1][tx]; deg += 1.f; }
-        if (x + 1 < W) { nsum += ps[ty + 1][tx + 2]; deg += 1.f; }
-        if (y > 0) { nsum += ps[ty][tx + 1]; deg += 1.f; }
-        if (y + 1 < H) { nsum += ps[ty + 2][tx + 1]; deg += 1.f; }
-        qi = deg * pi - nsum;
-        s += (double)pi * qi;
+        if (x > 0) { nsum += rs[ty + 1][tx]; deg += 1.f; }
+        if (x + 1 < W) { nsum += rs[ty + 1][tx + 2]; deg += 1.f; }
+        if (y > 0) { nsum += rs[ty][tx + 1]; deg += 1.f; }
+        if (y + 1 < H) { nsum += rs[ty + 2][tx + 1]; deg += 1.f; }
+        wn = deg * rn - nsum;
+        sg += (double)rn * rn;
+        sd += (double)wn * rn;
       }
-      pnew[i] = pi;
-      q[i] = qi;
+      wo[i] = wn;
     }
   }
-  wg_add2(s, 0.0, PQ + it * kHdSlots, nullptr);
-}
-
-// The other half: alpha = RR[it] / PQ[it]; u += alpha p; r -= alpha q;
-// RR[it + 1] += |r|^2 (pointwise: the workgroups stride over the pixels).
-__global__ __launch_bounds__(kHdThreads) void k_hd_update(const float *p, const float *q, int W, int H,
-                                                          const double *RR, const double *PQ, int it, float *u,
-                                                          float *r, double *RRn) {
-  const double pq = slot_sum(PQ + it * kHdSlots);
-  const float alpha = pq > 0.0 ? (float)(slot_sum(RR + it * kHdSlots) / pq) : 0.f;
-  const int n = W * H;
-  double s = 0.0;
-  for (int i = blockIdx.x * kHdThreads + threadIdx.x; i < n; i += gridDim.x * kHdThreads) {
-    const float ri = r[i] - alpha * q[i];
-    u[i] += alpha * p[i];
-    r[i] = ri;
-    s += (double)ri * ri;
-  }
-  wg_add2(s, 0.0, RRn, nullptr);
+  wg_add2(sg, sd, GAM + (it + 1) * kHdSlots, DEL + (it + 1) * kHdSlots);
 }
 
 __global__ __launch_bounds__(kHdThreads) void k_hd_zero(double *a, int n) {
@@ -214,14 +297,17 @@ hipError_t hd_residual(const uint8_t *m, const float *f, const float *u, int W, 
   hipLaunchKernelGGL(k_hd_residual, hd_tiles(W, H), dim3(kHdThreads), 0, s, m, f, u, W, H, r, rr, bb);
   return hipGetLastError();
 }
-hipError_t hd_iterate(const uint8_t *m, int W, int H, const double *RR, const double *PQ, int it, float *u, float *r,
-                      const float *pold, float *pnew, float *q, hipStream_t s) {
+hipError_t hd_start(const uint8_t *m, const float *r, int W, int H, float *w, double *del, hipStream_t s) {
+  hipLaunchKernelGGL(k_hd_aw, hd_tiles(W, H), dim3(kHdThreads), 0, s, m, r, W, H, w, del);
+  return hipGetLastError();
+}
+hipError_t hd_iterate(const uint8_t *m, int W, int H, double *GAM, double *DEL, double *ALPHA, const double *BB,
+                      double tol2, int it, float *u, float *p, const float *ri, const float *wi, const float *si,
+                      float *ro, float *wo, float *so, hipStream_t s) {
   const dim3 t = hd_tiles(W, H);
   const dim3 g(std::min<unsigned>(t.x * t.y, kHdWgs));
-  hipLaunchKernelGGL(k_hd_apply, g, dim3(kHdThreads), 0, s, m, r, pold, W, H, RR, it, pnew, q,
-                     const_cast<double *>(PQ));
-  hipLaunchKernelGGL(k_hd_update, g, dim3(kHdThreads), 0, s, pnew, q, W, H, RR, PQ, it, u, r,
-                     const_cast<double *>(RR) + (it + 1) * kHdSlots);
+  hipLaunchKernelGGL(k_hd_cg, g, dim3(kHdThreads), 0, s, m, W, H, GAM, DEL, ALPHA, BB, tol2, it, u, p, ri, wi, si, ro,
+                     wo, so);
   return hipGetLastError();
 }
 hipError_t hd_zero(double *a, int n, hipStream_t s) {

@@ -56,17 +56,19 @@ struct Workspace {
 // the pyramid (levels 1.. : mask, values, solution; level 0 reads the
 // caller's mask and values and solves into the caller's output), the CG
 // vectors of the finest level (reused by the coarser ones) and the FP64
-// scalars RR[0..max_iter], PQ[0..max_iter], BB (kHdSlots slots each).
+// scalars GAM[0..max_iter], DEL[0..max_iter], BB (kHdSlots slots each) and
+// ALPHA[0..max_iter].
 struct DiffWork {
   static constexpr int kMaxLevels = 12;
   int levels = 0;
   int w[kMaxLevels] = {0}, h[kMaxLevels] = {0};
   uint8_t *m[kMaxLevels] = {nullptr};
   float *f[kMaxLevels] = {nullptr}, *u[kMaxLevels] = {nullptr};
-  float *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+  float *p = nullptr, *rv[2] = {nullptr}, *wv[2] = {nullptr}, *sv[2] = {nullptr};  // CG vectors, full size
   double *sc = nullptr;
   int sc_cap = 0;     // doubles in sc
-  double *host = nullptr;  // pinned: the slots of RR[i] and BB, read back for the convergence test
+  double *host = nullptr;  // pinned: the slots of GAM[i..] and BB, read back for the convergence test
+  int host_cap = 0;        // doubles in host
 };
 
 static void free_diff(DiffWork &d) {
@@ -75,7 +77,7 @@ static void free_diff(DiffWork &d) {
     if (d.f[l]) (void)hipFree(d.f[l]);
     if (d.u[l]) (void)hipFree(d.u[l]);
   }
-  for (float *p : {d.r, d.p0, d.p1, d.q})
+  for (float *p : {d.p, d.rv[0], d.rv[1], d.wv[0], d.wv[1], d.sv[0], d.sv[1]})
     if (p) (void)hipFree(p);
   if (d.sc) (void)hipFree(d.sc);
   if (d.host) (void)hipHostFree(d.host);
@@ -901,6 +903,7 @@ void pdi_default_cg_params(pdi_cg_params *p) {
   p->tol = 1e-6;
   p->max_iter = 4000;
   p->check = 16;
+  p->coarse_tol = 1e-3;
 }
 
 int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, const float *f,
@@ -915,7 +918,8 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
   if (cp) P = *cp;
   if (!(P.tol > 0.0) || !(P.tol < 1.0)) return set_err(c, PDI_EINVAL, "tol must be in (0, 1)");
   if (P.max_iter < 1 || P.max_iter > (1 << 16)) return set_err(c, PDI_EINVAL, "max_iter must be in [1, 65536]");
-  if (P.check < 1) return set_err(c, PDI_EINVAL, "bad check");
+  if (P.check < 1 || P.check > 1024) return set_err(c, PDI_EINVAL, "check must be in [1, 1024]");
+  if (!(P.coarse_tol >= P.tol) || !(P.coarse_tol < 1.0)) return set_err(c, PDI_EINVAL, "coarse_tol must be in [tol, 1)");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   std::lock_guard<std::mutex> lock(c->mu);
@@ -939,19 +943,26 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
       if (!rc) rc = dev_alloc(c, (void **)&D.f[l], sizeof(float) * n, "diffusion pyramid");
       if (!rc) rc = dev_alloc(c, (void **)&D.u[l], sizeof(float) * n, "diffusion pyramid");
     }
-    if (!rc) rc = dev_alloc(c, (void **)&D.r, sizeof(float) * n0, "diffusion vectors");
-    if (!rc) rc = dev_alloc(c, (void **)&D.p0, sizeof(float) * n0, "diffusion vectors");
-    if (!rc) rc = dev_alloc(c, (void **)&D.p1, sizeof(float) * n0, "diffusion vectors");
-    if (!rc) rc = dev_alloc(c, (void **)&D.q, sizeof(float) * n0, "diffusion vectors");
-    if (!rc && hipHostMalloc((void **)&D.host, 2 * pdi::kHdSlots * sizeof(double)) != hipSuccess)
-      rc = set_err(c, PDI_ENOMEM, "pinned host word");
+    for (float **v : {&D.p, &D.rv[0], &D.rv[1], &D.wv[0], &D.wv[1], &D.sv[0], &D.sv[1]})
+      if (!rc) rc = dev_alloc(c, (void **)v, sizeof(float) * n0, "diffusion vectors");
     if (rc) {
       free_diff(D);
       c->diff.erase({width, height});
       return rc;
     }
   }
-  const int need = (2 * (P.max_iter + 1) + 1) * pdi::kHdSlots;
+  // GAM and DEL: slots per iteration; BB: one slotted scalar; ALPHA: one
+  // double per iteration.
+  const int need = (2 * (P.max_iter + 1) + 1) * pdi::kHdSlots + (P.max_iter + 1);
+  const int hneed = (P.check + 2) * pdi::kHdSlots;  // GAM[i..i+check] and BB
+  if (D.host_cap < hneed) {
+    if (D.host) (void)hipHostFree(D.host);
+    D.host = nullptr;
+    D.host_cap = 0;
+    if (hipHostMalloc((void **)&D.host, sizeof(double) * (size_t)hneed) != hipSuccess)
+      return set_err(c, PDI_ENOMEM, "pinned read-back buffer");
+    D.host_cap = hneed;
+  }
   if (D.sc_cap < need) {
     if (D.sc) (void)hipFree(D.sc);
     D.sc = nullptr;
@@ -963,7 +974,8 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
   D.m[0] = const_cast<uint8_t *>(mask);
   D.f[0] = const_cast<float *>(f);
   D.u[0] = u;
-  double *RR = D.sc, *PQ = D.sc + (P.max_iter + 1) * pdi::kHdSlots, *BB = D.sc + 2 * (P.max_iter + 1) * pdi::kHdSlots;
+  double *GAM = D.sc, *DEL = D.sc + (P.max_iter + 1) * pdi::kHdSlots, *BB = D.sc + 2 * (P.max_iter + 1) * pdi::kHdSlots,
+         *ALPHA = BB + pdi::kHdSlots;
   for (int l = 1; l < D.levels && e == hipSuccess; ++l)
     e = pdi::hd_restrict(D.m[l - 1], D.f[l - 1], D.w[l - 1], D.h[l - 1], D.m[l], D.f[l], D.w[l], D.h[l], s);
   bool converged = true;
@@ -973,31 +985,45 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
     e = pdi::hd_init(D.m[l], D.f[l], W, H, l + 1 < D.levels ? D.u[l + 1] : nullptr, l + 1 < D.levels ? D.w[l + 1] : 0,
                      D.u[l], s);
     if (e == hipSuccess) e = pdi::hd_zero(D.sc, need, s);
-    if (e == hipSuccess) e = pdi::hd_residual(D.m[l], D.f[l], D.u[l], W, H, D.r, RR, BB, s);
-    // CG; the residual norm is read back every P.check iterations.
-    int it = 0;
+    if (e == hipSuccess) e = pdi::hd_residual(D.m[l], D.f[l], D.u[l], W, H, D.rv[0], GAM, BB, s);
+    if (e == hipSuccess) e = pdi::hd_start(D.m[l], D.rv[0], W, H, D.wv[0], DEL, s);
+    // CG.  Each launch tests convergence on the device (GAM[it] against
+    // tol^2 BB) and does nothing once it holds; the host queues P.check
+    // launches at a time and reads back the norms GAM[seen..it] to find the
+    // first converged iteration.
+    int it = 0, seen = 0;
     bool done = false;
+    const double tol2 = l ? P.coarse_tol * P.coarse_tol : P.tol * P.tol;
     while (e == hipSuccess) {
       const size_t sb = sizeof(double) * pdi::kHdSlots;
-      e = hipMemcpyAsync(D.host, RR + (size_t)it * pdi::kHdSlots, sb, hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipMemcpyAsync(D.host + pdi::kHdSlots, BB, sb, hipMemcpyDeviceToHost, s);
+      const int n = it - seen + 1;
+      e = hipMemcpyAsync(D.host, GAM + (size_t)seen * pdi::kHdSlots, n * sb, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(D.host + (size_t)n * pdi::kHdSlots, BB, sb, hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) break;
-      double rr = 0.0, bb = 0.0;
-      for (int k = 0; k < pdi::kHdSlots; ++k) {
-        rr += D.host[k];
-        bb += D.host[pdi::kHdSlots + k];
+      double bb = 0.0;
+      for (int k = 0; k < pdi::kHdSlots; ++k) bb += D.host[(size_t)n * pdi::kHdSlots + k];
+      bool bad = false;
+      for (int i = 0; i < n && !done; ++i) {
+        double g = 0.0;
+        for (int k = 0; k < pdi::kHdSlots; ++k) g += D.host[(size_t)i * pdi::kHdSlots + k];
+        if (!(g == g)) {  // NaN: not converging
+          bad = true;
+          break;
+        }
+        if (g <= tol2 * bb) {
+          done = true;
+          it = seen + i;  // the launches after it did nothing
+        }
       }
-      if (!(rr == rr)) break;  // NaN: not converging
-      if (rr <= P.tol * P.tol * bb) {
-        done = true;
-        break;
-      }
-      if (it >= P.max_iter) break;
+      if (done || bad || it >= P.max_iter) break;
+      seen = it + 1;
       const int stop = std::min(P.max_iter, it + P.check);
-      for (; it < stop && e == hipSuccess; ++it)
-        e = pdi::hd_iterate(D.m[l], W, H, RR, PQ, it, D.u[l], D.r, (it & 1) ? D.p1 : D.p0, (it & 1) ? D.p0 : D.p1,
-                            D.q, s);
+      for (; it < stop && e == hipSuccess; ++it) {
+        const int a = it & 1, b = a ^ 1;
+        e = pdi::hd_iterate(D.m[l], W, H, GAM, DEL, ALPHA, BB, tol2, it, D.u[l], D.p, D.rv[a], D.wv[a], D.sv[a],
+                            D.rv[b], D.wv[b], D.sv[b], s);
+      }
     }
     if (l == 0) {
       its0 = it;

@@ -150,17 +150,23 @@ hipError_t launch_general_deferred(const FrameDev &f, hipStream_t stream);
 hipError_t launch_coef_general(const FrameDev &f, hipStream_t stream);  // coef: the deferred blocks
 
 // Global homogeneous diffusion inpainting (pdinp_diffusion.hip); all
-// asynchronous on the stream.  Scalars (RR per iteration, PQ per iteration,
-// BB) are kHdSlots doubles each, summed by their readers.
+// asynchronous on the stream.  Scalars (GAM = r.r and DEL = w.r per
+// iteration, BB = |b|^2) are kHdSlots doubles each, summed by their readers.
 constexpr int kHdSlots = 64;
 hipError_t hd_restrict(const uint8_t *mf, const float *ff, int Wf, int Hf, uint8_t *mc, float *fc, int Wc, int Hc,
                        hipStream_t s);
 hipError_t hd_init(const uint8_t *m, const float *f, int W, int H, const float *uc, int Wc, float *u, hipStream_t s);
 hipError_t hd_residual(const uint8_t *m, const float *f, const float *u, int W, int H, float *r, double *rr,
                        double *bb, hipStream_t s);
-// One CG iteration: k_hd_apply (pnew, q, PQ[it]) then k_hd_update (u, r, RR[it + 1]).
-hipError_t hd_iterate(const uint8_t *m, int W, int H, const double *RR, const double *PQ, int it, float *u, float *r,
-                      const float *pold, float *pnew, float *q, hipStream_t s);
+// w = A r on the unknowns and DEL[0] += w . r (start of a level's CG).
+hipError_t hd_start(const uint8_t *m, const float *r, int W, int H, float *w, double *del, hipStream_t s);
+// One CG iteration (k_hd_cg): u, p in place; r, w, s read from ri, wi, si
+// and written to ro, wo, so; GAM[it + 1], DEL[it + 1] accumulated and
+// ALPHA[it] recorded.  GAM and DEL hold kHdSlots slots per iteration.
+// Does nothing once GAM[it] <= tol2 * BB (converged).
+hipError_t hd_iterate(const uint8_t *m, int W, int H, double *GAM, double *DEL, double *ALPHA, const double *BB,
+                      double tol2, int it, float *u, float *p, const float *ri, const float *wi, const float *si,
+                      float *ro, float *wo, float *so, hipStream_t s);
 hipError_t hd_zero(double *a, int n, hipStream_t s);
 
 }  // namespace pdi

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2008_10273_amd", "csrc")
 # Sources with the per-file flags the build passes.
 SOURCES = [("pdinp_kernels.hip", []),
-           ("pdinp_wide.hip", ["-mllvm", "-pragma-unroll-threshold=1000000"])]
+           ("pdinp_wide.hip", ["-mllvm", "-pragma-unroll-threshold=1000000"]),
+           ("pdinp_diffusion.hip", [])]
 
 
 @pytest.fixture(scope="module")
