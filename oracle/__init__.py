@@ -69,6 +69,10 @@ def _lib():
             L.orc_dequant.restype = d
             L.orc_decode_coef.argtypes = [i, i, i, i, P, P, P, i, P, P, d, i, d, P, i]
             L.orc_decode_coef.restype = i
+            L.orc_quant.argtypes = [d, d]
+            L.orc_quant.restype = i
+            L.orc_encode_coef.argtypes = [i, i, i, i, P, P, P, i, P, i, d, P, P, P, i]
+            L.orc_encode_coef.restype = i
             _lib_handle = L
     return _lib_handle
 
@@ -209,6 +213,45 @@ def decode_coef(frame, coef, consts, steps, rho: float, op: int = 0, s: float = 
 def decode_coef_flat(frame, coef, consts, steps, rho: float, **kw) -> np.ndarray:
     """Like :func:`decode_coef` but returns the concatenated planes."""
     return np.concatenate([p.ravel() for p in decode_coef(frame, coef, consts, steps, rho, **kw)])
+
+
+def quant(c, step: float) -> np.ndarray:
+    """Dead-zone quantisation of coefficients (Sec. 2.3): sign(c) min(127,
+    floor(|c| / step)); |c| < step gives 0."""
+    c = np.asarray(c, dtype=np.float64)
+    L = _lib()
+    return np.array([L.orc_quant(float(v), float(step)) for v in c.ravel()], dtype=np.int64).reshape(c.shape)
+
+
+def encode_coef(frame, steps, op: int = 0, s: float = 1.0, nthreads: int = 0):
+    """Encode a frame's blocks (the encoder side of Sec. 2.2's split): per
+    block and value plane, c and a of the bordered system with the values at
+    the mask points, c quantised per plane by :func:`quant`.  Returns
+    (codes int8 laid out like ``frame.values``, c unquantised in the same
+    layout, consts float64: a of every block of every plane)."""
+    dims = plane_dims(frame.width, frame.height, frame.fmt)
+    b = frame.block_size
+    nblocks = sum(((W + b - 1) // b) * ((H + b - 1) // b) for W, H in dims)
+    bp = np.ascontiguousarray(frame.block_ptr, dtype=np.int32)
+    pos = np.ascontiguousarray(frame.pos, dtype=np.uint16)
+    vals = np.ascontiguousarray(frame.values, dtype=np.float32)
+    nv = max(vals.size, 1)
+    code = np.zeros(nv, np.int8)
+    cex = np.zeros(nv)
+    consts = np.zeros(nblocks)
+    st = np.zeros(3)
+    st[:len(steps)] = steps
+    if pos.size == 0:
+        pos = np.zeros(1, np.uint16)
+    if vals.size == 0:
+        vals = np.zeros(1, np.float32)
+    rc = _lib().orc_encode_coef(frame.width, frame.height, frame.fmt, b, _ptr(bp), _ptr(pos), _ptr(vals),
+                                int(bool(frame.chroma_shared)), _ptr(st), int(op), float(s),
+                                _ptr(code), _ptr(cex), _ptr(consts), int(nthreads))
+    if rc != 0:
+        raise ValueError("orc_encode_coef failed")
+    n = frame.values.size
+    return code[:n], cex[:n], consts
 
 
 def homogeneous_inpaint(mask, f) -> np.ndarray:

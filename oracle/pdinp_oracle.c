@@ -31,6 +31,10 @@
  *      Entries of G are read from the Toeplitz-plus-Hankel table of
  *      Sec. 2.2: with mirrored boundaries G depends on x - y and x + y.
  *
+ * Beside them: orc_decode_coef, the decoder of stored coefficients (Eq. 2
+ * summed directly from dequantised codes), and orc_encode_coef, the encoder
+ * side (c and a by route (2), dead-zone quantisation of c; Sec. 2.2-2.3).
+ *
  * Readings where the paper is silent: K = 0 gives u = 0 on the block; the
  * eigenvalues are those of the discrete 5-point operator (op 0) unless the
  * continuous symbol is asked for (op 1); lambda = mu^(-s) with lambda_00 = 0.
@@ -563,6 +567,131 @@ int orc_decode_coef(int width, int height, int fmt, int b, const int32_t *block_
                     dst[(long long)(I->y0 + t) * I->pw + I->x0 + j] = acc + a;
                 }
         }
+    }
+    for (it = 0; it < nshape; it++) free(shtab[it]);
+    free(items);
+    free(pblock);
+    return err ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* (4) The encoder side of that split: per block, c and a from the    */
+/*     bordered system of Sec. 2.2 (the values at the mask points as  */
+/*     right-hand side), c mapped to codes by dead-zone uniform       */
+/*     quantisation (Sec. 2.3), a kept.                               */
+/* ------------------------------------------------------------------ */
+
+/* Code of one coefficient: the interval [k step, (k+1) step) of |c| gives
+ * k, capped at 127, with the sign of c; |c| < step gives 0 (the dead zone
+ * around zero, so that zero coefficients stay zero).  orc_dequant maps a
+ * code back into its interval. */
+int orc_quant(double c, double step)
+{
+    double k = floor(fabs(c) / step);
+    if (k > 127.0) k = 127.0;
+    return c < 0.0 ? -(int)k : (int)k;
+}
+
+/* Encode every block of a frame.  Geometry, mask layout and chroma sharing
+ * as for orc_decode; values[] as for orc_decode.  Per block and value
+ * plane: c and a by orc_block_green_tab (dense LU of the bordered system in
+ * FP64); code[] (laid out like values) = orc_quant(c, steps[plane]);
+ * c_exact[] (same layout) = c unquantised; consts[] = a of every block of
+ * every plane (Y blocks, then Cb, then Cr, raster order; 0 for K = 0).
+ * Returns 0, or -1 on a position outside its block or a failed solve. */
+int orc_encode_coef(int width, int height, int fmt, int b, const int32_t *block_ptr,
+                    const uint16_t *pos, const float *values, int chroma_shared,
+                    const double *steps, int op, double s,
+                    int8_t *code, double *c_exact, double *consts, int nthreads)
+{
+    int PW[3], PH[3], NB[3], np_, g, ngroups, mp[3], vp[3][2], nv[3];
+    long long cbase[3], nnz;
+    int nitems = 0, cap, chroma_first = -1, m = 0, err = 0, it, k;
+    int nshape = 0, shw[16], shh[16];
+    double *shtab[16];
+    orc_item *items;
+    int *pblock;
+    if (fmt == 0) { np_ = 1; PW[0] = width; PH[0] = height; }
+    else { np_ = 3; PW[0] = width; PH[0] = height;
+           PW[1] = PW[2] = (width + 1) / 2; PH[1] = PH[2] = (height + 1) / 2; }
+    cbase[0] = 0;
+    for (g = 0; g < np_; g++) NB[g] = ((PW[g] + b - 1) / b) * ((PH[g] + b - 1) / b);
+    for (g = 1; g < np_; g++) cbase[g] = cbase[g - 1] + NB[g - 1];
+    if (fmt == 0) { ngroups = 1; mp[0] = 0; vp[0][0] = 0; nv[0] = 1; }
+    else if (chroma_shared) { ngroups = 2; mp[0] = 0; vp[0][0] = 0; nv[0] = 1;
+                              mp[1] = 1; vp[1][0] = 1; vp[1][1] = 2; nv[1] = 2; }
+    else { ngroups = 3; for (g = 0; g < 3; g++) { mp[g] = g; vp[g][0] = g; nv[g] = 1; } }
+    cap = 0;
+    for (g = 0; g < ngroups; g++) cap += NB[mp[g]];
+    items = (orc_item *)malloc(sizeof(orc_item) * (size_t)cap);
+    pblock = (int *)malloc(sizeof(int) * (size_t)cap);
+    for (g = 0; g < ngroups; g++) {
+        int W = PW[mp[g]], H = PH[mp[g]], bx, by;
+        if (mp[g] == 1) chroma_first = m;
+        for (by = 0; by < (H + b - 1) / b; by++)
+            for (bx = 0; bx < (W + b - 1) / b; bx++) {
+                orc_item *I = &items[nitems];
+                pblock[nitems++] = by * ((W + b - 1) / b) + bx;
+                I->m = m; I->x0 = bx * b; I->y0 = by * b;
+                I->w = W - I->x0 < b ? W - I->x0 : b;
+                I->h = H - I->y0 < b ? H - I->y0 : b;
+                I->pw = W; I->nplanes = nv[g];
+                for (k = 0; k < nv[g]; k++) I->plane[k] = vp[g][k];
+                m++;
+            }
+    }
+    nnz = block_ptr[m];
+    for (it = 0; it < nitems; it++) {
+        orc_item *I = &items[it];
+        for (k = 0; k < I->nplanes; k++) {
+            if (I->plane[k] == 2 && chroma_shared)
+                I->vbase[k] = nnz + (block_ptr[I->m] - block_ptr[chroma_first]);
+            else
+                I->vbase[k] = block_ptr[I->m];
+        }
+        for (k = 0; k < nshape; k++)
+            if (shw[k] == I->w && shh[k] == I->h) break;
+        if (k == nshape && nshape < 16) {
+            double *lam = (double *)malloc(sizeof(double) * (size_t)I->w * I->h);
+            shw[nshape] = I->w; shh[nshape] = I->h;
+            shtab[nshape] = (double *)malloc(sizeof(double) * (size_t)(I->w + 1) * (I->h + 1));
+            orc_eigenvalues(I->w, I->h, op, s, lam);
+            orc_green_table(I->w, I->h, lam, shtab[nshape]);
+            free(lam);
+            nshape++;
+        }
+    }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16) reduction(|:err)
+#endif
+    for (it = 0; it < nitems; it++) {
+        orc_item *I = &items[it];
+        int K = block_ptr[I->m + 1] - block_ptr[I->m];
+        int N = I->w * I->h, j, kk;
+        const uint16_t *ps = pos + block_ptr[I->m];
+        const double *tab = 0;
+        double *r = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1) * 2);
+        double *u = (double *)malloc(sizeof(double) * (size_t)N * 2);
+        double *c = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1) * 2);
+        double a[2] = {0.0, 0.0};
+        for (kk = 0; kk < nshape; kk++)
+            if (shw[kk] == I->w && shh[kk] == I->h) tab = shtab[kk];
+        for (kk = 0; kk < I->nplanes; kk++)
+            for (j = 0; j < K; j++) r[kk * K + j] = (double)values[I->vbase[kk] + j];
+        if (tab == 0 || orc_block_green_tab(I->w, I->h, tab, K, ps, I->nplanes, r, c, a, u) != 0) {
+            err |= 1;
+        } else {
+            for (kk = 0; kk < I->nplanes; kk++) {
+                int pl = I->plane[kk];
+                for (j = 0; j < K; j++) {
+                    code[I->vbase[kk] + j] = (int8_t)orc_quant(c[kk * K + j], steps[pl]);
+                    c_exact[I->vbase[kk] + j] = c[kk * K + j];
+                }
+                consts[cbase[pl] + pblock[it]] = a[kk];
+            }
+        }
+        free(r); free(u); free(c);
     }
     for (it = 0; it < nshape; it++) free(shtab[it]);
     free(items);

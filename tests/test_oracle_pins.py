@@ -429,6 +429,127 @@ def test_coef_round_trip_of_the_solve():
     assert np.abs(got - u.reshape(h, w)).max() <= bound
 
 
+# ------------------------------------------------- coefficient encoder
+
+def test_quant_codes():
+    """Dead-zone quantisation (Sec. 2.3): hand-computed codes; catches a
+    rounding instead of a floor, a lost dead zone, a wrong sign for negative
+    coefficients or a missing cap at 127."""
+    cases = [(0.3, 1.0, 0), (-0.99, 1.0, 0), (1.0, 1.0, 1), (-2.99, 1.0, -2), (3.75, 0.5, 7),
+             (-3.75, 0.5, -7), (-200.0, 1.0, -127), (0.0, 0.25, 0), (1000.0, 0.125, 127), (0.5, 0.25, 2)]
+    for c, step, want in cases:
+        assert oracle.quant([c], step)[0] == want, (c, step)
+
+
+def test_quant_inverts_dequant_intervals():
+    """A code is the interval its reconstruction lies in: for rho in [0, 1)
+    dequant(q) and c fall in the same interval [|q| step, (|q|+1) step) with
+    the same sign, and q = 0 exactly when |c| < step."""
+    rng = _rng(21)
+    c = rng.normal(0, 20, 4000)
+    step = 0.37
+    q = oracle.quant(c, step)
+    lo = oracle.dequant(q, step, 0.0)
+    hi = oracle.dequant(q, step, 1.0 - 1e-12)
+    nz = (q != 0) & (np.abs(q) < 127)
+    assert np.all(np.abs(lo[nz]) <= np.abs(c[nz]) + 1e-12) and np.all(np.abs(c[nz]) < np.abs(hi[nz]) + 1e-9)
+    assert np.all(np.sign(q[nz]) == np.sign(c[nz]))
+    assert np.all((q == 0) == (np.abs(c) < step))
+
+
+def _encode_frame(fmt, shared, seed):
+    W, H, b = 21, 13, 8
+    rng = _rng(seed)
+    ms, fs = [], []
+    dims = synth.plane_dims(W, H, fmt)
+    for k, (pw, ph) in enumerate(dims):
+        m = rng.uniform(size=(ph, pw)) < 0.3
+        if k == 0:
+            m[:8, :8] = False     # K = 0
+            m[:8, 8:16] = True    # K = w*h
+        ms.append(m)
+        fs.append(rng.uniform(-64, 64, (ph, pw)))
+    if fmt == synth.YUV420 and shared:
+        ms = ms[:2]
+    return synth.pack_dense(W, H, fmt, b, ms, fs)
+
+
+@pytest.mark.parametrize("fmt,shared", [(synth.GRAY, True), (synth.YUV420, True), (synth.YUV420, False)])
+def test_encode_coef_is_the_plain_solution(fmt, shared):
+    """The encoder's c and a on every block are those of the plain
+    definition: with u the Eq. (1) solution (dense Kronecker solve, no
+    Green's table), c = (A u) at the mask points and a = mean(u) (0 for an
+    empty block); the codes lie in c's quantiser interval.  Ragged edge
+    blocks, K = 0, K = w*h, shared and separate chroma masks; catches a
+    coefficient or constant written to the wrong run, block or plane."""
+    fr = _encode_frame(fmt, shared, 22)
+    W, H, b = fr.width, fr.height, fr.block_size
+    steps = (0.5, 0.25, 0.75)
+    code, cex, consts = oracle.encode_coef(fr, steps)
+    dims = synth.plane_dims(W, H, fmt)
+    bp = fr.block_ptr
+    groups = [[0]] if fmt == synth.GRAY else ([[0], [1, 2]] if fr.chroma_shared else [[0], [1], [2]])
+    cbase = np.concatenate([[0], np.cumsum(synth.plane_block_counts(W, H, fmt, b))])
+    m, chroma_first, runs = 0, None, []
+    for gp in groups:
+        pw, ph = dims[gp[0]]
+        if gp[0] == 1:
+            chroma_first = m
+        for k, (x0, y0, w, h) in enumerate(synth.block_grid(pw, ph, b)):
+            runs.append((gp, k, w, h, m))
+            m += 1
+    nnz = bp[m]
+    seen_full = seen_empty = 0
+    for gp, k, w, h, mb in runs:
+        lo, hi = bp[mb], bp[mb + 1]
+        pos = np.asarray(fr.pos[lo:hi], dtype=np.int64)
+        K = pos.size
+        seen_full += K == w * h
+        seen_empty += K == 0
+        for pl in gp:
+            vb = nnz + (lo - bp[chroma_first]) if (pl == 2 and fr.chroma_shared) else lo
+            r = np.asarray(fr.values[vb:vb + K], dtype=np.float64)
+            a = consts[cbase[pl] + k]
+            if K == 0:
+                assert a == 0.0
+                continue
+            u = brute.solve_eq1(w, h, pos, r, brute.operator(w, h, 1)).ravel()
+            c_ref = (brute.neg_laplacian(w, h) @ u)[pos]
+            np.testing.assert_allclose(cex[vb:vb + K], c_ref, atol=1e-8 * max(1.0, np.abs(c_ref).max()))
+            assert abs(a - u.mean()) <= 1e-9 * max(1.0, np.abs(u).max())
+            q = code[vb:vb + K].astype(np.int64)
+            c = cex[vb:vb + K]
+            st = steps[pl]
+            assert np.all((q == 0) == (np.abs(c) < st))
+            nz = (q != 0) & (np.abs(q) < 127)
+            assert np.all(np.abs(q[nz]) * st <= np.abs(c[nz]) + 1e-12)
+            assert np.all(np.abs(c[nz]) < (np.abs(q[nz]) + 1) * st)
+            assert np.all(np.sign(q[nz]) == np.sign(c[nz]))
+    assert seen_full >= 1 and seen_empty >= 1
+
+
+def test_encode_decode_round_trip():
+    """Codes and constants from the encoder decode (stored-coefficient
+    decoder) to the plain-definition inpainting of the same mask and values
+    within the quantisation bound: per pixel at most sum_i |c_i - c^_i|
+    |G(x, x_i)| <= step * K * max|G| with rho = 0.5; a fine step brings the
+    two together (Sec. 2.2's split reproduces the inpainting)."""
+    fr = synth.random_frame(40, 24, synth.YUV420, 8, (0.05, 0.3), seed=23)
+    ref = oracle.decode_flat(fr)
+    cmax = np.abs(oracle.encode_coef(fr, (1.0, 1.0, 1.0))[1]).max()
+    # steps that map every coefficient into [-127, 127] (no code saturates)
+    for step in (cmax / 32.0, cmax / 127.0):
+        steps = (step, step, step)
+        code, _, consts = oracle.encode_coef(fr, steps)
+        got = oracle.decode_coef_flat(fr, code, consts.astype(np.float32), steps, 0.5)
+        G = np.linalg.pinv(brute.neg_laplacian(8, 8))
+        Kmax = int(np.diff(fr.block_ptr).max())
+        bound = step * Kmax * np.abs(G).max() + 1e-3
+        err = np.abs(got - ref).max()
+        assert err <= bound, (step, err, bound)
+    assert err <= 0.5  # the fine step meets the decoder's acceptance bar
+
+
 # ------------------------------------- global homogeneous diffusion inpainting
 
 @pytest.mark.parametrize("W,H,d", [(7, 5, 0.3), (12, 9, 0.1), (16, 11, 0.05), (23, 14, 0.2)])
