@@ -20,6 +20,10 @@ Workloads (synthetic, seeded; the recipe is in paper_2008_10273_amd/synth.py):
   --config 5: the paper's decoder split - 1080p 4:2:0 frames with 8x8 blocks
       (masks as config 1) decoded from stored int8 codes and block constants
       by decode_coefficients_batch over --batch frames (no solve).
+  --config 7: the encoder side of that split - the same 1080p 4:2:0 frames
+      (8x8 blocks, masks and residual values) solved per block and quantised
+      to int8 codes + block constants by encode_coefficients_batch over
+      --batch frames.
   --config 6: intra prediction - global homogeneous diffusion inpainting of
       a 1920x1080 plane with a 4 % random mask (inpaint_homogeneous,
       cascadic CG to a relative residual of 1e-6); one step = one plane.
@@ -384,6 +388,107 @@ def bench_coef(args, torch, binding, synth):
     return rec
 
 
+def encode_bytes(fr) -> int:
+    """Bytes a coefficient encode must move: packed mask and values in, int8
+    codes and the FP32 constant of every block of every plane out."""
+    b = fr.block_size
+    dims = synth_plane_dims(fr)
+    nblocks = sum(((W + b - 1) // b) * ((H + b - 1) // b) for W, H in dims)
+    return int(4 * fr.block_ptr.size + 2 * fr.pos.size + 4 * fr.values.size + fr.values.size + 4 * nblocks)
+
+
+def synth_plane_dims(fr):
+    dims = [(fr.width, fr.height)]
+    if fr.fmt != 0:
+        dims += [((fr.width + 1) // 2, (fr.height + 1) // 2)] * 2
+    return dims
+
+
+def bench_encode(args, torch, binding, synth):
+    """Config 7: coefficient encode of 1080p 4:2:0 frames in 8x8 blocks
+    (encode_coefficients_batch: solve every block, quantise c, keep a).
+    One step = one call over --batch frames."""
+    B = args.batch
+    c = synth.ENCODE_CONFIG
+    items = generate([("coef", 5, k) for k in range(B)], args.workers if B > 1 else 1)
+    frs = [it[0] for it in items]
+    dec = binding.Decoder(0)
+    ds = [dec.alloc_coef(dec.upload(fr)) for fr in frs]
+    d = ds[0]
+    fr = frs[0]
+    stream = torch.cuda.Stream()
+    params = binding.default_params()
+    qp = binding.coef_params(c["steps"], 0.5)
+    log(f"config 7 ({c['name']}), {B} frames per step, {args.steps} steps")
+
+    def step():
+        if B == 1:
+            dec.encode_coef(d, qp, params, stream=stream)
+        else:
+            dec.encode_coef_batch(ds, qp, params, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    tm = StreamTimer(torch, stream)
+    t0 = time.perf_counter()
+    tm.start()
+    for _ in range(args.steps):
+        step()
+    secs = tm.stop()
+    wall = time.perf_counter() - t0
+    assert dec.sync(stream) == 0, binding.pdi_last_error(dec.ctx)
+    fps = B * args.steps / secs
+    n = fr.values.size
+    q = d["coef"].cpu().numpy()[:n].astype(np.int64)
+    a = d["consts"].cpu().numpy().astype(np.float64)
+    log(f"encode: {fps:.1f} frames/s, {1e3 * secs / args.steps:.4f} ms per step of {B} frames")
+    lat = []
+    for _ in range(args.latency_iters):
+        tm.start()
+        dec.encode_coef(d, qp, params, stream=stream)
+        lat.append(1e3 * tm.stop())
+    lat = np.array(lat)
+    log(f"single frame: p50 {np.percentile(lat, 50):.4f} ms, p99 {np.percentile(lat, 99):.4f} ms")
+    err = cpu = None
+    if not args.no_cpu:
+        import oracle
+        cores = host_cores()
+        n_run, tc0 = 0, time.perf_counter()
+        while n_run < 3 or time.perf_counter() - tc0 < 5.0:
+            qo, cex, ao = oracle.encode_coef(fr, c["steps"], nthreads=cores)
+            n_run += 1
+        dt = time.perf_counter() - tc0
+        cpu = dict(value=n_run / dt, unit="frames/s", cores=cores, kind="oracle",
+                   sample=f"{n_run} encodes of the benchmark frame (FP64 oracle: dense LU per block, "
+                          f"OpenMP over blocks), {dt:.1f} s", cpu_model=cpu_model(), nproc=os.cpu_count())
+        diff = q != qo.astype(np.int64)
+        err = dict(codes_differing=int(diff.sum()), codes=int(n), max_code_diff=int(np.abs(q - qo).max()),
+                   max_abs_const=float(np.abs(a - ao).max()))
+        log(f"oracle: {cpu['value']:.2f} frames/s on {cores} cores; {err}")
+    ab = sum(encode_bytes(f) for f in frs)
+    t_step = secs / args.steps
+    achieved = ab / t_step / 1e9
+    rec = dict(metric="1080p 4:2:0 residual frames/s encoded to quantised coefficients (8x8 blocks)", value=fps,
+               unit="frames/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=1e3 * t_step,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32 (int8 codes)",
+               data="synthetic",
+               config={"workload": c["name"], "width": c["width"], "height": c["height"], "format": "4:2:0",
+                       "block_size": c["block_size"], "density": list(c["density"]), "frames_per_step": B,
+                       "mask_blocks": fr.n_mask_blocks, "mask_points": int(fr.pos.size),
+                       "quantiser_steps": list(c["steps"])},
+               latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "mean": float(lat.mean()), "of": "one frame encoded alone"},
+               error_vs_oracle=err,
+               roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_fast (encode mode) + k_general_deferred",
+                         "algorithmic_bytes_per_launch": ab, "launch_ms": 1e3 * t_step},
+               cpu_baseline=cpu, wall_s=wall)
+    dec.close()
+    return rec
+
+
 def bench_intra(args, torch, binding, synth):
     """Config 6: global homogeneous diffusion inpainting of a 1080p plane
     (inpaint_homogeneous, cascadic CG, tol 1e-6); one step = one plane."""
@@ -616,7 +721,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2, 3, 4, 5, 6])
+    ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2, 3, 4, 5, 6, 7])
     ap.add_argument("--eval", default="fp32", choices=sorted(EVALS))
     ap.add_argument("--latency-iters", type=int, default=300)
     ap.add_argument("--nstreams", type=int, default=4, help="streams for overlapped / sequence decodes")
@@ -659,6 +764,8 @@ def main():
         rec = bench_coef(args, torch, binding, synth)
     elif args.config == 6:
         rec = bench_intra(args, torch, binding, synth)
+    elif args.config == 7:
+        rec = bench_encode(args, torch, binding, synth)
     else:
         rec = bench_serving(args, torch, binding, synth)
     assert torch.cuda.is_available()

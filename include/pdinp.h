@@ -180,6 +180,41 @@ int decode_coefficients_batch(pdi_ctx *ctx, int n, const pdi_frame *frame, const
                               const pdi_coef_params *qp, int block_size, const pdi_params *params,
                               float *const *outs, void *stream);
 
+/* ---- Encoding coefficients (the encoder side of that split) ----
+ * The encoder solves each block's bordered system (Sec. 2.2) for c and a
+ * from the residual at the block's mask points, maps c to codes in
+ * [-127, 127] by dead-zone uniform quantisation (Sec. 2.3) and keeps a.
+ * A code is q = sign(c) min(127, floor(|c| / step[plane])): |c| < step
+ * gives 0, and q is the interval that decode_coefficients reconstructs as
+ * sign(q) (|q| + rho) step.  Mask selection is the caller's (the mask is an
+ * input, as for decode_residual).
+ * frame, mask, values, block_size: DEVICE pointers as for decode_residual;
+ * qp: HOST pointer, step[] finite and > 0 (rho is not used).
+ *   coef:   int8 codes out, laid out exactly like values (caller owned,
+ *           one per mask point and value plane).
+ *   consts: FP32 constant a out for EVERY block of every plane, laid out as
+ *           decode_coefficients reads it (caller owned).
+ * Blocks with K = 0 get a = 0 (decode_residual gives u = 0 there); K = w*h
+ * is solved as well (the decoded block is then the values).  params: op, s,
+ * refine, refine_tau and validate apply as for decode_residual (blocks of
+ * at most 16x16 pixels take the wave-level solve, 32x32 blocks the
+ * per-block one); eval_dtype, out_int8 and path do not.  Asynchronous on
+ * `stream`; errors as decode_residual (PDI_EINVAL for a NULL pointer or a
+ * bad step; at pdi_sync PDI_EMASK / PDI_EVALUE for invalid input and
+ * PDI_ESOLVE for a non-finite c or a: the codes and constants of such
+ * blocks are then unspecified). */
+int encode_coefficients(pdi_ctx *ctx, const pdi_frame *frame, const pdi_mask *mask, const float *values,
+                        const pdi_coef_params *qp, int block_size, const pdi_params *params, int8_t *coef,
+                        float *consts, void *stream);
+
+/* Up to PDI_MAX_BATCH frames of one geometry in one launch of each kernel
+ * (arrays of n HOST-side entries of DEVICE pointers, as for
+ * decode_residual_batch). */
+int encode_coefficients_batch(pdi_ctx *ctx, int n, const pdi_frame *frame, const pdi_mask *masks,
+                              const float *const *values, const pdi_coef_params *qp, int block_size,
+                              const pdi_params *params, int8_t *const *coefs, float *const *consts,
+                              void *stream);
+
 /* ---- Global homogeneous diffusion inpainting (intra prediction) ----
  * The codec's intra frames are predicted by Eq. 1 of Sec. 2.1 on the whole
  * plane with A = -L (5-point Laplacian, reflecting boundaries): u = f at

@@ -24,7 +24,8 @@ ERROR_NAMES = {0: "PDI_OK", -1: "PDI_EINVAL", -2: "PDI_EMASK", -3: "PDI_ENOMEM",
                -5: "PDI_EBUSY", -6: "PDI_EVALUE", -7: "PDI_ESOLVE"}
 
 EXPORTS = ["pdi_default_params", "pdi_create", "pdi_destroy", "decode_residual", "decode_residual_batch",
-           "decode_coefficients", "decode_coefficients_batch", "pdi_sync",
+           "decode_coefficients", "decode_coefficients_batch", "encode_coefficients",
+           "encode_coefficients_batch", "pdi_sync",
            "pdi_default_cg_params", "inpaint_homogeneous",
            "pdi_last_error", "pdi_frame_info", "pdi_pack_dense", "pdi_validate_host", "pdi_autotune", "pdi_autotune_batch",
            "pdi_seq_create", "pdi_seq_launch", "pdi_seq_sync", "pdi_seq_destroy",
@@ -111,6 +112,13 @@ def lib() -> ctypes.CDLL:
                                                 VP, ctypes.POINTER(pdi_coef_params), i32,
                                                 ctypes.POINTER(pdi_params), VP, P]
         L.decode_coefficients_batch.restype = i32
+        L.encode_coefficients.argtypes = [P, ctypes.POINTER(pdi_frame), ctypes.POINTER(pdi_mask), P,
+                                          ctypes.POINTER(pdi_coef_params), i32, ctypes.POINTER(pdi_params), P, P, P]
+        L.encode_coefficients.restype = i32
+        L.encode_coefficients_batch.argtypes = [P, i32, ctypes.POINTER(pdi_frame), ctypes.POINTER(pdi_mask), VP,
+                                                ctypes.POINTER(pdi_coef_params), i32, ctypes.POINTER(pdi_params),
+                                                VP, VP, P]
+        L.encode_coefficients_batch.restype = i32
         L.pdi_default_cg_params.argtypes = [ctypes.POINTER(pdi_cg_params)]
         L.pdi_default_cg_params.restype = None
         L.inpaint_homogeneous.argtypes = [P, i32, i32, P, P, ctypes.POINTER(pdi_cg_params), P, P,
@@ -293,6 +301,67 @@ class Decoder:
         cs = np.ascontiguousarray(consts, np.float32)
         d["consts"] = torch.from_numpy(cs if cs.size else np.zeros(1, np.float32)).to(dev)
         return d
+
+    def alloc_coef(self, d):
+        """Add device buffers for an encode's outputs to a frame from upload():
+        int8 codes laid out like the values ("coef") and one FP32 constant
+        per block of every plane ("consts"), as upload_coef holds them."""
+        torch = self.torch
+        dev = torch.device("cuda", self.device)
+        fr = d["frame"]
+        d["coef"] = torch.zeros(max(int(d["values"].numel()), 1), dtype=torch.int8, device=dev)
+        d["consts"] = torch.zeros(max(int(self.plane_blocks(fr)), 1), dtype=torch.float32, device=dev)
+        return d
+
+    @staticmethod
+    def plane_blocks(fr) -> int:
+        """Blocks of every plane (the length of the constants array)."""
+        b = fr.block_size
+        dims = [(fr.width, fr.height)]
+        if fr.fmt != 0:
+            dims += [((fr.width + 1) // 2, (fr.height + 1) // 2)] * 2
+        return sum(((W + b - 1) // b) * ((H + b - 1) // b) for W, H in dims)
+
+    def encode_coef(self, d, qp: pdi_coef_params, params: Optional[pdi_params] = None, stream=None,
+                    check=True) -> int:
+        """encode_coefficients on a frame from upload() + alloc_coef(): codes
+        into d["coef"], constants into d["consts"]."""
+        fr = d["frame"]
+        s = stream.cuda_stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
+        f = pdi_frame(fr.width, fr.height, fr.fmt)
+        mk = pdi_mask(d["block_ptr"].data_ptr(), d["pos"].data_ptr(), d["n_mask_blocks"], int(bool(fr.chroma_shared)))
+        rc = lib().encode_coefficients(self.ctx, ctypes.byref(f), ctypes.byref(mk), d["values"].data_ptr(),
+                                       ctypes.byref(qp) if qp is not None else None, fr.block_size,
+                                       ctypes.byref(params) if params is not None else None,
+                                       d["coef"].data_ptr(), d["consts"].data_ptr(), s)
+        if check and rc != PDI_OK:
+            raise PdiError(rc, pdi_last_error(self.ctx))
+        return rc
+
+    def encode_coef_batch(self, ds, qp: pdi_coef_params, params: Optional[pdi_params] = None, stream=None,
+                          check=True) -> int:
+        """encode_coefficients_batch over frames from upload() + alloc_coef() (one geometry)."""
+        n = len(ds)
+        f0 = ds[0]["frame"]
+        fr = pdi_frame(f0.width, f0.height, f0.fmt)
+        masks = (pdi_mask * n)()
+        vs = (ctypes.c_void_p * n)()
+        qs = (ctypes.c_void_p * n)()
+        cs = (ctypes.c_void_p * n)()
+        for k, d in enumerate(ds):
+            f = d["frame"]
+            masks[k] = pdi_mask(d["block_ptr"].data_ptr(), d["pos"].data_ptr(), d["n_mask_blocks"],
+                                int(bool(f.chroma_shared)))
+            vs[k] = d["values"].data_ptr()
+            qs[k] = d["coef"].data_ptr()
+            cs[k] = d["consts"].data_ptr()
+        s = stream.cuda_stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
+        rc = lib().encode_coefficients_batch(self.ctx, n, ctypes.byref(fr), masks, vs,
+                                             ctypes.byref(qp) if qp is not None else None, f0.block_size,
+                                             ctypes.byref(params) if params is not None else None, qs, cs, s)
+        if check and rc != PDI_OK:
+            raise PdiError(rc, pdi_last_error(self.ctx))
+        return rc
 
     def decode_coef(self, d, qp: pdi_coef_params, params: Optional[pdi_params] = None, stream=None,
                     check=True) -> int:

@@ -10,10 +10,10 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Hand block m of frame fi to the general path: blocks whose bordered system
 // fits in LDS are listed from the front of the deferred list, larger ones from
-// the back.
+// the back (K = w*h is decoded by a copy, but solved when encoding).
 __device__ __forceinline__ void push_deferred(const FrameDev &f, int fi, int m, int K, int w, int h) {
   const int e = (fi << kDeferFrameShift) | m;
-  if (K > kLdsKMax && K < w * h) {
+  if (K > kLdsKMax && (K < w * h || f.enc)) {
     int idx = atomicAdd(&f.counters[1], 1);
     f.deferred[f.n_items * f.nframes - 1 - idx] = e;
   } else {
@@ -49,6 +49,14 @@ __device__ __forceinline__ void store_px(const PlaneOut &po, unsigned idx, float
 
 // Reconstruction of a stored code (dead-zone quantiser, Sec. 2.3 of the
 // paper): 0 stays 0, else sign(q) (|q| + rho) step.
+// Dead-zone quantisation of a coefficient (the inverse of coef_value's
+// intervals): |c| in [k step, (k + 1) step) gives code sign(c) k, k <= 127;
+// |c| < step gives 0.
+__device__ __forceinline__ int quant_code(float c, float step) {
+  const float k = fminf(floorf(fabsf(c) / step), 127.f);  // NaN -> 127: flagged by the caller
+  return c < 0.f ? -(int)k : (int)k;
+}
+
 __device__ __forceinline__ float coef_value(int q, float step, float rho) {
   const float m = ((float)abs(q) + rho) * step;
   return q == 0 ? 0.f : (q > 0 ? m : -m);

@@ -384,10 +384,10 @@ int ensure_workspace(pdi_ctx *c, Workspace *W, int n_items, int b, int nslots) {
     W->deferred_cap = n_items;
   }
   // Global-memory bordered systems: (K+1) rows of K+1+2 floats with
-  // K <= b*b - 1 (K = b*b is decoded by copying the values), one slot per
-  // workgroup that may need one.
+  // K <= b*b (decodes copy the values when K = b*b; encodes solve), one slot
+  // per workgroup that may need one.
   const int nmax = b * b;
-  const long long need = (long long)nmax * (nmax + 2);
+  const long long need = (long long)(nmax + 1) * (nmax + 3);
   if (nslots < pdi::kDeferredGrid) nslots = pdi::kDeferredGrid;
   if (need > W->slot_floats || nslots > W->slot_count) {
     const long long nf = need > W->slot_floats ? need : W->slot_floats;
@@ -475,14 +475,21 @@ int pdi_frame_info(const pdi_frame *frame, int block_size, int chroma_shared,
 static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask *masks,
                        const float *const *values, int block_size, const pdi_params *params,
                        float *const *outs, void *stream, const int8_t *const *coefs = nullptr,
-                       const float *const *consts = nullptr, const pdi_coef_params *qp = nullptr) {
+                       const float *const *consts = nullptr, const pdi_coef_params *qp = nullptr,
+                       int8_t *const *qouts = nullptr, float *const *aouts = nullptr) {
   if (!c) return PDI_EINVAL;
-  const bool coef = qp != nullptr;
+  const bool enc = qouts != nullptr;        // coefficient encode: values in, codes + constants out
+  const bool coef = qp != nullptr && !enc;  // stored-coefficient decode
   if (n < 1 || n > pdi::kMaxBatch) return set_err(c, PDI_EINVAL, "batch of %d frames (1..%d)", n, pdi::kMaxBatch);
-  if (!frame || !masks || !outs || (coef ? (!coefs || !consts) : !values))
-    return set_err(c, PDI_EINVAL, coef ? "null frame, mask, coefficients, constants or out"
-                                       : "null frame, mask, values or out");
-  if (coef) {
+  if (enc ? (!frame || !masks || !values || !aouts || !qp)
+          : (!frame || !masks || !outs || (coef ? (!coefs || !consts) : !values)))
+    return set_err(c, PDI_EINVAL, enc ? "null frame, mask, values, quantiser params, codes or constants"
+                                  : coef ? "null frame, mask, coefficients, constants or out"
+                                         : "null frame, mask, values or out");
+  if (enc) {
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(qp->step[k]) || !(qp->step[k] > 0.f)) return set_err(c, PDI_EINVAL, "bad quantiser step");
+  } else if (coef) {
     for (int k = 0; k < 3; ++k)
       if (!std::isfinite(qp->step[k]) || qp->step[k] < 0.f) return set_err(c, PDI_EINVAL, "bad quantiser step");
     if (!(qp->rho >= 0.f) || !(qp->rho < 1.f)) return set_err(c, PDI_EINVAL, "rho must be in [0, 1)");
@@ -510,9 +517,10 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
     if (sh != shared) return set_err(c, PDI_EINVAL, "frame %d: chroma sharing differs within the batch", k);
     if (nitems != mk.n_mask_blocks)
       return set_err(c, PDI_EINVAL, "n_mask_blocks %d, geometry needs %lld", mk.n_mask_blocks, nitems);
-    if (!mk.block_ptr || !mk.pos || !outs[k] || (coef ? (!coefs[k] || !consts[k]) : !values[k]))
-      return set_err(c, PDI_EINVAL, "frame %d: null block_ptr, pos, %s or out", k,
-                     coef ? "coefficients, constants" : "values");
+    if (enc ? (!mk.block_ptr || !mk.pos || !values[k] || !qouts[k] || !aouts[k])
+            : (!mk.block_ptr || !mk.pos || !outs[k] || (coef ? (!coefs[k] || !consts[k]) : !values[k])))
+      return set_err(c, PDI_EINVAL, "frame %d: null block_ptr, pos, %s", k,
+                     enc ? "values, codes or constants" : coef ? "coefficients, constants or out" : "values or out");
   }
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
@@ -537,7 +545,8 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
   F.eval = P.eval_dtype;
   F.out_i8 = P.out_int8;
   F.coef = coef ? 1 : 0;
-  if (coef) {
+  F.enc = enc ? 1 : 0;
+  if (coef || enc) {
     for (int k = 0; k < 3; ++k) F.qstep[k] = qp->step[k];
     F.qrho = qp->rho;
   }
@@ -574,11 +583,12 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
   for (int k = 0; k < ts->nshapes; ++k) F.s[k] = ts->s[k];
   // Shape-homogeneous runs of blocks for the batched paths: k_fast (b <= 16,
   // 16 blocks per workgroup) or k_wide (b = 32, 4 blocks per workgroup).
-  // Stored-coefficient decodes always take the batched paths (no solve).
+  // Stored-coefficient decodes always take the batched paths (no solve);
+  // encodes take k_fast for b <= 16 and the per-block path for b = 32.
   const bool fast = ((coef || P.path == PDI_PATH_AUTO) && block_size <= 16);
-  const bool wide = ((coef || P.path == PDI_PATH_AUTO) && block_size == 32);
+  const bool wide = ((coef || P.path == PDI_PATH_AUTO) && block_size == 32 && !enc);
   int ipw = fast ? pdi::kFastItemsPerWG : pdi::kWideItemsDefault;
-  if (!coef) {
+  if (!coef && !enc) {
     auto it = c->tune.find(TuneKey{frame->width, frame->height, frame->format, block_size, shared, P.op, P.s,
                                    P.eval_dtype, n});
     if (it != c->tune.end()) ipw = it->second;
@@ -640,14 +650,16 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
   if (rc) return rc;
   F.tab32_floats = ts->tab32_floats;
   F.nframes = n;
-  F.tail_in_wg = (n == 1 && !coef) ? 1 : 0;
+  F.tail_in_wg = (n == 1 && !coef && !enc) ? 1 : 0;
   for (int k = 0; k < n; ++k) {
     F.fp[k].block_ptr = masks[k].block_ptr;
     F.fp[k].pos = masks[k].pos;
     F.fp[k].values = coef ? nullptr : values[k];
-    F.fp[k].out = outs[k];
+    F.fp[k].out = enc ? nullptr : outs[k];
     F.fp[k].coef = coef ? coefs[k] : nullptr;
     F.fp[k].consts = coef ? consts[k] : nullptr;
+    F.fp[k].qout = enc ? qouts[k] : nullptr;
+    F.fp[k].aout = enc ? aouts[k] : nullptr;
   }
   F.tab32 = ts->tab32;
   F.tab64 = ts->tab64;
@@ -664,9 +676,9 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
     if (e == hipSuccess) e = pdi::launch_coef_general(F, s);
   } else if (fast) {
     // A single frame: one launch, the workgroups also decode their leftover
-    // blocks.  A batch: leftover blocks go to the deferred pass.
+    // blocks.  A batch or an encode: leftover blocks go to the deferred pass.
     e = pdi::launch_fast(F, s);
-    if (e == hipSuccess && n > 1) e = pdi::launch_general_deferred(F, s);
+    if (e == hipSuccess && (n > 1 || enc)) e = pdi::launch_general_deferred(F, s);
   } else if (wide) {
     e = pdi::launch_wide(F, s);  // leftover blocks go to the deferred list
     if (e == hipSuccess) e = pdi::launch_general_deferred(F, s);
@@ -703,6 +715,22 @@ int decode_coefficients_batch(pdi_ctx *c, int n, const pdi_frame *frame, const p
                               float *const *outs, void *stream) {
   if (c && !qp) return set_err(c, PDI_EINVAL, "null quantiser params");
   return decode_impl(c, n, frame, masks, nullptr, block_size, params, outs, stream, coefs, consts, qp);
+}
+
+int encode_coefficients(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, const float *values,
+                        const pdi_coef_params *qp, int block_size, const pdi_params *params, int8_t *coef,
+                        float *consts, void *stream) {
+  if (c && (!mask || !coef || !consts)) return set_err(c, PDI_EINVAL, "null mask, codes or constants");
+  return decode_impl(c, 1, frame, mask, &values, block_size, params, nullptr, stream, nullptr, nullptr, qp, &coef,
+                     &consts);
+}
+
+int encode_coefficients_batch(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask *masks,
+                              const float *const *values, const pdi_coef_params *qp, int block_size,
+                              const pdi_params *params, int8_t *const *coefs, float *const *consts, void *stream) {
+  if (c && (!coefs || !consts)) return set_err(c, PDI_EINVAL, "null codes or constants");
+  return decode_impl(c, n, frame, masks, values, block_size, params, nullptr, stream, nullptr, nullptr, qp, coefs,
+                     consts);
 }
 
 int pdi_sync(pdi_ctx *c, void *stream) {

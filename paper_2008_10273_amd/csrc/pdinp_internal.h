@@ -98,6 +98,8 @@ struct FramePtrs {
   float *out;  // FP32 planes, or int8 planes when out_i8
   const int8_t *coef;    // stored-coefficient decodes: codes, laid out like values
   const float *consts;   // and the constant of every block of every plane
+  int8_t *qout;          // coefficient encodes: codes out, laid out like values
+  float *aout;           // and the constant of every block of every plane
 };
 
 struct FrameDev {
@@ -113,7 +115,8 @@ struct FrameDev {
   int eval;          // PDI_EVAL_*
   int out_i8;        // 1: out holds int8 pixels, clamp(rint(u), -128, 127)
   int coef;          // 1: stored coefficients (codes + constants), no solve
-  float qstep[3];    // quantiser step per plane (coef)
+  int enc;           // 1: coefficient encode (solve, then quantise c and store a; no evaluation)
+  float qstep[3];    // quantiser step per plane (coef, enc)
   float qrho;        // reconstruction offset (coef)
   GroupDev g[kMaxGroups];
   ShapeDev s[kMaxShapes];

@@ -116,8 +116,18 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return s;
 }
 
+// Coefficient encodes: the constant of value column v of item `it`, and
+// codes 0 for its first n points (blocks that are not solved).
+__device__ __forceinline__ void enc_zero(const FrameDev &f, const FramePtrs &fp, const Item &it, int n) {
+  const GroupDev &G = f.g[it.g];
+  if (threadIdx.x < it.nv) fp.aout[G.cbase[threadIdx.x] + it.l] = 0.f;
+  for (int v = 0; v < it.nv; ++v)
+    for (int i = threadIdx.x; i < n; i += kGenThreads) fp.qout[it.vbase(v) + i] = 0;
+}
+
 // Decode one block with a whole workgroup.  M points at LDS (K <= kLdsKMax)
-// or at a global slot (ld = row stride).
+// or at a global slot (ld = row stride).  Coefficient encodes (f.enc) stop
+// after the solve and store the quantised c and a instead.
 template <int B>
 __device__ void general_block(const FrameDev &f, int fi, int m, GenScratch<B> &sh, float *M) {
   const int tid = threadIdx.x;
@@ -134,6 +144,10 @@ __device__ void general_block(const FrameDev &f, int fi, int m, GenScratch<B> &s
   __syncthreads();
   if (K < 0 || K > N) {
     if (tid == 0) atomicOr(f.status, kStatusMask);
+    if (f.enc) {
+      enc_zero(f, fp, it, 0);
+      return;
+    }
     for (int v = 0; v < it.nv; ++v)
       for (int p = tid; p < N; p += kGenThreads) store_px(po, (unsigned)(it.obase(v) + (p / w) * it.W + p % w), 0.f);
     return;
@@ -149,17 +163,29 @@ __device__ void general_block(const FrameDev &f, int fi, int m, GenScratch<B> &s
     if (bad) { atomicOr(f.status, bad); atomicOr(&sh.flag, 1); }
     __syncthreads();
     if (sh.flag) {
+      if (f.enc) {
+        enc_zero(f, fp, it, K);
+        return;
+      }
       for (int v = 0; v < it.nv; ++v)
         for (int p = tid; p < N; p += kGenThreads) store_px(po, (unsigned)(it.obase(v) + (p / w) * it.W + p % w), 0.f);
       return;
     }
   }
   if (K == 0) {
+    if (f.enc) {  // u = 0: a = 0
+      enc_zero(f, fp, it, 0);
+      return;
+    }
     for (int v = 0; v < it.nv; ++v)
       for (int p = tid; p < N; p += kGenThreads) store_px(po, (unsigned)(it.obase(v) + (p / w) * it.W + p % w), 0.f);
     return;
   }
-  if (K == N) {  // every pixel known: u = r (the system is singular here)
+  // Every pixel known: u = r.  G_K is then the whole G, singular on the
+  // constants; an encode solves with G + 1 1^T instead, which has the same
+  // solution (sum c = 0) and is positive definite.
+  const float shift = (f.enc && K == N) ? 1.f : 0.f;
+  if (K == N && !f.enc) {
     for (int v = 0; v < it.nv; ++v)
       for (int i = tid; i < K; i += kGenThreads) {
         int p = min((int)pos[it.base + i], N - 1);
@@ -182,7 +208,7 @@ __device__ void general_block(const FrameDev &f, int fi, int m, GenScratch<B> &s
   for (int i = wid; i < n; i += kGenThreads / 64)
     for (int k = lane; k < ld; k += 64) {
       float v;
-      if (k < K) v = (i < K) ? green_tab(sh.tab, w, h, sh.px[i], sh.py[i], sh.px[k], sh.py[k]) : 1.f;
+      if (k < K) v = (i < K) ? green_tab(sh.tab, w, h, sh.px[i], sh.py[i], sh.px[k], sh.py[k]) + shift : 1.f;
       else if (k == K) v = (i < K) ? 1.f : 0.f;
       else v = (i < K) ? values[it.vbase(k - n) + i] : 0.f;
       M[(long long)i * ld + k] = v;
@@ -244,7 +270,7 @@ __device__ void general_block(const FrameDev &f, int fi, int m, GenScratch<B> &s
           acc += green_tab(tab64, w, h, (int)sh.px[i], (int)sh.py[i], (int)sh.px[k], (int)sh.py[k]) *
                  (double)sh.c[v][k];
         double r = (double)values[it.vbase(v) + i];
-        sh.rho[i] = (float)(r - (double)(v ? a1 : a0) - acc);
+        sh.rho[i] = (float)(r - (double)(v ? a1 : a0) - acc - (double)shift * cs);
       }
       if (tid == 0) sh.rho[K] = (float)(-cs);
       // Replay the elimination on rho, then divide by the pivots.
@@ -261,6 +287,26 @@ __device__ void general_block(const FrameDev &f, int fi, int m, GenScratch<B> &s
       if (v) a1 += da; else a0 += da;
     }
     __syncthreads();
+  }
+
+  if (f.enc) {  // quantised c and a; no evaluation
+    const GroupDev &G = f.g[it.g];
+    bool bad = false;
+    for (int v = 0; v < it.nv; ++v) {
+      const float step = f.qstep[G.vplane[v]];
+      for (int i = tid; i < K; i += kGenThreads) {
+        const float c = sh.c[v][i];
+        bad |= !isfinite(c);
+        fp.qout[it.vbase(v) + i] = (int8_t)quant_code(c, step);
+      }
+    }
+    if (tid < it.nv) {
+      const float a = tid ? a1 : a0;
+      bad |= !isfinite(a);
+      fp.aout[G.cbase[tid] + it.l] = a;
+    }
+    if (bad) atomicOr(f.status, kStatusSolve);
+    return;
   }
 
   // Direct evaluation u(x) = sum_i c_i G(x, x_i) + a.
@@ -292,7 +338,7 @@ __global__ __launch_bounds__(kGenThreads) void k_plain_all(FrameDev f) {
   const int m = blockIdx.x, fi = blockIdx.y;
   if (m >= f.n_items) return;
   const Item it = load_item(f, f.fp[fi].block_ptr, m);
-  if (it.K > kLdsKMax && it.K < it.w * it.h) {
+  if (it.K > kLdsKMax && (it.K < it.w * it.h || f.enc)) {
     if (threadIdx.x == 0) push_deferred(f, fi, m, it.K, it.w, it.h);
     return;
   }
@@ -828,9 +874,34 @@ __device__ __forceinline__ void fast_eval_any(const FrameDev &f, const float *D,
   }
 }
 
-template <bool COEF>
+// Coefficient encodes: the quantised c and the a of the wave's solved blocks
+// (each lane stores the rows it solved).
+template <int R>
+__device__ __forceinline__ void fast_encode_store(const FrameDev &f, const FastItem *items, int slot, bool done,
+                                                  int t, int gi, const GroupDev &G, const FastStage &st) {
+  constexpr int NS = (R + 15) / 16;
+  if (!done) return;
+  const FramePtrs fp = f.fp[blockIdx.y];
+  const int K = items[slot].K, nv = items[slot].nv;
+  const float s0 = f.qstep[G.vplane[0]], s1 = f.qstep[G.vplane[nv > 1 ? 1 : 0]];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = t + 16 * s;
+    if (i < K) {
+      const FastPoint P = st.p[gi][i];
+      fp.qout[items[slot].vb0 + i] = (int8_t)quant_code(P.c0, s0);
+      if (nv > 1) fp.qout[items[slot].vb1 + i] = (int8_t)quant_code(P.c1, s1);
+    }
+  }
+  if (t < nv) fp.aout[G.cbase[t] + (items[slot].m - G.first)] = st.a[gi][t];
+}
+
+// MODE 0: residual decode (solve, evaluate); 1: stored coefficients
+// (evaluate only); 2: coefficient encode (solve, quantise, no evaluation).
+template <int MODE>
 __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(3, 8)))
 void k_fast(FrameDev f) {
+  constexpr bool COEF = MODE == 1, ENC = MODE == 2;
   extern __shared__ __attribute__((aligned(16))) float tabs[];  // J, Dw, Dh, lam of the workgroup's shape
   __shared__ FastItem items[kFastItems];
   __shared__ int order[kFastItems];
@@ -867,8 +938,8 @@ void k_fast(FrameDev f) {
     const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + S.fast + S.jt_floats);
     f4 *dst = reinterpret_cast<f4 *>(tabs);
     for (int i = tid; i < n4; i += kFastThreads) dst[i] = src[i];
-  } else {
-    const int n4 = (S.jt_floats + 3 * kDct16Floats) >> 2;
+  } else {  // J and the evaluation's matrices (encodes: J only)
+    const int n4 = (S.jt_floats + (ENC ? 0 : 3 * kDct16Floats)) >> 2;
     const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + S.fast);
     f4 *dst = reinterpret_cast<f4 *>(tabs);
     f4 buf[kTabVec];
@@ -958,7 +1029,11 @@ void k_fast(FrameDev f) {
 #pragma unroll
     for (int g = 0; g < kWaveItems; ++g) okmask |= ((em >> (16 * g)) & 1ull) ? (1u << g) : 0u;
     const long long ob0 = items[slot].ob0, ob1 = items[slot].ob1;
-    if (okmask) {
+    if constexpr (ENC) {
+      if (Kw <= 15) fast_encode_store<16>(f, items, slot, eval, t, gi, G, st);
+      else if (Kw <= 23) fast_encode_store<24>(f, items, slot, eval, t, gi, G, st);
+      else fast_encode_store<32>(f, items, slot, eval, t, gi, G, st);
+    } else if (okmask) {
       const float *D = tabs + (COEF ? 0 : S.jt_floats);
       if (Kw <= 15) fast_eval_any<16>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
       else if (Kw <= 23) fast_eval_any<24>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
@@ -970,7 +1045,7 @@ void k_fast(FrameDev f) {
   // or whose pivots asked for FP64 refinement: the whole workgroup runs the
   // general algorithm on them, one at a time, with the bordered system in
   // this workgroup's global slot.
-  if constexpr (!COEF) {
+  if constexpr (MODE == 0) {
     if (!f.tail_in_wg) return;
     __syncthreads();
     float *slot_mem = f.slots + (long long)blockIdx.x * f.slot_floats;
@@ -1080,8 +1155,9 @@ __global__ __launch_bounds__(kGenThreads) void k_coef_general(FrameDev f) {
 hipError_t launch_fast(const FrameDev &f, hipStream_t stream) {
   if (f.fast_wgs == 0) return hipSuccess;
   const size_t lds = sizeof(float) * (size_t)f.fast_lds;
-  if (f.coef) hipLaunchKernelGGL(k_fast<true>, dim3(f.fast_wgs, f.nframes), dim3(kFastThreads), lds, stream, f);
-  else hipLaunchKernelGGL(k_fast<false>, dim3(f.fast_wgs, f.nframes), dim3(kFastThreads), lds, stream, f);
+  if (f.coef) hipLaunchKernelGGL(k_fast<1>, dim3(f.fast_wgs, f.nframes), dim3(kFastThreads), lds, stream, f);
+  else if (f.enc) hipLaunchKernelGGL(k_fast<2>, dim3(f.fast_wgs, f.nframes), dim3(kFastThreads), lds, stream, f);
+  else hipLaunchKernelGGL(k_fast<0>, dim3(f.fast_wgs, f.nframes), dim3(kFastThreads), lds, stream, f);
   return hipGetLastError();
 }
 

@@ -260,6 +260,12 @@ CONFIGS: Dict[int, dict] = {
 COEF_CONFIG = dict(name="fhd420_b8_coef_d1-10", width=1920, height=1080, fmt=YUV420,
                    block_size=8, density=(0.01, 0.10), steps=(0.25, 0.25, 0.25), rho=0.5)
 
+# Coefficient encode: the masks and residual values of the stored-coefficient
+# workload's frames, solved per 8x8 block and quantised with a step that
+# maps the coefficients (|c| <= ~55 on these frames) into [-127, 127].
+ENCODE_CONFIG = dict(name="fhd420_b8_encode_d1-10", width=1920, height=1080, fmt=YUV420,
+                     block_size=8, density=(0.01, 0.10), steps=(0.5, 0.5, 0.5))
+
 # Serving mix: (width, height, count) per resolution class, 4:2:0, b16.
 SERVING_MIX = [(854, 480, 6), (1280, 720, 6), (1920, 1080, 4)]
 

@@ -1,0 +1,219 @@
+"""Parity of the coefficient encoder (encode_coefficients, through the C ABI)
+with the FP64 oracle's encoder, and the round trip through the GPU decoder
+of stored coefficients.
+
+Bars.  Constants a: within FP32_TOL (an FP32 solve of the bordered system:
+relative error ~ cond(G_K) 2^-24 < 10^3 * 6e-8, times values of at most 64
+-> ~4e-3, rounded up to 10^-2).  Codes are integers decided by floating
+point: c differs from the oracle's FP64 c by at most C_TOL (the same bound
+on coefficients of at most ~50), so a code may differ by one only where the
+oracle's |c| / step lies within C_TOL / step of an interval edge; everywhere
+else the codes are identical, and the codes that may differ are checked to
+be few.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_10273_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-2
+C_TOL = 1e-2
+STEPS = (0.4, 0.3, 0.5)
+
+
+@pytest.fixture(scope="module")
+def dec():
+    from paper_2008_10273_amd import binding
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = binding.Decoder(0)
+    yield d
+    d.close()
+
+
+def _dense_frame(W, H, fmt, b, counts_fn, seed, shared=True):
+    """Frame whose block k of every mask plane gets counts_fn(k, w*h) points."""
+    rng = np.random.default_rng(seed)
+    dims = synth.plane_dims(W, H, fmt)
+    nm = 1 if fmt == synth.GRAY else (2 if shared else 3)
+    ms, fs = [], []
+    for p in range(nm):
+        pw, ph = dims[p]
+        m = np.zeros((ph, pw), bool)
+        for k, (x0, y0, w, h) in enumerate(synth.block_grid(pw, ph, b)):
+            K = counts_fn(k, w * h)
+            idx = rng.choice(w * h, K, replace=False)
+            m[y0 + idx // w, x0 + idx % w] = True
+        ms.append(m)
+    for pw, ph in dims:
+        fs.append(rng.uniform(-64, 64, (ph, pw)))
+    return synth.pack_dense(W, H, fmt, b, ms, fs)
+
+
+CASES = {
+    "b8_420": lambda: synth.random_frame(100, 67, synth.YUV420, 8, (0.02, 0.3), seed=61),
+    "b16_420": lambda: synth.random_frame(150, 90, synth.YUV420, 16, (0.01, 0.12), seed=62),
+    "b16_separate": lambda: synth.random_frame(90, 52, synth.YUV420, 16, (0.01, 0.12), seed=63,
+                                               chroma_shared=False),
+    "b32_420": lambda: synth.random_frame(150, 90, synth.YUV420, 32, (0.02, 0.1), seed=64),
+    "b8_gray_ragged": lambda: synth.random_frame(37, 21, synth.GRAY, 8, (0.05, 0.5), seed=65),
+    # every K class: 0, 1, the staged limits, beyond them, the LDS limit, w*h
+    "b16_counts": lambda: _dense_frame(16 * 5 + 9, 16 * 3 + 5, synth.YUV420, 16,
+                                       lambda k, n: min(n, [0, 1, 15, 16, 31, 32, 60, n, n - 1, 200][k % 10]), 66),
+    "b8_counts": lambda: _dense_frame(8 * 6 + 3, 8 * 3 + 5, synth.YUV420, 8,
+                                      lambda k, n: min(n, [0, 1, 6, 31, 32, n, n - 1][k % 7]), 67),
+    "b32_counts": lambda: _dense_frame(32 * 3 + 11, 32 * 2 + 7, synth.GRAY, 32,
+                                       lambda k, n: min(n, [0, 1, 63, 96, 97, 300, n, n - 1][k % 8]), 68),
+}
+
+
+def _encode(dec, fr, steps=STEPS, **kw):
+    from paper_2008_10273_amd import binding
+    d = dec.alloc_coef(dec.upload(fr))
+    dec.encode_coef(d, binding.coef_params(steps, 0.5), binding.default_params(**kw))
+    rc = dec.sync()
+    assert rc == 0, binding.pdi_last_error(dec.ctx)
+    n = fr.values.size
+    return d, d["coef"].cpu().numpy()[:n].astype(np.int64), d["consts"].cpu().numpy().astype(np.float64)
+
+
+def _plane_steps(fr, steps):
+    """Step of every value (the plane each value run belongs to)."""
+    dims = synth.plane_dims(fr.width, fr.height, fr.fmt)
+    st = np.empty(fr.values.size)
+    bp = fr.block_ptr
+    if fr.fmt == synth.GRAY:
+        st[:] = steps[0]
+        return st
+    ny = sum(1 for _ in synth.block_grid(*dims[0], fr.block_size))
+    y_end = bp[ny]
+    st[:y_end] = steps[0]
+    if fr.chroma_shared:
+        nnz = bp[-1]
+        st[y_end:nnz] = steps[1]
+        st[nnz:] = steps[2]
+    else:
+        nc = sum(1 for _ in synth.block_grid(*dims[1], fr.block_size))
+        st[y_end:bp[ny + nc]] = steps[1]
+        st[bp[ny + nc]:] = steps[2]
+    return st
+
+
+def _check_codes(fr, got, ref, cex, steps):
+    st = _plane_steps(fr, steps)
+    x = np.abs(cex) / st
+    near = np.abs(x - np.rint(x)) * st <= C_TOL   # within C_TOL of an interval edge
+    diff = got != ref
+    print(f"  codes: {diff.sum()} of {got.size} differ, {near.sum()} near an edge", flush=True)
+    assert np.all(np.abs(got - ref) <= 1)
+    assert not np.any(diff & ~near)
+    assert diff.sum() <= max(2, 0.01 * got.size)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_encode_parity(dec, case):
+    fr = CASES[case]()
+    print(f"case encode {case} {fr.width}x{fr.height} b={fr.block_size}", flush=True)
+    _, q, a = _encode(dec, fr)
+    qo, cex, ao = oracle.encode_coef(fr, STEPS)
+    print(f"  max|a err|={np.abs(a - ao).max():.3e}", flush=True)
+    assert np.abs(a - ao).max() <= FP32_TOL
+    _check_codes(fr, q, qo.astype(np.int64), cex, STEPS)
+
+
+@pytest.mark.parametrize("case", ["b16_420", "b8_counts"])
+def test_encode_forced_refinement(dec, case):
+    """refine = 2 sends every block through the general path's FP64
+    refinement (the wave-level path defers them all)."""
+    fr = CASES[case]()
+    print(f"case encode {case} refine=2", flush=True)
+    _, q, a = _encode(dec, fr, refine=2)
+    qo, cex, ao = oracle.encode_coef(fr, STEPS)
+    assert np.abs(a - ao).max() <= 1e-4
+    _check_codes(fr, q, qo.astype(np.int64), cex, STEPS)
+
+
+@pytest.mark.parametrize("case", ["b8_420", "b16_counts", "b32_420"])
+def test_encode_decode_round_trip(dec, case):
+    """GPU encode, then GPU decode of the stored coefficients, against the
+    oracle's inpainting of the same mask and values: within the quantisation
+    bound step * K * max|G| (rho = 0.5) plus the FP32 bound; with steps that
+    just keep every coefficient inside [-127, 127]."""
+    from paper_2008_10273_amd import binding
+    fr = CASES[case]()
+    cmax = np.abs(oracle.encode_coef(fr, (1.0, 1.0, 1.0))[1]).max()
+    step = cmax / 127.0
+    steps = (step, step, step)
+    print(f"case encode round trip {case} step={step:.4f}", flush=True)
+    d, _, _ = _encode(dec, fr, steps)
+    dec.decode_coef(d, binding.coef_params(steps, 0.5))
+    assert dec.sync() == 0
+    got = d["out"].cpu().numpy().astype(np.float64)
+    ref = oracle.decode_flat(fr)
+    shapes = {(w, h) for pw, ph in synth.plane_dims(fr.width, fr.height, fr.fmt)
+              for (_, _, w, h) in synth.block_grid(pw, ph, fr.block_size)}
+    gmax = max(np.abs(oracle.green_matrix(w, h)).max() for w, h in shapes)
+    Kmax = int(np.diff(fr.block_ptr).max())
+    bound = step * Kmax * gmax + FP32_TOL
+    err = np.abs(got - ref).max()
+    print(f"  max|err|={err:.3e} bound={bound:.3e}", flush=True)
+    assert err <= bound
+
+
+def test_encode_full_frame(dec):
+    """The paper's codec configuration at full size: a 1920x1080 4:2:0 frame
+    in 8x8 blocks (the stored-coefficient workload's masks), every block."""
+    c = synth.COEF_CONFIG
+    fr = synth.coef_frame(0)[0]
+    print(f"case encode full frame {fr.width}x{fr.height} b={fr.block_size}", flush=True)
+    steps = tuple(c["steps"])
+    _, q, a = _encode(dec, fr, steps)
+    qo, cex, ao = oracle.encode_coef(fr, steps)
+    assert np.abs(a - ao).max() <= FP32_TOL
+    _check_codes(fr, q, qo.astype(np.int64), cex, steps)
+
+
+def test_encode_batch_equals_single(dec):
+    from paper_2008_10273_amd import binding
+    frs = [synth.random_frame(100, 67, synth.YUV420, 8, (0.02, 0.3), seed=70 + k) for k in range(3)]
+    print("case encode batch of 3", flush=True)
+    singles = [_encode(dec, fr)[1:] for fr in frs]
+    ds = [dec.alloc_coef(dec.upload(fr)) for fr in frs]
+    dec.encode_coef_batch(ds, binding.coef_params(STEPS, 0.5))
+    assert dec.sync() == 0
+    for d, fr, (q, a) in zip(ds, frs, singles):
+        assert np.array_equal(d["coef"].cpu().numpy()[:fr.values.size].astype(np.int64), q)
+        assert np.array_equal(d["consts"].cpu().numpy().astype(np.float64), a)
+
+
+def test_encode_errors(dec):
+    from paper_2008_10273_amd import binding
+    fr = CASES["b8_420"]()
+    d = dec.alloc_coef(dec.upload(fr))
+    for steps in ((0.0, 0.3, 0.5), (0.4, -1.0, 0.5), (0.4, 0.3, float("nan"))):
+        rc = dec.encode_coef(d, binding.coef_params(steps, 0.5), check=False)
+        assert rc == binding.PDI_EINVAL
+    rc = dec.encode_coef(d, None, check=False)
+    assert rc == binding.PDI_EINVAL
+    # a position outside its block: PDI_EMASK at sync (that block's output is unspecified)
+    bad = synth.random_frame(24, 16, synth.GRAY, 8, (0.2, 0.4), seed=77)
+    pos = np.array(bad.pos, copy=True)
+    k0 = int(bad.block_ptr[1] - bad.block_ptr[0])
+    assert k0 >= 2
+    pos[k0 - 1] = 64
+    bad = dataclasses.replace(bad, pos=pos)
+    d = dec.alloc_coef(dec.upload(bad))
+    d["coef"].fill_(5)
+    d["consts"].fill_(3.0)
+    dec.encode_coef(d, binding.coef_params(STEPS, 0.5), binding.default_params(validate=1))
+    assert dec.sync() == binding.PDI_EMASK
+    assert dec.sync() == 0  # the status word was cleared; the context stays usable
+    _, q, a = _encode(dec, CASES["b8_gray_ragged"]())
+    qo, _, ao = oracle.encode_coef(CASES["b8_gray_ragged"](), STEPS)
+    assert np.abs(a - ao).max() <= FP32_TOL
