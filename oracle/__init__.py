@@ -73,6 +73,8 @@ def _lib():
             L.orc_quant.restype = i
             L.orc_encode_coef.argtypes = [i, i, i, i, P, P, P, i, P, i, d, P, P, P, i]
             L.orc_encode_coef.restype = i
+            L.orc_select_mask.argtypes = [i, i, i, i, P, i, P, i, P, i]
+            L.orc_select_mask.restype = i
             _lib_handle = L
     return _lib_handle
 
@@ -252,6 +254,37 @@ def encode_coef(frame, steps, op: int = 0, s: float = 1.0, nthreads: int = 0):
         raise ValueError("orc_encode_coef failed")
     n = frame.values.size
     return code[:n], cex[:n], consts
+
+
+def select_mask(width: int, height: int, fmt: int, b: int, planes, chroma_shared: bool, thr,
+                max_rounds: int = 64, nthreads: int = 0) -> List[np.ndarray]:
+    """Per-block mask selection by rectangular subdivision (the encoder's
+    choice of each block's points, Sec. 2.3): see orc_select_block.
+    ``planes``: dense residual planes (Y, Cb, Cr for 4:2:0) as (H, W)
+    arrays; ``thr``: (luma, chroma) thresholds on a rectangle's mean squared
+    error.  Returns the masks of the mask planes (Y, then one shared chroma
+    mask or Cb and Cr) as (H, W) bool arrays."""
+    dims = plane_dims(width, height, fmt)
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.float64).ravel() for p in planes]))
+    if fmt == 0:
+        mdims = dims[:1]
+    elif chroma_shared:
+        mdims = dims[:2]
+    else:
+        mdims = dims
+    out = np.zeros(sum(W * H for W, H in mdims), np.uint8)
+    t = np.ascontiguousarray(np.asarray(thr, dtype=np.float64).reshape(-1)[:2])
+    if t.size == 1:
+        t = np.array([t[0], t[0]])
+    rc = _lib().orc_select_mask(width, height, fmt, b, _ptr(flat), int(bool(chroma_shared)), _ptr(t),
+                                int(max_rounds), _ptr(out), int(nthreads))
+    if rc != 0:
+        raise ValueError("orc_select_mask failed")
+    res, o = [], 0
+    for W, H in mdims:
+        res.append(out[o:o + W * H].reshape(H, W).astype(bool))
+        o += W * H
+    return res
 
 
 def homogeneous_inpaint(mask, f) -> np.ndarray:

@@ -698,3 +698,131 @@ int orc_encode_coef(int width, int height, int fmt, int b, const int32_t *block_
     free(pblock);
     return err ? -1 : 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* (5) Mask selection per block by rectangular subdivision (the       */
+/*     encoder picks each 8x8 block's mask points this way, Sec. 2.3; */
+/*     the scheme is cited there, this is the reading taken).         */
+/* ------------------------------------------------------------------ */
+
+/* One block (w x h pixels, nv value planes r[v][w*h] sharing the mask):
+ * rectangles are inclusive pixel ranges [x0, x1] x [y0, y1] whose four
+ * corners are mask points; neighbours share their common edge.  Starting
+ * from the whole block, each round inpaints the block from the corners of
+ * all current rectangles (Green's route, orc_block_green_tab), takes every
+ * rectangle's mean squared error over its pixels (averaged over the value
+ * planes) and halves every rectangle whose error exceeds thr and whose
+ * longer side spans at least 2 pixel gaps: along x when x1 - x0 >= y1 - y0,
+ * else along y, at mid = (lo + hi) / 2 (both halves keep the middle line).
+ * Rounds repeat until no rectangle is split (at most max_rounds).
+ * mask[w*h] receives 1 at the selected pixels.  Returns 0 / -1. */
+int orc_select_block(int w, int h, const double *Htab, int nv, const double *r, double thr,
+                     int max_rounds, uint8_t *mask)
+{
+    int N = w * h, nl = 1, round, i, j, v, rc = 0;
+    int rx0[256], rx1[256], ry0[256], ry1[256];
+    uint16_t pos[256];
+    double *rv = (double *)malloc(sizeof(double) * (size_t)N * 2);
+    double *c = (double *)malloc(sizeof(double) * (size_t)N * 2);
+    double *u = (double *)malloc(sizeof(double) * (size_t)N * 2);
+    double a[2];
+    if (N > 256 || nv < 1 || nv > 2) { free(rv); free(c); free(u); return -1; }
+    rx0[0] = 0; rx1[0] = w - 1; ry0[0] = 0; ry1[0] = h - 1;
+    for (round = 0; ; round++) {
+        int K = 0, nnew = 0;
+        memset(mask, 0, (size_t)N);
+        for (j = 0; j < nl; j++) {
+            mask[ry0[j] * w + rx0[j]] = 1; mask[ry0[j] * w + rx1[j]] = 1;
+            mask[ry1[j] * w + rx0[j]] = 1; mask[ry1[j] * w + rx1[j]] = 1;
+        }
+        if (round >= max_rounds) break;
+        for (i = 0; i < N; i++)
+            if (mask[i]) pos[K++] = (uint16_t)i;
+        if (K == N) break;  /* every pixel known: no error left */
+        for (v = 0; v < nv; v++)
+            for (i = 0; i < K; i++) rv[v * K + i] = r[v * N + pos[i]];
+        if (orc_block_green_tab(w, h, Htab, K, pos, nv, rv, c, a, u) != 0) { rc = -1; break; }
+        {
+            int n0 = nl;
+            for (j = 0; j < n0; j++) {
+                double e = 0.0;
+                int x, y, cnt = (rx1[j] - rx0[j] + 1) * (ry1[j] - ry0[j] + 1);
+                int gx = rx1[j] - rx0[j], gy = ry1[j] - ry0[j];
+                for (v = 0; v < nv; v++)
+                    for (y = ry0[j]; y <= ry1[j]; y++)
+                        for (x = rx0[j]; x <= rx1[j]; x++) {
+                            double d = u[v * N + y * w + x] - r[v * N + y * w + x];
+                            e += d * d;
+                        }
+                e /= (double)cnt * nv;
+                if (!(e > thr)) continue;
+                if (gx >= gy && gx >= 2) {
+                    int mid = (rx0[j] + rx1[j]) / 2;
+                    rx0[nl] = mid; rx1[nl] = rx1[j]; ry0[nl] = ry0[j]; ry1[nl] = ry1[j];
+                    rx1[j] = mid;
+                    nl++; nnew++;
+                } else if (gy > gx && gy >= 2) {
+                    int mid = (ry0[j] + ry1[j]) / 2;
+                    rx0[nl] = rx0[j]; rx1[nl] = rx1[j]; ry0[nl] = mid; ry1[nl] = ry1[j];
+                    ry1[j] = mid;
+                    nl++; nnew++;
+                }
+            }
+        }
+        if (nnew == 0) break;
+    }
+    free(rv); free(c); free(u);
+    return rc;
+}
+
+/* Select the mask of every block of a frame.  fmt, width, height and b as
+ * for orc_decode; planes[] holds the dense residual planes (Y, then Cb, Cr
+ * for 4:2:0), row-major, concatenated.  chroma_shared: one chroma mask
+ * chosen on both chroma planes (their errors averaged), else one per plane.
+ * thr[0] is the luma threshold, thr[1] the chroma one.  mask[] receives the
+ * dense masks of the mask planes (Y, then the chroma mask(s)), row-major,
+ * concatenated.  Returns 0 / -1. */
+int orc_select_mask(int width, int height, int fmt, int b, const double *planes, int chroma_shared,
+                    const double *thr, int max_rounds, uint8_t *mask, int nthreads)
+{
+    int PW[3], PH[3], np_, g, ngroups, mp[3], vp[3][2], nv[3], err = 0;
+    long long poff[3], moff[3];
+    if (fmt == 0) { np_ = 1; PW[0] = width; PH[0] = height; }
+    else { np_ = 3; PW[0] = width; PH[0] = height;
+           PW[1] = PW[2] = (width + 1) / 2; PH[1] = PH[2] = (height + 1) / 2; }
+    poff[0] = 0;
+    for (g = 1; g < np_; g++) poff[g] = poff[g - 1] + (long long)PW[g - 1] * PH[g - 1];
+    if (fmt == 0) { ngroups = 1; mp[0] = 0; vp[0][0] = 0; nv[0] = 1; }
+    else if (chroma_shared) { ngroups = 2; mp[0] = 0; vp[0][0] = 0; nv[0] = 1;
+                              mp[1] = 1; vp[1][0] = 1; vp[1][1] = 2; nv[1] = 2; }
+    else { ngroups = 3; for (g = 0; g < 3; g++) { mp[g] = g; vp[g][0] = g; nv[g] = 1; } }
+    moff[0] = 0;
+    for (g = 1; g < ngroups; g++) moff[g] = moff[g - 1] + (long long)PW[mp[g - 1]] * PH[mp[g - 1]];
+    for (g = 0; g < ngroups; g++) {
+        int W = PW[mp[g]], H = PH[mp[g]], nbx = (W + b - 1) / b, nby = (H + b - 1) / b, blk;
+        double t = thr[g == 0 ? 0 : 1];
+#ifdef _OPENMP
+        if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16) reduction(|:err)
+#endif
+        for (blk = 0; blk < nbx * nby; blk++) {
+            int x0 = (blk % nbx) * b, y0 = (blk / nbx) * b;
+            int w = W - x0 < b ? W - x0 : b, h = H - y0 < b ? H - y0 : b;
+            int N = w * h, v, x, y;
+            double lam[256], Htab[17 * 17], r[512];
+            uint8_t m[256];
+            if (N > 256) { err |= 1; continue; }
+            orc_eigenvalues(w, h, 0, 1.0, lam);
+            orc_green_table(w, h, lam, Htab);
+            for (v = 0; v < nv[g]; v++) {
+                const double *P = planes + poff[vp[g][v]];
+                for (y = 0; y < h; y++)
+                    for (x = 0; x < w; x++) r[v * N + y * w + x] = P[(long long)(y0 + y) * W + x0 + x];
+            }
+            if (orc_select_block(w, h, Htab, nv[g], r, t, max_rounds, m) != 0) { err |= 1; continue; }
+            for (y = 0; y < h; y++)
+                for (x = 0; x < w; x++) mask[moff[g] + (long long)(y0 + y) * W + x0 + x] = m[y * w + x];
+        }
+    }
+    return err ? -1 : 0;
+}

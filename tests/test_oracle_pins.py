@@ -550,6 +550,121 @@ def test_encode_decode_round_trip():
     assert err <= 0.5  # the fine step meets the decoder's acceptance bar
 
 
+# ----------------------------------------- mask selection (subdivision)
+
+@pytest.mark.parametrize("name", ["subdivide_5x1.txt", "subdivide_3x3.txt"])
+def test_golden_subdivision(name):
+    """Hand-derived subdivisions: catches a split at the wrong threshold side
+    (strictly greater), a wrong mid-point, the wrong axis on a tie, or an
+    error averaged over the wrong pixels."""
+    rows = _read_golden(name)
+    w, h = map(int, rows[0])
+    r = np.array(rows[1:1 + h])
+    for row in rows[1 + h:]:
+        T, want = row[0], np.array(row[1:], dtype=bool).reshape(h, w)
+        got = oracle.select_mask(w, h, synth.GRAY, 8, [r], True, (T, T))[0]
+        assert np.array_equal(got, want), (name, T, got.astype(int))
+
+
+def _corner_mask(W, H, b):
+    m = np.zeros((H, W), bool)
+    for (x0, y0, w, h) in synth.block_grid(W, H, b):
+        for x in (x0, x0 + w - 1):
+            for y in (y0, y0 + h - 1):
+                m[y, x] = True
+    return m
+
+
+@pytest.mark.parametrize("b", [8, 16])
+def test_subdivision_limits(b):
+    """No split (threshold above every error) leaves exactly the corners of
+    every block, ragged edge blocks included; splitting whenever possible
+    (negative threshold) reaches every pixel; constant planes never split."""
+    W, H = 2 * b + 5, b + 3
+    rng = _rng(31)
+    planes = [rng.uniform(-64, 64, (h, w)) for (w, h) in synth.plane_dims(W, H, synth.YUV420)]
+    dims = synth.plane_dims(W, H, synth.YUV420)
+    for shared in (True, False):
+        ms = oracle.select_mask(W, H, synth.YUV420, b, planes, shared, (1e300, 1e300))
+        for m, (pw, ph) in zip(ms, dims):
+            assert np.array_equal(m, _corner_mask(pw, ph, b))
+        ms = oracle.select_mask(W, H, synth.YUV420, b, planes, shared, (-1.0, -1.0))
+        assert all(m.all() for m in ms)
+    const = [np.full((h, w), 7.5) for (w, h) in dims]
+    ms = oracle.select_mask(W, H, synth.YUV420, b, const, True, (1e-9, 1e-9))
+    for m, (pw, ph) in zip(ms, dims):
+        assert np.array_equal(m, _corner_mask(pw, ph, b))
+
+
+def _subdivide_brute(r, T):
+    """The subdivision rounds on one block with Eq. (1) solved by the dense
+    Kronecker route (no Green's table): an independent inpainting and
+    independent bookkeeping (rectangles as sets of their pixels)."""
+    h, w = r.shape
+    rects = [(0, w - 1, 0, h - 1)]
+    while True:
+        known = set()
+        for x0, x1, y0, y1 in rects:
+            known |= {(x0, y0), (x1, y0), (x0, y1), (x1, y1)}
+        if len(known) == w * h:
+            break
+        pos = np.array(sorted(y * w + x for x, y in known))
+        u = brute.solve_eq1(w, h, pos, r.ravel()[pos], brute.operator(w, h, 1)).reshape(h, w)
+        new = []
+        for x0, x1, y0, y1 in rects:
+            e = ((u[y0:y1 + 1, x0:x1 + 1] - r[y0:y1 + 1, x0:x1 + 1]) ** 2).mean()
+            gx, gy = x1 - x0, y1 - y0
+            if e > T and max(gx, gy) >= 2:
+                if gx >= gy:
+                    m = (x0 + x1) // 2
+                    new += [(x0, m, y0, y1), (m, x1, y0, y1)]
+                else:
+                    m = (y0 + y1) // 2
+                    new += [(x0, x1, y0, m), (x0, x1, m, y1)]
+            else:
+                new.append((x0, x1, y0, y1))
+        if len(new) == len(rects):
+            break
+        rects = new
+    m = np.zeros((h, w), bool)
+    for x0, x1, y0, y1 in rects:
+        for x, y in ((x0, y0), (x1, y0), (x0, y1), (x1, y1)):
+            m[y, x] = True
+    return m
+
+
+@pytest.mark.parametrize("w,h", [(8, 8), (5, 7), (8, 3), (2, 6)])
+def test_subdivision_matches_brute_force(w, h):
+    """Random blocks and thresholds: the oracle's masks equal the dense-solve
+    re-run of the rounds (thresholds well away from every error, so FP64
+    rounding cannot flip a decision)."""
+    rng = _rng(32 + w * h)
+    for trial in range(6):
+        r = rng.uniform(-64, 64, (h, w)) if trial % 2 else \
+            np.cumsum(rng.normal(0, 6, (h, w)), axis=1)
+        for T in (2.0, 20.0, 150.0):
+            got = oracle.select_mask(w, h, synth.GRAY, 8, [r], True, (T, T))[0]
+            assert np.array_equal(got, _subdivide_brute(r, T)), (w, h, trial, T)
+
+
+def test_subdivision_shared_chroma_averages_errors():
+    """One chroma mask for both chroma planes (Sec. 2.3) is chosen on the
+    mean of their errors: equal planes give the single-plane mask; a zero Cr
+    plane halves the error, as doubling the threshold on Cb alone does."""
+    W, H = 40, 24
+    rng = _rng(33)
+    dims = synth.plane_dims(W, H, synth.YUV420)
+    y = rng.uniform(-64, 64, dims[0][::-1])
+    cb = np.cumsum(rng.normal(0, 5, dims[1][::-1]), axis=1)
+    T = 6.0
+    sep = oracle.select_mask(W, H, synth.YUV420, 8, [y, cb, cb], False, (T, T))
+    sh = oracle.select_mask(W, H, synth.YUV420, 8, [y, cb, cb], True, (T, T))
+    assert np.array_equal(sh[1], sep[1]) and np.array_equal(sh[0], sep[0])
+    sh0 = oracle.select_mask(W, H, synth.YUV420, 8, [y, cb, np.zeros_like(cb)], True, (T, T))
+    sep2 = oracle.select_mask(W, H, synth.YUV420, 8, [y, cb, cb], False, (T, 2 * T))
+    assert np.array_equal(sh0[1], sep2[1])
+
+
 # ------------------------------------- global homogeneous diffusion inpainting
 
 @pytest.mark.parametrize("W,H,d", [(7, 5, 0.3), (12, 9, 0.1), (16, 11, 0.05), (23, 14, 0.2)])
