@@ -24,6 +24,9 @@ Workloads (synthetic, seeded; the recipe is in paper_2008_10273_amd/synth.py):
       (8x8 blocks, masks and residual values) solved per block and quantised
       to int8 codes + block constants by encode_coefficients_batch over
       --batch frames.
+  --config 8: the encoder's mask selection - dense 1920x1080 4:2:0 residual
+      planes, every 8x8 block's mask chosen by rectangular subdivision and
+      the values at the points gathered (select_mask); one step = one frame.
   --config 6: intra prediction - global homogeneous diffusion inpainting of
       a 1920x1080 plane with a 4 % random mask (inpaint_homogeneous,
       cascadic CG to a relative residual of 1e-6); one step = one plane.
@@ -489,6 +492,81 @@ def bench_encode(args, torch, binding, synth):
     return rec
 
 
+def bench_select(args, torch, binding, synth):
+    """Config 8: mask selection by rectangular subdivision on dense 1080p
+    4:2:0 residual planes (select_mask); one step = one frame."""
+    c = synth.SELECT_CONFIG
+    W, H, fmt = c["width"], c["height"], c["fmt"]
+    planes = synth.residual_planes(W, H, fmt, 0)
+    dec = binding.Decoder(0)
+    pl = torch.from_numpy(np.concatenate([p.ravel() for p in planes])).cuda()
+    stream = torch.cuda.Stream()
+    sp = binding.select_params(*c["threshold"])
+    log(f"config 8 ({c['name']}), {args.steps} steps")
+    _, d = dec.select(W, H, fmt, pl, True, sp, stream=stream)
+
+    def step():
+        lib = binding.lib()
+        f = binding.pdi_frame(W, H, fmt)
+        rc = lib.select_mask(dec.ctx, ctypes.byref(f), 1, pl.data_ptr(), 8, ctypes.byref(sp),
+                             d["block_ptr"].data_ptr(), d["pos"].data_ptr(), d["values"].data_ptr(),
+                             stream.cuda_stream)
+        assert rc == 0
+
+    import ctypes
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    tm = StreamTimer(torch, stream)
+    t0 = time.perf_counter()
+    tm.start()
+    for _ in range(args.steps):
+        step()
+    secs = tm.stop()
+    wall = time.perf_counter() - t0
+    assert dec.sync(stream) == 0, binding.pdi_last_error(dec.ctx)
+    fps = args.steps / secs
+    bp = d["block_ptr"].cpu().numpy()
+    nnz = int(bp[-1])
+    ny = synth.plane_block_counts(W, H, fmt, 8)[0]
+    nvals = 2 * nnz - int(bp[ny])
+    npx = sum(w * h for w, h in synth.plane_dims(W, H, fmt))
+    log(f"select: {fps:.1f} frames/s, {1e3 * secs / args.steps:.4f} ms per frame, {nnz} mask points")
+    cpu = agree = None
+    if not args.no_cpu:
+        import oracle
+        cores = host_cores()
+        n_run, tc0 = 0, time.perf_counter()
+        while n_run < 2 or time.perf_counter() - tc0 < 5.0:
+            ref = oracle.select_mask(W, H, fmt, 8, planes, True, c["threshold"], nthreads=cores)
+            n_run += 1
+        dt = time.perf_counter() - tc0
+        cpu = dict(value=n_run / dt, unit="frames/s", cores=cores, kind="oracle",
+                   sample=f"{n_run} selections of the benchmark frame (FP64 oracle, OpenMP over blocks), {dt:.1f} s",
+                   cpu_model=cpu_model(), nproc=os.cpu_count())
+        refpts = int(sum(m.sum() for m in ref))
+        agree = dict(mask_points=nnz, oracle_mask_points=refpts)
+        log(f"oracle: {cpu['value']:.2f} frames/s on {cores} cores; {agree}")
+    ab = 4 * npx + 4 * (bp.size) + 2 * nnz + 4 * nvals
+    t_step = secs / args.steps
+    achieved = ab / t_step / 1e9
+    rec = dict(metric="1080p 4:2:0 residual frames/s through per-block mask selection (8x8, rectangular subdivision)",
+               value=fps, unit="frames/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=1e3 * t_step, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f32", data="synthetic",
+               config={"workload": c["name"], "width": W, "height": H, "format": "4:2:0", "block_size": 8,
+                       "threshold": list(c["threshold"]), "mask_points": nnz, "mask_density": nnz / float(
+                           W * H + ((W + 1) // 2) * ((H + 1) // 2))},
+               error_vs_oracle=agree,
+               roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_select8 + k_sel_scan + k_sel_pack",
+                         "algorithmic_bytes_per_launch": ab, "launch_ms": 1e3 * t_step},
+               cpu_baseline=cpu, wall_s=wall)
+    dec.close()
+    return rec
+
+
 def bench_intra(args, torch, binding, synth):
     """Config 6: global homogeneous diffusion inpainting of a 1080p plane
     (inpaint_homogeneous, cascadic CG, tol 1e-6); one step = one plane."""
@@ -721,7 +799,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2, 3, 4, 5, 6, 7])
+    ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2, 3, 4, 5, 6, 7, 8])
     ap.add_argument("--eval", default="fp32", choices=sorted(EVALS))
     ap.add_argument("--latency-iters", type=int, default=300)
     ap.add_argument("--nstreams", type=int, default=4, help="streams for overlapped / sequence decodes")
@@ -744,9 +822,9 @@ def main():
               "(blocks and frames shard across GPUs with no exchange step)", file=sys.stderr)
         sys.exit(2)
     if args.steps is None:
-        args.steps = {3: 30, 6: 50}.get(args.config, 500)
+        args.steps = {3: 30, 6: 50, 8: 100}.get(args.config, 500)
     if args.warmup is None:
-        args.warmup = {3: 3, 6: 3}.get(args.config, 50)
+        args.warmup = {3: 3, 6: 3, 8: 5}.get(args.config, 50)
 
     from paper_2008_10273_amd import synth
     # frames are generated before torch touches the GPU (worker processes)
@@ -766,6 +844,8 @@ def main():
         rec = bench_intra(args, torch, binding, synth)
     elif args.config == 7:
         rec = bench_encode(args, torch, binding, synth)
+    elif args.config == 8:
+        rec = bench_select(args, torch, binding, synth)
     else:
         rec = bench_serving(args, torch, binding, synth)
     assert torch.cuda.is_available()

@@ -215,6 +215,43 @@ int encode_coefficients_batch(pdi_ctx *ctx, int n, const pdi_frame *frame, const
                               const pdi_params *params, int8_t *const *coefs, float *const *consts,
                               void *stream);
 
+/* ---- Mask selection (encoder side) ----
+ * The encoder picks each 8x8 block's mask points by rectangular
+ * subdivision (Sec. 2.3 of the paper, which takes the scheme from the
+ * rectangular-subdivision codec it cites; this is the reading taken): the
+ * mask is the set of corners of rectangles (inclusive pixel ranges sharing
+ * their common edges) that start as the whole block; each round inpaints
+ * the block from the current corners (bordered system of Sec. 2.2, then
+ * Eq. 2, harmonic operator), and every rectangle whose mean squared error
+ * exceeds the threshold and whose longer side spans at least 2 pixel gaps
+ * is halved along that side (x on ties), both halves keeping the middle
+ * line.  Rounds end when nothing is split.  A shared chroma mask is chosen
+ * on the mean of the two chroma planes' errors (Sec. 2.3: one mask for
+ * both chroma channels). */
+typedef struct {
+    float threshold[2]; /* luma, chroma: split when a rectangle's mean squared error
+                           exceeds it (grey levels^2); not NaN; default 16, 32 */
+    int32_t max_rounds; /* rounds of splits at most, [0, 64]; default 16 (0: corners only) */
+} pdi_select_params;
+
+void pdi_default_select_params(pdi_select_params *p);
+
+/* Select the mask of every 8x8 block of a frame from its dense residual
+ * planes and gather the values at the selected points: the outputs are the
+ * inputs decode_residual and encode_coefficients take (mask with
+ * n_mask_blocks = pdi_frame_info's count for this chroma_shared).
+ *   frame:     geometry (HOST pointer); block_size must be 8.
+ *   planes:    DEVICE FP32 residual planes Y, then Cb, Cr for 4:2:0,
+ *              row-major, back to back (decode_residual's output layout).
+ *   block_ptr: DEVICE int32 [n_mask_blocks + 1] out.
+ *   pos:       DEVICE uint16 out, room for every pixel of the mask planes.
+ *   values:    DEVICE FP32 out, room for every pixel of all planes.
+ * All caller owned.  Asynchronous on `stream`.  Returns PDI_EINVAL for a
+ * NULL pointer, a bad geometry, a block size other than 8 or bad
+ * parameters; PDI_ENOMEM / PDI_EHIP as elsewhere. */
+int select_mask(pdi_ctx *ctx, const pdi_frame *frame, int chroma_shared, const float *planes, int block_size,
+                const pdi_select_params *sp, int32_t *block_ptr, uint16_t *pos, float *values, void *stream);
+
 /* ---- Global homogeneous diffusion inpainting (intra prediction) ----
  * The codec's intra frames are predicted by Eq. 1 of Sec. 2.1 on the whole
  * plane with A = -L (5-point Laplacian, reflecting boundaries): u = f at

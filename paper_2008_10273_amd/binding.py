@@ -25,7 +25,7 @@ ERROR_NAMES = {0: "PDI_OK", -1: "PDI_EINVAL", -2: "PDI_EMASK", -3: "PDI_ENOMEM",
 
 EXPORTS = ["pdi_default_params", "pdi_create", "pdi_destroy", "decode_residual", "decode_residual_batch",
            "decode_coefficients", "decode_coefficients_batch", "encode_coefficients",
-           "encode_coefficients_batch", "pdi_sync",
+           "encode_coefficients_batch", "pdi_default_select_params", "select_mask", "pdi_sync",
            "pdi_default_cg_params", "inpaint_homogeneous",
            "pdi_last_error", "pdi_frame_info", "pdi_pack_dense", "pdi_validate_host", "pdi_autotune", "pdi_autotune_batch",
            "pdi_seq_create", "pdi_seq_launch", "pdi_seq_sync", "pdi_seq_destroy",
@@ -59,6 +59,22 @@ def coef_params(steps, rho: float) -> pdi_coef_params:
         q.step[k] = float(st[k])
     q.rho = float(rho)
     return q
+
+
+class pdi_select_params(ctypes.Structure):
+    _fields_ = [("threshold", ctypes.c_float * 2), ("max_rounds", ctypes.c_int32)]
+
+
+def select_params(thr_luma: float = None, thr_chroma: float = None, max_rounds: int = None) -> pdi_select_params:
+    p = pdi_select_params()
+    lib().pdi_default_select_params(ctypes.byref(p))
+    if thr_luma is not None:
+        p.threshold[0] = thr_luma
+    if thr_chroma is not None:
+        p.threshold[1] = thr_chroma
+    if max_rounds is not None:
+        p.max_rounds = max_rounds
+    return p
 
 
 class pdi_cg_params(ctypes.Structure):
@@ -119,6 +135,11 @@ def lib() -> ctypes.CDLL:
                                                 ctypes.POINTER(pdi_coef_params), i32, ctypes.POINTER(pdi_params),
                                                 VP, VP, P]
         L.encode_coefficients_batch.restype = i32
+        L.pdi_default_select_params.argtypes = [ctypes.POINTER(pdi_select_params)]
+        L.pdi_default_select_params.restype = None
+        L.select_mask.argtypes = [P, ctypes.POINTER(pdi_frame), i32, P, i32, ctypes.POINTER(pdi_select_params),
+                                  P, P, P, P]
+        L.select_mask.restype = i32
         L.pdi_default_cg_params.argtypes = [ctypes.POINTER(pdi_cg_params)]
         L.pdi_default_cg_params.restype = None
         L.inpaint_homogeneous.argtypes = [P, i32, i32, P, P, ctypes.POINTER(pdi_cg_params), P, P,
@@ -301,6 +322,37 @@ class Decoder:
         cs = np.ascontiguousarray(consts, np.float32)
         d["consts"] = torch.from_numpy(cs if cs.size else np.zeros(1, np.float32)).to(dev)
         return d
+
+    def select(self, width: int, height: int, fmt: int, planes, chroma_shared: bool = True,
+               sp: Optional[pdi_select_params] = None, stream=None, check=True):
+        """select_mask on dense residual planes (a device FP32 tensor in the
+        decode output layout, or host arrays to upload).  Returns (rc, d)
+        with d a frame dict like upload()'s (block_ptr, pos, values on the
+        device; the frame record holds the geometry and, after sync(),
+        host copies via frame_from_selection)."""
+        import numpy as np
+        torch = self.torch
+        dev = torch.device("cuda", self.device)
+        rc, nb, nel = pdi_frame_info(width, height, fmt, 8, chroma_shared)
+        if isinstance(planes, torch.Tensor):
+            pl = planes
+        else:
+            pl = torch.from_numpy(np.ascontiguousarray(
+                np.concatenate([np.asarray(p, np.float32).ravel() for p in planes]))).to(dev)
+        nmask = width * height if fmt == 0 else (
+            width * height + ((width + 1) // 2) * ((height + 1) // 2) * (1 if chroma_shared else 2))
+        bp = torch.zeros(nb + 1, dtype=torch.int32, device=dev)
+        pos = torch.zeros(max(nmask, 1), dtype=torch.int16, device=dev)
+        vals = torch.zeros(max(nel, 1), dtype=torch.float32, device=dev)
+        s = stream.cuda_stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        f = pdi_frame(width, height, fmt)
+        rc = lib().select_mask(self.ctx, ctypes.byref(f), int(bool(chroma_shared)), pl.data_ptr(), 8,
+                               ctypes.byref(sp) if sp is not None else None, bp.data_ptr(), pos.data_ptr(),
+                               vals.data_ptr(), s)
+        if check and rc != PDI_OK:
+            raise PdiError(rc, pdi_last_error(self.ctx))
+        return rc, dict(width=width, height=height, fmt=fmt, chroma_shared=bool(chroma_shared), planes=pl,
+                        block_ptr=bp, pos=pos, values=vals, n_mask_blocks=nb)
 
     def alloc_coef(self, d):
         """Add device buffers for an encode's outputs to a frame from upload():

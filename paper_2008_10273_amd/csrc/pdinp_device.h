@@ -62,6 +62,19 @@ __device__ __forceinline__ float coef_value(int q, float step, float rho) {
   return q == 0 ? 0.f : (q > 0 ? m : -m);
 }
 
+// Green's function from the quarter-scaled compact table of a w x h shape:
+// G(x_a, x_b) = sum over the 4 (alpha, beta) pairs from |x_a - x_b| and the
+// reflected x_a + x_b + 1 per axis.
+template <typename T>
+__device__ __forceinline__ T green_tab(const T *tab, int w, int h, int xa, int ya, int xb, int yb) {
+  const int W1 = w + 1;
+  int dx = abs(xa - xb), dy = abs(ya - yb);
+  int sx = xa + xb + 1, sy = ya + yb + 1;
+  sx = min(sx, 2 * w - sx);
+  sy = min(sy, 2 * h - sy);
+  return (tab[dy * W1 + dx] + tab[dy * W1 + sx]) + (tab[sy * W1 + dx] + tab[sy * W1 + sx]);
+}
+
 // Make this lane's LDS writes visible to the other lanes of its wave (no
 // instruction beyond the wait the writes need).
 __device__ __forceinline__ void wave_sync() {

@@ -50,6 +50,8 @@ struct Workspace {
   float *slots = nullptr;   // global-memory bordered systems
   long long slot_floats = 0;
   int slot_count = 0;
+  unsigned long long *bits = nullptr;  // mask selection: one mask word per block
+  int bits_cap = 0;
 };
 
 // Buffers of global homogeneous diffusion inpainting for one plane size:
@@ -447,7 +449,9 @@ void pdi_destroy(pdi_ctx *c) {
     (void)hipFree(kv.second.status);
     (void)hipFree(kv.second.counters);
     (void)hipFree(kv.second.deferred);
+    (void)hipFree(kv.second.binlist);
     (void)hipFree(kv.second.slots);
+    (void)hipFree(kv.second.bits);
   }
   for (auto &kv : c->diff) free_diff(kv.second);
   delete c;
@@ -469,9 +473,44 @@ int pdi_frame_info(const pdi_frame *frame, int block_size, int chroma_shared,
   return PDI_OK;
 }
 
+// Mask groups of a frame (the plane each mask lives on, its value planes,
+// offsets of those planes in the concatenated planes and in consts[], block
+// grid, shape ids) into F.g; F.chroma_first is the first chroma block.
+static void fill_groups(const pdi_frame *frame, int block_size, int shared, const TableSet *ts, pdi::FrameDev &F) {
+  PlaneGeom pg[3];
+  planes_of(frame, pg);
+  long long poff[3] = {0, 0, 0};
+  int pbo[3] = {0, 0, 0};  // first block of each plane in consts[]
+  for (int i = 1; i < 3; ++i) {
+    poff[i] = poff[i - 1] + (long long)pg[i - 1].W * pg[i - 1].H;
+    pbo[i] = pbo[i - 1] + ((pg[i - 1].W + block_size - 1) / block_size) * ((pg[i - 1].H + block_size - 1) / block_size);
+  }
+  int mp[3], vp[3][2], nv[3];
+  F.ngroups = groups_of(frame, shared, mp, vp, nv);
+  int first = 0;
+  F.chroma_first = -1;
+  for (int g = 0; g < F.ngroups; ++g) {
+    pdi::GroupDev &G = F.g[g];
+    G.first = first;
+    G.W = pg[mp[g]].W;
+    G.H = pg[mp[g]].H;
+    G.nbx = (G.W + block_size - 1) / block_size;
+    G.nby = (G.H + block_size - 1) / block_size;
+    G.nv = nv[g];
+    for (int k = 0; k < nv[g]; ++k) {
+      G.vplane[k] = vp[g][k];
+      G.out_off[k] = poff[vp[g][k]];
+      G.cbase[k] = pbo[vp[g][k]];
+    }
+    for (int k = 0; k < 4; ++k) G.shape[k] = ts->group_shape[g][k];
+    if (mp[g] == 1) F.chroma_first = first;
+    first += G.nbx * G.nby;
+  }
+}
+
 // Decode n frames of one geometry (one launch per kernel for all of them):
-// residual decodes (values, qp == nullptr) or stored-coefficient decodes
-// (coefs + consts, qp != nullptr).
+// residual decodes (values, qp == nullptr), stored-coefficient decodes
+// (coefs + consts, qp != nullptr) or coefficient encodes (qouts + aouts).
 static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask *masks,
                        const float *const *values, int block_size, const pdi_params *params,
                        float *const *outs, void *stream, const int8_t *const *coefs = nullptr,
@@ -550,35 +589,7 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
     for (int k = 0; k < 3; ++k) F.qstep[k] = qp->step[k];
     F.qrho = qp->rho;
   }
-  PlaneGeom pg[3];
-  planes_of(frame, pg);
-  long long poff[3] = {0, 0, 0};
-  int pbo[3] = {0, 0, 0};  // first block of each plane in consts[]
-  for (int i = 1; i < 3; ++i) {
-    poff[i] = poff[i - 1] + (long long)pg[i - 1].W * pg[i - 1].H;
-    pbo[i] = pbo[i - 1] + ((pg[i - 1].W + block_size - 1) / block_size) * ((pg[i - 1].H + block_size - 1) / block_size);
-  }
-  int mp[3], vp[3][2], nv[3];
-  F.ngroups = groups_of(frame, shared, mp, vp, nv);
-  int first = 0;
-  F.chroma_first = -1;
-  for (int g = 0; g < F.ngroups; ++g) {
-    pdi::GroupDev &G = F.g[g];
-    G.first = first;
-    G.W = pg[mp[g]].W;
-    G.H = pg[mp[g]].H;
-    G.nbx = (G.W + block_size - 1) / block_size;
-    G.nby = (G.H + block_size - 1) / block_size;
-    G.nv = nv[g];
-    for (int k = 0; k < nv[g]; ++k) {
-      G.vplane[k] = vp[g][k];
-      G.out_off[k] = poff[vp[g][k]];
-      G.cbase[k] = pbo[vp[g][k]];
-    }
-    for (int k = 0; k < 4; ++k) G.shape[k] = ts->group_shape[g][k];
-    if (mp[g] == 1) F.chroma_first = first;
-    first += G.nbx * G.nby;
-  }
+  fill_groups(frame, block_size, shared, ts, F);
   F.nshapes = ts->nshapes;
   for (int k = 0; k < ts->nshapes; ++k) F.s[k] = ts->s[k];
   // Shape-homogeneous runs of blocks for the batched paths: k_fast (b <= 16,
@@ -731,6 +742,75 @@ int encode_coefficients_batch(pdi_ctx *c, int n, const pdi_frame *frame, const p
   if (c && (!coefs || !consts)) return set_err(c, PDI_EINVAL, "null codes or constants");
   return decode_impl(c, n, frame, masks, values, block_size, params, nullptr, stream, nullptr, nullptr, qp, coefs,
                      consts);
+}
+
+void pdi_default_select_params(pdi_select_params *p) {
+  if (!p) return;
+  p->threshold[0] = 16.0f;
+  p->threshold[1] = 32.0f;
+  p->max_rounds = 16;
+}
+
+int select_mask(pdi_ctx *c, const pdi_frame *frame, int chroma_shared, const float *planes, int block_size,
+                const pdi_select_params *sp, int32_t *block_ptr, uint16_t *pos, float *values, void *stream) {
+  if (!c) return PDI_EINVAL;
+  if (!frame || !planes || !block_ptr || !pos || !values)
+    return set_err(c, PDI_EINVAL, "null frame, planes, block_ptr, pos or values");
+  if (block_size != 8) return set_err(c, PDI_EINVAL, "mask selection takes 8x8 blocks (block %d)", block_size);
+  if (check_geometry(frame, block_size))
+    return set_err(c, PDI_EINVAL, "bad geometry %dx%d format %d", frame->width, frame->height, frame->format);
+  pdi_select_params S;
+  pdi_default_select_params(&S);
+  if (sp) S = *sp;
+  if (std::isnan(S.threshold[0]) || std::isnan(S.threshold[1])) return set_err(c, PDI_EINVAL, "NaN threshold");
+  if (S.max_rounds < 0 || S.max_rounds > 64) return set_err(c, PDI_EINVAL, "max_rounds must be in [0, 64]");
+  const int shared = (frame->format == PDI_YUV420 && chroma_shared) ? 1 : 0;
+  const long long nitems = mask_blocks_of(frame, block_size, shared);
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  std::lock_guard<std::mutex> lock(c->mu);
+  hipStream_t s = (hipStream_t)stream;
+  Workspace *W = nullptr;
+  int rc = get_workspace(c, s, &W);
+  if (rc) return rc;
+  if (W->bits_cap < nitems) {
+    dev_free(c, W->bits, sizeof(unsigned long long) * (size_t)W->bits_cap);
+    W->bits = nullptr;
+    W->bits_cap = 0;
+    rc = dev_alloc(c, (void **)&W->bits, sizeof(unsigned long long) * (size_t)nitems, "mask words");
+    if (rc) return rc;
+    W->bits_cap = (int)nitems;
+  }
+  pdi_params P;  // the residual operator: harmonic, discrete 5-point eigenvalues
+  pdi_default_params(&P);
+  TableSet *ts = nullptr;
+  rc = get_tables(c, frame, block_size, shared, P, &ts);
+  if (rc) return rc;
+  pdi::FrameDev F;
+  std::memset(&F, 0, sizeof F);
+  F.b = block_size;
+  F.n_items = (int)nitems;
+  F.shared = shared;
+  F.nframes = 1;
+  fill_groups(frame, block_size, shared, ts, F);
+  F.nshapes = ts->nshapes;
+  for (int k = 0; k < ts->nshapes; ++k) F.s[k] = ts->s[k];
+  F.tab32 = ts->tab32;
+  F.tab64 = ts->tab64;
+  F.tab32_floats = ts->tab32_floats;
+  F.status = W->status;
+  F.counters = W->counters;
+  F.sel_planes = planes;
+  F.sel_bits = W->bits;
+  F.sel_bp = block_ptr;
+  F.sel_pos = pos;
+  F.sel_vals = values;
+  F.sel_thr[0] = S.threshold[0];
+  F.sel_thr[1] = S.threshold[1];
+  F.sel_rounds = S.max_rounds;
+  e = pdi::launch_select(F, s);
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return PDI_OK;
 }
 
 int pdi_sync(pdi_ctx *c, void *stream) {

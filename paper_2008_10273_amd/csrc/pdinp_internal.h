@@ -116,6 +116,15 @@ struct FrameDev {
   int out_i8;        // 1: out holds int8 pixels, clamp(rint(u), -128, 127)
   int coef;          // 1: stored coefficients (codes + constants), no solve
   int enc;           // 1: coefficient encode (solve, then quantise c and store a; no evaluation)
+  // Mask selection (pdinp_select.hip): dense residual planes in, one 64-bit
+  // mask word per block, then the packed mask and values out.
+  const float *sel_planes;
+  unsigned long long *sel_bits;
+  int32_t *sel_bp;
+  uint16_t *sel_pos;
+  float *sel_vals;
+  float sel_thr[2];  // luma, chroma thresholds on a rectangle's mean squared error
+  int sel_rounds;
   float qstep[3];    // quantiser step per plane (coef, enc)
   float qrho;        // reconstruction offset (coef)
   GroupDev g[kMaxGroups];
@@ -151,6 +160,7 @@ hipError_t launch_wide(const FrameDev &f, hipStream_t stream);  // binning kerne
 hipError_t launch_plain_all(const FrameDev &f, hipStream_t stream);
 hipError_t launch_general_deferred(const FrameDev &f, hipStream_t stream);
 hipError_t launch_coef_general(const FrameDev &f, hipStream_t stream);  // coef: the deferred blocks
+hipError_t launch_select(const FrameDev &f, hipStream_t stream);        // mask selection, b = 8
 
 // Global homogeneous diffusion inpainting (pdinp_diffusion.hip); all
 // asynchronous on the stream.  Scalars (GAM = r.r and DEL = w.r per

@@ -342,6 +342,21 @@ def coef_frame(frame: int = 0) -> Tuple[Frame, np.ndarray, np.ndarray]:
     return fr, q, consts
 
 
+def residual_planes(width: int, height: int, fmt: int, seed) -> List[np.ndarray]:
+    """Dense residual planes (Y, then Cb and Cr for 4:2:0) from the residual
+    field recipe, float32 (H, W) arrays: the encoder's input.  Random numbers
+    only."""
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_ROOT, 8] + list(np.atleast_1d(seed))))
+    return [_field(rng, W, H, 20.0).astype(np.float32) for W, H in plane_dims(width, height, fmt)]
+
+
+# Mask selection workload: dense 1920x1080 4:2:0 residual planes, 8x8 blocks,
+# rectangles split above a mean squared error of 16 (luma) / 32 (chroma):
+# about 14 % / 9 % of the pixels become mask points on these planes.
+SELECT_CONFIG = dict(name="fhd420_b8_select_t16-32", width=1920, height=1080, fmt=YUV420, block_size=8,
+                     threshold=(16.0, 32.0))
+
+
 # Intra-frame workload for global homogeneous diffusion inpainting (Sec. 2.1):
 # one 1920x1080 plane, a uniform random mask of 4 % of the pixels, values
 # from the residual field recipe.

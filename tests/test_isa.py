@@ -17,7 +17,8 @@ CSRC = os.path.join(ROOT, "paper_2008_10273_amd", "csrc")
 # Sources with the per-file flags the build passes.
 SOURCES = [("pdinp_kernels.hip", []),
            ("pdinp_wide.hip", ["-mllvm", "-pragma-unroll-threshold=1000000"]),
-           ("pdinp_diffusion.hip", [])]
+           ("pdinp_diffusion.hip", []),
+           ("pdinp_select.hip", [])]
 
 
 @pytest.fixture(scope="module")
