@@ -560,7 +560,7 @@ def bench_select(args, torch, binding, synth):
                error_vs_oracle=agree,
                roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                         "kernel": "k_select8 + k_sel_scan + k_sel_pack",
+                         "kernel": "k_select8 + k_sel_count + k_sel_pack",
                          "algorithmic_bytes_per_launch": ab, "launch_ms": 1e3 * t_step},
                cpu_baseline=cpu, wall_s=wall)
     dec.close()

@@ -51,6 +51,7 @@ struct Workspace {
   long long slot_floats = 0;
   int slot_count = 0;
   unsigned long long *bits = nullptr;  // mask selection: one mask word per block
+  int *selx = nullptr;                 // and the packing's prefix scratch (blocks + tiles)
   int bits_cap = 0;
 };
 
@@ -452,6 +453,7 @@ void pdi_destroy(pdi_ctx *c) {
     (void)hipFree(kv.second.binlist);
     (void)hipFree(kv.second.slots);
     (void)hipFree(kv.second.bits);
+    (void)hipFree(kv.second.selx);
   }
   for (auto &kv : c->diff) free_diff(kv.second);
   delete c;
@@ -775,9 +777,12 @@ int select_mask(pdi_ctx *c, const pdi_frame *frame, int chroma_shared, const flo
   if (rc) return rc;
   if (W->bits_cap < nitems) {
     dev_free(c, W->bits, sizeof(unsigned long long) * (size_t)W->bits_cap);
+    dev_free(c, W->selx, sizeof(int) * (size_t)(W->bits_cap + W->bits_cap / 256 + 1));
     W->bits = nullptr;
+    W->selx = nullptr;
     W->bits_cap = 0;
     rc = dev_alloc(c, (void **)&W->bits, sizeof(unsigned long long) * (size_t)nitems, "mask words");
+    if (!rc) rc = dev_alloc(c, (void **)&W->selx, sizeof(int) * (size_t)(nitems + nitems / 256 + 1), "mask words");
     if (rc) return rc;
     W->bits_cap = (int)nitems;
   }
@@ -802,6 +807,7 @@ int select_mask(pdi_ctx *c, const pdi_frame *frame, int chroma_shared, const flo
   F.counters = W->counters;
   F.sel_planes = planes;
   F.sel_bits = W->bits;
+  F.sel_x = W->selx;
   F.sel_bp = block_ptr;
   F.sel_pos = pos;
   F.sel_vals = values;

@@ -120,6 +120,7 @@ struct FrameDev {
   // mask word per block, then the packed mask and values out.
   const float *sel_planes;
   unsigned long long *sel_bits;
+  int *sel_x;        // scratch: per-block prefix inside its tile of 256, then the tile totals
   int32_t *sel_bp;
   uint16_t *sel_pos;
   float *sel_vals;
