@@ -17,7 +17,7 @@
 
 namespace pdi {
 
-constexpr int kHdThreads = 1024;
+constexpr int kHdThreads = 512;
 
 // The value of a slotted scalar (uniform loads).
 __device__ __forceinline__ double slot_sum(const double *a) {
@@ -58,8 +58,8 @@ __device__ __forceinline__ void wg_add2(double v, double w, double *dst0, double
 // per workgroup (a 2D grid); the per-iteration kernel is persistent (at
 // most kHdWgs workgroups, each looping over tiles) so that the scalars are
 // read and the partial sums added once per workgroup, not once per tile.
-constexpr int kTx = 64, kTy = 16;
-constexpr int kHdWgs = 512;  // two 1024-thread workgroups per compute unit
+constexpr int kTx = 64, kTy = 8;
+constexpr int kHdWgs = 1024;  // four 512-thread workgroups per compute unit
 static_assert(kTx * kTy == kHdThreads, "one pixel per thread");
 
 // Coarser level: a pixel is known when one of its (up to 4) children is,
