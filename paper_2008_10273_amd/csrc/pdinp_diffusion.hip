@@ -53,8 +53,8 @@ __device__ __forceinline__ void wg_add2(double v, double w, double *dst0, double
   }
 }
 
-// Kernels run on 64 x 16 pixel tiles: thread (tx, ty) of tile (bx, by)
-// owns pixel (64 bx + tx, 16 by + ty).  The per-level kernels take one tile
+// Kernels run on 64 x 8 pixel tiles: thread (tx, ty) of tile (bx, by)
+// owns pixel (64 bx + tx, 8 by + ty).  The per-level kernels take one tile
 // per workgroup (a 2D grid); the per-iteration kernel is persistent (at
 // most kHdWgs workgroups, each looping over tiles) so that the scalars are
 // read and the partial sums added once per workgroup, not once per tile.
