@@ -220,3 +220,21 @@ def test_select_errors(dec):
     rc = binding.lib().select_mask(dec.ctx, ctypes.byref(f), 1, t.data_ptr(), 16, None, t.data_ptr(),
                                    t.data_ptr(), t.data_ptr(), None)
     assert rc == binding.PDI_EINVAL
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (1, 9), (9, 1), (3, 2), (17, 1)])
+def test_select_tiny_planes(dec, W, H):
+    """Degenerate blocks (one pixel, one row, one column): the corners already
+    cover 1-pixel-wide blocks and rows split down to every pixel, so the
+    masks are fixed without floating-point decisions near the threshold at
+    thresholds -1 and 1e30."""
+    from paper_2008_10273_amd import binding
+    planes = synth.residual_planes(W, H, synth.GRAY, 100 + W * H)
+    print(f"case select tiny {W}x{H}", flush=True)
+    for T in (-1.0, 1e30):
+        rc, d = dec.select(W, H, synth.GRAY, planes, True, binding.select_params(T, T))
+        assert dec.sync() == 0
+        masks, gathered = _host_masks(d, W, H, synth.GRAY, True)
+        ref = oracle.select_mask(W, H, synth.GRAY, 8, planes, True, (T, T))
+        assert np.array_equal(masks[0], ref[0])
+        assert np.array_equal(gathered[0][0][masks[0]], planes[0][masks[0]])
