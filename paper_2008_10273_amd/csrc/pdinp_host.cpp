@@ -72,6 +72,7 @@ struct DiffWork {
   int sc_cap = 0;     // doubles in sc
   double *host = nullptr;  // pinned: the slots of GAM[i..] and BB, read back for the convergence test
   int host_cap = 0;        // doubles in host
+  hipEvent_t ev = nullptr; // marks the completion of the read-back in flight
 };
 
 static void free_diff(DiffWork &d) {
@@ -84,6 +85,7 @@ static void free_diff(DiffWork &d) {
     if (p) (void)hipFree(p);
   if (d.sc) (void)hipFree(d.sc);
   if (d.host) (void)hipHostFree(d.host);
+  if (d.ev) (void)hipEventDestroy(d.ev);
   d = DiffWork();
 }
 
@@ -1016,7 +1018,7 @@ void pdi_default_cg_params(pdi_cg_params *p) {
   if (!p) return;
   p->tol = 1e-6;
   p->max_iter = 4000;
-  p->check = 16;
+  p->check = 8;
   p->coarse_tol = 1e-3;
 }
 
@@ -1069,6 +1071,8 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
   // double per iteration.
   const int need = (2 * (P.max_iter + 1) + 1) * pdi::kHdSlots + (P.max_iter + 1);
   const int hneed = (P.check + 2) * pdi::kHdSlots;  // GAM[i..i+check] and BB
+  if (!D.ev && hipEventCreateWithFlags(&D.ev, hipEventDisableTiming) != hipSuccess)
+    return set_err(c, PDI_EHIP, "event for the norm read-back");
   if (D.host_cap < hneed) {
     if (D.host) (void)hipHostFree(D.host);
     D.host = nullptr;
@@ -1102,23 +1106,45 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
     if (e == hipSuccess) e = pdi::hd_residual(D.m[l], D.f[l], D.u[l], W, H, D.rv[0], GAM, BB, s);
     if (e == hipSuccess) e = pdi::hd_start(D.m[l], D.rv[0], W, H, D.wv[0], DEL, s);
     // CG.  Each launch tests convergence on the device (GAM[it] against
-    // tol^2 BB) and does nothing once it holds; the host queues P.check
-    // launches at a time and reads back the norms GAM[seen..it] to find the
-    // first converged iteration.
-    int it = 0, seen = 0;
+    // tol^2 BB) and does nothing once it holds.  The host queues P.check
+    // launches at a time, each batch behind a read-back of the norms the
+    // previous batch produced, and examines a read-back only once the next
+    // batch is queued, so the device never waits for the host; the first
+    // converged iteration is found in the norms.
+    int it = 0;           // iterations queued
+    int lo = 0, hi = 0;   // the read-back in flight holds GAM[lo..hi]
+    int its = 0;          // iterations of the level's result
     bool done = false;
     const double tol2 = l ? P.coarse_tol * P.coarse_tol : P.tol * P.tol;
+    const size_t sb = sizeof(double) * pdi::kHdSlots;
+    auto read_back = [&]() -> hipError_t {
+      const int n = hi - lo + 1;
+      hipError_t r = hipMemcpyAsync(D.host, GAM + (size_t)lo * pdi::kHdSlots, n * sb, hipMemcpyDeviceToHost, s);
+      if (r == hipSuccess)
+        r = hipMemcpyAsync(D.host + (size_t)n * pdi::kHdSlots, BB, sb, hipMemcpyDeviceToHost, s);
+      if (r == hipSuccess) r = hipEventRecord(D.ev, s);
+      return r;
+    };
+    auto queue = [&]() -> hipError_t {
+      const int stop = std::min(P.max_iter, it + P.check);
+      hipError_t r = hipSuccess;
+      for (; it < stop && r == hipSuccess; ++it) {
+        const int a = it & 1, b = a ^ 1;
+        r = pdi::hd_iterate(D.m[l], W, H, GAM, DEL, ALPHA, BB, tol2, it, D.u[l], D.p, D.rv[a], D.wv[a], D.sv[a],
+                            D.rv[b], D.wv[b], D.sv[b], s);
+      }
+      return r;
+    };
+    if (e == hipSuccess) e = read_back();  // GAM[0]
+    if (e == hipSuccess) e = queue();
     while (e == hipSuccess) {
-      const size_t sb = sizeof(double) * pdi::kHdSlots;
-      const int n = it - seen + 1;
-      e = hipMemcpyAsync(D.host, GAM + (size_t)seen * pdi::kHdSlots, n * sb, hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipMemcpyAsync(D.host + (size_t)n * pdi::kHdSlots, BB, sb, hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      e = hipEventSynchronize(D.ev);
       if (e != hipSuccess) break;
+      const int n = hi - lo + 1;
       double bb = 0.0;
       for (int k = 0; k < pdi::kHdSlots; ++k) bb += D.host[(size_t)n * pdi::kHdSlots + k];
       bool bad = false;
-      for (int i = 0; i < n && !done; ++i) {
+      for (int i = 0; i < n; ++i) {
         double g = 0.0;
         for (int k = 0; k < pdi::kHdSlots; ++k) g += D.host[(size_t)i * pdi::kHdSlots + k];
         if (!(g == g)) {  // NaN: not converging
@@ -1127,20 +1153,23 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
         }
         if (g <= tol2 * bb) {
           done = true;
-          it = seen + i;  // the launches after it did nothing
+          its = lo + i;  // the launches after it did nothing
+          break;
         }
       }
-      if (done || bad || it >= P.max_iter) break;
-      seen = it + 1;
-      const int stop = std::min(P.max_iter, it + P.check);
-      for (; it < stop && e == hipSuccess; ++it) {
-        const int a = it & 1, b = a ^ 1;
-        e = pdi::hd_iterate(D.m[l], W, H, GAM, DEL, ALPHA, BB, tol2, it, D.u[l], D.p, D.rv[a], D.wv[a], D.sv[a],
-                            D.rv[b], D.wv[b], D.sv[b], s);
+      if (done || bad) break;
+      if (hi >= P.max_iter) {  // the norm after max_iter iterations did not meet tol
+        its = hi;
+        break;
       }
+      lo = hi + 1;  // everything queued so far (it > hi: at least one batch went out)
+      hi = it;
+      e = read_back();
+      if (e == hipSuccess) e = queue();
     }
+    if (!done && its == 0) its = it;
     if (l == 0) {
-      its0 = it;
+      its0 = its;
       converged = done;
     }
   }
