@@ -1125,8 +1125,8 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
       if (r == hipSuccess) r = hipEventRecord(D.ev, s);
       return r;
     };
-    auto queue = [&]() -> hipError_t {
-      const int stop = std::min(P.max_iter, it + P.check);
+    auto queue = [&](int count) -> hipError_t {
+      const int stop = std::min(P.max_iter, it + count);
       hipError_t r = hipSuccess;
       for (; it < stop && r == hipSuccess; ++it) {
         const int a = it & 1, b = a ^ 1;
@@ -1136,7 +1136,9 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
       return r;
     };
     if (e == hipSuccess) e = read_back();  // GAM[0]
-    if (e == hipSuccess) e = queue();
+    if (e == hipSuccess) e = queue(P.check);
+    double g_prev = -1.0;  // last norm examined and its iteration
+    int i_prev = -1;
     while (e == hipSuccess) {
       e = hipEventSynchronize(D.ev);
       if (e != hipSuccess) break;
@@ -1144,13 +1146,15 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
       double bb = 0.0;
       for (int k = 0; k < pdi::kHdSlots; ++k) bb += D.host[(size_t)n * pdi::kHdSlots + k];
       bool bad = false;
+      double g_first = -1.0, g = 0.0;
       for (int i = 0; i < n; ++i) {
-        double g = 0.0;
+        g = 0.0;
         for (int k = 0; k < pdi::kHdSlots; ++k) g += D.host[(size_t)i * pdi::kHdSlots + k];
         if (!(g == g)) {  // NaN: not converging
           bad = true;
           break;
         }
+        if (i == 0) g_first = g;
         if (g <= tol2 * bb) {
           done = true;
           its = lo + i;  // the launches after it did nothing
@@ -1162,10 +1166,24 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
         its = hi;
         break;
       }
+      // Next batch: the iterations the norm's decay so far says are left
+      // beyond the batch in flight (+1), at most P.check, at least 1.
+      int next = P.check;
+      {
+        const double g0 = i_prev >= 0 ? g_prev : g_first;
+        const int i0 = i_prev >= 0 ? i_prev : lo, span = hi - i0;
+        if (span > 0 && g > 0.0 && g0 > g) {
+          const double rate = std::log(g / g0) / span;  // per iteration, < 0
+          const double left = std::log(tol2 * bb / g) / rate - (double)(it - hi);
+          next = std::max(1, std::min(P.check, (int)std::ceil(left) + 1));
+        }
+      }
+      g_prev = g;
+      i_prev = hi;
       lo = hi + 1;  // everything queued so far (it > hi: at least one batch went out)
       hi = it;
       e = read_back();
-      if (e == hipSuccess) e = queue();
+      if (e == hipSuccess) e = queue(next);
     }
     if (!done && its == 0) its = it;
     if (l == 0) {
