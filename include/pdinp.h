@@ -135,7 +135,7 @@ int decode_residual(pdi_ctx *ctx, const pdi_frame *frame, const pdi_mask *mask,
  * only.  More blocks per launch keep more waves in flight, so a batch is
  * the throughput form of decode_residual; each frame's result is the same
  * as when decoded alone.  Errors as for decode_residual. */
-#define PDI_MAX_BATCH 8
+#define PDI_MAX_BATCH 16
 int decode_residual_batch(pdi_ctx *ctx, int n, const pdi_frame *frame, const pdi_mask *masks,
                           const float *const *values, int block_size, const pdi_params *params,
                           float *const *outs, void *stream);
@@ -371,7 +371,7 @@ void pdi_seq_destroy(pdi_seq *q);
  * admits queued frames in arrival order whenever a lane is free and the
  * device bytes of the running frames stay within hbm_budget_bytes (0 = no
  * cap): the oldest queued frame, joined by queued frames of the same
- * geometry and params (up to PDI_MAX_BATCH), is copied to the device and
+ * geometry and params (up to 8: a latency choice), is copied to the device and
  * decoded by one decode_residual_batch launch on the lane's stream (frames on
  * different lanes overlap on the GPU), and the results are copied back.  A
  * frame's result does not depend on what it is batched with or on what else
