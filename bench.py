@@ -5,7 +5,7 @@ Workloads (synthetic, seeded; the recipe is in paper_2008_10273_amd/synth.py):
   --config 1 (default): 1920x1080 4:2:0 residual frames, 16x16 blocks,
       per-block mask density U[1%, 10%] (3-26 points per full block), values
       = smooth sum of 4 random sinusoids + N(0, 2) noise, clipped to
-      [-64, 64].  One step = one decode_residual_batch call over --batch (16)
+      [-64, 64].  One step = one decode_residual_batch call over --batch (32)
       different frames: every block assembled, solved and evaluated on the
       GPU, inputs resident in HBM.  Single-frame throughput and latency are
       reported beside it.
@@ -56,7 +56,7 @@ EVALS = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16x2": 3}
 # launch shape the counters were taken on (null after a kernel change, or
 # when the autotuned launch choice differs).
 # (config, frames per step, launch choice): bytes per launch
-TRAFFIC = {(1, 16, 16): 221948647, (2, 16, 2): 231054424}
+TRAFFIC = {(1, 32, 16): 442338596, (2, 32, 2): 460454438}
 # HBM bytes of one finest-level k_hd_cg iteration of config 6 (same counters)
 TRAFFIC_HD_ITER = 85391197
 
@@ -803,7 +803,7 @@ def main():
     ap.add_argument("--eval", default="fp32", choices=sorted(EVALS))
     ap.add_argument("--latency-iters", type=int, default=300)
     ap.add_argument("--nstreams", type=int, default=4, help="streams for overlapped / sequence decodes")
-    ap.add_argument("--batch", type=int, default=16, help="frames per decode_residual_batch step (1 to 16)")
+    ap.add_argument("--batch", type=int, default=32, help="frames per decode_residual_batch step (1 to 32)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1), help="frame generator processes")
     ap.add_argument("--lanes", type=int, default=4, help="serving: GPU streams of the request loop")
     ap.add_argument("--budget-mb", type=int, default=2048, help="serving: HBM budget of admitted frames")

@@ -135,7 +135,7 @@ int decode_residual(pdi_ctx *ctx, const pdi_frame *frame, const pdi_mask *mask,
  * only.  More blocks per launch keep more waves in flight, so a batch is
  * the throughput form of decode_residual; each frame's result is the same
  * as when decoded alone.  Errors as for decode_residual. */
-#define PDI_MAX_BATCH 16
+#define PDI_MAX_BATCH 32
 int decode_residual_batch(pdi_ctx *ctx, int n, const pdi_frame *frame, const pdi_mask *masks,
                           const float *const *values, int block_size, const pdi_params *params,
                           float *const *outs, void *stream);

@@ -22,7 +22,7 @@ constexpr int kBinK0 = 84, kBinK1 = 64, kBinK2 = 42;
 // the deferred pass, then per frame fi of the launch and wave-per-block queue
 // q the lengths of its 4 bins at [kQueueCounters + 4 (fi kMaxShapes + q) + bin].
 constexpr int kQueueCounters = 8;
-constexpr int kMaxBatch = 16;  // frames of one geometry per launch (decode_residual_batch)
+constexpr int kMaxBatch = 32;  // frames of one geometry per launch (decode_residual_batch)
 // Deferred-list entries hold (frame << kDeferFrameShift) | block.
 constexpr int kDeferFrameShift = 24;
 constexpr int kDeferItemMask = (1 << kDeferFrameShift) - 1;

@@ -162,7 +162,7 @@ def test_serving_budget_admission_and_busy(dec):
 
 @pytest.mark.parametrize("b,path,i8", [(16, 0, 0), (32, 0, 0), (8, 0, 0), (16, 1, 0), (32, 1, 0), (16, 0, 1)])
 def test_batch_equals_single(dec, b, path, i8):
-    """decode_residual_batch over 1..16 frames equals decoding each frame alone,
+    """decode_residual_batch over 1..32 frames equals decoding each frame alone,
     bitwise, including blocks left to the general path (K = 0, K = w*h,
     large K) in every frame of the batch."""
     from paper_2008_10273_amd import binding
@@ -189,13 +189,13 @@ def test_batch_equals_single(dec, b, path, i8):
         dec.decode(d, params)
         assert dec.sync() == 0
         alone.append(d[key].cpu().numpy())
-    for n in (1, 3, 8, 16):
-        ds = [dec.upload(fr) for fr in (frames * 2)[-n:]]
+    for n in (1, 3, 8, 32):
+        ds = [dec.upload(fr) for fr in (frames * 4)[-n:]]
         for d in ds:
             d[key].zero_()
         dec.decode_batch(ds, params)
         assert dec.sync() == 0
-        for d, ref in zip(ds, (alone * 2)[-n:]):
+        for d, ref in zip(ds, (alone * 4)[-n:]):
             np.testing.assert_array_equal(d[key].cpu().numpy(), ref)
-    ds = [dec.upload(frames[0]) for _ in range(17)]
+    ds = [dec.upload(frames[0]) for _ in range(33)]
     assert dec.decode_batch(ds, params, check=False) == binding.PDI_EINVAL

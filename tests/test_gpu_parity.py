@@ -312,7 +312,7 @@ def test_autotune_batch_keeps_results(dec, b):
     for d, ref in zip(ds, alone):
         np.testing.assert_array_equal(d["out"].cpu().numpy().astype(np.float64), ref)
     with pytest.raises(binding.PdiError):
-        dec.autotune_batch(ds * 6)  # 18 frames: more than one launch takes
+        dec.autotune_batch(ds * 11)  # 33 frames: more than one launch takes
 
 
 @pytest.mark.parametrize("case", ["cfg0", "ragged420", "b8", "b32", "edge_counts"])
