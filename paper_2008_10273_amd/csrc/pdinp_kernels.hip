@@ -414,13 +414,18 @@ struct FastStage {
   float a[kWaveItems][2];
 };
 
-// Size class of a block for the wave-level path: 0, 1, 2 -> R = 16, 24, 32
-// rows (staged points); 3 -> not taken (general path).  Stored-coefficient
-// decodes (COEF) take K = 0 (u = a) and K = w*h as well.
-template <bool COEF>
+// Size class of a block for the wave-level path: 0, 1, 2, 3 -> R = 8, 16,
+// 24, 32 rows (the bordered system of K points has K + 1 rows); kClassDefer
+// -> not taken (general path); kClassNone marks an empty slot.  Only
+// coefficient encodes (ENC8) use R = 8: instantiating it in the decoders
+// grew their code past what their instruction cache holds, and decodes ran
+// several times slower.  Stored-coefficient decodes (COEF) take K = 0
+// (u = a) and K = w*h as well.
+constexpr int kClassDefer = 4, kClassNone = 5;
+template <bool COEF, bool ENC8>
 __device__ __forceinline__ int fast_class(int K, int N) {
-  if (COEF ? (K < 0 || K > N || K > kFastKMax) : (K < 1 || K >= N || K > kFastKMax)) return 3;
-  return K <= 15 ? 0 : (K <= 23 ? 1 : 2);
+  if (COEF ? (K < 0 || K > N || K > kFastKMax) : (K < 1 || K >= N || K > kFastKMax)) return kClassDefer;
+  return (ENC8 && K <= 7) ? 0 : (K <= 15 ? 1 : (K <= 23 ? 2 : 3));
 }
 
 // Stored-coefficient decodes: stage (x, y, c) of the wave's 4 blocks (codes
@@ -464,7 +469,7 @@ __device__ __forceinline__ void fast_coef_stage(const FrameDev &f, const FastIte
   if (bad) atomicOr(f.status, bad);
 }
 
-// Solve the bordered systems of the wave's 4 blocks (R = 16, 24 or 32 rows
+// Solve the bordered systems of the wave's 4 blocks (R = 8, 16, 24 or 32 rows
 // per block, two value columns) and stage the evaluation operands.  J is the
 // row-pair Green table of the workgroup's shape (LDS).  Returns false for a
 // block whose pivots call for FP64 refinement; such blocks are left to the
@@ -942,7 +947,7 @@ void k_fast(FrameDev f) {
   }
   if (tid < kFastItems) {
     FastItem r;
-    r.cls = 4;
+    r.cls = kClassNone;
     r.m = r.K = r.base = r.nv = r.pad_ = 0;
     r.vb0 = r.vb1 = r.ob0 = r.ob1 = 0;
     if (has) {
@@ -950,7 +955,7 @@ void k_fast(FrameDev f) {
       r.K = ihi - ilo;
       r.base = ilo;
       r.nv = G.nv;
-      r.cls = fast_class<COEF>(r.K, w * h);
+      r.cls = fast_class<COEF, ENC>(r.K, w * h);
       const long long pix = (long long)(iby * f.b) * G.W + ibx * f.b;
       r.vb0 = ilo;
       r.ob0 = G.out_off[0] + pix;
@@ -963,8 +968,8 @@ void k_fast(FrameDev f) {
     items[tid] = r;
     // Blocks the waves do not take: decoded by this workgroup at its end
     // (single-frame launches) or handed to the deferred pass (batches).
-    defer[tid] = (r.cls == 3 && f.tail_in_wg) ? 1 : 0;
-    if (r.cls == 3 && !f.tail_in_wg) push_deferred(f, blockIdx.y, r.m, r.K, w, h);
+    defer[tid] = (r.cls == kClassDefer && f.tail_in_wg) ? 1 : 0;
+    if (r.cls == kClassDefer && !f.tail_in_wg) push_deferred(f, blockIdx.y, r.m, r.K, w, h);
   }
   __syncthreads();
   // Bin by size class so that every wave solves blocks of one class.
@@ -982,7 +987,7 @@ void k_fast(FrameDev f) {
   const int lane = tid & 63, wv = tid >> 6;
   const int gi = lane >> 4, t = lane & 15;
   const int slot = order[wv * kWaveItems + gi];
-  const bool ok = items[slot].cls < 3;
+  const bool ok = items[slot].cls < kClassDefer;
   int kw = ok ? items[slot].K : 0, nvw = ok ? items[slot].nv : 0;
   for (int o = 32; o > 0; o >>= 1) {
     kw = max(kw, __shfl_xor(kw, o));
@@ -998,7 +1003,8 @@ void k_fast(FrameDev f) {
       else if (Kw <= 23) fast_coef_stage<24>(f, items, slot, ok, t, gi, w, h, G, st);
       else fast_coef_stage<32>(f, items, slot, ok, t, gi, w, h, G, st);
     } else {
-      if (Kw <= 15) solved = fast_solve<16>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
+      if (ENC && Kw <= 7) solved = fast_solve<8>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
+      else if (Kw <= 15) solved = fast_solve<16>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
       else if (Kw <= 23) solved = fast_solve<24>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
       else solved = fast_solve<32>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
     }
@@ -1017,7 +1023,8 @@ void k_fast(FrameDev f) {
     for (int g = 0; g < kWaveItems; ++g) okmask |= ((em >> (16 * g)) & 1ull) ? (1u << g) : 0u;
     const long long ob0 = items[slot].ob0, ob1 = items[slot].ob1;
     if constexpr (ENC) {
-      if (Kw <= 15) fast_encode_store<16>(f, items, slot, eval, t, gi, G, st);
+      if (Kw <= 7) fast_encode_store<8>(f, items, slot, eval, t, gi, G, st);
+      else if (Kw <= 15) fast_encode_store<16>(f, items, slot, eval, t, gi, G, st);
       else if (Kw <= 23) fast_encode_store<24>(f, items, slot, eval, t, gi, G, st);
       else fast_encode_store<32>(f, items, slot, eval, t, gi, G, st);
     } else if (okmask) {

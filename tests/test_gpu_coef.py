@@ -68,7 +68,7 @@ CASES = {
     "b8_gray_ragged": lambda: synth.random_frame(37, 21, synth.GRAY, 8, (0.05, 0.5), seed=45),
     # every K class: 0, 1, the staged limits (31 / 103), beyond them, w*h
     "b16_counts": lambda: _dense_frame(16 * 5 + 9, 16 * 3 + 5, synth.YUV420, 16,
-                                       lambda k, n: min(n, [0, 1, 15, 16, 31, 32, 60, n, n - 1, 200][k % 10]), 46),
+                                       lambda k, n: min(n, [0, 1, 15, 16, 31, 32, 60, n, n - 1, 200, 7, 8][k % 12]), 46),
     "b32_counts": lambda: _dense_frame(32 * 4 + 11, 32 * 2 + 7, synth.YUV420, 32,
                                        lambda k, n: min(n, [0, 1, 63, 64, 103, 104, 300, n, n - 1][k % 9]), 47),
 }

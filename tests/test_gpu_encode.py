@@ -67,7 +67,7 @@ CASES = {
     "b16_counts": lambda: _dense_frame(16 * 5 + 9, 16 * 3 + 5, synth.YUV420, 16,
                                        lambda k, n: min(n, [0, 1, 15, 16, 31, 32, 60, n, n - 1, 200][k % 10]), 66),
     "b8_counts": lambda: _dense_frame(8 * 6 + 3, 8 * 3 + 5, synth.YUV420, 8,
-                                      lambda k, n: min(n, [0, 1, 6, 31, 32, n, n - 1][k % 7]), 67),
+                                      lambda k, n: min(n, [0, 1, 6, 31, 32, n, n - 1, 7, 8][k % 9]), 67),
     "b32_counts": lambda: _dense_frame(32 * 3 + 11, 32 * 2 + 7, synth.GRAY, 32,
                                        lambda k, n: min(n, [0, 1, 63, 96, 97, 300, n, n - 1][k % 8]), 68),
 }

@@ -101,10 +101,10 @@ def _custom_frame(W, H, b, counts_fn, seed=0):
 def test_empty_full_and_extreme_blocks(dec, path):
     """K = 0 (u = 0), K = 1 (constant), K = w*h (u = r), K = w*h - 1 and a
     mix of every K class in one frame."""
-    choices = lambda k, n: [0, 1, n, n - 1, 2, 31, 32, 15, 16, 96, 97, n // 2][k % 12] if n > 97 else min(n, k % 5)
+    choices = lambda k, n: [0, 1, n, n - 1, 2, 31, 32, 15, 16, 96, 97, n // 2, 7, 8][k % 14] if n > 97 else min(n, k % 5)
     fr = _custom_frame(64 + 13, 48 + 7, 16, choices, seed=3)
     check(dec, fr, path=path)
-    fr = _custom_frame(40, 24, 8, lambda k, n: [0, 1, n, n - 1, 7, 31][k % 6], seed=4)
+    fr = _custom_frame(40, 24, 8, lambda k, n: [0, 1, n, n - 1, 7, 31, 8, 6][k % 8], seed=4)
     check(dec, fr, path=path)
 
 
