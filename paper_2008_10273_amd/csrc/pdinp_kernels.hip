@@ -851,18 +851,17 @@ __device__ __forceinline__ void fast_eval16(const FrameDev &f, const float *D, c
   }
 }
 
-template <int R>
+// The evaluation in the launch's dtype EV (a template parameter of k_fast:
+// each kernel holds one evaluation, which keeps its code small).
+template <int R, int EV>
 __device__ __forceinline__ void fast_eval_any(const FrameDev &f, const float *D, const FastStage &st,
                                               int lane, unsigned okmask, int nvw, int w, int h, int W,
                                               long long ob0, long long ob1) {
-  switch (f.eval) {
-    case 1: fast_eval16<R, 1>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1); break;
-    case 2: fast_eval16<R, 2>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1); break;
-    case 3: fast_eval16<R, 3>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1); break;
-    default:
-      if (f.b == 8) fast_eval8<R>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1);
-      else fast_eval<R>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1);
-      break;
+  if constexpr (EV != 0) {
+    fast_eval16<R, EV>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1);
+  } else {
+    if (f.b == 8) fast_eval8<R>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1);
+    else fast_eval<R>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1);
   }
 }
 
@@ -890,7 +889,8 @@ __device__ __forceinline__ void fast_encode_store(const FrameDev &f, const FastI
 
 // MODE 0: residual decode (solve, evaluate); 1: stored coefficients
 // (evaluate only); 2: coefficient encode (solve, quantise, no evaluation).
-template <int MODE>
+// EV: evaluation dtype (PDI_EVAL_*; encodes take 0).
+template <int MODE, int EV>
 __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(3, 8)))
 void k_fast(FrameDev f) {
   constexpr bool COEF = MODE == 1, ENC = MODE == 2;
@@ -1029,9 +1029,9 @@ void k_fast(FrameDev f) {
       else fast_encode_store<32>(f, items, slot, eval, t, gi, G, st);
     } else if (okmask) {
       const float *D = tabs + (COEF ? 0 : S.jt_floats);
-      if (Kw <= 15) fast_eval_any<16>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
-      else if (Kw <= 23) fast_eval_any<24>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
-      else fast_eval_any<32>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
+      if (Kw <= 15) fast_eval_any<16, EV>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
+      else if (Kw <= 23) fast_eval_any<24, EV>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
+      else fast_eval_any<32, EV>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
     }
   }
 
@@ -1149,9 +1149,24 @@ __global__ __launch_bounds__(kGenThreads) void k_coef_general(FrameDev f) {
 hipError_t launch_fast(const FrameDev &f, hipStream_t stream) {
   if (f.fast_wgs == 0) return hipSuccess;
   const size_t lds = sizeof(float) * (size_t)f.fast_lds;
-  if (f.coef) hipLaunchKernelGGL(k_fast<1>, dim3(f.fast_wgs, f.nframes), dim3(kFastThreads), lds, stream, f);
-  else if (f.enc) hipLaunchKernelGGL(k_fast<2>, dim3(f.fast_wgs, f.nframes), dim3(kFastThreads), lds, stream, f);
-  else hipLaunchKernelGGL(k_fast<0>, dim3(f.fast_wgs, f.nframes), dim3(kFastThreads), lds, stream, f);
+  const dim3 g(f.fast_wgs, f.nframes), b(kFastThreads);
+  if (f.enc) {
+    hipLaunchKernelGGL((k_fast<2, 0>), g, b, lds, stream, f);
+  } else if (f.coef) {
+    switch (f.eval) {
+      case 1: hipLaunchKernelGGL((k_fast<1, 1>), g, b, lds, stream, f); break;
+      case 2: hipLaunchKernelGGL((k_fast<1, 2>), g, b, lds, stream, f); break;
+      case 3: hipLaunchKernelGGL((k_fast<1, 3>), g, b, lds, stream, f); break;
+      default: hipLaunchKernelGGL((k_fast<1, 0>), g, b, lds, stream, f); break;
+    }
+  } else {
+    switch (f.eval) {
+      case 1: hipLaunchKernelGGL((k_fast<0, 1>), g, b, lds, stream, f); break;
+      case 2: hipLaunchKernelGGL((k_fast<0, 2>), g, b, lds, stream, f); break;
+      case 3: hipLaunchKernelGGL((k_fast<0, 3>), g, b, lds, stream, f); break;
+      default: hipLaunchKernelGGL((k_fast<0, 0>), g, b, lds, stream, f); break;
+    }
+  }
   return hipGetLastError();
 }
 
