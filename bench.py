@@ -259,6 +259,22 @@ def bench_frame(args, torch, binding, synth):
                      note="single-frame decodes of these frames in flight on several streams")
         log(f"overlapped on {args.nstreams} streams: {mfps:.1f} frames/s")
 
+    int8 = None
+    if B > 1:
+        # the same batched decode writing 8-bit planes clamp(rint(u)) (out_int8)
+        p8 = binding.default_params(eval_dtype=EVALS[args.eval], out_int8=1)
+        for _ in range(max(5, args.warmup // 4)):
+            dec.decode_batch(ds, p8, stream=stream)
+        s8 = max(10, args.steps // 2)
+        tm.start()
+        for _ in range(s8):
+            dec.decode_batch(ds, p8, stream=stream)
+        t8 = tm.stop()
+        assert dec.sync(stream) == 0, binding.pdi_last_error(dec.ctx)
+        int8 = dict(value=B * s8 / t8, unit="frames/s", ms_per_step=1e3 * t8 / s8,
+                    note="out_int8: 8-bit planes instead of FP32 (a quarter of the output bytes), same decode")
+        log(f"int8 output: {int8['value']:.1f} frames/s")
+
     plain = None
     if not args.no_plain:
         pp = binding.default_params(eval_dtype=EVALS[args.eval], path=binding.PDI_PATH_PLAIN)
@@ -290,7 +306,7 @@ def bench_frame(args, torch, binding, synth):
                        "blocks_per_workgroup": tune_b or None, "blocks_per_workgroup_single": tune or None},
                latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "mean": float(lat.mean()), "of": "one frame decoded alone"},
-               single_frame=single, error_vs_oracle=err, plain_path=plain, overlapped=multi,
+               single_frame=single, error_vs_oracle=err, plain_path=plain, overlapped=multi, int8_output=int8,
                roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS,
                          "traffic": TRAFFIC.get((args.config, B, tune_b)),
