@@ -326,10 +326,10 @@ class Decoder:
     def select(self, width: int, height: int, fmt: int, planes, chroma_shared: bool = True,
                sp: Optional[pdi_select_params] = None, stream=None, check=True):
         """select_mask on dense residual planes (a device FP32 tensor in the
-        decode output layout, or host arrays to upload).  Returns (rc, d)
-        with d a frame dict like upload()'s (block_ptr, pos, values on the
-        device; the frame record holds the geometry and, after sync(),
-        host copies via frame_from_selection)."""
+        decode output layout, or host arrays to upload).  Returns (rc, d):
+        d holds the geometry, the planes and the packed outputs on the
+        device (block_ptr, pos, values, sized for every pixel), ready once
+        the stream has run the call."""
         import numpy as np
         torch = self.torch
         dev = torch.device("cuda", self.device)
