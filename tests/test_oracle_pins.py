@@ -710,3 +710,31 @@ def test_homogeneous_invariants():
     one[3, 4] = True
     np.testing.assert_allclose(oracle.homogeneous_inpaint(one, f), f[3, 4], atol=1e-9)
     assert np.all(oracle.homogeneous_inpaint(np.zeros((H, W), bool), f) == 0)
+
+
+# ------------------------------------------------- property-based checks
+
+def test_routes_agree_on_random_blocks():
+    """Hypothesis-drawn blocks (any shape up to 7x7, any non-empty point
+    subset short of the whole block, any values): the plain definition
+    (banded Cholesky of Eq. 1) and the Green's route (Eqs. 2-4, dense LU of
+    the bordered system) give the same u, and c satisfies A u = M c - mean."""
+    hyp = pytest.importorskip("hypothesis")
+    st = hyp.strategies
+
+    @hyp.settings(max_examples=60, deadline=None, derandomize=True)
+    @hyp.given(st.integers(1, 7), st.integers(1, 7), st.data())
+    def check(w, h, data):
+        N = w * h
+        if N < 2:
+            return
+        K = data.draw(st.integers(1, N - 1))
+        pos = np.array(sorted(data.draw(st.lists(st.integers(0, N - 1), min_size=K, max_size=K, unique=True))),
+                       dtype=np.uint16)
+        r = np.array(data.draw(st.lists(st.floats(-64, 64, allow_nan=False), min_size=K, max_size=K)))
+        u1 = oracle.block_direct(w, h, pos, r)
+        c, a, u2 = oracle.block_green(w, h, pos, r)
+        np.testing.assert_allclose(u2[0], u1, atol=1e-8 * max(1.0, np.abs(r).max()))
+        _coef_identity(w, h, pos, c[0], a[0], u2[0])
+
+    check()
