@@ -23,9 +23,11 @@ constexpr int kWideStagePts = 112;  // points staged (multiple of 16, > kWideKMa
 constexpr int kTileN = 7;           // 16 x 16 tiles per side: n = K + 1 <= 104 <= 112
 constexpr int kTb = 20;             // row stride of the per-wave tile buffer (floats)
 static_assert(16 * kTileN == kWideStagePts && kWideKMax + 1 <= kWideStagePts, "tile cover");
-// Index of tile (i, j), i <= j, in the packed upper triangle.
-__host__ __device__ constexpr int tix(int i, int j) { return i * kTileN - i * (i - 1) / 2 + (j - i); }
-constexpr int kNumTiles = tix(kTileN - 1, kTileN - 1) + 1;
+// Index of tile (i, j), i <= j, in the packed upper triangle of TN x TN tiles.
+template <int TN>
+__host__ __device__ constexpr int tixn(int i, int j) { return i * TN - i * (i - 1) / 2 + (j - i); }
+template <int TN>
+constexpr int kNumTilesN = tixn<TN>(TN - 1, TN - 1) + 1;
 typedef int i4 __attribute__((ext_vector_type(4)));
 
 struct WidePoint {
@@ -109,7 +111,9 @@ __device__ __forceinline__ float tab_at(const float *Hc, int byte_off) {
 
 // Assemble, factor and solve the bordered system of one block; stage (x, y,
 // c) of the K points and a for the evaluation.  Returns false when the pivots
-// call for FP64 refinement (the general path refines).
+// call for FP64 refinement (the general path refines).  TN: tiles per side
+// at most (7: K <= 103; 4: K <= 63, fewer registers).
+template <int TN>
 __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb, int lane, int w, int h,
                                            const float *Hc, WideStage &st) {
   const int K = jb.K, n = K + 1, N = w * h, W1 = w + 1;
@@ -149,14 +153,14 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
   // < K, 1 in the border row and column, 0 at (K, K), identity past K.  G is
   // the sum of four quarter-scaled compact-table entries: (|dx|, |dy|) and
   // the reflections x_i + x_k + 1, y_i + y_k + 1 folded into [0, w], [0, h].
-  f4 T[kNumTiles], R[kTileN];
+  f4 T[kNumTilesN<TN>], R[TN];
   const int xcr = 4 * (2 * w - 1), ycr = 4 * (2 * h - 1) * W1, W4 = 4 * W1;
 #pragma unroll
-  for (int ti = 0; ti < kTileN; ++ti) {
+  for (int ti = 0; ti < TN; ++ti) {
     if (ti < NT) {
       const i4 rowp = *reinterpret_cast<const i4 *>(&st.xy[16 * ti + 4 * hi]);
 #pragma unroll
-      for (int tj = ti; tj < kTileN; ++tj) {
+      for (int tj = ti; tj < TN; ++tj) {
         if (tj < NT) {
           const int k = 16 * tj + lo, ck = st.xy[k];
           const int xk = ck & 0xffff, yk = ck >> 16;
@@ -173,7 +177,7 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
             const bool one = (i == K && k < K) || (k == K && i < K) || (i == k && i > K);
             t[r] = (i < K && k < K) ? g : (one ? 1.f : 0.f);
           }
-          T[tix(ti, tj)] = t;
+          T[tixn<TN>(ti, tj)] = t;
         }
       }
       const f4 rv = *reinterpret_cast<const f4 *>(&st.rv[lo & 1][16 * ti + 4 * hi]);
@@ -187,12 +191,12 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
   for (int r = 0; r < 4; ++r) ident[r] = (lo == 4 * hi + r) ? 1.f : 0.f;
   float dmin = 3.0e38f, dmax = 0.f;
 #pragma unroll
-  for (int p = 0; p < kTileN; ++p) {
+  for (int p = 0; p < TN; ++p) {
     if (p < NT) {
       // Row lo of A_pp in every lane.
       float e[16];
       {
-        const f4 t = T[tix(p, p)];
+        const f4 t = T[tixn<TN>(p, p)];
 #pragma unroll
         for (int r = 0; r < 4; ++r) st.tb[(4 * hi + r) * kTb + lo] = t[r];
         wave_sync();
@@ -230,30 +234,30 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
       }
       // lv is (L^-1)^T in accumulator layout.  Keep L^-1 itself (for the back
       // substitution) in place of A_pp, and the reciprocal pivots in LDS.
-      T[tix(p, p)] = mma_tn(lv, ident, f4{0.f, 0.f, 0.f, 0.f});
+      T[tixn<TN>(p, p)] = mma_tn(lv, ident, f4{0.f, 0.f, 0.f, 0.f});
       if (lo == 0) *reinterpret_cast<f4 *>(&st.dv[16 * p + 4 * hi]) = ds;
       // W_pj = L^-1 A_pj in place of A_pj for the trailing updates.
 #pragma unroll
-      for (int j = p + 1; j < kTileN; ++j)
-        if (j < NT) T[tix(p, j)] = mma_tn(lv, T[tix(p, j)], f4{0.f, 0.f, 0.f, 0.f});
+      for (int j = p + 1; j < TN; ++j)
+        if (j < NT) T[tixn<TN>(p, j)] = mma_tn(lv, T[tixn<TN>(p, j)], f4{0.f, 0.f, 0.f, 0.f});
       R[p] = mma_tn(lv, R[p], f4{0.f, 0.f, 0.f, 0.f});
       // A_ij -= W_pi^T D^-1 W_pj, r_i -= W_pi^T D^-1 r_p.
 #pragma unroll
-      for (int i = p + 1; i < kTileN; ++i) {
+      for (int i = p + 1; i < TN; ++i) {
         if (i < NT) {
           f4 x;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) x[r] = -ds[r] * T[tix(p, i)][r];
+          for (int r = 0; r < 4; ++r) x[r] = -ds[r] * T[tixn<TN>(p, i)][r];
 #pragma unroll
-          for (int j = i; j < kTileN; ++j)
-            if (j < NT) T[tix(i, j)] = mma_tn(x, T[tix(p, j)], T[tix(i, j)]);
+          for (int j = i; j < TN; ++j)
+            if (j < NT) T[tixn<TN>(i, j)] = mma_tn(x, T[tixn<TN>(p, j)], T[tixn<TN>(i, j)]);
           R[i] = mma_tn(x, R[p], R[i]);
         }
       }
       // W_pj^T (= W_pj^T I) kept for the back substitution.
 #pragma unroll
-      for (int j = p + 1; j < kTileN; ++j)
-        if (j < NT) T[tix(p, j)] = mma_tn(T[tix(p, j)], ident, f4{0.f, 0.f, 0.f, 0.f});
+      for (int j = p + 1; j < TN; ++j)
+        if (j < NT) T[tixn<TN>(p, j)] = mma_tn(T[tixn<TN>(p, j)], ident, f4{0.f, 0.f, 0.f, 0.f});
     }
   }
   const bool need = (f.refine == 2) || (f.refine == 1 && !(dmin >= f.tau * dmax));
@@ -262,13 +266,13 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
 
   // Back substitution: x_p = L_p^-T D_p^-1 (r_p - sum_{j > p} W_pj x_j).
 #pragma unroll
-  for (int p = kTileN - 1; p >= 0; --p) {
+  for (int p = TN - 1; p >= 0; --p) {
     if (p < NT) {
       f4 y = R[p];
 #pragma unroll
-      for (int j = p + 1; j < kTileN; ++j) {
+      for (int j = p + 1; j < TN; ++j) {
         if (j < NT) {
-          f4 wt = T[tix(p, j)];
+          f4 wt = T[tixn<TN>(p, j)];
 #pragma unroll
           for (int r = 0; r < 4; ++r) wt[r] = -wt[r];
           y = mma_tn(wt, R[j], y);
@@ -277,7 +281,7 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
       const f4 dv = *reinterpret_cast<const f4 *>(&st.dv[16 * p + 4 * hi]);
 #pragma unroll
       for (int r = 0; r < 4; ++r) y[r] *= dv[r];
-      R[p] = mma_tn(T[tix(p, p)], y, f4{0.f, 0.f, 0.f, 0.f});
+      R[p] = mma_tn(T[tixn<TN>(p, p)], y, f4{0.f, 0.f, 0.f, 0.f});
     }
   }
 
@@ -285,7 +289,7 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
   // a = x_K; staged points past K keep c = 0.
   bool fin = true;
 #pragma unroll
-  for (int p = 0; p < kTileN; ++p) {
+  for (int p = 0; p < TN; ++p) {
     if (p < NT) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -547,8 +551,15 @@ __global__ __launch_bounds__(256) void k_bin(FrameDev f) {
 
 // One block per wave, WAVES waves per workgroup (the workgroup shares the
 // shape's tables in LDS); each wave takes the next block of its queue.
-template <int WAVES, bool COEF>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, COEF ? 3 : 2))) void k_wide(FrameDev f) {
+// PART 0 takes the whole queue; batched residual decodes split it in two launches:
+// PART 1 the bins of K >= kBinK1 (up to 7 tiles per side), PART 2 the bins
+// below (at most 4 tiles: the smaller register file lets more waves share a
+// SIMD and hide the latency of the elimination's dependent steps).
+template <int WAVES, bool COEF, int PART>
+__global__ __launch_bounds__(64 * WAVES)
+__attribute__((amdgpu_waves_per_eu(PART == 2 ? 3 : 2, COEF ? 3 : (PART == 2 ? 4 : 2)))) void k_wide(FrameDev f) {
+  constexpr int TN = PART == 2 ? 4 : kTileN;
+  static_assert(PART != 2 || 16 * 4 >= kBinK1, "the small bins fit 4 tiles");
   extern __shared__ __attribute__((aligned(16))) float tabs[];  // Hc | Dw | Dh | lam of the shape
   __shared__ WideStage stage[WAVES];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -559,6 +570,15 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, C
   const QueueDev Q = f.q[qi];
   const ShapeDev S = f.s[Q.shape];
   const int w = S.w, h = S.h;
+  // Queue position of this wave's block: workgroups start in index order, so
+  // the first ones take the large-K blocks at the front of the queue.
+  const int fi = blockIdx.y;
+  const int32_t *bp = f.fp[fi].block_ptr;
+  const int *cnt = f.counters + kQueueCounters + 4 * (kMaxShapes * fi + qi);
+  const int n0 = cnt[0], n1 = cnt[1], n2 = cnt[2], n3 = cnt[3];
+  const int p_lo = PART == 2 ? n0 + n1 : 0, p_hi = PART == 1 ? n0 + n1 : n0 + n1 + n2 + n3;
+  const int p0 = p_lo + (wg - Q.first_wg) * WAVES;  // the workgroup's first position
+  if (p0 >= p_hi || p0 >= Q.count) return;          // uniform: no wave of this workgroup has a block
   {  // stored-coefficient decodes need the evaluation's matrices only
     const int n4 = ((COEF ? 0 : S.jt_floats) + 3 * kDct32Floats) >> 2;
     const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + S.fast + (COEF ? S.jt_floats : 0));
@@ -566,15 +586,8 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, C
     for (int i = tid; i < n4; i += 64 * WAVES) dst[i] = src[i];
   }
   __syncthreads();  // the only workgroup barrier: waves are independent from here on
-
-  // Queue position of this wave's block: workgroups start in index order, so
-  // the first ones take the large-K blocks at the front of the queue.
-  const int p = (wg - Q.first_wg) * WAVES + wv;
-  const int fi = blockIdx.y;
-  const int32_t *bp = f.fp[fi].block_ptr;
-  const int *cnt = f.counters + kQueueCounters + 4 * (kMaxShapes * fi + qi);
-  const int n0 = cnt[0], n1 = cnt[1], n2 = cnt[2], n3 = cnt[3];
-  if (p >= Q.count || n0 + n1 > Q.count || n2 + n3 > Q.count) return;
+  const int p = p0 + wv;
+  if (p >= p_hi || p >= Q.count || n0 + n1 > Q.count || n2 + n3 > Q.count) return;
   const int *h0 = f.binlist + 2 * f.n_items * fi + 2 * Q.base, *h1 = h0 + Q.count;
   int m;
   if (p < n0) m = h0[p];
@@ -612,7 +625,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, C
     jb.cidx1 = G.cbase[1] + bl;
     wide_coef_stage(f, jb, lane, w, h, st);
   } else {
-    const bool solved = wide_solve(f, jb, lane, w, h, tabs, st);
+    const bool solved = wide_solve<TN>(f, jb, lane, w, h, tabs, st);
     if (!solved) {
       if (lane == 0) push_deferred(f, fi, m, K, w, h);
       return;
@@ -634,18 +647,39 @@ hipError_t launch_wide(const FrameDev &f, hipStream_t stream) {
   if (f.coef) {
     hipLaunchKernelGGL(k_bin<true>, bgrid, dim3(256), 0, stream, f);
     switch (f.ipw) {
-      case 1: hipLaunchKernelGGL((k_wide<1, true>), grid, dim3(64), lds, stream, f); break;
-      case 2: hipLaunchKernelGGL((k_wide<2, true>), grid, dim3(128), lds, stream, f); break;
-      case 4: hipLaunchKernelGGL((k_wide<4, true>), grid, dim3(256), lds, stream, f); break;
+      case 1: hipLaunchKernelGGL((k_wide<1, true, 0>), grid, dim3(64), lds, stream, f); break;
+      case 2: hipLaunchKernelGGL((k_wide<2, true, 0>), grid, dim3(128), lds, stream, f); break;
+      case 4: hipLaunchKernelGGL((k_wide<4, true, 0>), grid, dim3(256), lds, stream, f); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     hipLaunchKernelGGL(k_bin<false>, bgrid, dim3(256), 0, stream, f);
-    switch (f.ipw) {
-      case 1: hipLaunchKernelGGL((k_wide<1, false>), grid, dim3(64), lds, stream, f); break;
-      case 2: hipLaunchKernelGGL((k_wide<2, false>), grid, dim3(128), lds, stream, f); break;
-      case 4: hipLaunchKernelGGL((k_wide<4, false>), grid, dim3(256), lds, stream, f); break;
-      default: return hipErrorInvalidValue;
+    if (f.nframes > 1) {
+      // batches: the large-K bins first (longest solves start first), then
+      // the rest with the smaller kernel.  A single frame keeps one launch:
+      // with few blocks the second launch would only add its latency.
+      switch (f.ipw) {
+        case 1:
+          hipLaunchKernelGGL((k_wide<1, false, 1>), grid, dim3(64), lds, stream, f);
+          hipLaunchKernelGGL((k_wide<1, false, 2>), grid, dim3(64), lds, stream, f);
+          break;
+        case 2:
+          hipLaunchKernelGGL((k_wide<2, false, 1>), grid, dim3(128), lds, stream, f);
+          hipLaunchKernelGGL((k_wide<2, false, 2>), grid, dim3(128), lds, stream, f);
+          break;
+        case 4:
+          hipLaunchKernelGGL((k_wide<4, false, 1>), grid, dim3(256), lds, stream, f);
+          hipLaunchKernelGGL((k_wide<4, false, 2>), grid, dim3(256), lds, stream, f);
+          break;
+        default: return hipErrorInvalidValue;
+      }
+    } else {
+      switch (f.ipw) {
+        case 1: hipLaunchKernelGGL((k_wide<1, false, 0>), grid, dim3(64), lds, stream, f); break;
+        case 2: hipLaunchKernelGGL((k_wide<2, false, 0>), grid, dim3(128), lds, stream, f); break;
+        case 4: hipLaunchKernelGGL((k_wide<4, false, 0>), grid, dim3(256), lds, stream, f); break;
+        default: return hipErrorInvalidValue;
+      }
     }
   }
   return hipGetLastError();
