@@ -295,7 +295,8 @@ def bench_frame(args, torch, binding, synth):
     achieved = ab / t_step / 1e9
     copy_gbs = copy_bandwidth(torch, stream=stream)
     log(f"copy kernel: {copy_gbs:.0f} GB/s")
-    kern = "k_fast" if cfg["block_size"] <= 16 else "k_wide"
+    kern = "k_fast" if cfg["block_size"] <= 16 else ("k_bin + k_wide (bins K >= 64, then K < 64)" if B > 1 else
+                                                     "k_bin + k_wide")
     rec = dict(metric=METRIC, value=fps, unit="frames/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=1e3 * t_step, higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="f32" if args.eval == "fp32" else f"f32 solve, {args.eval} eval", data="synthetic",
