@@ -56,7 +56,7 @@ EVALS = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16x2": 3}
 # launch shape the counters were taken on (null after a kernel change, or
 # when the autotuned launch choice differs).
 # (config, frames per step, launch choice): bytes per launch
-TRAFFIC = {(1, 32, 16): 442017721}
+TRAFFIC = {(1, 32, 16): 441958329, (2, 32, 2): 464640229, (2, 32, 4): 459408434}
 # HBM bytes of one finest-level k_hd_cg iteration of config 6 (same counters)
 TRAFFIC_HD_ITER = 85391197
 
