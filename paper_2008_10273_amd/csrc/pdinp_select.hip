@@ -50,7 +50,7 @@ __device__ __forceinline__ unsigned long long corner_bits(const SelStage &st, in
   return __ballot(k && valid);
 }
 
-// Value of x in lane `src` (uniform; src a constant after unrolling).
+// Value of x in lane `src` (src uniform across the wave).
 __device__ __forceinline__ float lane_f(float x, int src) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), src));
 }
@@ -110,7 +110,8 @@ __device__ __forceinline__ void sel_solve(SelStage &st, int lane, int K, int nv,
   }
 }
 
-__global__ __launch_bounds__(kSelThreads) void k_select8(FrameDev f) {
+// At most 96 VGPRs (5 waves per SIMD): the 64-column solve still fits without spills.
+__global__ __launch_bounds__(kSelThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_select8(FrameDev f) {
   __shared__ SelStage stage[kSelWaves];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int m = blockIdx.x * kSelWaves + wv;  // mask block
@@ -148,21 +149,43 @@ __global__ __launch_bounds__(kSelThreads) void k_select8(FrameDev f) {
     // points in ascending pixel order
     if ((bits >> lane) & 1ull) st.pt[__popcll(bits & ((1ull << lane) - 1ull))] = lane;
     wave_sync();
-    if (K < 16) sel_solve<16>(st, lane, K, nv, w, h);
-    else if (K < 32) sel_solve<32>(st, lane, K, nv, w, h);
-    else sel_solve<64>(st, lane, K, nv, w, h);
+    // (this order of the tests keeps the kernel within 96 VGPRs without spills)
+    if (K >= 32) sel_solve<64>(st, lane, K, nv, w, h);
+    else if (K >= 16) sel_solve<32>(st, lane, K, nv, w, h);
+    else if (K >= 8) sel_solve<16>(st, lane, K, nv, w, h);
+    else sel_solve<8>(st, lane, K, nv, w, h);
     wave_sync();
-    // Eq. 2 at every pixel and its squared error
+    // Eq. 2 at every pixel and its squared error.  Point i's pixel and
+    // coefficients sit in lane i's registers and are broadcast by readlane;
+    // each Green's function value serves both value planes.  Steps go in
+    // fours: lanes K .. K4-1 hold pixel 0 and zero coefficients, so the
+    // padding adds exact zeros (K4 <= 64 as K <= 63).
+    const int myq = lane < K ? st.pt[lane] : 0;
+    const float myc0 = lane < K ? st.c[0][lane] : 0.f;
+    const float myc1 = lane < K ? st.c[1][lane] : 0.f;
+    const int K4 = (K + 3) & ~3;
     float err = 0.f;
     if (valid) {
-      for (int v = 0; v < nv; ++v) {
-        float u = 0.f;
-        for (int i = 0; i < K; ++i) {
-          const int q = st.pt[i];
-          u = fmaf(st.c[v][i], green_tab(st.tab, w, h, px, py, q & 7, q >> 3), u);
+      float u0 = 0.f, u1 = 0.f;
+      for (int i0 = 0; i0 < K4; i0 += 4) {
+        float gv[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int q = __builtin_amdgcn_readlane(myq, i0 + t);
+          gv[t] = green_tab(st.tab, w, h, px, py, q & 7, q >> 3);
         }
-        const float d = (u + st.a[v]) - st.r[v][lane];
-        err = fmaf(d, d, err);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) u0 = fmaf(lane_f(myc0, i0 + t), gv[t], u0);
+        if (nv > 1) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) u1 = fmaf(lane_f(myc1, i0 + t), gv[t], u1);
+        }
+      }
+      const float d0 = (u0 + st.a[0]) - st.r[0][lane];
+      err = d0 * d0;
+      if (nv > 1) {
+        const float d1 = (u1 + st.a[1]) - st.r[1][lane];
+        err = fmaf(d1, d1, err);
       }
     }
     // summed-area table: prefix along x inside each row of 8 lanes, then along y
