@@ -264,7 +264,9 @@ typedef struct {
     double tol;       /* stop the finest level when |r|_2 <= tol |b|_2 (b: right-hand side of the
                          unknowns' system); in (0, 1), default 1e-6 */
     int32_t max_iter; /* CG iterations per level at most, in [1, 65536]; default 4000 */
-    int32_t check;    /* iterations queued between host read-backs, in [1, 1024]; default 8.
+    int32_t check;    /* iterations queued between host read-backs at most, in [1, 1024];
+                         default 8 (fewer where the norms' decay, or the count of the
+                         previous call on this plane size, says fewer are left).
                          Convergence is tested on the device before every iteration and
                          the iterations queued past it do nothing, so a level stops at the
                          first iteration that meets tol whatever check is */

@@ -73,6 +73,9 @@ struct DiffWork {
   double *host = nullptr;  // pinned: the slots of GAM[i..] and BB, read back for the convergence test
   int host_cap = 0;        // doubles in host
   hipEvent_t ev = nullptr; // marks the completion of the read-back in flight
+  // Iterations each level took in the previous solve of this plane size (0:
+  // none yet); a guess that sizes the first batches of launches only.
+  int hint[kMaxLevels] = {0};
 };
 
 static void free_diff(DiffWork &d) {
@@ -1135,8 +1138,11 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
       }
       return r;
     };
+    // First batch: the previous solve's count for this level when there is
+    // one (the read-back after it then already holds the converged norm).
+    const int hint = D.hint[l];
     if (e == hipSuccess) e = read_back();  // GAM[0]
-    if (e == hipSuccess) e = queue(P.check);
+    if (e == hipSuccess) e = queue(hint > 0 ? std::min(P.check, hint) : P.check);
     double g_prev = -1.0;  // last norm examined and its iteration
     int i_prev = -1;
     while (e == hipSuccess) {
@@ -1167,7 +1173,8 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
         break;
       }
       // Next batch: the iterations the norm's decay so far says are left
-      // beyond the batch in flight (+1), at most P.check, at least 1.
+      // beyond the batch in flight (+1), at most P.check, at least 1; with
+      // no decay seen yet (only GAM[0]), those the hint leaves (+1).
       int next = P.check;
       {
         const double g0 = i_prev >= 0 ? g_prev : g_first;
@@ -1176,6 +1183,8 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
           const double rate = std::log(g / g0) / span;  // per iteration, < 0
           const double left = std::log(tol2 * bb / g) / rate - (double)(it - hi);
           next = std::max(1, std::min(P.check, (int)std::ceil(left) + 1));
+        } else if (span == 0 && hint > 0) {
+          next = std::max(1, std::min(P.check, hint - it + 1));
         }
       }
       g_prev = g;
@@ -1186,6 +1195,7 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
       if (e == hipSuccess) e = queue(next);
     }
     if (!done && its == 0) its = it;
+    D.hint[l] = done ? std::max(1, its) : 0;
     if (l == 0) {
       its0 = its;
       converged = done;

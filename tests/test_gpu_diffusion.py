@@ -125,3 +125,23 @@ def test_homogeneous_stop_independent_of_check(dec):
     for its, u in res[1:]:
         assert abs(its - res[0][0]) <= 1
         np.testing.assert_allclose(u, res[0][1], atol=1e-3)
+
+
+def test_homogeneous_hint_from_previous_call(dec):
+    """The launch batches of a level are sized from the iteration count of
+    the previous call on the same plane size; a call whose mask needs far
+    more or far fewer iterations than that guess still solves to tol."""
+    W, H = 200, 136
+    ma, fa = synth.intra_frame(W, H, 0.04, 11)
+    mb, fb = synth.intra_frame(W, H, 0.005, 12)   # sparser: more iterations
+    print(f"case hd hint {W}x{H} masks 4% / 0.5% / 4%", flush=True)
+    its_a = []
+    for m, f in ((ma, fa), (mb, fb), (ma, fa), (ma, fa)):
+        rc, u, its = dec.inpaint(m, f)
+        assert rc == 0
+        ref = oracle.homogeneous_inpaint(m, f.astype(np.float64))
+        assert np.abs(u.cpu().numpy().astype(np.float64) - ref).max() <= HD_TOL
+        if m is ma:
+            its_a.append(its)
+    print("  iterations of the 4% mask", its_a, flush=True)
+    assert max(its_a) - min(its_a) <= 1
