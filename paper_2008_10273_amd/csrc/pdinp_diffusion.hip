@@ -217,17 +217,20 @@ __global__ __launch_bounds__(kHdThreads) void k_hd_cg(const uint8_t *m, int W, i
     const int i = y * W + x;
     bool free_px = false;
     __syncthreads();  // the previous tile's LDS reads are done
-    // own pixel: coalesced rows of 64
+    // own pixel: coalesced rows of 64.  The vectors are read whatever the
+    // mask says (zero at known pixels), so that no load waits for the mask.
     float rn = 0.f;
     if (in) {
-      free_px = !m[i];
+      const bool known = m[i];
+      const float rv = ri[i], wv = wi[i], uv = u[i];
+      const float pv = first ? 0.f : p[i], sv = first ? 0.f : si[i];
+      free_px = !known;
       float pn = 0.f, sn = 0.f;
       if (free_px) {
-        const float rv = ri[i], wv = wi[i];
-        pn = first ? rv : fmaf(beta, p[i], rv);
-        sn = first ? wv : fmaf(beta, si[i], wv);
+        pn = first ? rv : fmaf(beta, pv, rv);
+        sn = first ? wv : fmaf(beta, sv, wv);
         rn = fmaf(-alpha, sn, rv);
-        u[i] = fmaf(alpha, pn, u[i]);
+        u[i] = fmaf(alpha, pn, uv);
       }
       p[i] = pn;
       so[i] = sn;
@@ -247,9 +250,10 @@ __global__ __launch_bounds__(kHdThreads) void k_hd_cg(const uint8_t *m, int W, i
       float v = 0.f;
       if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
         const int j = gy * W + gx;
-        if (!m[j]) {
-          const float rv = ri[j], wv = wi[j];
-          const float sn = first ? wv : fmaf(beta, si[j], wv);
+        const bool known = m[j];
+        const float rv = ri[j], wv = wi[j], sv = first ? 0.f : si[j];
+        if (!known) {
+          const float sn = first ? wv : fmaf(beta, sv, wv);
           v = fmaf(-alpha, sn, rv);
         }
       }
