@@ -180,8 +180,10 @@ struct TileWalk {
 // the stencil; r, w and s are read at the halo, so they are double-buffered
 // (ri, wi, si in, ro, wo, so out); u and p are updated in place.  All
 // vectors are zero on the mask.  Workgroup 0 records alpha in ALPHA[i].
-// Once g_i <= tol2 |b|^2 (BB) every workgroup returns at once, leaving
-// GAM[i+1] = 0, so the launches queued after convergence do nothing.
+// Once g_i <= tol2 max(|b|^2, g_0) (BB; g_0 = |r_0|^2 of the level's start,
+// which keeps the test reachable when b = 0 but the start is not) every
+// workgroup returns at once, leaving GAM[i+1] = 0, so the launches queued
+// after convergence do nothing.
 __global__ __launch_bounds__(kHdThreads) void k_hd_cg(const uint8_t *m, int W, int H, double *GAM, double *DEL,
                                                       double *ALPHA, const double *BB, double tol2, int it, float *u, float *p,
                                                       const float *ri, const float *wi, const float *si, float *ro,
@@ -192,7 +194,7 @@ __global__ __launch_bounds__(kHdThreads) void k_hd_cg(const uint8_t *m, int W, i
   float alpha = 0.f, beta = 0.f;
   {
     const double g = slot_sum(GAM + it * kHdSlots), d = slot_sum(DEL + it * kHdSlots);
-    if (g <= tol2 * slot_sum(BB)) return;  // converged (uniform over the grid)
+    if (g <= tol2 * fmax(slot_sum(BB), slot_sum(GAM))) return;  // converged (uniform over the grid)
     double a = 0.0, bt = 0.0;
     if (it == 0) {
       if (d > 0.0) a = g / d;

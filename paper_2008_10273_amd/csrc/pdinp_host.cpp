@@ -1145,6 +1145,7 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
     if (e == hipSuccess) e = queue(hint > 0 ? std::min(P.check, hint) : P.check);
     double g_prev = -1.0;  // last norm examined and its iteration
     int i_prev = -1;
+    double g0 = -1.0;      // |r_0|^2 of the level (the first read-back holds it)
     while (e == hipSuccess) {
       e = hipEventSynchronize(D.ev);
       if (e != hipSuccess) break;
@@ -1161,6 +1162,10 @@ int inpaint_homogeneous(pdi_ctx *c, int width, int height, const uint8_t *mask, 
           break;
         }
         if (i == 0) g_first = g;
+        if (lo + i == 0) g0 = g;
+        // the device's test: relative to |b| or, when the start is worse than
+        // zero (|r_0| > |b|, e.g. b = 0), to |r_0|
+        bb = std::max(bb, g0);
         if (g <= tol2 * bb) {
           done = true;
           its = lo + i;  // the launches after it did nothing

@@ -159,28 +159,38 @@ __global__ __launch_bounds__(kSelThreads) __attribute__((amdgpu_waves_per_eu(5, 
     // coefficients sit in lane i's registers and are broadcast by readlane;
     // each Green's function value serves both value planes.  Steps go in
     // fours: lanes K .. K4-1 hold pixel 0 and zero coefficients, so the
-    // padding adds exact zeros (K4 <= 64 as K <= 63).
+    // padding adds exact zeros (K4 <= 64 as K <= 63).  Lane i holds point i
+    // whatever its own pixel is, so the broadcasts run with the whole wave
+    // active (uniform loop, scalar results); only the lanes of in-block
+    // pixels then evaluate.
     const int myq = lane < K ? st.pt[lane] : 0;
     const float myc0 = lane < K ? st.c[0][lane] : 0.f;
     const float myc1 = lane < K ? st.c[1][lane] : 0.f;
     const int K4 = (K + 3) & ~3;
-    float err = 0.f;
-    if (valid) {
-      float u0 = 0.f, u1 = 0.f;
-      for (int i0 = 0; i0 < K4; i0 += 4) {
+    float u0 = 0.f, u1 = 0.f;
+    for (int i0 = 0; i0 < K4; i0 += 4) {
+      int q[4];
+      float c0[4], c1[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        q[t] = __builtin_amdgcn_readlane(myq, i0 + t);
+        c0[t] = lane_f(myc0, i0 + t);
+        c1[t] = lane_f(myc1, i0 + t);
+      }
+      if (valid) {
         float gv[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int q = __builtin_amdgcn_readlane(myq, i0 + t);
-          gv[t] = green_tab(st.tab, w, h, px, py, q & 7, q >> 3);
-        }
+        for (int t = 0; t < 4; ++t) gv[t] = green_tab(st.tab, w, h, px, py, q[t] & 7, q[t] >> 3);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) u0 = fmaf(lane_f(myc0, i0 + t), gv[t], u0);
+        for (int t = 0; t < 4; ++t) u0 = fmaf(c0[t], gv[t], u0);
         if (nv > 1) {
 #pragma unroll
-          for (int t = 0; t < 4; ++t) u1 = fmaf(lane_f(myc1, i0 + t), gv[t], u1);
+          for (int t = 0; t < 4; ++t) u1 = fmaf(c1[t], gv[t], u1);
         }
       }
+    }
+    float err = 0.f;
+    if (valid) {
       const float d0 = (u0 + st.a[0]) - st.r[0][lane];
       err = d0 * d0;
       if (nv > 1) {

@@ -145,3 +145,26 @@ def test_homogeneous_hint_from_previous_call(dec):
             its_a.append(its)
     print("  iterations of the 4% mask", its_a, flush=True)
     assert max(its_a) - min(its_a) <= 1
+
+
+def test_homogeneous_zero_rhs_with_nonzero_start(dec):
+    """A known cluster whose ring is 0 and whose centre is not: every unknown
+    pixel's known neighbours are 0, so the right-hand side b of the
+    unknowns' system is 0 and the exact solution is u = 0 off the mask
+    (the oracle agrees).  The coarse level restricted from the cluster is
+    not zero, so the finest level starts away from the solution; the stop
+    test, relative to max(|b|, |r_0|), still ends the solve (a test
+    relative to |b| alone never would)."""
+    W = H = 128
+    m = np.zeros((H, W), bool)
+    f = np.zeros((H, W), np.float32)
+    m[61:64, 61:64] = True
+    f[62, 62] = 10.0
+    print("case hd zero rhs 128x128", flush=True)
+    rc, u, its = dec.inpaint(m, f)
+    assert rc == 0 and its >= 1
+    u = u.cpu().numpy()
+    ref = oracle.homogeneous_inpaint(m, f.astype(np.float64))
+    assert np.abs(ref[~m]).max() == 0.0
+    assert np.abs(u[~m]).max() <= HD_TOL
+    assert np.array_equal(u[m], f[m])

@@ -247,7 +247,12 @@ def test_eval_dtypes(dec, ev, case):
 
 
 def test_eval_dtypes_config1(dec):
-    """FullHD frame: split BF16 within the bars; FP16 within 0.5 grey levels."""
+    """FullHD frame: split BF16 meets both acceptance bars (max-abs <= 0.5,
+    identical 8-bit rounding on >= 99.9 % of pixels).  FP16 operands meet
+    the max-abs bar but NOT the rounding clause: their rounding (2^-11
+    relative on values up to 64) moves ~0.4 % of pixels across a rounding
+    edge, so FP16 is a reduced-precision option outside the acceptance bar;
+    this test pins that reading (FP16 disagrees on between 0.1 % and 2 %)."""
     fr = synth.config_frame(1, keep_fields=False)
     ref = oracle.decode_flat(fr)
     for ev in (1, 3):
@@ -257,6 +262,8 @@ def test_eval_dtypes_config1(dec):
         assert mx <= EVAL_TOL[ev] and mx <= 0.5
         if ev == 3:
             assert agree >= 0.999
+        else:
+            assert 0.98 <= agree < 0.999
 
 
 def test_eval_dtypes_config2(dec):

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+import test_gpu_select
 from paper_2008_10273_amd import synth
 
 torch = pytest.importorskip("torch")
@@ -72,19 +73,12 @@ def test_sweep_select(dec, W, H, fmt, b, dens, shared, seed):
     print(f"case sweep select {W}x{H} fmt={fmt} shared={shared}", flush=True)
     rc, d = dec.select(W, H, fmt, planes, shared, binding.select_params(*T))
     assert dec.sync() == 0
-    bp = d["block_ptr"].cpu().numpy().astype(np.int64)
-    pos = d["pos"].cpu().numpy().view(np.uint16).astype(np.int64)
-    ref = oracle.select_mask(W, H, fmt, 8, planes, shared, T)
-    dims = synth.plane_dims(W, H, fmt)
+    # every block whose mask differs from the oracle's must equal the
+    # oracle's mask at a slightly shifted threshold (a decision within FP32
+    # reach of the threshold), as in the dedicated selection tests
+    masks, gathered = test_gpu_select._host_masks(d, W, H, fmt, shared)
+    test_gpu_select._compare(planes, W, H, fmt, shared, T, masks, max_frac=0.02)
     groups = [[0]] if fmt == synth.GRAY else ([[0], [1, 2]] if shared else [[0], [1], [2]])
-    m, nflip, nb = 0, 0, 0
     for gi, gp in enumerate(groups):
-        pw, ph = dims[gp[0]]
-        for (x0, y0, w, h) in synth.block_grid(pw, ph, 8):
-            p = pos[bp[m]:bp[m + 1]]
-            mk = np.zeros((h, w), bool)
-            mk[p // w, p % w] = True
-            nflip += not np.array_equal(mk, ref[gi][y0:y0 + h, x0:x0 + w])
-            nb += 1
-            m += 1
-    assert nflip <= max(1, 0.02 * nb), (nflip, nb)
+        for pl in gp:
+            assert np.array_equal(gathered[gi][pl][masks[gi]], planes[pl][masks[gi]])

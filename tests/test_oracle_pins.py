@@ -96,6 +96,46 @@ def test_eigenvalues_are_operator_spectrum():
     np.testing.assert_allclose(got, mu, atol=1e-12)
 
 
+@pytest.mark.parametrize("w,h", [(8, 8), (5, 3), (16, 12), (32, 28)])
+def test_continuous_symbol_is_the_refined_grid_limit(w, h):
+    """Op 1 (Sec. 2.2: the eigenvalues alone define the operator) is the
+    Laplacian of the continuous w x h rectangle with reflecting sides.  Its
+    eigenvalue of mode (p, q) is the limit of m^2 times the 5-point
+    operator's eigenvalue of that mode on the rectangle sampled m times finer
+    (spacing 1/m).  That spectrum comes from numpy.linalg.eigvalsh of the
+    1-D path Laplacians (the 2-D grid is their Cartesian product, so mode
+    (p, q) is the sum of the p-th and q-th 1-D values; checked on a small
+    grid below); the error falls as 1/m^2, and Richardson's step from m and
+    2m cancels that term."""
+    def scaled_1d(n, m):
+        return m * m * np.sort(np.linalg.eigvalsh(brute.path_laplacian(n * m)))
+
+    def grid_mu(m):
+        ex, ey = scaled_1d(w, m), scaled_1d(h, m)
+        return ey[:h, None] + ex[None, :w]
+
+    m = 24
+    extrap = (4.0 * grid_mu(2 * m) - grid_mu(m)) / 3.0
+    lam = oracle.eigenvalues(w, h, 1, 1.0)
+    assert lam[0, 0] == 0.0
+    mu = np.where(lam > 0, 1.0 / np.where(lam > 0, lam, 1.0), 0.0)
+    np.testing.assert_allclose(mu[lam > 0], extrap[lam > 0], rtol=2e-6)
+    # s enters as lam = mu^-s for every mode (biharmonic and fractional)
+    for s in (2.0, 0.5):
+        np.testing.assert_allclose(oracle.eigenvalues(w, h, 1, s)[lam > 0], mu[lam > 0] ** -s, rtol=1e-12)
+
+
+def test_grid_spectrum_is_the_sum_of_path_spectra():
+    """The Cartesian-product structure the previous pin relies on: the 2-D
+    5-point operator's spectrum is every sum of one eigenvalue of each 1-D
+    path Laplacian."""
+    w, h = 7, 5
+    ex = np.linalg.eigvalsh(brute.path_laplacian(w))
+    ey = np.linalg.eigvalsh(brute.path_laplacian(h))
+    got = np.sort((ey[:, None] + ex[None, :]).ravel())
+    np.testing.assert_allclose(got, np.sort(np.linalg.eigvalsh(brute.neg_laplacian(w, h))), atol=1e-12)
+
+
 # --------------------------------------------------- brute-force Eq. (1)
 
 @pytest.mark.parametrize("w,h", SHAPES)
