@@ -261,8 +261,10 @@ int select_mask(pdi_ctx *ctx, const pdi_frame *frame, int chroma_shared, const f
  * with their mean value), CG on the coarsest level, each finer level
  * started from the coarser solution. */
 typedef struct {
-    double tol;       /* stop the finest level when |r|_2 <= tol |b|_2 (b: right-hand side of the
-                         unknowns' system); in (0, 1), default 1e-6 */
+    double tol;       /* stop the finest level when |r|_2 <= tol max(|b|_2, |r_0|_2) (b: right-hand
+                         side of the unknowns' system, r_0: residual of the level's start, which
+                         matters only when the start is worse than zero, e.g. b = 0 with a
+                         nonzero coarse start); in (0, 1), default 1e-6 */
     int32_t max_iter; /* CG iterations per level at most, in [1, 65536]; default 4000 */
     int32_t check;    /* iterations queued between host read-backs at most, in [1, 1024];
                          default 8 (fewer where the norms' decay, or the count of the
@@ -373,7 +375,9 @@ void pdi_seq_destroy(pdi_seq *q);
  * admits queued frames in arrival order whenever a lane is free and the
  * device bytes of the running frames stay within hbm_budget_bytes (0 = no
  * cap): the oldest queued frame, joined by queued frames of the same
- * geometry and params (up to 8: a latency choice), is copied to the device and
+ * geometry and params (up to PDI_MAX_BATCH: only frames already waiting join, so
+ * a light load admits frames one by one and a deep queue drains in large
+ * launches), is copied to the device and
  * decoded by one decode_residual_batch launch on the lane's stream (frames on
  * different lanes overlap on the GPU), and the results are copied back.  A
  * frame's result does not depend on what it is batched with or on what else

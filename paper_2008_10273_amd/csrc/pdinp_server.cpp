@@ -6,7 +6,9 @@
 // HBM budget are free, without waiting for the running ones to finish.
 //
 // Queued frames of one geometry and parameters are admitted together, up to
-// 8 at a time, and decoded by one decode_residual_batch launch;
+// PDI_MAX_BATCH at a time, and decoded by one decode_residual_batch launch
+// (only frames already waiting join: a light load admits frames one by one,
+// a deep queue drains in large launches);
 // a frame's result does not depend on what it is batched with or on what
 // else is in flight, so it is the same alone and in the mix.
 #include "../../include/pdinp.h"
@@ -73,7 +75,7 @@ struct pdi_server {
   size_t in_use = 0;     // device bytes of running requests
   size_t allocated = 0;  // device bytes held (running requests + pool)
   int max_queue = 0;
-  int max_batch = 8;  // frames joined per launch: a latency choice (PDI_MAX_BATCH allows more)
+  int max_batch = PDI_MAX_BATCH;  // frames joined per launch
   std::vector<hipStream_t> lanes;
   std::vector<int> lane_busy;
   std::mutex mu;
