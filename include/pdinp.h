@@ -140,6 +140,40 @@ int decode_residual_batch(pdi_ctx *ctx, int n, const pdi_frame *frame, const pdi
                           const float *const *values, int block_size, const pdi_params *params,
                           float *const *outs, void *stream);
 
+/* decode_residual_batch for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results as decode_residual_batch
+ * (1..PDI_MAX_BATCH frames of one geometry; DEVICE pointers, caller owned),
+ * but the decode's device scratch (status word, counters, deferred-block
+ * list, wave-per-block queues, global-memory bordered systems) lives in a
+ * static device array of PDI_NOALLOC_SCRATCH_BYTES that each GPU the
+ * library runs on holds until the process ends, and the call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine).
+ * Preconditions and limits:
+ *   - the context's tables for this geometry, block size, chroma sharing and
+ *     operator (op, s) must exist: one decode_residual / decode_residual_batch
+ *     call with them builds them (that call allocates); otherwise
+ *     PDI_EINVAL with nothing launched;
+ *   - the scratch must hold the status word and counters (4.4 KB), 4 bytes
+ *     per mask block and frame (12 per mask block and frame with 32x32
+ *     blocks) and at least one (b*b + 1)(b*b + 3)-float system; more systems
+ *     fit, up to 64 are used (more workgroups of the general pass then work on
+ *     K > 96 blocks at once; results do not depend on it).  A larger decode
+ *     returns PDI_ENOMEM with nothing launched.  32 frames of 1080p 4:2:0
+ *     need at least 1.6 MB with 16x16 blocks, 5.2 MB with 8x8 and 5.2 MB
+ *     with 32x32 blocks, so any batch of up to 4K frames fits;
+ *   - every call on a GPU shares that GPU's scratch: calls that overlap on
+ *     one GPU (different streams, contexts or threads) race and must be
+ *     serialised by the caller.  Each decode leaves its counters at zero;
+ *     the status word keeps what kernels report until pdi_sync(ctx, stream)
+ *     (on the stream of the call) reads and clears it.
+ * Errors as decode_residual_batch, plus PDI_EHIP when the scratch's device
+ * address could not be taken at pdi_create. */
+#define PDI_NOALLOC_SCRATCH_BYTES (32u << 20)
+int decode_residual_batch_noalloc(pdi_ctx *ctx, int n, const pdi_frame *frame, const pdi_mask *masks,
+                                  const float *const *values, int block_size, const pdi_params *params,
+                                  float *const *outs, void *stream);
+
 /* ---- Decoding stored coefficients (the paper's decoder split) ----
  * When the encoder keeps each block's Green's-function coefficients c and
  * constant a (Sec. 2.2, last paragraph), the decoder only evaluates Eq. 2,

@@ -24,6 +24,7 @@ ERROR_NAMES = {0: "PDI_OK", -1: "PDI_EINVAL", -2: "PDI_EMASK", -3: "PDI_ENOMEM",
                -5: "PDI_EBUSY", -6: "PDI_EVALUE", -7: "PDI_ESOLVE"}
 
 EXPORTS = ["pdi_default_params", "pdi_create", "pdi_destroy", "decode_residual", "decode_residual_batch",
+           "decode_residual_batch_noalloc",
            "decode_coefficients", "decode_coefficients_batch", "encode_coefficients",
            "encode_coefficients_batch", "pdi_default_select_params", "select_mask", "pdi_sync",
            "pdi_default_cg_params", "inpaint_homogeneous",
@@ -120,6 +121,8 @@ def lib() -> ctypes.CDLL:
                                             ctypes.POINTER(ctypes.c_void_p), i32, ctypes.POINTER(pdi_params),
                                             ctypes.POINTER(ctypes.c_void_p), P]
         L.decode_residual_batch.restype = i32
+        L.decode_residual_batch_noalloc.argtypes = L.decode_residual_batch.argtypes
+        L.decode_residual_batch_noalloc.restype = i32
         VP = ctypes.POINTER(ctypes.c_void_p)
         L.decode_coefficients.argtypes = [P, ctypes.POINTER(pdi_frame), ctypes.POINTER(pdi_mask), P, P,
                                           ctypes.POINTER(pdi_coef_params), i32, ctypes.POINTER(pdi_params), P, P]
@@ -514,6 +517,29 @@ class Decoder:
         s = stream.cuda_stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
         rc = lib().decode_residual_batch(self.ctx, n, ctypes.byref(fr), masks, vals, f0.block_size,
                                          ctypes.byref(params) if params is not None else None, outs, s)
+        if check and rc != PDI_OK:
+            raise PdiError(rc, pdi_last_error(self.ctx))
+        return rc
+
+    def decode_batch_noalloc(self, ds, params: Optional[pdi_params] = None, stream=None, check=True) -> int:
+        """decode_residual_batch_noalloc over uploaded frames of one geometry
+        (the library's static device scratch; nothing is allocated)."""
+        n = len(ds)
+        f0 = ds[0]["frame"]
+        fr = pdi_frame(f0.width, f0.height, f0.fmt)
+        masks = (pdi_mask * n)()
+        vals = (ctypes.c_void_p * n)()
+        outs = (ctypes.c_void_p * n)()
+        i8 = params is not None and params.out_int8
+        for k, d in enumerate(ds):
+            f = d["frame"]
+            masks[k] = pdi_mask(d["block_ptr"].data_ptr(), d["pos"].data_ptr(), d["n_mask_blocks"],
+                                int(bool(f.chroma_shared)))
+            vals[k] = d["values"].data_ptr()
+            outs[k] = (d["out_i8"] if i8 else d["out"]).data_ptr()
+        s = stream.cuda_stream if stream is not None else self.torch.cuda.current_stream(self.device).cuda_stream
+        rc = lib().decode_residual_batch_noalloc(self.ctx, n, ctypes.byref(fr), masks, vals, f0.block_size,
+                                                 ctypes.byref(params) if params is not None else None, outs, s)
         if check and rc != PDI_OK:
             raise PdiError(rc, pdi_last_error(self.ctx))
         return rc

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdinp.so")
 SOURCES = [os.path.join(CSRC, n) for n in
            ("pdinp_host.cpp", "pdinp_graph.cpp", "pdinp_server.cpp", "pdinp_kernels.hip",
-            "pdinp_wide.hip", "pdinp_diffusion.hip", "pdinp_select.hip")]
+            "pdinp_wide.hip", "pdinp_diffusion.hip", "pdinp_select.hip", "pdinp_noalloc.hip")]
 ARCH = os.environ.get("PDI_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 VALU forms are kept out of the generated code.

@@ -102,6 +102,12 @@ struct pdi_ctx {
   std::map<hipStream_t, Workspace> ws;
   std::map<TuneKey, int> tune;  // blocks per workgroup of the wave-per-block path
   std::map<std::pair<int, int>, DiffWork> diff;  // per plane size (W, H)
+  // decode_residual_batch_noalloc: this device's copy of the static scratch
+  // (from hipGetSymbolAddress at pdi_create; null if that failed) and
+  // whether a call used it (pdi_sync then reads its status word too)
+  void *noalloc = nullptr;
+  hipError_t noalloc_err = hipSuccess;
+  bool noalloc_used = false;
 };
 
 namespace {
@@ -359,6 +365,18 @@ int get_tables(pdi_ctx *c, const pdi_frame *f, int b, int shared, const pdi_para
   return PDI_OK;
 }
 
+// The cached tables of a geometry and operator, or PDI_EINVAL when no call
+// has built them yet (never allocates).
+int find_tables(pdi_ctx *c, const pdi_frame *f, int b, int shared, const pdi_params &P, TableSet **out) {
+  auto it = c->tables.find(TableKey{f->width, f->height, f->format, b, shared, P.op, P.s});
+  if (it == c->tables.end())
+    return set_err(c, PDI_EINVAL,
+                   "no tables for this geometry and operator yet: one decode_residual or decode_residual_batch "
+                   "call with them builds them (that call allocates)");
+  *out = &it->second;
+  return PDI_OK;
+}
+
 int get_workspace(pdi_ctx *c, hipStream_t stream, Workspace **out) {
   auto it = c->ws.find(stream);
   if (it != c->ws.end()) {
@@ -439,6 +457,10 @@ int pdi_create(pdi_ctx **out, int device, size_t hbm_budget_bytes) {
   c->budget = hbm_budget_bytes;
   hipError_t e = hipSetDevice(device);
   if (e != hipSuccess) { delete c; return PDI_EHIP; }
+  // The device address of this device's static scratch (no allocation);
+  // a failure only disables decode_residual_batch_noalloc.
+  c->noalloc_err = pdi::noalloc_setup(device, &c->noalloc);
+  if (c->noalloc_err != hipSuccess) c->noalloc = nullptr;
   *out = c;
   return PDI_OK;
 }
@@ -518,11 +540,13 @@ static void fill_groups(const pdi_frame *frame, int block_size, int shared, cons
 // Decode n frames of one geometry (one launch per kernel for all of them):
 // residual decodes (values, qp == nullptr), stored-coefficient decodes
 // (coefs + consts, qp != nullptr) or coefficient encodes (qouts + aouts).
+// With `scratch` (residual decodes only) the decode's device scratch is
+// carved from that static array and nothing is allocated.
 static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask *masks,
                        const float *const *values, int block_size, const pdi_params *params,
                        float *const *outs, void *stream, const int8_t *const *coefs = nullptr,
                        const float *const *consts = nullptr, const pdi_coef_params *qp = nullptr,
-                       int8_t *const *qouts = nullptr, float *const *aouts = nullptr) {
+                       int8_t *const *qouts = nullptr, float *const *aouts = nullptr, void *scratch = nullptr) {
   if (!c) return PDI_EINVAL;
   const bool enc = qouts != nullptr;        // coefficient encode: values in, codes + constants out
   const bool coef = qp != nullptr && !enc;  // stored-coefficient decode
@@ -572,12 +596,15 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   std::lock_guard<std::mutex> lock(c->mu);
   hipStream_t s = (hipStream_t)stream;
-  Workspace *W = nullptr;
-  int rcw = get_workspace(c, s, &W);
-  if (rcw) return rcw;
+  Workspace SW;  // static-scratch decodes: the pieces of the static array
+  Workspace *W = &SW;
+  if (!scratch) {
+    int rcw = get_workspace(c, s, &W);
+    if (rcw) return rcw;
+  }
 
   TableSet *ts = nullptr;
-  int rc = get_tables(c, frame, block_size, shared, P, &ts);
+  int rc = scratch ? find_tables(c, frame, block_size, shared, P, &ts) : get_tables(c, frame, block_size, shared, P, &ts);
   if (rc) return rc;
 
   pdi::FrameDev F;
@@ -664,11 +691,43 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
     F.nq = nq;
     F.fast_wgs = wgs;
   }
-  rc = ensure_workspace(c, W, (int)nitems * n, block_size, fast ? F.fast_wgs : 0);
-  if (rc) return rc;
+  F.slot_wgs = pdi::kDeferredGrid;
+  if (scratch) {
+    // status word, counters, deferred list, queues (wave-per-block path),
+    // then as many global-memory systems as fit, up to one per workgroup of
+    // the deferred pass that takes them
+    auto up = [](long long x) { return (x + 255) & ~255ll; };
+    const long long items = nitems * n, nmax = (long long)block_size * block_size;
+    const long long slot_floats = (nmax + 1) * (nmax + 3);
+    long long off = pdi::kNoAllocHeadBytes;
+    const long long def_off = off;
+    off += up(4 * items);
+    const long long bin_off = off;
+    if (wide) off += up(8 * items);
+    const long long room = pdi::kNoAllocScratchBytes - off;
+    const long long nsl = room > 0 ? std::min<long long>(pdi::kDeferredGrid, room / (4 * slot_floats)) : 0;
+    if (nsl < 1)
+      return set_err(c, PDI_ENOMEM,
+                     "%d frames of %lld mask blocks with %dx%d blocks need %lld bytes of scratch; the static "
+                     "scratch holds %lld", n, nitems, block_size, block_size, off + 4 * slot_floats,
+                     (long long)pdi::kNoAllocScratchBytes);
+    char *base = static_cast<char *>(scratch);
+    W->status = reinterpret_cast<int *>(base);
+    W->counters = reinterpret_cast<int *>(base + pdi::kNoAllocCountersOff);
+    W->deferred = reinterpret_cast<int *>(base + def_off);
+    W->binlist = wide ? reinterpret_cast<int *>(base + bin_off) : nullptr;
+    W->slots = reinterpret_cast<float *>(base + off);
+    W->slot_floats = slot_floats;
+    F.slot_wgs = (int)nsl;
+  } else {
+    rc = ensure_workspace(c, W, (int)nitems * n, block_size, fast ? F.fast_wgs : 0);
+    if (rc) return rc;
+  }
   F.tab32_floats = ts->tab32_floats;
   F.nframes = n;
-  F.tail_in_wg = (n == 1 && !coef && !enc) ? 1 : 0;
+  // A single frame's k_fast workgroups decode their leftover blocks in their
+  // own global slots; static-scratch decodes hand them to the deferred pass.
+  F.tail_in_wg = (n == 1 && !coef && !enc && !scratch) ? 1 : 0;
   for (int k = 0; k < n; ++k) {
     F.fp[k].block_ptr = masks[k].block_ptr;
     F.fp[k].pos = masks[k].pos;
@@ -696,7 +755,7 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
     // A single frame: one launch, the workgroups also decode their leftover
     // blocks.  A batch or an encode: leftover blocks go to the deferred pass.
     e = pdi::launch_fast(F, s);
-    if (e == hipSuccess && (n > 1 || enc)) e = pdi::launch_general_deferred(F, s);
+    if (e == hipSuccess && !F.tail_in_wg) e = pdi::launch_general_deferred(F, s);
   } else if (wide) {
     e = pdi::launch_wide(F, s);  // leftover blocks go to the deferred list
     if (e == hipSuccess) e = pdi::launch_general_deferred(F, s);
@@ -718,6 +777,20 @@ int decode_residual_batch(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_m
                           const float *const *values, int block_size, const pdi_params *params,
                           float *const *outs, void *stream) {
   return decode_impl(c, n, frame, masks, values, block_size, params, outs, stream);
+}
+
+int decode_residual_batch_noalloc(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask *masks,
+                                  const float *const *values, int block_size, const pdi_params *params,
+                                  float *const *outs, void *stream) {
+  if (!c) return PDI_EINVAL;
+  if (!c->noalloc)
+    return set_err(c, PDI_EHIP, "static scratch unavailable: %s", hipGetErrorString(c->noalloc_err));
+  {
+    std::lock_guard<std::mutex> lock(c->mu);
+    c->noalloc_used = true;
+  }
+  return decode_impl(c, n, frame, masks, values, block_size, params, outs, stream, nullptr, nullptr, nullptr,
+                     nullptr, nullptr, c->noalloc);
 }
 
 int decode_coefficients(pdi_ctx *c, const pdi_frame *frame, const pdi_mask *mask, const int8_t *coef,
@@ -830,17 +903,32 @@ int pdi_sync(pdi_ctx *c, void *stream) {
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
   std::lock_guard<std::mutex> lock(c->mu);
+  // the stream's workspace (if it decoded anything) and, once static-scratch
+  // decodes ran, the status word of the device's static scratch
+  int *status[2] = {nullptr, nullptr}, *counters[2] = {nullptr, nullptr};
   auto it = c->ws.find((hipStream_t)stream);
-  if (it == c->ws.end()) return PDI_OK;  // nothing decoded on this stream yet
-  Workspace &W = it->second;
+  if (it != c->ws.end()) {
+    status[0] = it->second.status;
+    counters[0] = it->second.counters;
+  }
+  if (c->noalloc_used) {
+    status[1] = static_cast<int *>(c->noalloc);
+    counters[1] = reinterpret_cast<int *>(static_cast<char *>(c->noalloc) + pdi::kNoAllocCountersOff);
+  }
   int st = 0;
-  e = hipMemcpy(&st, W.status, sizeof(int), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(c, e, "status read");
-  if (st) {
-    e = hipMemset(W.status, 0, sizeof(int));
-    if (e == hipSuccess) e = hipMemset(W.counters, 0, sizeof(int) * pdi::kNumCounters);
+  for (int k = 0; k < 2; ++k) {
+    if (!status[k]) continue;
+    int sk = 0;
+    e = hipMemcpy(&sk, status[k], sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "status read");
+    if (!sk) continue;
+    st |= sk;
+    e = hipMemset(status[k], 0, sizeof(int));
+    if (e == hipSuccess) e = hipMemset(counters[k], 0, sizeof(int) * pdi::kNumCounters);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(c, e, "status reset");
+  }
+  if (st) {
     if (st & pdi::kStatusMask) return set_err(c, PDI_EMASK, "device validation: bad mask positions");
     if (st & pdi::kStatusValue) return set_err(c, PDI_EVALUE, "device validation: non-finite value");
     return set_err(c, PDI_ESOLVE, "a block system broke down (non-finite solution)");

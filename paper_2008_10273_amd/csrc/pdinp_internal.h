@@ -69,6 +69,18 @@ struct SegDev {
 constexpr int kMaxSegs = 4 * kMaxGroups;
 constexpr int kNumCounters = kQueueCounters + 4 * kMaxShapes * kMaxBatch;
 
+// Static device scratch of decode_residual_batch_noalloc (pdinp_noalloc.hip):
+// the status word (4 ints) at byte 0, the counters at kNoAllocCountersOff
+// (both start at zero), then the deferred list, the wave-per-block queues
+// and the global-memory systems of one decode.
+constexpr long long kNoAllocScratchBytes = 32ll << 20;
+constexpr long long kNoAllocCountersOff = 256;
+constexpr long long kNoAllocHeadBytes = kNoAllocCountersOff + ((4ll * kNumCounters + 255) / 256) * 256;
+// Device address of the given device's copy of that scratch (taken once per
+// device by hipGetSymbolAddress with the device current; its head is zeroed
+// then).
+hipError_t noalloc_setup(int device, void **ptr);
+
 // The blocks of one shape for the wave-per-block path.  binlist[2 base ..
 // 2 base + 2 count) holds them by point count: bin 0 from the front of the
 // first half, bin 1 from its back, bins 2 and 3 likewise in the second half;
@@ -153,6 +165,7 @@ struct FrameDev {
   int *status;     // device status word
   float *slots;    // global-memory systems for K > kLdsKMax, one slot per workgroup
   long long slot_floats;
+  int slot_wgs;    // workgroups of the deferred pass that own a slot (<= kDeferredGrid)
 };
 
 // Launchers (pdinp_kernels.hip).  All asynchronous on `stream`.

@@ -347,9 +347,9 @@ __global__ __launch_bounds__(kGenThreads) void k_general_deferred(FrameDev f) {
     const int e = f.deferred[idx];
     general_block<32>(f, e >> kDeferFrameShift, e & kDeferItemMask, sh.g, sh.M);
   }
-  if (blockIdx.x < kDeferredGrid) {
+  if ((int)blockIdx.x < f.slot_wgs) {
     float *slot = f.slots + (long long)blockIdx.x * f.slot_floats;
-    for (int idx = blockIdx.x; idx < nlarge; idx += kDeferredGrid) {
+    for (int idx = blockIdx.x; idx < nlarge; idx += f.slot_wgs) {
       __syncthreads();
       const int e = f.deferred[cap - 1 - idx];
       general_block<32>(f, e >> kDeferFrameShift, e & kDeferItemMask, sh.g, slot);
