@@ -143,6 +143,22 @@ def error_vs(got, ref):
     return dict(max_abs=float(e.max()), round_agree=float(np.mean(q(got) == q(ref))))
 
 
+def host_outputs(ds):
+    return [dd["out"].cpu().numpy() for dd in ds]
+
+
+def error_frames(outs, refs):
+    """error_vs over the FP32 outputs of several frames (host arrays), one
+    frame at a time (max of the maxima, pixel-weighted agreement)."""
+    mx, agree, npx = 0.0, 0.0, 0
+    for o, ref in zip(outs, refs):
+        e = error_vs(o.astype(np.float64), ref)
+        mx = max(mx, e["max_abs"])
+        agree += e["round_agree"] * ref.size
+        npx += ref.size
+    return dict(max_abs=mx, round_agree=agree / npx, frames_checked=len(refs))
+
+
 def log(msg):
     print(f"# {msg}", file=sys.stderr, flush=True)
 
@@ -205,6 +221,46 @@ def overlapped(torch, dec, ds, params, nstreams, steps):
     return steps / dt
 
 
+def oracle_flat(fr):
+    import oracle
+    return oracle.decode_flat(fr, nthreads=host_cores())
+
+
+def meets_bar(err):
+    """The acceptance bar: max-abs <= 0.5 grey levels and identical 8-bit
+    rounding on >= 99.9 % of the pixels."""
+    return bool(err["max_abs"] <= 0.5 and err["round_agree"] >= 0.999)
+
+
+def dtype_sweep(args, torch, binding, dec, ds, refs, stream, tune_b):
+    """The batched decode of the same frames with each evaluation dtype
+    (FP32 solve; FP32, FP16, BF16 or split-BF16 operands in the evaluation,
+    FP32 accumulation): frames/s over --dtype-steps steps and the error of
+    every frame against the FP64 oracle."""
+    out = {}
+    B = len(ds)
+    tm = StreamTimer(torch, stream)
+    for name, ev in EVALS.items():
+        p = binding.default_params(eval_dtype=ev)
+        for _ in range(3):
+            dec.decode_batch(ds, p, stream=stream)
+        tm.start()
+        for _ in range(args.dtype_steps):
+            dec.decode_batch(ds, p, stream=stream)
+        secs = tm.stop()
+        assert dec.sync(stream) == 0, binding.pdi_last_error(dec.ctx)
+        rec = dict(value=B * args.dtype_steps / secs, unit="frames/s", ms_per_step=1e3 * secs / args.dtype_steps)
+        if refs is not None:
+            e = error_frames(host_outputs(ds), refs)
+            rec.update(max_abs=e["max_abs"], round_agree=e["round_agree"], meets_bar=meets_bar(e),
+                       frames_checked=len(ds))
+        out[name] = rec
+        log(f"  eval {name}: {rec['value']:.1f} frames/s" +
+            (f", max|err| {rec['max_abs']:.3e}, 8-bit agreement {rec['round_agree']:.6f}, "
+             f"{'meets' if rec['meets_bar'] else 'FAILS'} the bar" if refs is not None else ""))
+    return out
+
+
 def bench_frame(args, torch, binding, synth):
     """One step = one decode_residual_batch call over `--batch` different
     frames of the workload (decode_residual for --batch 1)."""
@@ -242,7 +298,7 @@ def bench_frame(args, torch, binding, synth):
     wall = time.perf_counter() - t0
     assert dec.sync(stream) == 0, binding.pdi_last_error(dec.ctx)
     fps = B * args.steps / secs
-    got = d["out"].cpu().numpy().astype(np.float64)
+    timed_outs = host_outputs(ds)  # every frame of the last timed step
     log(f"decode: {fps:.1f} frames/s, {1e3 * secs / args.steps:.4f} ms per step of {B} frames")
 
     # single frames: throughput and latency of one frame decoded alone
@@ -284,11 +340,15 @@ def bench_frame(args, torch, binding, synth):
                      path="one workgroup per block, FP32 LDS Gauss-Jordan, direct VALU evaluation, single frames")
         log(f"plain path: {plain['value']:.1f} frames/s")
 
-    err = cpu = None
+    err = cpu = refs = None
     if not args.no_cpu:
-        ref, cpu = cpu_baseline(fr)
-        err = error_vs(got, ref)
-        log(f"oracle: {cpu['value']:.2f} frames/s on {cpu['cores']} cores; max|err| {err['max_abs']:.3e}")
+        ref, cpu = cpu_baseline(fr, min_seconds=args.cpu_seconds)
+        # every frame of the timed batch against the oracle (the outputs of the last timed step)
+        refs = [ref] + [oracle_flat(f) for f in frames[1:]]
+        err = error_frames(timed_outs, refs)
+        log(f"oracle: {cpu['value']:.2f} frames/s on {cpu['cores']} cores; max|err| over the {len(frames)} "
+            f"timed frames {err['max_abs']:.3e}, 8-bit agreement {err['round_agree']:.6f}")
+    per_dtype = dtype_sweep(args, torch, binding, dec, ds, refs, stream, tune_b) if args.dtypes else None
 
     ab = sum(algorithmic_bytes(f) for f in frames)
     t_step = secs / args.steps
@@ -307,7 +367,8 @@ def bench_frame(args, torch, binding, synth):
                        "blocks_per_workgroup": tune_b or None, "blocks_per_workgroup_single": tune or None},
                latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "mean": float(lat.mean()), "of": "one frame decoded alone"},
-               single_frame=single, error_vs_oracle=err, plain_path=plain, overlapped=multi, int8_output=int8,
+               single_frame=single, error_vs_oracle=err, per_dtype=per_dtype, plain_path=plain, overlapped=multi,
+               int8_output=int8,
                roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS,
                          "traffic": TRAFFIC.get((args.config, B, tune_b)),
@@ -359,7 +420,7 @@ def bench_coef(args, torch, binding, synth):
     wall = time.perf_counter() - t0
     assert dec.sync(stream) == 0, binding.pdi_last_error(dec.ctx)
     fps = B * args.steps / secs
-    got = d["out"].cpu().numpy().astype(np.float64)
+    timed_outs = host_outputs(ds)  # every frame of the last timed step
     log(f"decode: {fps:.1f} frames/s, {1e3 * secs / args.steps:.4f} ms per step of {B} frames")
     lat = []
     for _ in range(args.latency_iters):
@@ -712,7 +773,7 @@ def bench_sequence(args, torch, binding, synth):
     err = cpu = None
     got = ds[0]["out"].cpu().numpy().astype(np.float64)
     if not args.no_cpu:
-        ref, cpu = cpu_baseline(frames[0], what="frame 0 of the sequence")
+        ref, cpu = cpu_baseline(frames[0], min_seconds=args.cpu_seconds, what="frame 0 of the sequence")
         err = error_vs(got, ref)
         log(f"oracle: {cpu['value']:.2f} frames/s; max|err| {err['max_abs']:.3e}")
     ab = sum(algorithmic_bytes(f) for f in frames)
@@ -808,7 +869,8 @@ def bench_serving(args, torch, binding, synth):
         d = dec.upload(frames[s1080][0])
         dec.decode(d, params)
         assert dec.sync() == 0
-        ref, cpu = cpu_baseline(frames[s1080][0], what="one 1080p frame of the serving mix")
+        ref, cpu = cpu_baseline(frames[s1080][0], min_seconds=args.cpu_seconds,
+                                what="one 1080p frame of the serving mix")
         err = error_vs(d["out"].cpu().numpy().astype(np.float64), ref)
     mix_px = sum(w * h * c for w, h, c in synth.SERVING_MIX) / nstreams
     rec = dict(metric=METRIC, value=served_fps, unit="frames/s", n_gpus=1, steps=done_w, warmup=len(tickets) - done_w,
@@ -826,6 +888,32 @@ def bench_serving(args, torch, binding, synth):
                error_vs_oracle=err, roofline=None, cpu_baseline=cpu, wall_s=wall)
     dec.close()
     return rec
+
+
+def nested_legs(args, torch, binding, synth):
+    """The other decode workloads of the metric, carried in the default
+    config-1 line: config 2 (32x32 blocks; every evaluation dtype against the
+    oracle), config 3 (64-frame sequence as HIP-graph replays) and config 4
+    (serving mix: p50/p99 latency and capacity), each a full record of its
+    own with shorter timing."""
+    import copy
+    out = {}
+    a2 = copy.copy(args)
+    a2.config, a2.steps, a2.warmup = 2, min(args.steps, 20), min(args.warmup, 5)
+    a2.latency_iters, a2.no_plain, a2.cpu_seconds = 50, True, 3.0
+    log("---- nested leg: config 2")
+    out["config_2"] = bench_frame(a2, torch, binding, synth)
+    a3 = copy.copy(args)
+    a3.config, a3.steps, a3.warmup, a3.latency_iters, a3.dtypes = 3, 10, 2, 50, False
+    a3.no_cpu = True  # its frames are config-1 frames: checked above
+    log("---- nested leg: config 3")
+    out["config_3"] = bench_sequence(a3, torch, binding, synth)
+    a4 = copy.copy(args)
+    a4.config, a4.duration, a4.warm_s, a4.burst_rounds, a4.dtypes = 4, 4.0, 0.5, 4, False
+    a4.cpu_seconds = 3.0
+    log("---- nested leg: config 4")
+    out["config_4"] = bench_serving(a4, torch, binding, synth)
+    return out
 
 
 def main():
@@ -851,6 +939,12 @@ def main():
                     help="only run a device copy of this many MiB 10 times (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-path comparison")
+    ap.add_argument("--no-nested", action="store_true",
+                    help="config 1: skip the nested config 2 / 3 / 4 legs (profiling runs)")
+    ap.add_argument("--no-dtypes", dest="dtypes", action="store_false",
+                    help="configs 0-2: skip the per-dtype sweep")
+    ap.add_argument("--dtype-steps", type=int, default=20, help="steps per dtype in the sweep")
+    ap.add_argument("--cpu-seconds", type=float, default=5.0, help="oracle timing sample (seconds)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this decoder runs on one GPU; --gpus {args.gpus} is not supported "
@@ -871,6 +965,8 @@ def main():
         return
     if args.config <= 2:
         rec = bench_frame(args, torch, binding, synth)
+        if args.config == 1 and not args.no_nested:
+            rec.update(nested_legs(args, torch, binding, synth))
     elif args.config == 3:
         rec = bench_sequence(args, torch, binding, synth)
     elif args.config == 5:
