@@ -45,7 +45,7 @@ struct Workspace {
   int *status = nullptr;    // device status word
   int *counters = nullptr;  // device counters [kNumCounters]
   int *deferred = nullptr;  // device list of deferred mask blocks
-  int *binlist = nullptr;   // device queues of the wave-per-block path
+  int *binlist = nullptr;   // device queues of the binned paths (4 ints per mask block and frame)
   int deferred_cap = 0;
   float *slots = nullptr;   // global-memory bordered systems
   long long slot_floats = 0;
@@ -398,14 +398,20 @@ int get_workspace(pdi_ctx *c, hipStream_t stream, Workspace **out) {
   return PDI_OK;
 }
 
+// Ints of the queue buffer for n_items mask blocks x frames: the binned
+// paths' queues (4 per block) and the binning's per-workgroup bin counts
+// (kMaxSegs * 8 bins for each workgroup of 256 blocks of one frame; at most
+// 32 frames add a partial workgroup each).
+long long binlist_ints(long long n_items) { return 4 * n_items + 8ll * pdi::kMaxSegs * (n_items / 256 + 33); }
+
 int ensure_workspace(pdi_ctx *c, Workspace *W, int n_items, int b, int nslots) {
   if (n_items > W->deferred_cap) {
     dev_free(c, W->deferred, sizeof(int) * (size_t)W->deferred_cap);
-    dev_free(c, W->binlist, sizeof(int) * 2 * (size_t)W->deferred_cap);
+    dev_free(c, W->binlist, sizeof(int) * (size_t)binlist_ints(W->deferred_cap));
     W->deferred = W->binlist = nullptr;
     W->deferred_cap = 0;
     int rc = dev_alloc(c, (void **)&W->deferred, sizeof(int) * (size_t)n_items, "deferred list");
-    if (!rc) rc = dev_alloc(c, (void **)&W->binlist, sizeof(int) * 2 * (size_t)n_items, "block queues");
+    if (!rc) rc = dev_alloc(c, (void **)&W->binlist, sizeof(int) * (size_t)binlist_ints(n_items), "block queues");
     if (rc) return rc;
     W->deferred_cap = n_items;
   }
@@ -655,6 +661,7 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
     for (int e = 0; e < 4; ++e) {
       const int nx = segs[e][1], ny = segs[e][3];
       if (nx <= 0 || ny <= 0) continue;
+      F.qge[g][e] = F.nsegs;
       pdi::SegDev &S = F.seg[F.nsegs++];
       S.group = g;
       S.shape = G.shape[e];
@@ -669,6 +676,27 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
       const int need = (coef ? 0 : SH.jt_floats) + dct_floats;  // coef: the matrices only
       if (need > F.fast_lds) F.fast_lds = need;
     }
+  }
+  // Batched residual decodes with b <= 16 take the binned path (k_fbin +
+  // k_fast2): one queue per segment (mask-plane group and edge kind) with
+  // four regions of its blocks x frames entries (two size classes each),
+  // k_fast2 workgroups for every queued block plus one partial workgroup
+  // per bin.  A binned queue keeps its group in first_wg.
+  const bool binned = fast && !coef && !enc && n > 1;
+  if (binned) {
+    long long base = 0;
+    F.nq = 0;
+    for (int k = 0; k < F.nsegs; ++k) {
+      const pdi::SegDev &S = F.seg[k];
+      pdi::QueueDev &Q = F.q[F.nq];
+      Q.shape = S.shape;
+      Q.count = S.count;
+      Q.base = (int)base;
+      Q.first_wg = S.group;
+      base += 4ll * S.count * n;
+      F.nq++;  // queue k is segment k (F.qge was filled with the segments)
+    }
+    F.fast_wgs = (int)((nitems * n + ipw - 1) / ipw) + 8 * F.nq;
   }
   if (wide) {
     // One queue per block shape, the smallest first so that the few edge
@@ -704,6 +732,7 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
     off += up(4 * items);
     const long long bin_off = off;
     if (wide) off += up(8 * items);
+    if (binned) off += up(4 * binlist_ints(items));
     const long long room = pdi::kNoAllocScratchBytes - off;
     const long long nsl = room > 0 ? std::min<long long>(pdi::kDeferredGrid, room / (4 * slot_floats)) : 0;
     if (nsl < 1)
@@ -715,7 +744,7 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
     W->status = reinterpret_cast<int *>(base);
     W->counters = reinterpret_cast<int *>(base + pdi::kNoAllocCountersOff);
     W->deferred = reinterpret_cast<int *>(base + def_off);
-    W->binlist = wide ? reinterpret_cast<int *>(base + bin_off) : nullptr;
+    W->binlist = (wide || binned) ? reinterpret_cast<int *>(base + bin_off) : nullptr;
     W->slots = reinterpret_cast<float *>(base + off);
     W->slot_floats = slot_floats;
     F.slot_wgs = (int)nsl;
@@ -742,6 +771,7 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
   F.tab64 = ts->tab64;
   F.deferred = W->deferred;
   F.binlist = W->binlist;
+  F.hist = binned ? W->binlist + 4 * nitems * n : nullptr;
   F.counters = W->counters;
   F.status = W->status;
   F.slots = W->slots;
@@ -751,9 +781,13 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
     // Batched kernels, then the blocks with more points than they stage.
     e = fast ? pdi::launch_fast(F, s) : pdi::launch_wide(F, s);
     if (e == hipSuccess) e = pdi::launch_coef_general(F, s);
+  } else if (binned) {
+    // binning, the binned wave-level kernel, then the deferred blocks
+    e = pdi::launch_fast2(F, s);
+    if (e == hipSuccess) e = pdi::launch_general_deferred(F, s);
   } else if (fast) {
     // A single frame: one launch, the workgroups also decode their leftover
-    // blocks.  A batch or an encode: leftover blocks go to the deferred pass.
+    // blocks.  An encode: leftover blocks go to the deferred pass.
     e = pdi::launch_fast(F, s);
     if (e == hipSuccess && !F.tail_in_wg) e = pdi::launch_general_deferred(F, s);
   } else if (wide) {

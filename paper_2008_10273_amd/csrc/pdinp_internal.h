@@ -145,10 +145,14 @@ struct FrameDev {
   SegDev seg[kMaxSegs];
   int nsegs;
   int ipw;           // blocks per workgroup of the batched path
-  int nq;            // wave-per-block queues (one per block shape), smallest first
-                     // (0: no queue counters to clear after the decode)
-  QueueDev q[kMaxShapes];
-  int qof[kMaxShapes];  // queue of each shape
+  int nq;            // queues of the binned paths (0: no queue counters to clear after
+                     // the decode): the wave-per-block path (b = 32) has one per block
+                     // shape, smallest first; the binned wave-level path (b <= 16) one
+                     // per mask-plane group and edge kind (q[].shape is then the shape of
+                     // that group's full, right-edge, bottom-edge or corner blocks)
+  QueueDev q[kMaxSegs];
+  int qof[kMaxShapes];  // queue of each shape (wave-per-block path)
+  int qge[kMaxGroups][4];  // queue of each group and edge kind (binned wave-level path)
   int fast_wgs;      // workgroups per frame of the batched path (k_fast or k_wide)
   int fast_lds;      // its dynamic LDS (floats): largest table block
   int tab32_floats;  // size of the FP32 table buffer (floats)
@@ -160,7 +164,8 @@ struct FrameDev {
   const double *tab64;
   int *deferred;   // mask blocks left to the general path, as (fi << 24) | m
                    // (n_items * nframes entries)
-  int *binlist;    // wave-per-block queues (2 n_items entries per frame)
+  int *binlist;    // queues of the binned paths (4 n_items entries per frame)
+  int *hist;       // binned wave-level path: per-workgroup bin counts / offsets of the binning
   int *counters;   // kNumCounters device counters (layout above)
   int *status;     // device status word
   float *slots;    // global-memory systems for K > kLdsKMax, one slot per workgroup
@@ -170,6 +175,9 @@ struct FrameDev {
 
 // Launchers (pdinp_kernels.hip).  All asynchronous on `stream`.
 hipError_t launch_fast(const FrameDev &f, hipStream_t stream);
+// Binned residual decode for b <= 16 (k_fbin + k_fast2): f.q / f.qof / f.nq
+// describe one queue per block shape, f.fast_wgs the k_fast2 grid.
+hipError_t launch_fast2(const FrameDev &f, hipStream_t stream);
 hipError_t launch_wide(const FrameDev &f, hipStream_t stream);  // binning kernel + k_wide
 hipError_t launch_plain_all(const FrameDev &f, hipStream_t stream);
 hipError_t launch_general_deferred(const FrameDev &f, hipStream_t stream);

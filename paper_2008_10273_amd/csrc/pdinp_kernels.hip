@@ -399,7 +399,7 @@ static_assert(kTabVec * kFastThreads * 4 <= kTabPadFloats, "table reads stay ins
 // A block of the workgroup, as staged by the prologue.
 struct FastItem {
   int m, K, base, cls, nv;
-  int pad_;
+  int fi;  // frame of the launch
   long long vb0, vb1, ob0, ob1;
 };
 
@@ -474,10 +474,10 @@ __device__ __forceinline__ void fast_coef_stage(const FrameDev &f, const FastIte
 // row-pair Green table of the workgroup's shape (LDS).  Returns false for a
 // block whose pivots call for FP64 refinement; such blocks are left to the
 // general path, which refines.
-template <int R>
+template <int R, int KCH = (R % 8 == 0 ? 8 : 4)>
 __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *items, int slot, bool ok,
                                            int t, int gi, int Kw, int w, int h, const float *J,
-                                           FastStage &st) {
+                                           FastStage &st, const uint16_t *posp, const float *vals) {
   constexpr int NS = (R + 15) / 16;
   constexpr int NV = 2;
   const int K = ok ? items[slot].K : 0;
@@ -493,14 +493,13 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *it
     T[s][0] = T[s][1] = 0.f;
     if (i < K) {
       const int base = items[slot].base;
-      int p = f.fp[blockIdx.y].pos[base + i];
+      int p = posp[base + i];
       if (f.validate) {
-        if (p >= N || (i > 0 && (int)f.fp[blockIdx.y].pos[base + i - 1] >= p)) bad |= kStatusMask;
+        if (p >= N || (i > 0 && (int)posp[base + i - 1] >= p)) bad |= kStatusMask;
       }
       p = min(p, N - 1);
       xr[s] = p % w;
       yr[s] = p / w;
-      const float *vals = f.fp[blockIdx.y].values;
       T[s][0] = vals[items[slot].vb0 + i];
       if (items[slot].nv > 1) T[s][1] = vals[items[slot].vb1 + i];
       if (f.validate && !(isfinite(T[s][0]) && isfinite(T[s][1]))) bad |= kStatusValue;
@@ -526,7 +525,8 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *it
   // they issue back to back; the border and padding pattern is applied by
   // selects afterwards.
   float A[NS][R];
-  constexpr int KC = 8;  // columns whose lookups are issued together
+  constexpr int KC = KCH;  // columns whose lookups are issued together (R is a multiple of KC)
+  static_assert(R % KC == 0 && (KC == 4 || KC == 8), "lookup chunks");
 #pragma unroll
   for (int k0 = 0; k0 < R; k0 += KC) {
     float g1[NS][KC], g2[NS][KC];
@@ -551,10 +551,15 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *it
     // entry).  They emit no instruction.
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      asm volatile("" : "+v"(g1[s][0]), "+v"(g1[s][1]), "+v"(g1[s][2]), "+v"(g1[s][3]),
-                        "+v"(g1[s][4]), "+v"(g1[s][5]), "+v"(g1[s][6]), "+v"(g1[s][7]));
-      asm volatile("" : "+v"(g2[s][0]), "+v"(g2[s][1]), "+v"(g2[s][2]), "+v"(g2[s][3]),
-                        "+v"(g2[s][4]), "+v"(g2[s][5]), "+v"(g2[s][6]), "+v"(g2[s][7]));
+      if constexpr (KC == 8) {
+        asm volatile("" : "+v"(g1[s][0]), "+v"(g1[s][1]), "+v"(g1[s][2]), "+v"(g1[s][3]),
+                          "+v"(g1[s][4]), "+v"(g1[s][5]), "+v"(g1[s][6]), "+v"(g1[s][7]));
+        asm volatile("" : "+v"(g2[s][0]), "+v"(g2[s][1]), "+v"(g2[s][2]), "+v"(g2[s][3]),
+                          "+v"(g2[s][4]), "+v"(g2[s][5]), "+v"(g2[s][6]), "+v"(g2[s][7]));
+      } else {
+        asm volatile("" : "+v"(g1[s][0]), "+v"(g1[s][1]), "+v"(g1[s][2]), "+v"(g1[s][3]));
+        asm volatile("" : "+v"(g2[s][0]), "+v"(g2[s][1]), "+v"(g2[s][2]), "+v"(g2[s][3]));
+      }
     }
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
@@ -645,12 +650,11 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *it
 // u = Dh^T (lam .* (Dw[:,X] diag(c) Dh[:,Y]^T)^T) Dw + a for the wave's 4
 // blocks (one shape), as interleaved FP32 MFMA 16x16x4 chains: lane l supplies
 // A[l%16][l/16] and B[l/16][l%16]; the result D[4(l/16)+r][l%16] is register r.
-template <int R>
+template <int R, bool UNR2 = true>
 __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, const FastStage &st,
                                           int lane, unsigned okmask, int nvw, int w, int h,
-                                          int W, long long ob0, long long ob1) {
+                                          int W, long long ob0, long long ob1, int fi) {
   constexpr int nch = R / 4;  // staged rows K..R-1 hold zero coefficients
-  const PlaneOut po = plane_out(f, blockIdx.y);
   const float *Dw = D, *Dh = D + kDct16Floats, *lam = D + 2 * kDct16Floats;
   const int lo = lane & 15, hi = lane >> 4;
   float lam4[4], dwb[4], dha[4];
@@ -665,7 +669,7 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
     f4 acc[kWaveItems];
 #pragma unroll
     for (int g = 0; g < kWaveItems; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+#pragma unroll UNR2 ? 2 : 1
     for (int ch = 0; ch < nch; ++ch) {
       float aop[kWaveItems], bop[kWaveItems];
 #pragma unroll
@@ -700,6 +704,7 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
       if (!((okmask >> g) & 1u)) continue;
       const float a = st.a[g][v];
       const long long o = lane_i64(v ? ob1 : ob0, 16 * g);
+      const PlaneOut po = plane_out(f, __builtin_amdgcn_readlane(fi, 16 * g));
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int y = 4 * hi + j, x = lo;
@@ -720,9 +725,8 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
 template <int R>
 __device__ __forceinline__ void fast_eval8(const FrameDev &f, const float *D, const FastStage &st,
                                            int lane, unsigned okmask, int nvw, int w, int h,
-                                           int W, long long ob0, long long ob1) {
+                                           int W, long long ob0, long long ob1, int fi) {
   constexpr int nch = R / 4;  // staged rows K..R-1 hold zero coefficients
-  const PlaneOut po = plane_out(f, blockIdx.y);
   const float *Dw = D, *Dh = D + kDct16Floats, *lam = D + 2 * kDct16Floats;
   const int lo = lane & 15, hi = lane >> 4, l8 = lo & 7, half = lo >> 3;
   float lam4[4], dwb[4], dha[4];
@@ -753,9 +757,14 @@ __device__ __forceinline__ void fast_eval8(const FrameDev &f, const float *D, co
 #pragma unroll
     for (int j = 0; j < 4; ++j) U = __builtin_amdgcn_mfma_f32_16x16x4f32(dha[j], Sx[j], U, 0, 0, 0);
     long long ob[kWaveItems];
+    int fb[kWaveItems];
 #pragma unroll
-    for (int g = 0; g < kWaveItems; ++g) ob[g] = lane_i64(v ? ob1 : ob0, 16 * g);
+    for (int g = 0; g < kWaveItems; ++g) {
+      ob[g] = lane_i64(v ? ob1 : ob0, 16 * g);
+      fb[g] = __builtin_amdgcn_readlane(fi, 16 * g);
+    }
     const long long o = b == 0 ? ob[0] : b == 1 ? ob[1] : b == 2 ? ob[2] : ob[3];
+    const PlaneOut po = plane_out(f, b == 0 ? fb[0] : b == 1 ? fb[1] : b == 2 ? fb[2] : fb[3]);
     if ((okmask >> b) & 1u) {
       const float a = st.a[b][v];
 #pragma unroll
@@ -804,9 +813,8 @@ __device__ __forceinline__ f4 mma16(f4 acc, const float a[4], const float b[4]) 
 template <int R, int EV>
 __device__ __forceinline__ void fast_eval16(const FrameDev &f, const float *D, const FastStage &st,
                                             int lane, unsigned okmask, int nvw, int w, int h,
-                                            int W, long long ob0, long long ob1) {
+                                            int W, long long ob0, long long ob1, int fi) {
   constexpr int nch = (R + 15) / 16;
-  const PlaneOut po = plane_out(f, blockIdx.y);
   const float *Dw = D, *Dh = D + kDct16Floats, *lam = D + 2 * kDct16Floats;
   const int lo = lane & 15, hi = lane >> 4;
   float lam4[4], dwb[4], dha[4];
@@ -842,6 +850,7 @@ __device__ __forceinline__ void fast_eval16(const FrameDev &f, const float *D, c
       const f4 U = mma16<EV>(f4{0.f, 0.f, 0.f, 0.f}, dha, sx);  // U[y = 4 hi + r][x = lo]
       const float av = st.a[g][v];
       const long long o = lane_i64(v ? ob1 : ob0, 16 * g);
+      const PlaneOut po = plane_out(f, __builtin_amdgcn_readlane(fi, 16 * g));
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int y = 4 * hi + j, x = lo;
@@ -853,15 +862,15 @@ __device__ __forceinline__ void fast_eval16(const FrameDev &f, const float *D, c
 
 // The evaluation in the launch's dtype EV (a template parameter of k_fast:
 // each kernel holds one evaluation, which keeps its code small).
-template <int R, int EV>
+template <int R, int EV, bool UNR2 = true>
 __device__ __forceinline__ void fast_eval_any(const FrameDev &f, const float *D, const FastStage &st,
                                               int lane, unsigned okmask, int nvw, int w, int h, int W,
-                                              long long ob0, long long ob1) {
+                                              long long ob0, long long ob1, int fi) {
   if constexpr (EV != 0) {
-    fast_eval16<R, EV>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1);
+    fast_eval16<R, EV>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1, fi);
   } else {
-    if (f.b == 8) fast_eval8<R>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1);
-    else fast_eval<R>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1);
+    if (f.b == 8) fast_eval8<R>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1, fi);
+    else fast_eval<R, UNR2>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1, fi);
   }
 }
 
@@ -948,7 +957,8 @@ void k_fast(FrameDev f) {
   if (tid < kFastItems) {
     FastItem r;
     r.cls = kClassNone;
-    r.m = r.K = r.base = r.nv = r.pad_ = 0;
+    r.m = r.K = r.base = r.nv = 0;
+    r.fi = blockIdx.y;
     r.vb0 = r.vb1 = r.ob0 = r.ob1 = 0;
     if (has) {
       r.m = im;
@@ -1003,10 +1013,12 @@ void k_fast(FrameDev f) {
       else if (Kw <= 23) fast_coef_stage<24>(f, items, slot, ok, t, gi, w, h, G, st);
       else fast_coef_stage<32>(f, items, slot, ok, t, gi, w, h, G, st);
     } else {
-      if (ENC && Kw <= 7) solved = fast_solve<8>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
-      else if (Kw <= 15) solved = fast_solve<16>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
-      else if (Kw <= 23) solved = fast_solve<24>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
-      else solved = fast_solve<32>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st);
+      const uint16_t *posp = f.fp[blockIdx.y].pos;
+      const float *vals = f.fp[blockIdx.y].values;
+      if (ENC && Kw <= 7) solved = fast_solve<8>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st, posp, vals);
+      else if (Kw <= 15) solved = fast_solve<16>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st, posp, vals);
+      else if (Kw <= 23) solved = fast_solve<24>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st, posp, vals);
+      else solved = fast_solve<32>(f, items, slot, ok, t, gi, Kw, w, h, tabs, st, posp, vals);
     }
     if (ok && !solved && t == 0) {
       if (f.tail_in_wg) defer[slot] = 1;
@@ -1029,9 +1041,10 @@ void k_fast(FrameDev f) {
       else fast_encode_store<32>(f, items, slot, eval, t, gi, G, st);
     } else if (okmask) {
       const float *D = tabs + (COEF ? 0 : S.jt_floats);
-      if (Kw <= 15) fast_eval_any<16, EV>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
-      else if (Kw <= 23) fast_eval_any<24, EV>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
-      else fast_eval_any<32, EV>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1);
+      const int fi = blockIdx.y;
+      if (Kw <= 15) fast_eval_any<16, EV>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1, fi);
+      else if (Kw <= 23) fast_eval_any<24, EV>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1, fi);
+      else fast_eval_any<32, EV>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1, fi);
     }
   }
 
@@ -1049,6 +1062,296 @@ void k_fast(FrameDev f) {
         general_block<16>(f, 0, items[j].m, gs, slot_mem);
       }
     }
+  }
+}
+
+// ------------------------------------------- binned wave-level path (b <= 16)
+
+// Bordered-system size class of a block for k_fast2: R = 4 (c + 1) rows,
+// the smallest multiple of 4 that holds the K + 1 rows (K = 1 .. 31).
+__device__ __forceinline__ int fast2_class(int K) { return ((K + 4) >> 2) - 1; }
+
+// Binning for k_fast2: every mask block of every frame of the launch whose
+// system the wave-level path solves goes to the queue of its mask-plane
+// group and edge kind (so a queue holds blocks of one shape, one plane width
+// and one value-plane count), into the bin of its size class; the others
+// (K = 0, K = w*h, K > 31, invalid counts) go to the general path's lists.
+// Entries are (frame << 24) | block.  Bins 2p and 2p + 1 of a queue share
+// region p of it (one grows from the front, the other from the back;
+// together they hold at most every block of the queue, so they never meet).
+// Three passes without global atomics (counting, a scan per bin, placing):
+// thousands of workgroups adding to a few dozen counters serialise.  The
+// order inside a bin is that of the blocks (frame, then block index).
+constexpr int kBinThreads = 256;
+constexpr int kMaxBins = 8 * kMaxSegs;
+
+// The bin of mask block m of frame fi (-1: not queued), and its shape.
+__device__ __forceinline__ int fbin_key(const FrameDev &f, int fi, int m, bool defer) {
+  if (m >= f.n_items) return -1;
+  const int32_t *bp = f.fp[fi].block_ptr;
+  int g = 0;
+  if (f.ngroups > 1 && m >= f.g[1].first) g = 1;
+  if (f.ngroups > 2 && m >= f.g[2].first) g = 2;
+  const GroupDev &G = f.g[g];
+  const int l = m - G.first, bx = l % G.nbx, by = l / G.nbx;
+  const int e = ((bx == G.nbx - 1) && (G.W % f.b) ? 1 : 0) + ((by == G.nby - 1) && (G.H % f.b) ? 2 : 0);
+  const int shape = G.shape[e];
+  const int w = f.s[shape].w, h = f.s[shape].h;
+  const int K = bp[m + 1] - bp[m];
+  if (K < 1 || K >= w * h || K > kFastKMax) {
+    if (defer) push_deferred(f, fi, m, K, w, h);
+    return -1;
+  }
+  return 8 * f.qge[g][e] + fast2_class(K);
+}
+
+// Per wave: how many of its lanes fall in each bin (wc[wave][bin]) and each
+// lane's rank among them (lanes in order).
+__device__ __forceinline__ int fbin_wave_rank(int key, int (*wc)[kMaxBins]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int rank = 0;
+  unsigned long long todo = __ballot(key >= 0);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int k = __shfl(key, leader);
+    const unsigned long long mine = __ballot(key == k);
+    todo &= ~mine;
+    if (key == k) rank = __popcll(mine & ((1ull << lane) - 1ull));
+    if (lane == leader) wc[wv][k] = __popcll(mine);
+  }
+  return rank;
+}
+
+// Pass 1: the count of every bin in each workgroup's 256 blocks (one frame).
+__global__ __launch_bounds__(kBinThreads) void k_fbin_count(FrameDev f) {
+  __shared__ int wc[kBinThreads / 64][kMaxBins];
+  const int nb = 8 * f.nq, tid = threadIdx.x;
+  for (int i = tid; i < (kBinThreads / 64) * kMaxBins; i += kBinThreads) (&wc[0][0])[i] = 0;
+  __syncthreads();
+  const int key = fbin_key(f, blockIdx.y, blockIdx.x * kBinThreads + tid, true);
+  fbin_wave_rank(key, wc);
+  __syncthreads();
+  if (tid < nb) {
+    int t = 0;
+#pragma unroll
+    for (int w = 0; w < kBinThreads / 64; ++w) t += wc[w][tid];
+    f.hist[(long long)(blockIdx.y * gridDim.x + blockIdx.x) * nb + tid] = t;
+  }
+}
+
+// Pass 2: one workgroup per bin: exclusive scan of its counts over the
+// workgroups of pass 1 (in place) and the bin's total into its counter.
+__global__ __launch_bounds__(kBinThreads) void k_fbin_scan(FrameDev f, int nwg) {
+  __shared__ int wsum[kBinThreads / 64];
+  const int nb = 8 * f.nq, bin = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int carry = 0;
+  for (int w0 = 0; w0 < nwg; w0 += kBinThreads) {
+    const int w = w0 + tid;
+    const int v = w < nwg ? f.hist[(long long)w * nb + bin] : 0;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int off = carry, tot = carry;
+#pragma unroll
+    for (int k = 0; k < kBinThreads / 64; ++k) {
+      off += k < wv ? wsum[k] : 0;
+      tot += wsum[k];
+    }
+    if (w < nwg) f.hist[(long long)w * nb + bin] = off + x - v;
+    carry = tot;
+    __syncthreads();
+  }
+  if (tid == 0) f.counters[kQueueCounters + bin] = carry;
+}
+
+// Pass 3: every queued block to its place in its bin.
+__global__ __launch_bounds__(kBinThreads) void k_fbin_place(FrameDev f) {
+  __shared__ int wc[kBinThreads / 64][kMaxBins];
+  const int nb = 8 * f.nq, tid = threadIdx.x, wv = tid >> 6;
+  for (int i = tid; i < (kBinThreads / 64) * kMaxBins; i += kBinThreads) (&wc[0][0])[i] = 0;
+  __syncthreads();
+  const int fi = blockIdx.y, m = blockIdx.x * kBinThreads + tid;
+  const int key = fbin_key(f, fi, m, false);
+  const int rank = fbin_wave_rank(key, wc);
+  __syncthreads();
+  if (key >= 0) {
+    int idx = f.hist[(long long)(blockIdx.y * gridDim.x + blockIdx.x) * nb + key] + rank;
+    for (int w = 0; w < wv; ++w) idx += wc[w][key];
+    const QueueDev &Q = f.q[key >> 3];
+    const int c = key & 7, cap = Q.count * f.nframes;
+    int *region = f.binlist + Q.base + (long long)(c >> 1) * cap;
+    if (idx < cap) region[(c & 1) ? cap - 1 - idx : idx] = (fi << kDeferFrameShift) | m;
+  }
+}
+
+// The wave-level solve and evaluation of one workgroup's blocks, all of one
+// size class R (R rows per block system, four blocks per wave).
+template <int R, int EV>
+__device__ __forceinline__ void fast2_body(const FrameDev &f, const FastItem *items, const uint16_t *const *ipos,
+                                           const float *const *ivals, FastStage &st, const float *tabs,
+                                           const ShapeDev &S, int W) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int gi = lane >> 4, t = lane & 15;
+  const int slot = wv * kWaveItems + gi;
+  const bool ok = items[slot].cls < kClassDefer;
+  int kw = ok ? items[slot].K : 0, nvw = ok ? items[slot].nv : 0;
+  for (int o = 32; o > 0; o >>= 1) {
+    kw = max(kw, __shfl_xor(kw, o));
+    nvw = max(nvw, __shfl_xor(nvw, o));
+  }
+  const int Kw = __builtin_amdgcn_readfirstlane(kw);
+  const int NVw = __builtin_amdgcn_readfirstlane(nvw);
+  if (Kw == 0) return;  // no block in this wave
+  const int w = S.w, h = S.h;
+  // (for two-slice systems the lookups go in chunks of 4 columns and the
+  // evaluation's point chunks one at a time: the register file then holds
+  // four waves per SIMD for every class)
+  const bool solved = fast_solve<R, R <= 16 ? (R % 8 == 0 ? 8 : 4) : 4>(f, items, slot, ok, t, gi, Kw, w, h, tabs,
+                                                                         st, ipos[slot], ivals[slot]);
+  if (ok && !solved && t == 0) push_deferred(f, items[slot].fi, items[slot].m, items[slot].K, w, h);
+  const bool eval = ok && solved;
+  wave_sync();
+  const unsigned long long em = __ballot(eval);
+  unsigned okmask = 0;
+#pragma unroll
+  for (int g = 0; g < kWaveItems; ++g) okmask |= ((em >> (16 * g)) & 1ull) ? (1u << g) : 0u;
+  if (okmask)
+    fast_eval_any<R, EV, false>(f, tabs + S.jt_floats, st, lane, okmask, NVw, w, h, W, items[slot].ob0,
+                                items[slot].ob1, items[slot].fi);
+}
+
+// Residual decodes with b <= 16, binned (k_fbin first): each workgroup takes
+// up to f.ipw blocks of one bin - one block shape and one size class - so
+// every wave solves four systems of nearly the same size with code sized for
+// them, and workgroups of one class run one after another (bins are handed
+// out class by class, the largest systems first).  The block arithmetic is
+// that of k_fast (same solve and evaluation, padding rows and columns are
+// exact identities and zeros), so results do not depend on the path.
+template <int EV>
+__global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_fast2(FrameDev f) {
+  extern __shared__ __attribute__((aligned(16))) float tabs[];  // J, Dw, Dh, lam of the bin's shape
+  __shared__ FastItem items[kFastItems];
+  __shared__ const uint16_t *ipos[kFastItems];
+  __shared__ const float *ivals[kFastItems];
+  __shared__ FastStage stage[kFastWaves];
+  __shared__ int sbin[3];
+  const int tid = threadIdx.x, wg = blockIdx.x;
+  // This workgroup's bin: bins in hand-out order (class 7 .. 0, queues in
+  // order), ceil(count / ipw) workgroups each; wave 0 scans the bins 64 at
+  // a time (8 classes x at most 12 queues).
+  if (tid < 64) {
+    const int nb = 8 * f.nq;
+    if (tid == 0) sbin[0] = -1;
+    int carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += 64) {
+      const int b = b0 + tid;
+      int qi = 0, c = 0, cnt = 0;
+      if (b < nb) {
+        c = 7 - b / f.nq;
+        qi = b % f.nq;
+        cnt = f.counters[kQueueCounters + 8 * qi + c];
+      }
+      const int nw = (cnt + f.ipw - 1) / f.ipw;
+      int incl = nw;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int x = __shfl_up(incl, o, 64);
+        if (tid >= o) incl += x;
+      }
+      incl += carry;
+      if (b < nb && wg >= incl - nw && wg < incl) {
+        sbin[0] = qi;
+        sbin[1] = c;
+        sbin[2] = (wg - (incl - nw)) * f.ipw;
+      }
+      carry = __shfl(incl, 63, 64);
+    }
+  }
+  __syncthreads();
+  const int qi = __builtin_amdgcn_readfirstlane(sbin[0]);
+  if (qi < 0) return;  // uniform: no bin reaches this workgroup
+  const int c = __builtin_amdgcn_readfirstlane(sbin[1]), p0 = __builtin_amdgcn_readfirstlane(sbin[2]);
+  const QueueDev Q = f.q[qi];
+  const ShapeDev S = f.s[Q.shape];
+  const int count = f.counters[kQueueCounters + 8 * qi + c];
+  const int cap = Q.count * f.nframes;
+  const int *region = f.binlist + Q.base + (long long)(c >> 1) * cap;
+  // the blocks (queue entries first: their loads are issued before the tables')
+  const int p = p0 + tid;
+  const bool has = tid < f.ipw && p < count && count <= cap;
+  int e = 0;
+  if (has) e = region[(c & 1) ? cap - 1 - p : p];
+  {  // J and the evaluation's matrices into LDS (16-byte loads, all in flight before the first store)
+    const int n4 = (S.jt_floats + 3 * kDct16Floats) >> 2;
+    const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + S.fast);
+    f4 *dst = reinterpret_cast<f4 *>(tabs);
+    f4 buf[kTabVec];
+#pragma unroll
+    for (int r = 0; r < kTabVec; ++r) buf[r] = src[tid + r * kFastThreads];  // buffer is padded
+#pragma unroll
+    for (int r = 0; r < kTabVec; ++r) asm volatile("" : "+v"(buf[r]));
+#pragma unroll
+    for (int r = 0; r < kTabVec; ++r) {
+      const int i = tid + r * kFastThreads;
+      if (i < n4) dst[i] = buf[r];
+    }
+  }
+  int W;
+  if (tid < kFastItems) {
+    FastItem r;
+    r.cls = kClassNone;
+    r.m = r.K = r.base = r.nv = r.fi = 0;
+    r.vb0 = r.vb1 = r.ob0 = r.ob1 = 0;
+    const uint16_t *pp = nullptr;
+    const float *vv = nullptr;
+    if (has) {
+      const int fi = e >> kDeferFrameShift, m = e & kDeferItemMask;
+      int g = 0;
+      if (f.ngroups > 1 && m >= f.g[1].first) g = 1;
+      if (f.ngroups > 2 && m >= f.g[2].first) g = 2;
+      const GroupDev &G = f.g[g];
+      const int l = m - G.first, bx = l % G.nbx, by = l / G.nbx;
+      const FramePtrs fp = f.fp[fi];
+      const int lo = fp.block_ptr[m], hi = fp.block_ptr[m + 1];
+      r.m = m;
+      r.fi = fi;
+      r.K = hi - lo;
+      r.base = lo;
+      r.nv = G.nv;
+      r.cls = 0;  // taken (the size class is the workgroup's)
+      const long long pix = (long long)(by * f.b) * G.W + bx * f.b;
+      r.vb0 = lo;
+      r.ob0 = G.out_off[0] + pix;
+      if (G.nv > 1) {
+        // a shared chroma mask: the Cr run follows every other value
+        r.vb1 = f.shared ? (long long)fp.block_ptr[f.n_items] - fp.block_ptr[f.chroma_first] + lo : lo;
+        r.ob1 = G.out_off[1] + pix;
+      }
+      pp = fp.pos;
+      vv = fp.values;
+    }
+    items[tid] = r;
+    ipos[tid] = pp;
+    ivals[tid] = vv;
+  }
+  W = f.g[Q.first_wg].W;  // the queue's group (binned queues keep it in first_wg)
+  __syncthreads();
+  FastStage &st = stage[tid >> 6];
+  switch (c) {
+    case 0: fast2_body<4, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
+    case 1: fast2_body<8, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
+    case 2: fast2_body<12, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
+    case 3: fast2_body<16, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
+    case 4: fast2_body<20, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
+    case 5: fast2_body<24, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
+    case 6: fast2_body<28, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
+    default: fast2_body<32, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
   }
 }
 
@@ -1166,6 +1469,23 @@ hipError_t launch_fast(const FrameDev &f, hipStream_t stream) {
       case 3: hipLaunchKernelGGL((k_fast<0, 3>), g, b, lds, stream, f); break;
       default: hipLaunchKernelGGL((k_fast<0, 0>), g, b, lds, stream, f); break;
     }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fast2(const FrameDev &f, hipStream_t stream) {
+  if (f.fast_wgs == 0) return hipSuccess;
+  const dim3 bg((f.n_items + kBinThreads - 1) / kBinThreads, f.nframes);
+  hipLaunchKernelGGL(k_fbin_count, bg, dim3(kBinThreads), 0, stream, f);
+  hipLaunchKernelGGL(k_fbin_scan, dim3(8 * f.nq), dim3(kBinThreads), 0, stream, f, (int)(bg.x * bg.y));
+  hipLaunchKernelGGL(k_fbin_place, bg, dim3(kBinThreads), 0, stream, f);
+  const size_t lds = sizeof(float) * (size_t)f.fast_lds;
+  const dim3 g(f.fast_wgs), b(kFastThreads);
+  switch (f.eval) {
+    case 1: hipLaunchKernelGGL((k_fast2<1>), g, b, lds, stream, f); break;
+    case 2: hipLaunchKernelGGL((k_fast2<2>), g, b, lds, stream, f); break;
+    case 3: hipLaunchKernelGGL((k_fast2<3>), g, b, lds, stream, f); break;
+    default: hipLaunchKernelGGL((k_fast2<0>), g, b, lds, stream, f); break;
   }
   return hipGetLastError();
 }
