@@ -696,7 +696,7 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
       base += 4ll * S.count * n;
       F.nq++;  // queue k is segment k (F.qge was filled with the segments)
     }
-    F.fast_wgs = (int)((nitems * n + ipw - 1) / ipw) + 8 * F.nq;
+    F.fast_wgs = (int)((nitems * n + 15) / 16) + 8 * F.nq;  // k_fast2 takes 16 blocks per workgroup
   }
   if (wide) {
     // One queue per block shape, the smallest first so that the few edge

@@ -378,13 +378,26 @@ __device__ __forceinline__ long long lane_i64(long long v, int src) {
   return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
-// Reductions over the 16 lanes of a DPP row.
+// Minimum / maximum over the 16 lanes of a DPP row, in DPP lane moves
+// (quad swaps, then the half-row and row mirrors): no LDS round trip.
+__device__ __forceinline__ float row_dpp(float v, int ctrl) {
+  int r = 0;
+  switch (ctrl) {
+    case 0: r = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false); break;   // quad [1,0,3,2]
+    case 1: r = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false); break;   // quad [2,3,0,1]
+    case 2: r = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xF, 0xF, false); break;  // row_half_mirror
+    default: r = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x140, 0xF, 0xF, false); break; // row_mirror
+  }
+  return __builtin_bit_cast(float, r);
+}
 __device__ __forceinline__ float row_min(float v) {
-  for (int o = 8; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 16));
+#pragma unroll
+  for (int c = 0; c < 4; ++c) v = fminf(v, row_dpp(v, c));
   return v;
 }
 __device__ __forceinline__ float row_max(float v) {
-  for (int o = 8; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 16));
+#pragma unroll
+  for (int c = 0; c < 4; ++c) v = fmaxf(v, row_dpp(v, c));
   return v;
 }
 
@@ -474,7 +487,12 @@ __device__ __forceinline__ void fast_coef_stage(const FrameDev &f, const FastIte
 // row-pair Green table of the workgroup's shape (LDS).  Returns false for a
 // block whose pivots call for FP64 refinement; such blocks are left to the
 // general path, which refines.
-template <int R, int KCH = (R % 8 == 0 ? 8 : 4)>
+//
+// BIN: the wave's blocks come from one size class of the binned path, so
+// every taken block has K >= R - 4 (columns and rows below R - 4 hold
+// Green's-function entries only, and the first R - 4 elimination steps are
+// never past a block's border).
+template <int R, int KCH = (R % 8 == 0 ? 8 : 4), bool BIN = false>
 __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *items, int slot, bool ok,
                                            int t, int gi, int Kw, int w, int h, const float *J,
                                            FastStage &st, const uint16_t *posp, const float *vals) {
@@ -482,6 +500,9 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *it
   constexpr int NV = 2;
   const int K = ok ? items[slot].K : 0;
   const int N = w * h, W1 = w + 1;
+  // y = floor(p / w) for p < 256, w <= 16: (p + 1/2) / w is at least 1/32
+  // away from an integer, far beyond the rounding of the reciprocal
+  const float rw = __builtin_amdgcn_rcpf((float)w);
   int xr[NS], yr[NS];
   float T[NS][NV];
   int bad = 0;
@@ -498,8 +519,8 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *it
         if (p >= N || (i > 0 && (int)posp[base + i - 1] >= p)) bad |= kStatusMask;
       }
       p = min(p, N - 1);
-      xr[s] = p % w;
-      yr[s] = p / w;
+      yr[s] = (int)(((float)p + 0.5f) * rw);
+      xr[s] = p - yr[s] * w;
       T[s][0] = vals[items[slot].vb0 + i];
       if (items[slot].nv > 1) T[s][1] = vals[items[slot].vb1 + i];
       if (f.validate && !(isfinite(T[s][0]) && isfinite(T[s][1]))) bad |= kStatusValue;
@@ -572,7 +593,12 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *it
     const bool prow = i < K, brow = i == K;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
+      if (BIN && k < R - 4 && 16 * s + 15 < R - 4) continue;  // every row and column a point's
       const float inner = prow ? A[s][k] : (brow ? 1.f : 0.f);            // columns k < K
+      if (BIN && k < R - 4) {
+        A[s][k] = inner;
+        continue;
+      }
       const float outer = ((k == K) && prow) || (i > K && i == k) ? 1.f : 0.f;  // columns k >= K
       A[s][k] = (k < K) ? inner : outer;
     }
@@ -584,7 +610,7 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *it
   for (int s = 0; s < NS; ++s) diag[s] = 1.f;
 #pragma unroll
   for (int j = 0; j < R; ++j) {
-    if (j <= Kw) {
+    if ((BIN && j < R - 4) || j <= Kw) {
       const int jl = j & 15, js = j >> 4;
       const float piv = bcast_f(A[js][j], jl);
       const float rp = __builtin_amdgcn_rcpf(piv);
@@ -647,9 +673,39 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *it
   return !need;
 }
 
+// Four consecutive pixels of one row: one 16-byte store (FP32 planes) or one
+// 4-byte store (int8 planes) where the address is aligned for it, else one
+// store per pixel; pixels from x0 + n on are outside the block (n <= 4).
+__device__ __forceinline__ void store_px4(const PlaneOut &po, unsigned idx, const float u[4], int n) {
+  if (po.i8) {
+    int8_t q[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) q[r] = (int8_t)(int)fminf(fmaxf(__builtin_rintf(u[r]), -128.f), 127.f);
+    if (n == 4 && (reinterpret_cast<uintptr_t>(po.i8 + idx) & 3u) == 0) {
+      *reinterpret_cast<int *>(po.i8 + idx) =
+          (int)((unsigned)(uint8_t)q[0] | ((unsigned)(uint8_t)q[1] << 8) | ((unsigned)(uint8_t)q[2] << 16) |
+                ((unsigned)(uint8_t)q[3] << 24));
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (r < n) po.i8[idx + r] = q[r];
+    }
+  } else if (n == 4 && (reinterpret_cast<uintptr_t>(po.f32 + idx) & 15u) == 0) {
+    *reinterpret_cast<f4 *>(po.f32 + idx) = f4{u[0], u[1], u[2], u[3]};
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (r < n) po.f32[idx + r] = u[r];
+  }
+}
+
 // u = Dh^T (lam .* (Dw[:,X] diag(c) Dh[:,Y]^T)^T) Dw + a for the wave's 4
 // blocks (one shape), as interleaved FP32 MFMA 16x16x4 chains: lane l supplies
 // A[l%16][l/16] and B[l/16][l%16]; the result D[4(l/16)+r][l%16] is register r.
+// Both value planes of a shared chroma mask go through the point chunks
+// together (they share every gathered operand but the coefficient).  The
+// last product is taken as U^T = S^T Dh, so that lane l holds pixels
+// x = 4(l/16) .. 4(l/16)+3 of row y = l%16: one 16-byte store per lane.
 template <int R, bool UNR2 = true>
 __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, const FastStage &st,
                                           int lane, unsigned okmask, int nvw, int w, int h,
@@ -665,51 +721,72 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
     dwb[j] = Dw[pq * kDct16Ld + lo];    // Dw[p][x], p = 4 hi + j, x = lo
     dha[j] = Dh[pq * kDct16Ld + lo];    // Dh[q][y], q = 4 hi + j, y = lo
   }
-  for (int v = 0; v < nvw; ++v) {
-    f4 acc[kWaveItems];
+  f4 acc[2][kWaveItems];
 #pragma unroll
-    for (int g = 0; g < kWaveItems; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int v = 0; v < 2; ++v)
+#pragma unroll
+    for (int g = 0; g < kWaveItems; ++g) acc[v][g] = f4{0.f, 0.f, 0.f, 0.f};
+  if (nvw > 1) {
+#pragma unroll UNR2 ? 2 : 1
+    for (int ch = 0; ch < nch; ++ch) {
+      float a0[kWaveItems], a1[kWaveItems], bop[kWaveItems];
+#pragma unroll
+      for (int g = 0; g < kWaveItems; ++g) {
+        const FastPoint P = st.p[g][ch * 4 + hi];
+        const float dw = Dw[lo * kDct16Ld + P.x];
+        a0[g] = P.c0 * dw;                      // A[p][i], p = lo
+        a1[g] = P.c1 * dw;
+        bop[g] = Dh[lo * kDct16Ld + P.y];       // B[i][q], q = lo
+      }
+#pragma unroll
+      for (int g = 0; g < kWaveItems; ++g) {
+        acc[0][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[g], bop[g], acc[0][g], 0, 0, 0);
+        acc[1][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[g], bop[g], acc[1][g], 0, 0, 0);
+      }
+    }
+  } else {
 #pragma unroll UNR2 ? 2 : 1
     for (int ch = 0; ch < nch; ++ch) {
       float aop[kWaveItems], bop[kWaveItems];
 #pragma unroll
       for (int g = 0; g < kWaveItems; ++g) {
         const FastPoint P = st.p[g][ch * 4 + hi];
-        aop[g] = (v ? P.c1 : P.c0) * Dw[lo * kDct16Ld + P.x];  // A[p][i], p = lo
-        bop[g] = Dh[lo * kDct16Ld + P.y];                      // B[i][q], q = lo
+        aop[g] = P.c0 * Dw[lo * kDct16Ld + P.x];
+        bop[g] = Dh[lo * kDct16Ld + P.y];
       }
 #pragma unroll
       for (int g = 0; g < kWaveItems; ++g)
-        acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[g], bop[g], acc[g], 0, 0, 0);
+        acc[0][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[g], bop[g], acc[0][g], 0, 0, 0);
     }
-    // acc[g][j] = V^T[p = 4 hi + j][q = lo]; scale by lam[q][p], then
-    // S[q][x] = sum_p U^[q][p] Dw[p][x] and U[y][x] = sum_q Dh[q][y] S[q][x].
-    f4 Sx[kWaveItems], U[kWaveItems];
+  }
+  for (int v = 0; v < nvw; ++v) {
+    // acc[v][g][j] = V^T[p = 4 hi + j][q = lo]; scale by lam[q][p], then
+    // S[q][x] = sum_p U^[q][p] Dw[p][x] and U^T[x][y] = sum_q S[q][x] Dh[q][y].
+    f4 Sx[kWaveItems], Ut[kWaveItems];
 #pragma unroll
     for (int g = 0; g < kWaveItems; ++g) Sx[g] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int g = 0; g < kWaveItems; ++g)
-        Sx[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(acc[g][j] * lam4[j], dwb[j], Sx[g], 0, 0, 0);
+        Sx[g] = __builtin_amdgcn_mfma_f32_16x16x4f32((v ? acc[1][g][j] : acc[0][g][j]) * lam4[j], dwb[j], Sx[g],
+                                                     0, 0, 0);
 #pragma unroll
-    for (int g = 0; g < kWaveItems; ++g) U[g] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int g = 0; g < kWaveItems; ++g) Ut[g] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int g = 0; g < kWaveItems; ++g)
-        U[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(dha[j], Sx[g][j], U[g], 0, 0, 0);
+        Ut[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(Sx[g][j], dha[j], Ut[g], 0, 0, 0);
+    const int y = lo, x0 = 4 * hi, n = min(4, w - x0);
 #pragma unroll
     for (int g = 0; g < kWaveItems; ++g) {
       if (!((okmask >> g) & 1u)) continue;
       const float a = st.a[g][v];
       const long long o = lane_i64(v ? ob1 : ob0, 16 * g);
       const PlaneOut po = plane_out(f, __builtin_amdgcn_readlane(fi, 16 * g));
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int y = 4 * hi + j, x = lo;
-        if (x < w && y < h) store_px(po, (unsigned)(o + (long long)y * W + x), U[g][j] + a);
-      }
+      const float u[4] = {Ut[g][0] + a, Ut[g][1] + a, Ut[g][2] + a, Ut[g][3] + a};
+      if (y < h && n > 0) store_px4(po, (unsigned)(o + (long long)y * W + x0), u, n);
     }
   }
 }
@@ -1191,6 +1268,12 @@ __global__ __launch_bounds__(kBinThreads) void k_fbin_place(FrameDev f) {
 
 // The wave-level solve and evaluation of one workgroup's blocks, all of one
 // size class R (R rows per block system, four blocks per wave).
+constexpr int kF2Threads = 256;                  // k_fast2: 4 waves per workgroup
+constexpr int kF2Waves = kF2Threads / 64;
+constexpr int kF2Items = kF2Waves * kWaveItems;  // 16 blocks per workgroup
+constexpr int kTabVec2 = ((16 * jrow(16, 16) + 3) / 4 + 3 * kDct16Floats / 4 + kF2Threads - 1) / kF2Threads;
+static_assert(kTabVec2 * kF2Threads * 4 <= kTabPadFloats, "table reads stay inside the padded buffer");
+
 template <int R, int EV>
 __device__ __forceinline__ void fast2_body(const FrameDev &f, const FastItem *items, const uint16_t *const *ipos,
                                            const float *const *ivals, FastStage &st, const float *tabs,
@@ -1199,20 +1282,19 @@ __device__ __forceinline__ void fast2_body(const FrameDev &f, const FastItem *it
   const int gi = lane >> 4, t = lane & 15;
   const int slot = wv * kWaveItems + gi;
   const bool ok = items[slot].cls < kClassDefer;
-  int kw = ok ? items[slot].K : 0, nvw = ok ? items[slot].nv : 0;
-  for (int o = 32; o > 0; o >>= 1) {
-    kw = max(kw, __shfl_xor(kw, o));
-    nvw = max(nvw, __shfl_xor(nvw, o));
-  }
-  const int Kw = __builtin_amdgcn_readfirstlane(kw);
-  const int NVw = __builtin_amdgcn_readfirstlane(nvw);
+  const int kw = ok ? items[slot].K : 0, nvw = ok ? items[slot].nv : 0;
+  // (uniform in each 16-lane row: the wave's largest from one lane per row)
+  const int Kw = max(max(__builtin_amdgcn_readlane(kw, 0), __builtin_amdgcn_readlane(kw, 16)),
+                     max(__builtin_amdgcn_readlane(kw, 32), __builtin_amdgcn_readlane(kw, 48)));
+  const int NVw = max(max(__builtin_amdgcn_readlane(nvw, 0), __builtin_amdgcn_readlane(nvw, 16)),
+                      max(__builtin_amdgcn_readlane(nvw, 32), __builtin_amdgcn_readlane(nvw, 48)));
   if (Kw == 0) return;  // no block in this wave
   const int w = S.w, h = S.h;
   // (for two-slice systems the lookups go in chunks of 4 columns and the
   // evaluation's point chunks one at a time: the register file then holds
   // four waves per SIMD for every class)
-  const bool solved = fast_solve<R, R <= 16 ? (R % 8 == 0 ? 8 : 4) : 4>(f, items, slot, ok, t, gi, Kw, w, h, tabs,
-                                                                         st, ipos[slot], ivals[slot]);
+  const bool solved = fast_solve<R, R <= 16 ? (R % 8 == 0 ? 8 : 4) : 4, true>(f, items, slot, ok, t, gi, Kw, w, h,
+                                                                               tabs, st, ipos[slot], ivals[slot]);
   if (ok && !solved && t == 0) push_deferred(f, items[slot].fi, items[slot].m, items[slot].K, w, h);
   const bool eval = ok && solved;
   wave_sync();
@@ -1225,25 +1307,25 @@ __device__ __forceinline__ void fast2_body(const FrameDev &f, const FastItem *it
                                 items[slot].ob1, items[slot].fi);
 }
 
-// Residual decodes with b <= 16, binned (k_fbin first): each workgroup takes
-// up to f.ipw blocks of one bin - one block shape and one size class - so
+// Residual decodes with b <= 16, binned (k_fbin_* first): each workgroup takes
+// up to 16 blocks of one bin - one block shape and one size class - so
 // every wave solves four systems of nearly the same size with code sized for
 // them, and workgroups of one class run one after another (bins are handed
 // out class by class, the largest systems first).  The block arithmetic is
 // that of k_fast (same solve and evaluation, padding rows and columns are
 // exact identities and zeros), so results do not depend on the path.
 template <int EV>
-__global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ __launch_bounds__(kF2Threads) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_fast2(FrameDev f) {
   extern __shared__ __attribute__((aligned(16))) float tabs[];  // J, Dw, Dh, lam of the bin's shape
-  __shared__ FastItem items[kFastItems];
-  __shared__ const uint16_t *ipos[kFastItems];
-  __shared__ const float *ivals[kFastItems];
-  __shared__ FastStage stage[kFastWaves];
+  __shared__ FastItem items[kF2Items];
+  __shared__ const uint16_t *ipos[kF2Items];
+  __shared__ const float *ivals[kF2Items];
+  __shared__ FastStage stage[kF2Waves];
   __shared__ int sbin[3];
   const int tid = threadIdx.x, wg = blockIdx.x;
   // This workgroup's bin: bins in hand-out order (class 7 .. 0, queues in
-  // order), ceil(count / ipw) workgroups each; wave 0 scans the bins 64 at
+  // order), ceil(count / 16) workgroups each; wave 0 scans the bins 64 at
   // a time (8 classes x at most 12 queues).
   if (tid < 64) {
     const int nb = 8 * f.nq;
@@ -1257,7 +1339,7 @@ void k_fast2(FrameDev f) {
         qi = b % f.nq;
         cnt = f.counters[kQueueCounters + 8 * qi + c];
       }
-      const int nw = (cnt + f.ipw - 1) / f.ipw;
+      const int nw = (cnt + kF2Items - 1) / kF2Items;
       int incl = nw;
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) {
@@ -1268,7 +1350,7 @@ void k_fast2(FrameDev f) {
       if (b < nb && wg >= incl - nw && wg < incl) {
         sbin[0] = qi;
         sbin[1] = c;
-        sbin[2] = (wg - (incl - nw)) * f.ipw;
+        sbin[2] = (wg - (incl - nw)) * kF2Items;
       }
       carry = __shfl(incl, 63, 64);
     }
@@ -1284,26 +1366,26 @@ void k_fast2(FrameDev f) {
   const int *region = f.binlist + Q.base + (long long)(c >> 1) * cap;
   // the blocks (queue entries first: their loads are issued before the tables')
   const int p = p0 + tid;
-  const bool has = tid < f.ipw && p < count && count <= cap;
+  const bool has = tid < kF2Items && p < count && count <= cap;
   int e = 0;
   if (has) e = region[(c & 1) ? cap - 1 - p : p];
   {  // J and the evaluation's matrices into LDS (16-byte loads, all in flight before the first store)
     const int n4 = (S.jt_floats + 3 * kDct16Floats) >> 2;
     const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + S.fast);
     f4 *dst = reinterpret_cast<f4 *>(tabs);
-    f4 buf[kTabVec];
+    f4 buf[kTabVec2];
 #pragma unroll
-    for (int r = 0; r < kTabVec; ++r) buf[r] = src[tid + r * kFastThreads];  // buffer is padded
+    for (int r = 0; r < kTabVec2; ++r) buf[r] = src[tid + r * kF2Threads];  // buffer is padded
 #pragma unroll
-    for (int r = 0; r < kTabVec; ++r) asm volatile("" : "+v"(buf[r]));
+    for (int r = 0; r < kTabVec2; ++r) asm volatile("" : "+v"(buf[r]));
 #pragma unroll
-    for (int r = 0; r < kTabVec; ++r) {
-      const int i = tid + r * kFastThreads;
+    for (int r = 0; r < kTabVec2; ++r) {
+      const int i = tid + r * kF2Threads;
       if (i < n4) dst[i] = buf[r];
     }
   }
   int W;
-  if (tid < kFastItems) {
+  if (tid < kF2Items) {
     FastItem r;
     r.cls = kClassNone;
     r.m = r.K = r.base = r.nv = r.fi = 0;
@@ -1480,7 +1562,7 @@ hipError_t launch_fast2(const FrameDev &f, hipStream_t stream) {
   hipLaunchKernelGGL(k_fbin_scan, dim3(8 * f.nq), dim3(kBinThreads), 0, stream, f, (int)(bg.x * bg.y));
   hipLaunchKernelGGL(k_fbin_place, bg, dim3(kBinThreads), 0, stream, f);
   const size_t lds = sizeof(float) * (size_t)f.fast_lds;
-  const dim3 g(f.fast_wgs), b(kFastThreads);
+  const dim3 g(f.fast_wgs), b(kF2Threads);
   switch (f.eval) {
     case 1: hipLaunchKernelGGL((k_fast2<1>), g, b, lds, stream, f); break;
     case 2: hipLaunchKernelGGL((k_fast2<2>), g, b, lds, stream, f); break;
