@@ -19,6 +19,8 @@
 //    and the fallback for blocks the fast path does not take.
 #include "pdinp_device.h"
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 namespace pdi {
@@ -855,43 +857,76 @@ __device__ __forceinline__ void fast_eval8(const FrameDev &f, const float *D, co
 
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 
-// acc += A * B on a 16x16x16 MFMA with reduced-precision operands: lane l
-// supplies A[l%16][4(l/16)+e] = a[e] and B[4(l/16)+e][l%16] = b[e], e < 4.
-template <int EV>
-__device__ __forceinline__ f4 mma16(f4 acc, const float a[4], const float b[4]) {
-  if constexpr (EV == 1) {  // FP16 operands
-    h4 ha, hb;
+// MFMA operands of N values in the evaluation dtype EV: FP16 (1), BF16 (2),
+// or split BF16 (3: x = hi + lo with hi = bf16(x), lo = bf16(x - hi)).
+template <int EV, int N> struct RedOp {
+  typedef _Float16 H __attribute__((ext_vector_type(N)));
+  typedef __bf16 B __attribute__((ext_vector_type(N)));
+  typedef typename std::conditional<EV == 1, H, B>::type T;
+  T hi, lo;
+};
+
+template <int EV, int N>
+__device__ __forceinline__ RedOp<EV, N> red_op(const float *x) {
+  RedOp<EV, N> r;
+  if constexpr (EV == 1) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) { ha[e] = (_Float16)a[e]; hb[e] = (_Float16)b[e]; }
-    return __builtin_amdgcn_mfma_f32_16x16x16f16(ha, hb, acc, 0, 0, 0);
-  } else if constexpr (EV == 2) {  // BF16 operands
-    b4 ba, bb;
+    for (int e = 0; e < N; ++e) r.hi[e] = (_Float16)x[e];
+  } else if constexpr (EV == 2) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) { ba[e] = (__bf16)a[e]; bb[e] = (__bf16)b[e]; }
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ba, bb, acc, 0, 0, 0);
-  } else {  // split BF16: x = hi + lo, A B ~ hi*hi + hi*lo + lo*hi
-    b4 ah, al, bh, bl;
+    for (int e = 0; e < N; ++e) r.hi[e] = (__bf16)x[e];
+  } else {
+    // hi rounded to nearest, then the residual rounded again
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      ah[e] = (__bf16)a[e];
-      al[e] = (__bf16)(a[e] - (float)ah[e]);
-      bh[e] = (__bf16)b[e];
-      bl[e] = (__bf16)(b[e] - (float)bh[e]);
+    for (int e = 0; e < N; ++e) {
+      r.hi[e] = (__bf16)x[e];
+      r.lo[e] = (__bf16)(x[e] - (float)r.hi[e]);
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+  }
+  return r;
+}
+
+// acc += A B on a 16x16x16 MFMA (lane l: A[l%16][4(l/16)+e], B[4(l/16)+e][l%16])
+// or a 16x16x32 one (8 values per lane, k = 8(l/16)+e); split BF16 adds the
+// hi*lo and lo*hi products (lo*lo is below FP32 rounding of the sum).
+template <int EV>
+__device__ __forceinline__ f4 mma16(f4 acc, const RedOp<EV, 4> &a, const RedOp<EV, 4> &b) {
+  if constexpr (EV == 1) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a.hi, b.hi, acc, 0, 0, 0);
+  } else {
+    if constexpr (EV == 3) {
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.lo, b.hi, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.lo, acc, 0, 0, 0);
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.hi, acc, 0, 0, 0);
+  }
+}
+template <int EV>
+__device__ __forceinline__ f4 mma32(f4 acc, const RedOp<EV, 8> &a, const RedOp<EV, 8> &b) {
+  if constexpr (EV == 1) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi, b.hi, acc, 0, 0, 0);
+  } else {
+    if constexpr (EV == 3) {
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, acc, 0, 0, 0);
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, acc, 0, 0, 0);
   }
 }
 
 // The evaluation of fast_eval with FP16 / BF16 / split-BF16 operands and
-// FP32 accumulation: one 16x16x16 MFMA per 16 points and one per transform.
+// FP32 accumulation, on gfx950's matrix forms: the points of a block (at
+// most 32) in one 16x16x32 product (lane l supplies points 8(l/16) ..
+// 8(l/16)+7; both chroma planes share the Dh operand), the two transforms as
+// 16x16x16 products with the constant matrices converted once per wave, the
+// last one transposed as in fast_eval (16-byte stores).
 template <int R, int EV>
 __device__ __forceinline__ void fast_eval16(const FrameDev &f, const float *D, const FastStage &st,
                                             int lane, unsigned okmask, int nvw, int w, int h,
                                             int W, long long ob0, long long ob1, int fi) {
-  constexpr int nch = (R + 15) / 16;
   const float *Dw = D, *Dh = D + kDct16Floats, *lam = D + 2 * kDct16Floats;
   const int lo = lane & 15, hi = lane >> 4;
   float lam4[4], dwb[4], dha[4];
@@ -902,37 +937,43 @@ __device__ __forceinline__ void fast_eval16(const FrameDev &f, const float *D, c
     dwb[j] = Dw[pq * kDct16Ld + lo];
     dha[j] = Dh[pq * kDct16Ld + lo];
   }
-  for (int v = 0; v < nvw; ++v) {
+  const RedOp<EV, 4> dwo = red_op<EV, 4>(dwb), dho = red_op<EV, 4>(dha);
+  const int y = lo, x0 = 4 * hi, n = min(4, w - x0);
 #pragma unroll 1
-    for (int g = 0; g < kWaveItems; ++g) {
-      if (!((okmask >> g) & 1u)) continue;
-      f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+  for (int g = 0; g < kWaveItems; ++g) {
+    if (!((okmask >> g) & 1u)) continue;
+    // V^T of both planes: points 8 hi .. 8 hi + 7 (staged rows past K hold
+    // zero coefficients; rows past R are not staged: zeros here)
+    float a0[8], a1[8], b[8];
 #pragma unroll
-      for (int ch = 0; ch < nch; ++ch) {
-        float a[4], b[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const FastPoint P = st.p[g][ch * 16 + 4 * hi + e];
-          a[e] = (v ? P.c1 : P.c0) * Dw[lo * kDct16Ld + P.x];  // A[p = lo][i]
-          b[e] = Dh[lo * kDct16Ld + P.y];                      // B[i][q = lo]
-        }
-        acc = mma16<EV>(acc, a, b);
+    for (int e = 0; e < 8; ++e) {
+      a0[e] = a1[e] = b[e] = 0.f;
+      const int k = 8 * hi + e;
+      if (k < R) {
+        const FastPoint P = st.p[g][k];
+        const float dw = Dw[lo * kDct16Ld + P.x];
+        a0[e] = P.c0 * dw;
+        a1[e] = P.c1 * dw;
+        b[e] = Dh[lo * kDct16Ld + P.y];
       }
-      float a[4], sx[4];
+    }
+    const RedOp<EV, 8> bo = red_op<EV, 8>(b);
+    f4 acc[2];
+    acc[0] = mma32<EV>(f4{0.f, 0.f, 0.f, 0.f}, red_op<EV, 8>(a0), bo);
+    if (nvw > 1) acc[1] = mma32<EV>(f4{0.f, 0.f, 0.f, 0.f}, red_op<EV, 8>(a1), bo);
+    for (int v = 0; v < nvw; ++v) {
+      float u[4], sx[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) a[e] = acc[e] * lam4[e];  // U^[q = lo][p = 4 hi + e]
-      const f4 S = mma16<EV>(f4{0.f, 0.f, 0.f, 0.f}, a, dwb);  // S[q = 4 hi + r][x = lo]
+      for (int e = 0; e < 4; ++e) u[e] = (v ? acc[1][e] : acc[0][e]) * lam4[e];  // U^[q = lo][p = 4 hi + e]
+      const f4 S = mma16<EV>(f4{0.f, 0.f, 0.f, 0.f}, red_op<EV, 4>(u), dwo);    // S[q = 4 hi + r][x = lo]
 #pragma unroll
       for (int e = 0; e < 4; ++e) sx[e] = S[e];
-      const f4 U = mma16<EV>(f4{0.f, 0.f, 0.f, 0.f}, dha, sx);  // U[y = 4 hi + r][x = lo]
+      const f4 Ut = mma16<EV>(f4{0.f, 0.f, 0.f, 0.f}, red_op<EV, 4>(sx), dho);  // U[y = lo][x = 4 hi + r]
       const float av = st.a[g][v];
       const long long o = lane_i64(v ? ob1 : ob0, 16 * g);
       const PlaneOut po = plane_out(f, __builtin_amdgcn_readlane(fi, 16 * g));
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int y = 4 * hi + j, x = lo;
-        if (x < w && y < h) store_px(po, (unsigned)(o + (long long)y * W + x), U[j] + av);
-      }
+      const float uu[4] = {Ut[0] + av, Ut[1] + av, Ut[2] + av, Ut[3] + av};
+      if (y < h && n > 0) store_px4(po, (unsigned)(o + (long long)y * W + x0), uu, n);
     }
   }
 }
