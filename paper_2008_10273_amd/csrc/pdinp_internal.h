@@ -15,9 +15,11 @@ constexpr int kWaveItems = 4;      // blocks per wave in the wave-level path
 constexpr int kFastItemsPerWG = 16;  // blocks per workgroup of the wave-level path (b <= 16)
 constexpr int kWideItemsDefault = 2;  // blocks per workgroup of the wave-per-block path (1, 2 or 4)
 constexpr int kWideKMax = 103;       // largest K of the wave-per-block path
-// Point-count bins of the wave-per-block queues, handed out largest first:
-// bin 0 K >= 84, bin 1 K >= 64, bin 2 K >= 42, bin 3 the rest.
-constexpr int kBinK0 = 84, kBinK1 = 64, kBinK2 = 42;
+// Point-count bins of the wave-per-block queues, handed out largest first,
+// one per tile count of the bordered system (n = K + 1 rows, 16 per tile):
+// bin 0 K >= 96 (7 tiles), bin 1 K >= 80 (6), bin 2 K >= 64 (5), bin 3 the
+// rest (at most 4).
+constexpr int kBinK0 = 96, kBinK1 = 80, kBinK2 = 64;
 // Device counters: [0], [1] deferred-list lengths, [2] finished workgroups of
 // the deferred pass, then per frame fi of the launch and wave-per-block queue
 // q the lengths of its 4 bins at [kQueueCounters + 4 (fi kMaxShapes + q) + bin].

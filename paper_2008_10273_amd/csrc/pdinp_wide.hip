@@ -112,7 +112,10 @@ __device__ __forceinline__ float tab_at(const float *Hc, int byte_off) {
 // Assemble, factor and solve the bordered system of one block; stage (x, y,
 // c) of the K points and a for the evaluation.  Returns false when the pivots
 // call for FP64 refinement (the general path refines).  TN: tiles per side
-// at most (7: K <= 103; 4: K <= 63, fewer registers).
+// at most (7: K <= 103; 6: K <= 95; 5: K <= 79; 4: K <= 63: fewer registers).
+// (Making the tile count a compile-time constant for the bins of one tile
+// count turns the elimination into one straight-line region; the scheduler
+// then hoists so much that every part spills hundreds of registers.)
 template <int TN>
 __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb, int lane, int w, int h,
                                            const float *Hc, WideStage &st) {
@@ -551,15 +554,20 @@ __global__ __launch_bounds__(256) void k_bin(FrameDev f) {
 
 // One block per wave, WAVES waves per workgroup (the workgroup shares the
 // shape's tables in LDS); each wave takes the next block of its queue.
-// PART 0 takes the whole queue; batched residual decodes split it in two launches:
-// PART 1 the bins of K >= kBinK1 (up to 7 tiles per side), PART 2 the bins
-// below (at most 4 tiles: the smaller register file lets more waves share a
-// SIMD and hide the latency of the elimination's dependent steps).
+// PART 0 takes the whole queue; batched residual decodes launch one part per
+// bin, largest systems first: PART 1 bin 0 (7 tiles per side), PART 2 bin 1
+// (6), PART 3 bin 2 (5), PART 4 bin 3 (at most 4): the smaller register file
+// of the smaller systems lets more waves share a SIMD and hide the latency
+// of the elimination's dependent steps.
+template <int PART> struct WidePart {
+  static constexpr int TN = PART == 2 ? 6 : PART == 3 ? 5 : PART == 4 ? 4 : kTileN;
+  static constexpr int WMIN = TN >= 7 ? 2 : TN == 6 ? 3 : 4;  // waves per SIMD asked for
+};
 template <int WAVES, bool COEF, int PART>
 __global__ __launch_bounds__(64 * WAVES)
-__attribute__((amdgpu_waves_per_eu(PART == 2 ? 3 : 2, COEF ? 3 : (PART == 2 ? 4 : 2)))) void k_wide(FrameDev f) {
-  constexpr int TN = PART == 2 ? 4 : kTileN;
-  static_assert(PART != 2 || 16 * 4 >= kBinK1, "the small bins fit 4 tiles");
+__attribute__((amdgpu_waves_per_eu(COEF ? 2 : WidePart<PART>::WMIN, COEF ? 3 : 8))) void k_wide(FrameDev f) {
+  constexpr int TN = WidePart<PART>::TN;
+  static_assert(16 * 4 >= kBinK2 && 16 * 5 >= kBinK1 && 16 * 6 >= kBinK0, "each bin fits its part's tiles");
   extern __shared__ __attribute__((aligned(16))) float tabs[];  // Hc | Dw | Dh | lam of the shape
   __shared__ WideStage stage[WAVES];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -576,7 +584,8 @@ __attribute__((amdgpu_waves_per_eu(PART == 2 ? 3 : 2, COEF ? 3 : (PART == 2 ? 4 
   const int32_t *bp = f.fp[fi].block_ptr;
   const int *cnt = f.counters + kQueueCounters + 4 * (kMaxShapes * fi + qi);
   const int n0 = cnt[0], n1 = cnt[1], n2 = cnt[2], n3 = cnt[3];
-  const int p_lo = PART == 2 ? n0 + n1 : 0, p_hi = PART == 1 ? n0 + n1 : n0 + n1 + n2 + n3;
+  const int p_lo = PART == 2 ? n0 : PART == 3 ? n0 + n1 : PART == 4 ? n0 + n1 + n2 : 0;
+  const int p_hi = PART == 1 ? n0 : PART == 2 ? n0 + n1 : PART == 3 ? n0 + n1 + n2 : n0 + n1 + n2 + n3;
   const int p0 = p_lo + (wg - Q.first_wg) * WAVES;  // the workgroup's first position
   if (p0 >= p_hi || p0 >= Q.count) return;          // uniform: no wave of this workgroup has a block
   {  // stored-coefficient decodes need the evaluation's matrices only
@@ -662,14 +671,20 @@ hipError_t launch_wide(const FrameDev &f, hipStream_t stream) {
         case 1:
           hipLaunchKernelGGL((k_wide<1, false, 1>), grid, dim3(64), lds, stream, f);
           hipLaunchKernelGGL((k_wide<1, false, 2>), grid, dim3(64), lds, stream, f);
+          hipLaunchKernelGGL((k_wide<1, false, 3>), grid, dim3(64), lds, stream, f);
+          hipLaunchKernelGGL((k_wide<1, false, 4>), grid, dim3(64), lds, stream, f);
           break;
         case 2:
           hipLaunchKernelGGL((k_wide<2, false, 1>), grid, dim3(128), lds, stream, f);
           hipLaunchKernelGGL((k_wide<2, false, 2>), grid, dim3(128), lds, stream, f);
+          hipLaunchKernelGGL((k_wide<2, false, 3>), grid, dim3(128), lds, stream, f);
+          hipLaunchKernelGGL((k_wide<2, false, 4>), grid, dim3(128), lds, stream, f);
           break;
         case 4:
           hipLaunchKernelGGL((k_wide<4, false, 1>), grid, dim3(256), lds, stream, f);
           hipLaunchKernelGGL((k_wide<4, false, 2>), grid, dim3(256), lds, stream, f);
+          hipLaunchKernelGGL((k_wide<4, false, 3>), grid, dim3(256), lds, stream, f);
+          hipLaunchKernelGGL((k_wide<4, false, 4>), grid, dim3(256), lds, stream, f);
           break;
         default: return hipErrorInvalidValue;
       }
