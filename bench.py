@@ -50,15 +50,14 @@ sys.path.insert(0, ROOT)
 METRIC = "1080p residual frames/s at ≤0.5 grey-level error; p99 frame latency"
 HBM_PEAK_GBS = 8000.0
 EVALS = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16x2": 3}
-# HBM bytes per launch of the decode kernel from rocprofv3 FETCH_SIZE +
-# WRITE_SIZE counters, scaled by the same counters read on a copy kernel of
-# known size (profiles/*_hbm_counters.txt); only for the kernel build and
-# launch shape the counters were taken on (null after a kernel change, or
-# when the autotuned launch choice differs).
-# (config, frames per step, launch choice): bytes per launch
-TRAFFIC = {(1, 32, 16): 441958329, (2, 32, 2): 464640229, (2, 32, 4): 459408434}
-# HBM bytes of one finest-level k_hd_cg iteration of config 6 (same counters)
-TRAFFIC_HD_ITER = 85394071
+# HBM bytes per batched step from rocprofv3 FETCH_SIZE + WRITE_SIZE counters
+# of its kernels, scaled by the same counters read on a copy kernel of known
+# size (profiles/*_counters.txt); only for the kernel build the counters were
+# taken on (null after a kernel change).  (config, frames per step): bytes.
+# Config 1: k_fbin_* + k_fast2 + deferred pass (k_fast2 ignores the launch
+# choice).  Config 2's parts follow one another, and lines written back after
+# a dispatch ends are counted in a later one: no per-step figure.
+TRAFFIC = {(1, 32): 494928000}
 
 
 def algorithmic_bytes(fr) -> int:
@@ -355,8 +354,9 @@ def bench_frame(args, torch, binding, synth):
     achieved = ab / t_step / 1e9
     copy_gbs = copy_bandwidth(torch, stream=stream)
     log(f"copy kernel: {copy_gbs:.0f} GB/s")
-    kern = "k_fast" if cfg["block_size"] <= 16 else ("k_bin + k_wide (bins K >= 64, then K < 64)" if B > 1 else
-                                                     "k_bin + k_wide")
+    binned = B > 1 and fr.n_mask_blocks * B >= 32768  # the library's threshold for the binned path
+    kern = (("k_fbin_count + k_fbin_scan + k_fbin_place + k_fast2" if binned else "k_fast") if cfg["block_size"] <= 16
+            else ("k_bin + k_wide (one launch per tile count: 7, 6, 5, <= 4)" if B > 1 else "k_bin + k_wide"))
     rec = dict(metric=METRIC, value=fps, unit="frames/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=1e3 * t_step, higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="f32" if args.eval == "fp32" else f"f32 solve, {args.eval} eval", data="synthetic",
@@ -371,7 +371,7 @@ def bench_frame(args, torch, binding, synth):
                int8_output=int8,
                roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": TRAFFIC.get((args.config, B, tune_b)),
+                         "traffic": TRAFFIC.get((args.config, B)) if args.eval == "fp32" else None,
                          "kernel": kern + (" (+ deferred pass)" if B > 1 or cfg["block_size"] > 16 else ""),
                          "algorithmic_bytes_per_launch": ab, "launch_ms": 1e3 * t_step,
                          "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs},
@@ -420,7 +420,7 @@ def bench_coef(args, torch, binding, synth):
     wall = time.perf_counter() - t0
     assert dec.sync(stream) == 0, binding.pdi_last_error(dec.ctx)
     fps = B * args.steps / secs
-    timed_outs = host_outputs(ds)  # every frame of the last timed step
+    got = d["out"].cpu().numpy().astype(np.float64)
     log(f"decode: {fps:.1f} frames/s, {1e3 * secs / args.steps:.4f} ms per step of {B} frames")
     lat = []
     for _ in range(args.latency_iters):
@@ -722,7 +722,7 @@ def bench_intra(args, torch, binding, synth):
                properties={"exact_at_mask": exact_at_mask, "min": float(g.min()), "max": float(g.max())},
                roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": float(np.mean(its_all)) * TRAFFIC_HD_ITER,
+                         "traffic": None,  # the counters in profiles/ predate the current stop test
                          "kernel": "k_hd_cg, finest level (whole solve timed)",
                          "algorithmic_bytes_per_launch": ab, "launch_ms": 1e3 * secs / args.steps},
                cpu_baseline=cpu, wall_s=wall)

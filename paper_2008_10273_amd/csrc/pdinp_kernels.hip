@@ -801,7 +801,9 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
 // the work of four (fast_eval spends a zero-padded tile per block).  Lane
 // l, register r then holds pixel (y = 4 (l/16) + r, x = l%16) of the tile:
 // block 2 (x / 8) + y / 8, pixel (x % 8, y % 8).
-template <int R>
+// UNI: the wave's blocks are of one frame (k_fast), so the output planes are
+// one scalar pointer.
+template <int R, bool UNI = false>
 __device__ __forceinline__ void fast_eval8(const FrameDev &f, const float *D, const FastStage &st,
                                            int lane, unsigned okmask, int nvw, int w, int h,
                                            int W, long long ob0, long long ob1, int fi) {
@@ -843,7 +845,7 @@ __device__ __forceinline__ void fast_eval8(const FrameDev &f, const float *D, co
       fb[g] = __builtin_amdgcn_readlane(fi, 16 * g);
     }
     const long long o = b == 0 ? ob[0] : b == 1 ? ob[1] : b == 2 ? ob[2] : ob[3];
-    const PlaneOut po = plane_out(f, b == 0 ? fb[0] : b == 1 ? fb[1] : b == 2 ? fb[2] : fb[3]);
+    const PlaneOut po = plane_out(f, UNI ? fb[0] : b == 0 ? fb[0] : b == 1 ? fb[1] : b == 2 ? fb[2] : fb[3]);
     if ((okmask >> b) & 1u) {
       const float a = st.a[b][v];
 #pragma unroll
@@ -980,15 +982,19 @@ __device__ __forceinline__ void fast_eval16(const FrameDev &f, const float *D, c
 
 // The evaluation in the launch's dtype EV (a template parameter of k_fast:
 // each kernel holds one evaluation, which keeps its code small).
-template <int R, int EV, bool UNR2 = true>
+// B8: 8 x 8 blocks (the FP32 evaluation packs four per tile); a template
+// parameter of the kernels, so that a kernel holds one FP32 evaluation and
+// the register file it needs (the 16 x 16 one needs more).
+template <int R, int EV, bool UNR2 = true, bool UNI = false, int B8 = 0>
 __device__ __forceinline__ void fast_eval_any(const FrameDev &f, const float *D, const FastStage &st,
                                               int lane, unsigned okmask, int nvw, int w, int h, int W,
                                               long long ob0, long long ob1, int fi) {
   if constexpr (EV != 0) {
     fast_eval16<R, EV>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1, fi);
+  } else if constexpr (B8 != 0) {
+    fast_eval8<R, UNI>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1, fi);
   } else {
-    if (f.b == 8) fast_eval8<R>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1, fi);
-    else fast_eval<R, UNR2>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1, fi);
+    fast_eval<R, UNR2>(f, D, st, lane, okmask, nvw, w, h, W, ob0, ob1, fi);
   }
 }
 
@@ -1017,8 +1023,8 @@ __device__ __forceinline__ void fast_encode_store(const FrameDev &f, const FastI
 // MODE 0: residual decode (solve, evaluate); 1: stored coefficients
 // (evaluate only); 2: coefficient encode (solve, quantise, no evaluation).
 // EV: evaluation dtype (PDI_EVAL_*; encodes take 0).
-template <int MODE, int EV>
-__global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(3, 8)))
+template <int MODE, int EV, int B8 = 0>
+__global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_fast(FrameDev f) {
   constexpr bool COEF = MODE == 1, ENC = MODE == 2;
   extern __shared__ __attribute__((aligned(16))) float tabs[];  // J, Dw, Dh, lam of the workgroup's shape
@@ -1160,9 +1166,9 @@ void k_fast(FrameDev f) {
     } else if (okmask) {
       const float *D = tabs + (COEF ? 0 : S.jt_floats);
       const int fi = blockIdx.y;
-      if (Kw <= 15) fast_eval_any<16, EV>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1, fi);
-      else if (Kw <= 23) fast_eval_any<24, EV>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1, fi);
-      else fast_eval_any<32, EV>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1, fi);
+      if (Kw <= 15) fast_eval_any<16, EV, true, true, B8>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1, fi);
+      else if (Kw <= 23) fast_eval_any<24, EV, true, true, B8>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1, fi);
+      else fast_eval_any<32, EV, true, true, B8>(f, D, st, lane, okmask, NVw, w, h, G.W, ob0, ob1, fi);
     }
   }
 
@@ -1315,7 +1321,7 @@ constexpr int kF2Items = kF2Waves * kWaveItems;  // 16 blocks per workgroup
 constexpr int kTabVec2 = ((16 * jrow(16, 16) + 3) / 4 + 3 * kDct16Floats / 4 + kF2Threads - 1) / kF2Threads;
 static_assert(kTabVec2 * kF2Threads * 4 <= kTabPadFloats, "table reads stay inside the padded buffer");
 
-template <int R, int EV>
+template <int R, int EV, int B8>
 __device__ __forceinline__ void fast2_body(const FrameDev &f, const FastItem *items, const uint16_t *const *ipos,
                                            const float *const *ivals, FastStage &st, const float *tabs,
                                            const ShapeDev &S, int W) {
@@ -1344,7 +1350,7 @@ __device__ __forceinline__ void fast2_body(const FrameDev &f, const FastItem *it
 #pragma unroll
   for (int g = 0; g < kWaveItems; ++g) okmask |= ((em >> (16 * g)) & 1ull) ? (1u << g) : 0u;
   if (okmask)
-    fast_eval_any<R, EV, false>(f, tabs + S.jt_floats, st, lane, okmask, NVw, w, h, W, items[slot].ob0,
+    fast_eval_any<R, EV, false, false, B8>(f, tabs + S.jt_floats, st, lane, okmask, NVw, w, h, W, items[slot].ob0,
                                 items[slot].ob1, items[slot].fi);
 }
 
@@ -1355,7 +1361,7 @@ __device__ __forceinline__ void fast2_body(const FrameDev &f, const FastItem *it
 // out class by class, the largest systems first).  The block arithmetic is
 // that of k_fast (same solve and evaluation, padding rows and columns are
 // exact identities and zeros), so results do not depend on the path.
-template <int EV>
+template <int EV, int B8 = 0>
 __global__ __launch_bounds__(kF2Threads) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_fast2(FrameDev f) {
   extern __shared__ __attribute__((aligned(16))) float tabs[];  // J, Dw, Dh, lam of the bin's shape
@@ -1467,14 +1473,14 @@ void k_fast2(FrameDev f) {
   __syncthreads();
   FastStage &st = stage[tid >> 6];
   switch (c) {
-    case 0: fast2_body<4, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
-    case 1: fast2_body<8, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
-    case 2: fast2_body<12, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
-    case 3: fast2_body<16, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
-    case 4: fast2_body<20, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
-    case 5: fast2_body<24, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
-    case 6: fast2_body<28, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
-    default: fast2_body<32, EV>(f, items, ipos, ivals, st, tabs, S, W); break;
+    case 0: fast2_body<4, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
+    case 1: fast2_body<8, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
+    case 2: fast2_body<12, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
+    case 3: fast2_body<16, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
+    case 4: fast2_body<20, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
+    case 5: fast2_body<24, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
+    case 6: fast2_body<28, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
+    default: fast2_body<32, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
   }
 }
 
@@ -1583,14 +1589,20 @@ hipError_t launch_fast(const FrameDev &f, hipStream_t stream) {
       case 1: hipLaunchKernelGGL((k_fast<1, 1>), g, b, lds, stream, f); break;
       case 2: hipLaunchKernelGGL((k_fast<1, 2>), g, b, lds, stream, f); break;
       case 3: hipLaunchKernelGGL((k_fast<1, 3>), g, b, lds, stream, f); break;
-      default: hipLaunchKernelGGL((k_fast<1, 0>), g, b, lds, stream, f); break;
+      default:
+        if (f.b == 8) hipLaunchKernelGGL((k_fast<1, 0, 1>), g, b, lds, stream, f);
+        else hipLaunchKernelGGL((k_fast<1, 0, 0>), g, b, lds, stream, f);
+        break;
     }
   } else {
     switch (f.eval) {
       case 1: hipLaunchKernelGGL((k_fast<0, 1>), g, b, lds, stream, f); break;
       case 2: hipLaunchKernelGGL((k_fast<0, 2>), g, b, lds, stream, f); break;
       case 3: hipLaunchKernelGGL((k_fast<0, 3>), g, b, lds, stream, f); break;
-      default: hipLaunchKernelGGL((k_fast<0, 0>), g, b, lds, stream, f); break;
+      default:
+        if (f.b == 8) hipLaunchKernelGGL((k_fast<0, 0, 1>), g, b, lds, stream, f);
+        else hipLaunchKernelGGL((k_fast<0, 0, 0>), g, b, lds, stream, f);
+        break;
     }
   }
   return hipGetLastError();
@@ -1608,7 +1620,10 @@ hipError_t launch_fast2(const FrameDev &f, hipStream_t stream) {
     case 1: hipLaunchKernelGGL((k_fast2<1>), g, b, lds, stream, f); break;
     case 2: hipLaunchKernelGGL((k_fast2<2>), g, b, lds, stream, f); break;
     case 3: hipLaunchKernelGGL((k_fast2<3>), g, b, lds, stream, f); break;
-    default: hipLaunchKernelGGL((k_fast2<0>), g, b, lds, stream, f); break;
+    default:
+      if (f.b == 8) hipLaunchKernelGGL((k_fast2<0, 1>), g, b, lds, stream, f);
+      else hipLaunchKernelGGL((k_fast2<0, 0>), g, b, lds, stream, f);
+      break;
   }
   return hipGetLastError();
 }
