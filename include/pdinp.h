@@ -155,13 +155,13 @@ int decode_residual_batch(pdi_ctx *ctx, int n, const pdi_frame *frame, const pdi
  *     call with them builds them (that call allocates); otherwise
  *     PDI_EINVAL with nothing launched;
  *   - the scratch must hold the status word and counters (4.4 KB), 4 bytes
- *     per mask block and frame (about 21.5 for batches of more than one frame
+ *     per mask block and frame (about 22 for batches of more than one frame
  *     with 8x8 or 16x16 blocks, 12 with 32x32 blocks: the size-class queues) and
  *     at least one (b*b + 1)(b*b + 3)-float system; more systems fit, up to
  *     64 are used (more workgroups of the general pass then work on K > 96
  *     blocks at once; results do not depend on it).  A larger decode returns
  *     PDI_ENOMEM with nothing launched.  32 frames of 1080p 4:2:0 need at
- *     least 7.3 MB with 16x16 blocks, 28 MB with 8x8 and 5.2 MB with 32x32
+ *     least 7.4 MB with 16x16 blocks, 28 MB with 8x8 and 5.2 MB with 32x32
  *     blocks, so any batch of up to 32 1080p frames fits;
  *   - every call on a GPU shares that GPU's scratch: calls that overlap on
  *     one GPU (different streams, contexts or threads) race and must be

@@ -7,6 +7,8 @@
 namespace pdi {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef int i4 __attribute__((ext_vector_type(4)));
+typedef int i2 __attribute__((ext_vector_type(2)));
 
 // Hand block m of frame fi to the general path: blocks whose bordered system
 // fits in LDS are listed from the front of the deferred list, larger ones from

@@ -401,11 +401,20 @@ int get_workspace(pdi_ctx *c, hipStream_t stream, Workspace **out) {
   return PDI_OK;
 }
 
-// Ints of the queue buffer for n_items mask blocks x frames: the binned
-// paths' queues (4 per block) and the binning's per-workgroup bin counts
-// (kMaxSegs * 8 bins for each workgroup of 256 blocks of one frame; at most
-// 32 frames add a partial workgroup each).
-long long binlist_ints(long long n_items) { return 4 * n_items + 8ll * pdi::kMaxSegs * (n_items / 256 + 33); }
+// k_fast2 workgroups for n_items mask blocks x frames: 16 blocks each, every
+// one of at most 8 kMaxSegs bins padded to whole workgroups.
+long long f2_wgs_max(long long n_items) { return (n_items + 15) / 16 + 8ll * pdi::kMaxSegs; }
+
+// Ints of the queue buffer for n_items mask blocks x frames.  Wave-per-block
+// path: 2 per block.  Binned wave-level path: the entries (4 ints for each of
+// the 16 slots of every k_fast2 workgroup), the workgroup descriptors (2
+// ints), then the binning's per-workgroup bin counts (kMaxSegs * 8 bins for
+// each workgroup of 256 blocks of one frame; at most 32 frames add a partial
+// workgroup each).
+long long f2_desc_ints(long long n_items) { return (2 * f2_wgs_max(n_items) + 3) & ~3ll; }
+long long binlist_ints(long long n_items) {
+  return 64 * f2_wgs_max(n_items) + f2_desc_ints(n_items) + 8ll * pdi::kMaxSegs * (n_items / 256 + 33);
+}
 
 int ensure_workspace(pdi_ctx *c, Workspace *W, int n_items, int b, int nslots) {
   if (n_items > W->deferred_cap) {
@@ -690,16 +699,14 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
   // 28 us per batch against 41 us.)
   const bool binned = fast && !coef && !enc && n > 1 && nitems * n >= kBinnedMinBlocks;
   if (binned) {
-    long long base = 0;
     F.nq = 0;
     for (int k = 0; k < F.nsegs; ++k) {
       const pdi::SegDev &S = F.seg[k];
       pdi::QueueDev &Q = F.q[F.nq];
       Q.shape = S.shape;
       Q.count = S.count;
-      Q.base = (int)base;
+      Q.base = 0;
       Q.first_wg = S.group;
-      base += 4ll * S.count * n;
       F.nq++;  // queue k is segment k (F.qge was filled with the segments)
     }
     F.fast_wgs = (int)((nitems * n + 15) / 16) + 8 * F.nq;  // k_fast2 takes 16 blocks per workgroup
@@ -777,7 +784,9 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
   F.tab64 = ts->tab64;
   F.deferred = W->deferred;
   F.binlist = W->binlist;
-  F.hist = binned ? W->binlist + 4 * nitems * n : nullptr;
+  F.fl = binned ? W->binlist : nullptr;
+  F.wgdesc = binned ? F.fl + 64 * f2_wgs_max(nitems * n) : nullptr;
+  F.hist = binned ? F.wgdesc + f2_desc_ints(nitems * n) : nullptr;
   F.counters = W->counters;
   F.status = W->status;
   F.slots = W->slots;

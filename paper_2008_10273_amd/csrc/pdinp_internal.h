@@ -86,7 +86,9 @@ hipError_t noalloc_setup(int device, void **ptr);
 // The blocks of one shape for the wave-per-block path.  binlist[2 base ..
 // 2 base + 2 count) holds them by point count: bin 0 from the front of the
 // first half, bin 1 from its back, bins 2 and 3 likewise in the second half;
-// workgroups first_wg .. take them in bin order.
+// workgroups first_wg .. take them in bin order.  In the binned wave-level
+// path a queue is one segment (mask-plane group and edge kind) with the
+// group's index in first_wg; its blocks are placed in f.fl.
 struct QueueDev {
   int shape, count, base, first_wg;
 };
@@ -166,8 +168,16 @@ struct FrameDev {
   const double *tab64;
   int *deferred;   // mask blocks left to the general path, as (fi << 24) | m
                    // (n_items * nframes entries)
-  int *binlist;    // queues of the binned paths (4 n_items entries per frame)
-  int *hist;       // binned wave-level path: per-workgroup bin counts / offsets of the binning
+  int *binlist;    // queues of the wave-per-block path (2 n_items entries per frame)
+  // binned wave-level path: its blocks in hand-out order, 16 per k_fast2
+  // workgroup (4 ints each: (fi << 24) | m, first point, K, first Cr value
+  // or -1 for one value plane), a descriptor per workgroup (2 ints: bin |
+  // valid entries << 8 | 16-byte table vectors << 16, or -1: none; the float
+  // offset of the bin's shape tables) and the binning's per-workgroup bin
+  // counts / offsets
+  int *fl;
+  int *wgdesc;
+  int *hist;
   int *counters;   // kNumCounters device counters (layout above)
   int *status;     // device status word
   float *slots;    // global-memory systems for K > kLdsKMax, one slot per workgroup

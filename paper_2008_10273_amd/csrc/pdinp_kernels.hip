@@ -427,6 +427,7 @@ struct FastPoint {
 struct FastStage {
   FastPoint p[kWaveItems][32];
   float a[kWaveItems][2];
+  int e[kWaveItems];  // binned path: (frame << 24) | block of each row, kept over the solve
 };
 
 // Size class of a block for the wave-level path: 0, 1, 2, 3 -> R = 8, 16,
@@ -484,51 +485,86 @@ __device__ __forceinline__ void fast_coef_stage(const FrameDev &f, const FastIte
   if (bad) atomicOr(f.status, bad);
 }
 
-// Solve the bordered systems of the wave's 4 blocks (R = 8, 16, 24 or 32 rows
-// per block, two value columns) and stage the evaluation operands.  J is the
-// row-pair Green table of the workgroup's shape (LDS).  Returns false for a
-// block whose pivots call for FP64 refinement; such blocks are left to the
-// general path, which refines.
+// The points of a wave-level block (row i < K of the system in lane
+// t = i mod 16, slice i / 16): in-block coordinates and the value(s) at them.
+template <int NS>
+struct FastPts {
+  int xr[NS], yr[NS];
+  float T[NS][2];
+};
+
+// Loads the K points of a block (positions from posp[base..], values from
+// vals[vb0..] and, with nv = 2, vals[vb1..]), checking them when the
+// launch validates.
+template <int R>
+__device__ __forceinline__ FastPts<(R + 15) / 16> fast_load(const FrameDev &f, int K, int t, int w, int h,
+                                                           const uint16_t *posp, const float *vals,
+                                                           long long base, long long vb0, long long vb1, int nv) {
+  constexpr int NS = (R + 15) / 16;
+  // (the runs are in device memory: global loads, not flat ones)
+  typedef const __attribute__((address_space(1))) uint16_t gpos_t;
+  typedef const __attribute__((address_space(1))) float gval_t;
+  gpos_t *gpos = (gpos_t *)posp;
+  gval_t *gval = (gval_t *)vals;
+  FastPts<NS> P;
+  int pr[NS];
+  // every slice's loads first (one wait for all of them)
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = t + 16 * s;
+    pr[s] = 0;
+    P.T[s][0] = P.T[s][1] = 0.f;
+    if (i < K) {
+      pr[s] = gpos[base + i];
+      P.T[s][0] = gval[vb0 + i];
+      if (nv > 1) P.T[s][1] = gval[vb1 + i];
+    }
+  }
+  const int N = w * h;
+  // y = floor(p / w) for p < 256, w <= 16: (p + 1/2) / w is at least 1/32
+  // away from an integer, far beyond the rounding of the reciprocal
+  const float rw = __builtin_amdgcn_rcpf((float)w);
+  int bad = 0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = t + 16 * s;
+    P.xr[s] = 0;
+    P.yr[s] = 0;
+    if (i < K) {
+      int p = pr[s];
+      if (f.validate) {
+        if (p >= N || (i > 0 && (int)gpos[base + i - 1] >= p)) bad |= kStatusMask;
+        if (!(isfinite(P.T[s][0]) && isfinite(P.T[s][1]))) bad |= kStatusValue;
+      }
+      p = min(p, N - 1);
+      P.yr[s] = (int)(((float)p + 0.5f) * rw);
+      P.xr[s] = p - P.yr[s] * w;
+    }
+  }
+  if (bad) atomicOr(f.status, bad);
+  return P;
+}
+
+// Solve the bordered systems of the wave's 4 blocks (R rows per block, two
+// value columns; the points loaded by fast_load) and stage the evaluation
+// operands.  J is the row-pair Green table of the workgroup's shape (LDS).
+// Returns false for a block whose pivots call for FP64 refinement; such
+// blocks are left to the general path, which refines.
 //
 // BIN: the wave's blocks come from one size class of the binned path, so
 // every taken block has K >= R - 4 (columns and rows below R - 4 hold
 // Green's-function entries only, and the first R - 4 elimination steps are
 // never past a block's border).
-template <int R, int KCH = (R % 8 == 0 ? 8 : 4), bool BIN = false>
-__device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *items, int slot, bool ok,
-                                           int t, int gi, int Kw, int w, int h, const float *J,
-                                           FastStage &st, const uint16_t *posp, const float *vals) {
+template <int R, int KCH, bool BIN>
+__device__ __forceinline__ bool fast_solve_pts(const FrameDev &f, bool ok, int K, int t, int gi, int Kw, int w,
+                                               int h, const float *J, FastStage &st,
+                                               FastPts<(R + 15) / 16> &pts) {
   constexpr int NS = (R + 15) / 16;
   constexpr int NV = 2;
-  const int K = ok ? items[slot].K : 0;
-  const int N = w * h, W1 = w + 1;
-  // y = floor(p / w) for p < 256, w <= 16: (p + 1/2) / w is at least 1/32
-  // away from an integer, far beyond the rounding of the reciprocal
-  const float rw = __builtin_amdgcn_rcpf((float)w);
-  int xr[NS], yr[NS];
-  float T[NS][NV];
-  int bad = 0;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int i = t + 16 * s;
-    xr[s] = 0;
-    yr[s] = 0;
-    T[s][0] = T[s][1] = 0.f;
-    if (i < K) {
-      const int base = items[slot].base;
-      int p = posp[base + i];
-      if (f.validate) {
-        if (p >= N || (i > 0 && (int)posp[base + i - 1] >= p)) bad |= kStatusMask;
-      }
-      p = min(p, N - 1);
-      yr[s] = (int)(((float)p + 0.5f) * rw);
-      xr[s] = p - yr[s] * w;
-      T[s][0] = vals[items[slot].vb0 + i];
-      if (items[slot].nv > 1) T[s][1] = vals[items[slot].vb1 + i];
-      if (f.validate && !(isfinite(T[s][0]) && isfinite(T[s][1]))) bad |= kStatusValue;
-    }
-  }
-  if (bad) atomicOr(f.status, bad);
+  const int W1 = w + 1;
+  int(&xr)[NS] = pts.xr;
+  int(&yr)[NS] = pts.yr;
+  float(&T)[NS][NV] = pts.T;
 
   // Assembly of row i of [G_K 1; 1^T 0] (identity on padding rows):
   // G(x_i, x_k) = J[y_i, y_k][|x_i - x_k|] + J[y_i, y_k][refl(x_i + x_k + 1)].
@@ -673,6 +709,16 @@ __device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *it
   }
   if (ok && !need && !fin) atomicOr(f.status, kStatusSolve);
   return !need;
+}
+
+template <int R, int KCH = (R % 8 == 0 ? 8 : 4), bool BIN = false>
+__device__ __forceinline__ bool fast_solve(const FrameDev &f, const FastItem *items, int slot, bool ok,
+                                           int t, int gi, int Kw, int w, int h, const float *J,
+                                           FastStage &st, const uint16_t *posp, const float *vals) {
+  const int K = ok ? items[slot].K : 0;
+  FastPts<(R + 15) / 16> P = fast_load<R>(f, K, t, w, h, posp, vals, items[slot].base, items[slot].vb0,
+                                          items[slot].vb1, items[slot].nv);
+  return fast_solve_pts<R, KCH, BIN>(f, ok, K, t, gi, Kw, w, h, J, st, P);
 }
 
 // Four consecutive pixels of one row: one 16-byte store (FP32 planes) or one
@@ -1200,17 +1246,28 @@ __device__ __forceinline__ int fast2_class(int K) { return ((K + 4) >> 2) - 1; }
 // group and edge kind (so a queue holds blocks of one shape, one plane width
 // and one value-plane count), into the bin of its size class; the others
 // (K = 0, K = w*h, K > 31, invalid counts) go to the general path's lists.
-// Entries are (frame << 24) | block.  Bins 2p and 2p + 1 of a queue share
-// region p of it (one grows from the front, the other from the back;
-// together they hold at most every block of the queue, so they never meet).
 // Three passes without global atomics (counting, a scan per bin, placing):
 // thousands of workgroups adding to a few dozen counters serialise.  The
-// order inside a bin is that of the blocks (frame, then block index).
+// placing pass writes every block's entry straight into its k_fast2
+// workgroup's slice of f.fl: bins in hand-out order (classes from the
+// largest systems down, queues in order), each padded to whole workgroups of
+// kF2Items entries, the order inside a bin that of the blocks (frame, then
+// block index).  An entry carries everything a workgroup needs to start
+// loading the block's points (frame, block, first point, K, first Cr value),
+// and the first entry of each workgroup's slice writes the workgroup's
+// descriptor (bin, valid entries), so k_fast2 reads its blocks with one load
+// and no search.
 constexpr int kBinThreads = 256;
 constexpr int kMaxBins = 8 * kMaxSegs;
+constexpr int kF2Threads = 256;                  // k_fast2: 4 waves per workgroup
+constexpr int kF2Waves = kF2Threads / 64;
+constexpr int kF2Items = kF2Waves * kWaveItems;  // 16 blocks per workgroup
 
-// The bin of mask block m of frame fi (-1: not queued), and its shape.
-__device__ __forceinline__ int fbin_key(const FrameDev &f, int fi, int m, bool defer) {
+// The bin of mask block m of frame fi (-1: not queued), with its first
+// point, point count and value-plane count.
+__device__ __forceinline__ int fbin_key(const FrameDev &f, int fi, int m, bool defer, int &lo, int &K, int &nv) {
+  lo = K = 0;
+  nv = 1;
   if (m >= f.n_items) return -1;
   const int32_t *bp = f.fp[fi].block_ptr;
   int g = 0;
@@ -1221,7 +1278,9 @@ __device__ __forceinline__ int fbin_key(const FrameDev &f, int fi, int m, bool d
   const int e = ((bx == G.nbx - 1) && (G.W % f.b) ? 1 : 0) + ((by == G.nby - 1) && (G.H % f.b) ? 2 : 0);
   const int shape = G.shape[e];
   const int w = f.s[shape].w, h = f.s[shape].h;
-  const int K = bp[m + 1] - bp[m];
+  lo = bp[m];
+  K = bp[m + 1] - lo;
+  nv = G.nv;
   if (K < 1 || K >= w * h || K > kFastKMax) {
     if (defer) push_deferred(f, fi, m, K, w, h);
     return -1;
@@ -1246,20 +1305,27 @@ __device__ __forceinline__ int fbin_wave_rank(int key, int (*wc)[kMaxBins]) {
   return rank;
 }
 
-// Pass 1: the count of every bin in each workgroup's 256 blocks (one frame).
+// Pass 1: the count of every bin in each workgroup's 256 blocks (one frame);
+// also marks every k_fast2 workgroup empty (pass 3 describes the used ones).
 __global__ __launch_bounds__(kBinThreads) void k_fbin_count(FrameDev f) {
   __shared__ int wc[kBinThreads / 64][kMaxBins];
   const int nb = 8 * f.nq, tid = threadIdx.x;
+  const int wgi = blockIdx.y * gridDim.x + blockIdx.x;
+  for (int i = wgi * kBinThreads + tid; i < f.fast_wgs; i += gridDim.x * gridDim.y * kBinThreads) {
+    f.wgdesc[2 * i] = -1;
+    f.wgdesc[2 * i + 1] = 0;
+  }
   for (int i = tid; i < (kBinThreads / 64) * kMaxBins; i += kBinThreads) (&wc[0][0])[i] = 0;
   __syncthreads();
-  const int key = fbin_key(f, blockIdx.y, blockIdx.x * kBinThreads + tid, true);
+  int lo, K, nv;
+  const int key = fbin_key(f, blockIdx.y, blockIdx.x * kBinThreads + tid, true, lo, K, nv);
   fbin_wave_rank(key, wc);
   __syncthreads();
   if (tid < nb) {
     int t = 0;
 #pragma unroll
     for (int w = 0; w < kBinThreads / 64; ++w) t += wc[w][tid];
-    f.hist[(long long)(blockIdx.y * gridDim.x + blockIdx.x) * nb + tid] = t;
+    f.hist[(long long)wgi * nb + tid] = t;
   }
 }
 
@@ -1293,65 +1359,165 @@ __global__ __launch_bounds__(kBinThreads) void k_fbin_scan(FrameDev f, int nwg) 
   if (tid == 0) f.counters[kQueueCounters + bin] = carry;
 }
 
-// Pass 3: every queued block to its place in its bin.
+// Pass 3: every queued block's entry to its place in f.fl.
 __global__ __launch_bounds__(kBinThreads) void k_fbin_place(FrameDev f) {
   __shared__ int wc[kBinThreads / 64][kMaxBins];
+  __shared__ int bstart[kMaxBins], bcount[kMaxBins];
   const int nb = 8 * f.nq, tid = threadIdx.x, wv = tid >> 6;
   for (int i = tid; i < (kBinThreads / 64) * kMaxBins; i += kBinThreads) (&wc[0][0])[i] = 0;
+  if (tid < 64) {
+    // first entry of every bin: bins in hand-out order (class 7 .. 0, queues
+    // in order), each a whole number of workgroup slices
+    int carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += 64) {
+      const int b = b0 + tid;
+      int key = 0, cnt = 0;
+      if (b < nb) {
+        key = 8 * (b % f.nq) + 7 - b / f.nq;
+        cnt = f.counters[kQueueCounters + key];
+      }
+      const int len = (cnt + kF2Items - 1) / kF2Items * kF2Items;
+      int incl = len;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int x = __shfl_up(incl, o, 64);
+        if (tid >= o) incl += x;
+      }
+      incl += carry;
+      if (b < nb) {
+        bstart[key] = incl - len;
+        bcount[key] = cnt;
+      }
+      carry = __shfl(incl, 63, 64);
+    }
+  }
   __syncthreads();
   const int fi = blockIdx.y, m = blockIdx.x * kBinThreads + tid;
-  const int key = fbin_key(f, fi, m, false);
+  int lo, K, nv;
+  const int key = fbin_key(f, fi, m, false, lo, K, nv);
   const int rank = fbin_wave_rank(key, wc);
   __syncthreads();
   if (key >= 0) {
     int idx = f.hist[(long long)(blockIdx.y * gridDim.x + blockIdx.x) * nb + key] + rank;
     for (int w = 0; w < wv; ++w) idx += wc[w][key];
-    const QueueDev &Q = f.q[key >> 3];
-    const int c = key & 7, cap = Q.count * f.nframes;
-    int *region = f.binlist + Q.base + (long long)(c >> 1) * cap;
-    if (idx < cap) region[(c & 1) ? cap - 1 - idx : idx] = (fi << kDeferFrameShift) | m;
+    const long long j = (long long)bstart[key] + idx;
+    if (idx < bcount[key] && j < (long long)kF2Items * f.fast_wgs) {
+      // a shared chroma mask: the Cr run follows every other value (-1:
+      // one value plane)
+      const int32_t *bp = f.fp[fi].block_ptr;
+      const int vb1 = nv < 2 ? -1 : f.shared ? bp[f.n_items] - bp[f.chroma_first] + lo : lo;
+      i4 ent;
+      ent.x = (fi << kDeferFrameShift) | m;
+      ent.y = lo;
+      ent.z = K;
+      ent.w = vb1;
+      reinterpret_cast<i4 *>(f.fl)[j] = ent;
+      if (idx % kF2Items == 0) {
+        const ShapeDev &S = f.s[f.q[key >> 3].shape];
+        i2 d;
+        d.x = key | (min(kF2Items, bcount[key] - idx) << 8) | (((S.jt_floats + 3 * kDct16Floats) >> 2) << 16);
+        d.y = S.fast;
+        reinterpret_cast<i2 *>(f.wgdesc)[j / kF2Items] = d;
+      }
+    }
   }
 }
 
 // The wave-level solve and evaluation of one workgroup's blocks, all of one
-// size class R (R rows per block system, four blocks per wave).
-constexpr int kF2Threads = 256;                  // k_fast2: 4 waves per workgroup
-constexpr int kF2Waves = kF2Threads / 64;
-constexpr int kF2Items = kF2Waves * kWaveItems;  // 16 blocks per workgroup
+// size class R (R rows per block system, four blocks per wave): d is the
+// workgroup's descriptor, ent this row's entry.
 constexpr int kTabVec2 = ((16 * jrow(16, 16) + 3) / 4 + 3 * kDct16Floats / 4 + kF2Threads - 1) / kF2Threads;
 static_assert(kTabVec2 * kF2Threads * 4 <= kTabPadFloats, "table reads stay inside the padded buffer");
+static_assert(kTabVec2 * kF2Threads < (1 << 15), "the table's 16-byte count fits a descriptor");
+
+// The launch's FrameDev read in place in the kernel-argument segment (the
+// kernels that use it take it as their only argument, at offset 0): data-
+// dependent indexes into a by-value kernel argument can make the compiler
+// copy all of it to private memory first.
+__device__ __forceinline__ const __attribute__((address_space(4))) FrameDev *kernarg_frame() {
+  return (const __attribute__((address_space(4))) FrameDev *)__builtin_amdgcn_kernarg_segment_ptr();
+}
 
 template <int R, int EV, int B8>
-__device__ __forceinline__ void fast2_body(const FrameDev &f, const FastItem *items, const uint16_t *const *ipos,
-                                           const float *const *ivals, FastStage &st, const float *tabs,
-                                           const ShapeDev &S, int W) {
+__device__ __forceinline__ void fast2_run(const FrameDev &f, int d, int tabo, const i4 ent, float *tabs,
+                                          FastStage *stage) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int gi = lane >> 4, t = lane & 15;
   const int slot = wv * kWaveItems + gi;
-  const bool ok = items[slot].cls < kClassDefer;
-  const int kw = ok ? items[slot].K : 0, nvw = ok ? items[slot].nv : 0;
-  // (uniform in each 16-lane row: the wave's largest from one lane per row)
-  const int Kw = max(max(__builtin_amdgcn_readlane(kw, 0), __builtin_amdgcn_readlane(kw, 16)),
-                     max(__builtin_amdgcn_readlane(kw, 32), __builtin_amdgcn_readlane(kw, 48)));
-  const int NVw = max(max(__builtin_amdgcn_readlane(nvw, 0), __builtin_amdgcn_readlane(nvw, 16)),
-                      max(__builtin_amdgcn_readlane(nvw, 32), __builtin_amdgcn_readlane(nvw, 48)));
-  if (Kw == 0) return;  // no block in this wave
+  const int qi = (d & 0xff) >> 3, nval = (d >> 8) & 0xff, n4 = d >> 16;
+  // the tables' loads: J and the evaluation's matrices (16-byte loads; the
+  // buffer is padded)
+  const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + tabo);
+  f4 buf[kTabVec2];
+#pragma unroll
+  for (int r = 0; r < kTabVec2; ++r) buf[r] = src[tid + r * kF2Threads];
+  // this row's block: its point loads go out before the tables are stored,
+  // so that the two latencies overlap
+  const bool ok = slot < nval;
+  const int K = ok ? ent.z : 0;
+  // the frame's point runs: its index is uniform in each 16-lane row, so
+  // the pointers come from the kernel arguments by scalar loads (a hit in
+  // the scalar cache, not a vector round trip)
+  const uint16_t *ppos;
+  const float *pval;
+  {
+    const uint16_t *pr[kWaveItems];
+    const float *vr[kWaveItems];
+#pragma unroll
+    for (int g = 0; g < kWaveItems; ++g) {
+      const int fr = (__builtin_amdgcn_readfirstlane(wv) * kWaveItems + g < nval)
+                         ? __builtin_amdgcn_readlane(ent.x, 16 * g) >> kDeferFrameShift : 0;
+      pr[g] = f.fp[fr].pos;
+      vr[g] = f.fp[fr].values;
+    }
+    ppos = gi == 0 ? pr[0] : gi == 1 ? pr[1] : gi == 2 ? pr[2] : pr[3];
+    pval = gi == 0 ? vr[0] : gi == 1 ? vr[1] : gi == 2 ? vr[2] : vr[3];
+  }
+  const QueueDev Q = f.q[qi];
+  const ShapeDev S = f.s[Q.shape];
   const int w = S.w, h = S.h;
+  FastPts<(R + 15) / 16> P =
+      fast_load<R>(f, K, t, w, h, ppos, pval, ent.y, ent.y, ent.w, ent.w < 0 ? 1 : 2);
+  {  // the tables into LDS (all loads in flight before the first store)
+    f4 *dst = reinterpret_cast<f4 *>(tabs);
+#pragma unroll
+    for (int r = 0; r < kTabVec2; ++r) asm volatile("" : "+v"(buf[r]));
+#pragma unroll
+    for (int r = 0; r < kTabVec2; ++r) {
+      const int i = tid + r * kF2Threads;
+      if (i < n4) dst[i] = buf[r];
+    }
+  }
+  // (uniform in each 16-lane row: the wave's largest from one lane per row)
+  const int Kw = max(max(__builtin_amdgcn_readlane(K, 0), __builtin_amdgcn_readlane(K, 16)),
+                     max(__builtin_amdgcn_readlane(K, 32), __builtin_amdgcn_readlane(K, 48)));
+  __syncthreads();
+  if (Kw == 0) return;  // no block in this wave
+  const GroupDev G = f.g[Q.first_wg];  // the queue's group (binned queues keep it in first_wg)
+  const int nv = G.nv;
+  FastStage &st = stage[wv];
+  if (t == 0) st.e[gi] = ok ? ent.x : 0;  // (read back after the solve: two registers fewer)
   // (for two-slice systems the lookups go in chunks of 4 columns and the
   // evaluation's point chunks one at a time: the register file then holds
   // four waves per SIMD for every class)
-  const bool solved = fast_solve<R, R <= 16 ? (R % 8 == 0 ? 8 : 4) : 4, true>(f, items, slot, ok, t, gi, Kw, w, h,
-                                                                               tabs, st, ipos[slot], ivals[slot]);
-  if (ok && !solved && t == 0) push_deferred(f, items[slot].fi, items[slot].m, items[slot].K, w, h);
+  const bool solved = fast_solve_pts<R, R <= 16 ? (R % 8 == 0 ? 8 : 4) : 4, true>(f, ok, K, t, gi, Kw, w, h, tabs,
+                                                                                   st, P);
+  const int e = st.e[gi], fi = e >> kDeferFrameShift, m = e & kDeferItemMask;
+  if (ok && !solved && t == 0) push_deferred(f, fi, m, K, w, h);
   const bool eval = ok && solved;
   wave_sync();
   const unsigned long long em = __ballot(eval);
   unsigned okmask = 0;
 #pragma unroll
   for (int g = 0; g < kWaveItems; ++g) okmask |= ((em >> (16 * g)) & 1ull) ? (1u << g) : 0u;
-  if (okmask)
-    fast_eval_any<R, EV, false, false, B8>(f, tabs + S.jt_floats, st, lane, okmask, NVw, w, h, W, items[slot].ob0,
-                                items[slot].ob1, items[slot].fi);
+  if (okmask) {  // (every block of the queue has its group's value-plane count)
+    const int l = m - G.first, bx = l % G.nbx, by = l / G.nbx;
+    const long long pix = (long long)(by * f.b) * G.W + bx * f.b;
+    const long long ob0 = ok ? G.out_off[0] + pix : 0, ob1 = (ok && nv > 1) ? G.out_off[1] + pix : 0;
+    // (FP32: the lane index recomputed, nothing to keep in a register over the solve)
+    const int ln = EV == 0 ? (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)) : lane;
+    fast_eval_any<R, EV, false, false, B8>(f, tabs + S.jt_floats, st, ln, okmask, nv, w, h, G.W, ob0, ob1, fi);
+  }
 }
 
 // Residual decodes with b <= 16, binned (k_fbin_* first): each workgroup takes
@@ -1363,124 +1529,29 @@ __device__ __forceinline__ void fast2_body(const FrameDev &f, const FastItem *it
 // exact identities and zeros), so results do not depend on the path.
 template <int EV, int B8 = 0>
 __global__ __launch_bounds__(kF2Threads) __attribute__((amdgpu_waves_per_eu(4, 8)))
-void k_fast2(FrameDev f) {
+void k_fast2(FrameDev arg) {
   extern __shared__ __attribute__((aligned(16))) float tabs[];  // J, Dw, Dh, lam of the bin's shape
-  __shared__ FastItem items[kF2Items];
-  __shared__ const uint16_t *ipos[kF2Items];
-  __shared__ const float *ivals[kF2Items];
   __shared__ FastStage stage[kF2Waves];
-  __shared__ int sbin[3];
-  const int tid = threadIdx.x, wg = blockIdx.x;
-  // This workgroup's bin: bins in hand-out order (class 7 .. 0, queues in
-  // order), ceil(count / 16) workgroups each; wave 0 scans the bins 64 at
-  // a time (8 classes x at most 12 queues).
-  if (tid < 64) {
-    const int nb = 8 * f.nq;
-    if (tid == 0) sbin[0] = -1;
-    int carry = 0;
-    for (int b0 = 0; b0 < nb; b0 += 64) {
-      const int b = b0 + tid;
-      int qi = 0, c = 0, cnt = 0;
-      if (b < nb) {
-        c = 7 - b / f.nq;
-        qi = b % f.nq;
-        cnt = f.counters[kQueueCounters + 8 * qi + c];
-      }
-      const int nw = (cnt + kF2Items - 1) / kF2Items;
-      int incl = nw;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int x = __shfl_up(incl, o, 64);
-        if (tid >= o) incl += x;
-      }
-      incl += carry;
-      if (b < nb && wg >= incl - nw && wg < incl) {
-        sbin[0] = qi;
-        sbin[1] = c;
-        sbin[2] = (wg - (incl - nw)) * kF2Items;
-      }
-      carry = __shfl(incl, 63, 64);
-    }
-  }
-  __syncthreads();
-  const int qi = __builtin_amdgcn_readfirstlane(sbin[0]);
-  if (qi < 0) return;  // uniform: no bin reaches this workgroup
-  const int c = __builtin_amdgcn_readfirstlane(sbin[1]), p0 = __builtin_amdgcn_readfirstlane(sbin[2]);
-  const QueueDev Q = f.q[qi];
-  const ShapeDev S = f.s[Q.shape];
-  const int count = f.counters[kQueueCounters + 8 * qi + c];
-  const int cap = Q.count * f.nframes;
-  const int *region = f.binlist + Q.base + (long long)(c >> 1) * cap;
-  // the blocks (queue entries first: their loads are issued before the tables')
-  const int p = p0 + tid;
-  const bool has = tid < kF2Items && p < count && count <= cap;
-  int e = 0;
-  if (has) e = region[(c & 1) ? cap - 1 - p : p];
-  {  // J and the evaluation's matrices into LDS (16-byte loads, all in flight before the first store)
-    const int n4 = (S.jt_floats + 3 * kDct16Floats) >> 2;
-    const f4 *src = reinterpret_cast<const f4 *>(f.tab32 + S.fast);
-    f4 *dst = reinterpret_cast<f4 *>(tabs);
-    f4 buf[kTabVec2];
-#pragma unroll
-    for (int r = 0; r < kTabVec2; ++r) buf[r] = src[tid + r * kF2Threads];  // buffer is padded
-#pragma unroll
-    for (int r = 0; r < kTabVec2; ++r) asm volatile("" : "+v"(buf[r]));
-#pragma unroll
-    for (int r = 0; r < kTabVec2; ++r) {
-      const int i = tid + r * kF2Threads;
-      if (i < n4) dst[i] = buf[r];
-    }
-  }
-  int W;
-  if (tid < kF2Items) {
-    FastItem r;
-    r.cls = kClassNone;
-    r.m = r.K = r.base = r.nv = r.fi = 0;
-    r.vb0 = r.vb1 = r.ob0 = r.ob1 = 0;
-    const uint16_t *pp = nullptr;
-    const float *vv = nullptr;
-    if (has) {
-      const int fi = e >> kDeferFrameShift, m = e & kDeferItemMask;
-      int g = 0;
-      if (f.ngroups > 1 && m >= f.g[1].first) g = 1;
-      if (f.ngroups > 2 && m >= f.g[2].first) g = 2;
-      const GroupDev &G = f.g[g];
-      const int l = m - G.first, bx = l % G.nbx, by = l / G.nbx;
-      const FramePtrs fp = f.fp[fi];
-      const int lo = fp.block_ptr[m], hi = fp.block_ptr[m + 1];
-      r.m = m;
-      r.fi = fi;
-      r.K = hi - lo;
-      r.base = lo;
-      r.nv = G.nv;
-      r.cls = 0;  // taken (the size class is the workgroup's)
-      const long long pix = (long long)(by * f.b) * G.W + bx * f.b;
-      r.vb0 = lo;
-      r.ob0 = G.out_off[0] + pix;
-      if (G.nv > 1) {
-        // a shared chroma mask: the Cr run follows every other value
-        r.vb1 = f.shared ? (long long)fp.block_ptr[f.n_items] - fp.block_ptr[f.chroma_first] + lo : lo;
-        r.ob1 = G.out_off[1] + pix;
-      }
-      pp = fp.pos;
-      vv = fp.values;
-    }
-    items[tid] = r;
-    ipos[tid] = pp;
-    ivals[tid] = vv;
-  }
-  W = f.g[Q.first_wg].W;  // the queue's group (binned queues keep it in first_wg)
-  __syncthreads();
-  FastStage &st = stage[tid >> 6];
-  switch (c) {
-    case 0: fast2_body<4, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
-    case 1: fast2_body<8, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
-    case 2: fast2_body<12, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
-    case 3: fast2_body<16, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
-    case 4: fast2_body<20, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
-    case 5: fast2_body<24, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
-    case 6: fast2_body<28, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
-    default: fast2_body<32, EV, B8>(f, items, ipos, ivals, st, tabs, S, W); break;
+  (void)arg;
+  const FrameDev &f = *(const FrameDev *)kernarg_frame();  // (read in place: see kernarg_frame)
+  const int wg = blockIdx.x, slot = (threadIdx.x >> 6) * kWaveItems + ((threadIdx.x & 63) >> 4);
+  // the descriptor and the entries in one round trip (the 16 lanes of a row
+  // read the same entry).  A workgroup no bin reaches (descriptor -1) runs
+  // the smallest class with no valid entry: its waves leave after the
+  // barrier (no branch ahead of the entry load, which then issues at once).
+  const i2 dv = reinterpret_cast<const i2 *>(f.wgdesc)[wg];
+  const i4 ent = reinterpret_cast<const i4 *>(f.fl)[(long long)wg * kF2Items + slot];
+  const int d0 = __builtin_amdgcn_readfirstlane(dv.x), tabo = __builtin_amdgcn_readfirstlane(dv.y);
+  const int d = d0 < 0 ? 0 : d0;
+  switch (d & 7) {
+    case 0: fast2_run<4, EV, B8>(f, d, tabo, ent, tabs, stage); break;
+    case 1: fast2_run<8, EV, B8>(f, d, tabo, ent, tabs, stage); break;
+    case 2: fast2_run<12, EV, B8>(f, d, tabo, ent, tabs, stage); break;
+    case 3: fast2_run<16, EV, B8>(f, d, tabo, ent, tabs, stage); break;
+    case 4: fast2_run<20, EV, B8>(f, d, tabo, ent, tabs, stage); break;
+    case 5: fast2_run<24, EV, B8>(f, d, tabo, ent, tabs, stage); break;
+    case 6: fast2_run<28, EV, B8>(f, d, tabo, ent, tabs, stage); break;
+    default: fast2_run<32, EV, B8>(f, d, tabo, ent, tabs, stage); break;
   }
 }
 
