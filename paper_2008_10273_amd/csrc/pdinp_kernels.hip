@@ -827,6 +827,11 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
       for (int g = 0; g < kWaveItems; ++g)
         Ut[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(Sx[g][j], dha[j], Ut[g], 0, 0, 0);
     const int y = lo, x0 = 4 * hi, n = min(4, w - x0);
+    // full 16x16 blocks of FP32 planes whose rows start 16-byte aligned take
+    // one 16-byte store per lane with the block's base in scalar registers
+    // (a uniform test per block instead of per-lane address checks)
+    const bool full = w == 16 && h == 16 && !f.out_i8 && (W & 3) == 0;
+    const unsigned loff = (unsigned)(y * W + x0);
 #pragma unroll
     for (int g = 0; g < kWaveItems; ++g) {
       if (!((okmask >> g) & 1u)) continue;
@@ -834,7 +839,11 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
       const long long o = lane_i64(v ? ob1 : ob0, 16 * g);
       const PlaneOut po = plane_out(f, __builtin_amdgcn_readlane(fi, 16 * g));
       const float u[4] = {Ut[g][0] + a, Ut[g][1] + a, Ut[g][2] + a, Ut[g][3] + a};
-      if (y < h && n > 0) store_px4(po, (unsigned)(o + (long long)y * W + x0), u, n);
+      float *bp = po.f32 + o;
+      if (full && (reinterpret_cast<uintptr_t>(bp) & 15u) == 0)
+        *reinterpret_cast<f4 *>(bp + loff) = f4{u[0], u[1], u[2], u[3]};
+      else if (y < h && n > 0)
+        store_px4(po, (unsigned)(o + loff), u, n);
     }
   }
 }
