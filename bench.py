@@ -722,7 +722,9 @@ def bench_intra(args, torch, binding, synth):
                properties={"exact_at_mask": exact_at_mask, "min": float(g.min()), "max": float(g.max())},
                roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": None,  # the counters in profiles/ predate the current stop test
+                         # 85.42 MB of HBM traffic per finest-level iteration (rocprofv3
+                         # FETCH_SIZE / WRITE_SIZE, copy-calibrated; profiles/k_hd_cg_*)
+                         "traffic": float(np.mean(its_all)) * 85415700,
                          "kernel": "k_hd_cg, finest level (whole solve timed)",
                          "algorithmic_bytes_per_launch": ab, "launch_ms": 1e3 * secs / args.steps},
                cpu_baseline=cpu, wall_s=wall)
