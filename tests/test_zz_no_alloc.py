@@ -1,10 +1,12 @@
 """decode_residual_batch_noalloc: the residual decode with its device scratch
 in the library's static device array (nothing allocated), called through
 the C ABI and compared with decode_residual_batch, the allocating entry
-point, on the same frames: two calls in a row, the second with a smaller
-input (another block size, fewer frames).  The two entry points run the same
-kernels with the same arithmetic, so results must be bitwise equal; each is
-also within FP32_TOL of the FP64 oracle (the parity bar of the decoder).
+point, on the same frames: calls in a row, each with a smaller input (a
+batch large enough for the binned path, then fewer frames, then another
+block size).  The two entry points run the same
+kernels with the same arithmetic, so results must be bitwise equal; the
+first four frames of each call are also within FP32_TOL of the FP64 oracle
+(the parity bar of the decoder).
 Densities up to 45 % put blocks past the wave-level path (K > 31) and past
 the LDS-sized systems (K > 96, global-memory systems in the scratch)."""
 import numpy as np
@@ -34,7 +36,8 @@ def _host(ds):
 
 
 def test_noalloc_matches_batch_two_calls(dec):
-    cases = [(300, 170, 16, 4, (0.01, 0.45), 500),   # K up to 115: all three paths of b = 16
+    cases = [(650, 490, 16, 24, (0.01, 0.12), 400),  # 38568 mask blocks: the binned path, its entries in the scratch
+             (300, 170, 16, 4, (0.01, 0.45), 500),   # K up to 115: all three paths of b = 16
              (100, 60, 32, 2, (0.02, 0.12), 600)]     # smaller: wave-per-block path, queues in the scratch
     for W, H, b, n, dens, seed in cases:
         print(f"case noalloc {W}x{H} 4:2:0 b{b} n={n} density {dens}", flush=True)
@@ -50,8 +53,9 @@ def test_noalloc_matches_batch_two_calls(dec):
         got = _host(ds)
         for k, fr in enumerate(frames):
             np.testing.assert_array_equal(got[k], ref[k])
-            err = np.abs(got[k].astype(np.float64) - oracle.decode_flat(fr)).max()
-            assert err <= FP32_TOL, (k, err)
+            if k < 4:
+                err = np.abs(got[k].astype(np.float64) - oracle.decode_flat(fr)).max()
+                assert err <= FP32_TOL, (k, err)
 
 
 def test_noalloc_limits(dec):
