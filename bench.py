@@ -946,7 +946,7 @@ def main():
     ap.add_argument("--no-dtypes", dest="dtypes", action="store_false",
                     help="configs 0-2: skip the per-dtype sweep")
     ap.add_argument("--dtype-steps", type=int, default=20, help="steps per dtype in the sweep")
-    ap.add_argument("--cpu-seconds", type=float, default=5.0, help="oracle timing sample (seconds)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle timing sample (seconds)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this decoder runs on one GPU; --gpus {args.gpus} is not supported "
