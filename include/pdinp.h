@@ -134,7 +134,12 @@ int decode_residual(pdi_ctx *ctx, const pdi_frame *frame, const pdi_mask *mask,
  * owned); the host arrays masks, values and outs are read during the call
  * only.  More blocks per launch keep more waves in flight, so a batch is
  * the throughput form of decode_residual; each frame's result is the same
- * as when decoded alone.  Errors as for decode_residual. */
+ * as when decoded alone.  With 32x32 blocks (n > 1, outside graph capture)
+ * the batch's four wave-per-block launches run side by side on three
+ * streams the context creates on first use: they are forked from `stream`
+ * and joined back to it with events, so work queued on `stream` afterwards
+ * (and pdi_sync) sees the whole decode; batches of different caller streams
+ * share those streams.  Errors as for decode_residual. */
 #define PDI_MAX_BATCH 32
 int decode_residual_batch(pdi_ctx *ctx, int n, const pdi_frame *frame, const pdi_mask *masks,
                           const float *const *values, int block_size, const pdi_params *params,

@@ -111,9 +111,22 @@ struct pdi_ctx {
   void *noalloc = nullptr;
   hipError_t noalloc_err = hipSuccess;
   bool noalloc_used = false;
+  // streams and events of the batched wave-per-block path's parts (created
+  // on the first such decode; captured decodes do not use them)
+  pdi::WideFork wf = {};
+  bool wf_ready = false;
 };
 
 namespace {
+
+void destroy_wide_fork(pdi::WideFork &w) {
+  for (hipStream_t &a : w.aux)
+    if (a) (void)hipStreamDestroy(a);
+  if (w.fork) (void)hipEventDestroy(w.fork);
+  for (hipEvent_t &j : w.join)
+    if (j) (void)hipEventDestroy(j);
+  w = pdi::WideFork();
+}
 
 int set_err(pdi_ctx *c, int code, const char *fmt, ...) {
   if (c) {
@@ -487,6 +500,7 @@ void pdi_destroy(pdi_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  destroy_wide_fork(c->wf);
   for (auto &kv : c->tables) {
     (void)hipFree(kv.second.tab32);
     (void)hipFree(kv.second.tab64);
@@ -806,7 +820,30 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
     e = pdi::launch_fast(F, s);
     if (e == hipSuccess && !F.tail_in_wg) e = pdi::launch_general_deferred(F, s);
   } else if (wide) {
-    e = pdi::launch_wide(F, s);  // leftover blocks go to the deferred list
+    // Batches run the parts side by side on the context's streams, except
+    // for static-scratch decodes and inside a graph capture (forking a
+    // capture onto streams shared by every caller crashed the runtime when a
+    // capture spanned several caller streams; captured decodes keep the
+    // parts in order on the caller's stream).
+    const pdi::WideFork *fork = nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusActive;
+    if (n > 1 && !scratch && hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+      if (!c->wf_ready) {
+        pdi::WideFork w = {};
+        hipError_t ce = hipSuccess;
+        for (int i = 0; i < 3 && ce == hipSuccess; ++i) ce = hipStreamCreateWithFlags(&w.aux[i], hipStreamNonBlocking);
+        if (ce == hipSuccess) ce = hipEventCreateWithFlags(&w.fork, hipEventDisableTiming);
+        for (int i = 0; i < 3 && ce == hipSuccess; ++i) ce = hipEventCreateWithFlags(&w.join[i], hipEventDisableTiming);
+        if (ce != hipSuccess) {
+          destroy_wide_fork(w);
+          return hip_fail(c, ce, "streams of the wave-per-block parts");
+        }
+        c->wf = w;
+        c->wf_ready = true;
+      }
+      fork = &c->wf;
+    }
+    e = pdi::launch_wide(F, s, fork);  // leftover blocks go to the deferred list
     if (e == hipSuccess) e = pdi::launch_general_deferred(F, s);
   } else {
     e = pdi::launch_plain_all(F, s);

@@ -649,7 +649,19 @@ __attribute__((amdgpu_waves_per_eu(COEF ? 2 : WidePart<PART>::WMIN, COEF ? 3 : 8
   }
 }
 
-hipError_t launch_wide(const FrameDev &f, hipStream_t stream) {
+// One part of a batched residual decode (the workgroup size is the launch choice).
+template <int PART>
+hipError_t launch_wide_part(const FrameDev &f, dim3 grid, size_t lds, hipStream_t st) {
+  switch (f.ipw) {
+    case 1: hipLaunchKernelGGL((k_wide<1, false, PART>), grid, dim3(64), lds, st, f); break;
+    case 2: hipLaunchKernelGGL((k_wide<2, false, PART>), grid, dim3(128), lds, st, f); break;
+    case 4: hipLaunchKernelGGL((k_wide<4, false, PART>), grid, dim3(256), lds, st, f); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_wide(const FrameDev &f, hipStream_t stream, const WideFork *fork) {
   if (f.n_items == 0) return hipSuccess;
   const dim3 bgrid((f.n_items + 255) / 256, f.nframes), grid(f.fast_wgs, f.nframes);
   const size_t lds = sizeof(float) * (size_t)f.fast_lds;
@@ -664,30 +676,33 @@ hipError_t launch_wide(const FrameDev &f, hipStream_t stream) {
   } else {
     hipLaunchKernelGGL(k_bin<false>, bgrid, dim3(256), 0, stream, f);
     if (f.nframes > 1) {
-      // batches: the large-K bins first (longest solves start first), then
-      // the rest with the smaller kernel.  A single frame keeps one launch:
-      // with few blocks the second launch would only add its latency.
-      switch (f.ipw) {
-        case 1:
-          hipLaunchKernelGGL((k_wide<1, false, 1>), grid, dim3(64), lds, stream, f);
-          hipLaunchKernelGGL((k_wide<1, false, 2>), grid, dim3(64), lds, stream, f);
-          hipLaunchKernelGGL((k_wide<1, false, 3>), grid, dim3(64), lds, stream, f);
-          hipLaunchKernelGGL((k_wide<1, false, 4>), grid, dim3(64), lds, stream, f);
-          break;
-        case 2:
-          hipLaunchKernelGGL((k_wide<2, false, 1>), grid, dim3(128), lds, stream, f);
-          hipLaunchKernelGGL((k_wide<2, false, 2>), grid, dim3(128), lds, stream, f);
-          hipLaunchKernelGGL((k_wide<2, false, 3>), grid, dim3(128), lds, stream, f);
-          hipLaunchKernelGGL((k_wide<2, false, 4>), grid, dim3(128), lds, stream, f);
-          break;
-        case 4:
-          hipLaunchKernelGGL((k_wide<4, false, 1>), grid, dim3(256), lds, stream, f);
-          hipLaunchKernelGGL((k_wide<4, false, 2>), grid, dim3(256), lds, stream, f);
-          hipLaunchKernelGGL((k_wide<4, false, 3>), grid, dim3(256), lds, stream, f);
-          hipLaunchKernelGGL((k_wide<4, false, 4>), grid, dim3(256), lds, stream, f);
-          break;
-        default: return hipErrorInvalidValue;
+      // batches: one launch per bin, the large-K bins first (longest solves
+      // start first).  With a fork the parts run side by side, so the tail of
+      // one (the few K >= 96 blocks at 2 waves per SIMD) overlaps the others.
+      // A single frame keeps one launch: with few blocks more launches would
+      // only add their latency.
+      hipStream_t st[4] = {stream, stream, stream, stream};
+      hipError_t e = hipSuccess;
+      if (fork) {
+        e = hipEventRecord(fork->fork, stream);
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+          e = hipStreamWaitEvent(fork->aux[i], fork->fork, 0);
+          st[i] = fork->aux[i];
+        }
+        if (e != hipSuccess) return e;
       }
+      e = launch_wide_part<1>(f, grid, lds, st[0]);
+      if (e == hipSuccess) e = launch_wide_part<2>(f, grid, lds, st[1]);
+      if (e == hipSuccess) e = launch_wide_part<3>(f, grid, lds, st[2]);
+      if (e == hipSuccess) e = launch_wide_part<4>(f, grid, lds, st[3]);
+      if (fork) {  // join (also after a failed launch: the caller's stream waits for what was queued)
+        for (int i = 0; i < 3; ++i) {
+          const hipError_t r = hipEventRecord(fork->join[i], fork->aux[i]);
+          const hipError_t w = r == hipSuccess ? hipStreamWaitEvent(stream, fork->join[i], 0) : r;
+          if (e == hipSuccess) e = w;
+        }
+      }
+      if (e != hipSuccess) return e;
     } else {
       switch (f.ipw) {
         case 1: hipLaunchKernelGGL((k_wide<1, false, 0>), grid, dim3(64), lds, stream, f); break;

@@ -95,6 +95,29 @@ def test_concurrent_streams_match_sequential(dec):
             np.testing.assert_array_equal(d["out"].cpu().numpy(), r)
 
 
+def test_concurrent_batched_b32_streams(dec):
+    """Batched 32x32-block decodes on three streams at once: each batch runs
+    its four wave-per-block parts side by side on the context's streams
+    (shared by the three callers); every frame equals its decode alone."""
+    print("case concurrent b32 batches on 3 streams", flush=True)
+    groups = [[synth.random_frame(290, 170, synth.YUV420, 32, (0.02, 0.1), seed=4100 + 10 * g + k)
+               for k in range(5)] for g in range(3)]
+    ref = [[_eager(dec, f) for f in grp] for grp in groups]
+    dss = [[dec.upload(f) for f in grp] for grp in groups]
+    streams = [torch.cuda.Stream() for _ in groups]
+    for rep in range(2):
+        for ds in dss:
+            for d in ds:
+                d["out"].zero_()
+        torch.cuda.synchronize()
+        for ds, st in zip(dss, streams):
+            dec.decode_batch(ds, stream=st)
+        for ds, st, rs in zip(dss, streams, ref):
+            assert dec.sync(st) == 0
+            for k, (d, r) in enumerate(zip(ds, rs)):
+                np.testing.assert_array_equal(d["out"].cpu().numpy(), r, err_msg=f"rep {rep} frame {k}")
+
+
 def test_serving_alone_equals_mix(dec):
     """Each frame of the 16-stream serving mix (6x 480p, 6x 720p, 4x 1080p,
     4:2:0, b16) decodes to the same result alone as inside the mix."""
