@@ -141,6 +141,25 @@ def test_serving_alone_equals_mix(dec):
     srv.close()
 
 
+def test_serving_b32_batches_equal_alone(dec):
+    """32x32-block frames through the serving loop (lanes join queued frames
+    of one geometry into batches, whose wave-per-block parts run on the
+    context's extra streams): every frame equals its decode alone."""
+    from paper_2008_10273_amd import binding
+    print("case serving b32", flush=True)
+    frames = [synth.random_frame(290, 170, synth.YUV420, 32, (0.02, 0.1), seed=4300 + k) for k in range(12)]
+    alone = [_eager(dec, fr) for fr in frames]
+    srv = binding.Server(dec, nlanes=2)
+    assert srv.hold(True) == 0  # queue everything first, so that the lanes form batches
+    subs = [srv.submit(fr) for fr in frames]
+    assert srv.hold(False) == 0
+    for (rc, t, out), ref in zip(subs, alone):
+        assert rc == 0
+        assert srv.wait(t)[0] == 0
+        np.testing.assert_array_equal(out, ref)
+    srv.close()
+
+
 def test_serving_budget_admission_and_busy(dec):
     """A budget that fits about one 1080p frame still completes every
     request; a full queue answers PDI_EBUSY; bad masks are refused at
