@@ -98,6 +98,18 @@ __device__ __forceinline__ f4 mma_tn(const f4 &x, const f4 &y, f4 c) {
   return c;
 }
 
+// x^T of a 16 x 16 tile in accumulator layout, through the wave's tile
+// buffer (4 scalar LDS writes and one 16-byte read per lane; as a product
+// with the identity it took four matrix-core steps in the elimination's
+// dependent chain).
+__device__ __forceinline__ f4 tile_t(const f4 &x, float *tb, int lo, int hi) {
+  wave_sync();  // earlier reads of the buffer done
+#pragma unroll
+  for (int r = 0; r < 4; ++r) tb[(4 * hi + r) * kTb + lo] = x[r];
+  wave_sync();
+  return *reinterpret_cast<const f4 *>(tb + lo * kTb + 4 * hi);
+}
+
 // Row broadcast kept as a standalone move (see bcast_i).
 __device__ __forceinline__ float bcast_pin(float x, int src) {
   int v = bcast_i(__builtin_bit_cast(int, x), src);
@@ -189,9 +201,6 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
   }
 
   // Forward elimination, one diagonal tile p at a time.
-  f4 ident;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) ident[r] = (lo == 4 * hi + r) ? 1.f : 0.f;
   float dmin = 3.0e38f, dmax = 0.f;
 #pragma unroll
   for (int p = 0; p < TN; ++p) {
@@ -237,7 +246,7 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
       }
       // lv is (L^-1)^T in accumulator layout.  Keep L^-1 itself (for the back
       // substitution) in place of A_pp, and the reciprocal pivots in LDS.
-      T[tixn<TN>(p, p)] = mma_tn(lv, ident, f4{0.f, 0.f, 0.f, 0.f});
+      T[tixn<TN>(p, p)] = tile_t(lv, st.tb, lo, hi);
       if (lo == 0) *reinterpret_cast<f4 *>(&st.dv[16 * p + 4 * hi]) = ds;
       // W_pj = L^-1 A_pj in place of A_pj for the trailing updates.
 #pragma unroll
@@ -257,10 +266,10 @@ __device__ __forceinline__ bool wide_solve(const FrameDev &f, const WideJob &jb,
           R[i] = mma_tn(x, R[p], R[i]);
         }
       }
-      // W_pj^T (= W_pj^T I) kept for the back substitution.
+      // W_pj^T kept for the back substitution.
 #pragma unroll
       for (int j = p + 1; j < TN; ++j)
-        if (j < NT) T[tixn<TN>(p, j)] = mma_tn(T[tixn<TN>(p, j)], ident, f4{0.f, 0.f, 0.f, 0.f});
+        if (j < NT) T[tixn<TN>(p, j)] = tile_t(T[tixn<TN>(p, j)], st.tb, lo, hi);
     }
   }
   const bool need = (f.refine == 2) || (f.refine == 1 && !(dmin >= f.tau * dmax));
