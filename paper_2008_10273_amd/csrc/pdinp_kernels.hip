@@ -853,9 +853,10 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
 // (its p rows, its q columns), with the DCT matrices block-diagonal and lam
 // repeated in every quadrant.  A point product of block g only reaches its
 // quadrant and both transforms act quadrant by quadrant, so one tile does
-// the work of four (fast_eval spends a zero-padded tile per block).  Lane
-// l, register r then holds pixel (y = 4 (l/16) + r, x = l%16) of the tile:
-// block 2 (x / 8) + y / 8, pixel (x % 8, y % 8).
+// the work of four (fast_eval spends a zero-padded tile per block).  With
+// the last product taken transposed, lane l, register r holds pixel
+// (x = 4 (l/16) + r, y = l%16) of the tile: block 2 (x / 8) + y / 8, pixel
+// (x % 8, y % 8).
 // UNI: the wave's blocks are of one frame (k_fast), so the output planes are
 // one scalar pointer.
 template <int R, bool UNI = false>
@@ -873,8 +874,6 @@ __device__ __forceinline__ void fast_eval8(const FrameDev &f, const float *D, co
     dwb[j] = (pq >> 3) == half ? Dw[(pq & 7) * kDct16Ld + l8] : 0.f;  // block-diagonal Dw[p][x], x = lo
     dha[j] = (pq >> 3) == half ? Dh[(pq & 7) * kDct16Ld + l8] : 0.f;  // block-diagonal Dh[q][y], y = lo
   }
-  const int b = 2 * half + (hi >> 1);  // block of this lane's pixels
-  const int y0 = 4 * (hi & 1);         // their first row inside the block
   for (int v = 0; v < nvw; ++v) {
     f4 acc = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
@@ -887,11 +886,14 @@ __device__ __forceinline__ void fast_eval8(const FrameDev &f, const float *D, co
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
       }
     }
-    f4 Sx = f4{0.f, 0.f, 0.f, 0.f}, U = f4{0.f, 0.f, 0.f, 0.f};
+    // the last product taken transposed (U^T = S^T Dh): lane l, register r
+    // holds pixel (x = 4 (l/16) + r, y = l%16) of the tile, so each lane
+    // writes four consecutive pixels of one block row with one store
+    f4 Sx = f4{0.f, 0.f, 0.f, 0.f}, Ut = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < 4; ++j) Sx = __builtin_amdgcn_mfma_f32_16x16x4f32(acc[j] * lam4[j], dwb[j], Sx, 0, 0, 0);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) U = __builtin_amdgcn_mfma_f32_16x16x4f32(dha[j], Sx[j], U, 0, 0, 0);
+    for (int j = 0; j < 4; ++j) Ut = __builtin_amdgcn_mfma_f32_16x16x4f32(Sx[j], dha[j], Ut, 0, 0, 0);
     long long ob[kWaveItems];
     int fb[kWaveItems];
 #pragma unroll
@@ -899,15 +901,14 @@ __device__ __forceinline__ void fast_eval8(const FrameDev &f, const float *D, co
       ob[g] = lane_i64(v ? ob1 : ob0, 16 * g);
       fb[g] = __builtin_amdgcn_readlane(fi, 16 * g);
     }
-    const long long o = b == 0 ? ob[0] : b == 1 ? ob[1] : b == 2 ? ob[2] : ob[3];
-    const PlaneOut po = plane_out(f, UNI ? fb[0] : b == 0 ? fb[0] : b == 1 ? fb[1] : b == 2 ? fb[2] : fb[3]);
-    if ((okmask >> b) & 1u) {
-      const float a = st.a[b][v];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int y = y0 + r, x = l8;
-        if (x < w && y < h) store_px(po, (unsigned)(o + (long long)y * W + x), U[r] + a);
-      }
+    const int bt = 2 * (hi >> 1) + half;  // block of this lane's pixels (x / 8 = hi / 2, y / 8 = half)
+    const long long o = bt == 0 ? ob[0] : bt == 1 ? ob[1] : bt == 2 ? ob[2] : ob[3];
+    const PlaneOut po = plane_out(f, UNI ? fb[0] : bt == 0 ? fb[0] : bt == 1 ? fb[1] : bt == 2 ? fb[2] : fb[3]);
+    if ((okmask >> bt) & 1u) {
+      const float a = st.a[bt][v];
+      const int y = l8, x0 = 4 * (hi & 1), n = min(4, w - x0);
+      const float u[4] = {Ut[0] + a, Ut[1] + a, Ut[2] + a, Ut[3] + a};
+      if (y < h && n > 0) store_px4(po, (unsigned)(o + (long long)y * W + x0), u, n);
     }
   }
 }
