@@ -49,6 +49,32 @@ __device__ __forceinline__ void store_px(const PlaneOut &po, unsigned idx, float
   }
 }
 
+// Four consecutive pixels of one row: one 16-byte store (FP32 planes) or one
+// 4-byte store (int8 planes) where the address is aligned for it, else one
+// store per pixel; pixels from x0 + n on are outside the block (n <= 4).
+__device__ __forceinline__ void store_px4(const PlaneOut &po, unsigned idx, const float u[4], int n) {
+  if (po.i8) {
+    int8_t q[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) q[r] = (int8_t)(int)fminf(fmaxf(__builtin_rintf(u[r]), -128.f), 127.f);
+    if (n == 4 && (reinterpret_cast<uintptr_t>(po.i8 + idx) & 3u) == 0) {
+      *reinterpret_cast<int *>(po.i8 + idx) =
+          (int)((unsigned)(uint8_t)q[0] | ((unsigned)(uint8_t)q[1] << 8) | ((unsigned)(uint8_t)q[2] << 16) |
+                ((unsigned)(uint8_t)q[3] << 24));
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (r < n) po.i8[idx + r] = q[r];
+    }
+  } else if (n == 4 && (reinterpret_cast<uintptr_t>(po.f32 + idx) & 15u) == 0) {
+    *reinterpret_cast<f4 *>(po.f32 + idx) = f4{u[0], u[1], u[2], u[3]};
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (r < n) po.f32[idx + r] = u[r];
+  }
+}
+
 // Reconstruction of a stored code (dead-zone quantiser, Sec. 2.3 of the
 // paper): 0 stays 0, else sign(q) (|q| + rho) step.
 // Dead-zone quantisation of a coefficient (the inverse of coef_value's

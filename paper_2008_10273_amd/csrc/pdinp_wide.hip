@@ -386,18 +386,21 @@ __device__ __forceinline__ void wide_eval32(const FrameDev &f, const WideJob &jb
     for (int yt = 0; yt < 2; ++yt)
 #pragma unroll
       for (int xt = 0; xt < 2; ++xt) {
+        // Taken transposed (u^T = S^T Dh), so that register r is pixel
+        // (x = 16 xt + 4 hi + r, y = 16 yt + lo): four consecutive pixels of
+        // a block row per lane, one 16-byte store.
         f4 u4 = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int qt = 0; qt < 2; ++qt)
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int q = 16 * qt + 4 * hi + j;
-            u4 = __builtin_amdgcn_mfma_f32_16x16x4f32(Dh[q * kDct32Ld + 16 * yt + lo], S[qt][xt][j], u4, 0, 0, 0);
+            u4 = __builtin_amdgcn_mfma_f32_16x16x4f32(S[qt][xt][j], Dh[q * kDct32Ld + 16 * yt + lo], u4, 0, 0, 0);
           }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int y = 16 * yt + 4 * hi + r, x = 16 * xt + lo;
-          if (x < w && y < h) store_px(po, (unsigned)(ob + (long long)y * W + x), u4[r] + av);
+        const int y = 16 * yt + lo, x0 = 16 * xt + 4 * hi;
+        if (x0 < w && y < h) {
+          const float u[4] = {u4[0] + av, u4[1] + av, u4[2] + av, u4[3] + av};
+          store_px4(po, (unsigned)(ob + (long long)y * W + x0), u, min(4, w - x0));
         }
       }
   }
@@ -493,6 +496,8 @@ __device__ __forceinline__ void wide_eval16(const FrameDev &f, const WideJob &jb
     for (int yt = 0; yt < 2; ++yt)
 #pragma unroll
       for (int xt = 0; xt < 2; ++xt) {
+        // Transposed as in wide_eval32: register r is pixel
+        // (x = 16 xt + 4 hi + r, y = 16 yt + lo).
         f4 u4 = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int qt = 0; qt < 2; ++qt) {
@@ -500,15 +505,15 @@ __device__ __forceinline__ void wide_eval16(const FrameDev &f, const WideJob &jb
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int q = 16 * qt + 4 * hi + e;
-            a[e] = Dh[q * kDct32Ld + 16 * yt + lo];
-            b[e] = S[qt][xt][e];
+            a[e] = S[qt][xt][e];
+            b[e] = Dh[q * kDct32Ld + 16 * yt + lo];
           }
           u4 = wmma16<EV>(u4, a, b);
         }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int y = 16 * yt + 4 * hi + r, x = 16 * xt + lo;
-          if (x < w && y < h) store_px(po, (unsigned)(ob + (long long)y * W + x), u4[r] + av);
+        const int y = 16 * yt + lo, x0 = 16 * xt + 4 * hi;
+        if (x0 < w && y < h) {
+          const float u[4] = {u4[0] + av, u4[1] + av, u4[2] + av, u4[3] + av};
+          store_px4(po, (unsigned)(ob + (long long)y * W + x0), u, min(4, w - x0));
         }
       }
   }
