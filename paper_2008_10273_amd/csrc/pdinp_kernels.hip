@@ -815,7 +815,7 @@ __device__ __forceinline__ void fast_eval(const FrameDev &f, const float *D, con
       const float u[4] = {Ut[g][0] + a, Ut[g][1] + a, Ut[g][2] + a, Ut[g][3] + a};
       float *bp = po.f32 + o;
       if (full && (reinterpret_cast<uintptr_t>(bp) & 15u) == 0)
-        *reinterpret_cast<f4 *>(bp + loff) = f4{u[0], u[1], u[2], u[3]};
+        __builtin_nontemporal_store(f4{u[0], u[1], u[2], u[3]}, reinterpret_cast<f4 *>(bp + loff));
       else if (y < h && n > 0)
         store_px4(po, (unsigned)(o + loff), u, n);
     }
