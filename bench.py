@@ -57,7 +57,7 @@ EVALS = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16x2": 3}
 # Config 1: k_fbin_* + k_fast2 + deferred pass (k_fast2 ignores the launch
 # choice).  Config 2's parts follow one another, and lines written back after
 # a dispatch ends are counted in a later one: no per-step figure.
-TRAFFIC = {(1, 32): 493289267}
+TRAFFIC = {(1, 32): 510339566}
 
 
 def algorithmic_bytes(fr) -> int:
