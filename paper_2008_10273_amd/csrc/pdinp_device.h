@@ -40,13 +40,15 @@ __device__ __forceinline__ PlaneOut plane_out(const FrameDev &f, int fi) {
   po.i8 = f.out_i8 ? reinterpret_cast<int8_t *>(o) : nullptr;
   return po;
 }
-// Pixel stores are non-temporal: the planes are written once and not read
-// back by the decode, so they stream to HBM instead of displacing the
-// tables, entries and point runs held in the caches.
+// FP32 pixel stores are non-temporal: the planes are written once and not
+// read back by the decode, so they stream to HBM instead of displacing the
+// tables, entries and point runs held in the caches.  int8 planes keep
+// ordinary stores: a wave writes them in pieces of a few bytes per row,
+// which the L2 must merge before they go to HBM.
 __device__ __forceinline__ void store_px(const PlaneOut &po, unsigned idx, float u) {
   if (po.i8) {
     const float q = fminf(fmaxf(__builtin_rintf(u), -128.f), 127.f);
-    __builtin_nontemporal_store((int8_t)(int)q, po.i8 + idx);
+    po.i8[idx] = (int8_t)(int)q;
   } else {
     __builtin_nontemporal_store(u, po.f32 + idx);
   }
@@ -61,14 +63,13 @@ __device__ __forceinline__ void store_px4(const PlaneOut &po, unsigned idx, cons
 #pragma unroll
     for (int r = 0; r < 4; ++r) q[r] = (int8_t)(int)fminf(fmaxf(__builtin_rintf(u[r]), -128.f), 127.f);
     if (n == 4 && (reinterpret_cast<uintptr_t>(po.i8 + idx) & 3u) == 0) {
-      __builtin_nontemporal_store(
+      *reinterpret_cast<int *>(po.i8 + idx) =
           (int)((unsigned)(uint8_t)q[0] | ((unsigned)(uint8_t)q[1] << 8) | ((unsigned)(uint8_t)q[2] << 16) |
-                ((unsigned)(uint8_t)q[3] << 24)),
-          reinterpret_cast<int *>(po.i8 + idx));
+                ((unsigned)(uint8_t)q[3] << 24));
     } else {
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (r < n) __builtin_nontemporal_store(q[r], po.i8 + idx + r);
+        if (r < n) po.i8[idx + r] = q[r];
     }
   } else if (n == 4 && (reinterpret_cast<uintptr_t>(po.f32 + idx) & 15u) == 0) {
     __builtin_nontemporal_store(f4{u[0], u[1], u[2], u[3]}, reinterpret_cast<f4 *>(po.f32 + idx));
