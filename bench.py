@@ -55,9 +55,10 @@ EVALS = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16x2": 3}
 # size (profiles/*_counters.txt); only for the kernel build the counters were
 # taken on (null after a kernel change).  (config, frames per step): bytes.
 # Config 1: k_fbin_* + k_fast2 + deferred pass (k_fast2 ignores the launch
-# choice).  Config 2's parts follow one another, and lines written back after
-# a dispatch ends are counted in a later one: no per-step figure.
-TRAFFIC = {(1, 32): 510339566}
+# choice).  Config 2: k_bin + the four k_wide parts + deferred pass, for the
+# launch choice of 4 blocks per workgroup only (the (config, frames, blocks
+# per workgroup) key); the 1- and 2-wave choices counted ~40 % more writes.
+TRAFFIC = {(1, 32): 510339566, (2, 32, 4): 462664444}
 
 
 def algorithmic_bytes(fr) -> int:
@@ -371,7 +372,8 @@ def bench_frame(args, torch, binding, synth):
                int8_output=int8,
                roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": TRAFFIC.get((args.config, B)) if args.eval == "fp32" else None,
+                         "traffic": (TRAFFIC.get((args.config, B, tune_b), TRAFFIC.get((args.config, B)))
+                                     if args.eval == "fp32" else None),
                          "kernel": kern + (" (+ deferred pass)" if B > 1 or cfg["block_size"] > 16 else ""),
                          "algorithmic_bytes_per_launch": ab, "launch_ms": 1e3 * t_step,
                          "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs},
