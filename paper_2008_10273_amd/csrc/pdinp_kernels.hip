@@ -1244,6 +1244,7 @@ __device__ __forceinline__ int fast2_class(int K) { return ((K + 4) >> 2) - 1; }
 constexpr int kBinThreads = 256;
 constexpr int kMaxBins = 8 * kMaxSegs;
 constexpr int kF2Threads = 256;                  // k_fast2: 4 waves per workgroup
+constexpr int kScanRun = 8;                      // k_fbin_scan: counts per thread in one round
 constexpr int kF2Waves = kF2Threads / 64;
 constexpr int kF2Items = kF2Waves * kWaveItems;  // 16 blocks per workgroup
 
@@ -1318,11 +1319,10 @@ __global__ __launch_bounds__(kBinThreads) void k_fbin_count(FrameDev f) {
 __global__ __launch_bounds__(kBinThreads) void k_fbin_scan(FrameDev f, int nwg) {
   __shared__ int wsum[kBinThreads / 64];
   const int nb = 8 * f.nq, bin = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  int carry = 0;
-  for (int w0 = 0; w0 < nwg; w0 += kBinThreads) {
-    const int w = w0 + tid;
-    const int v = w < nwg ? f.hist[(long long)w * nb + bin] : 0;
-    int x = v;
+  // Exclusive scan over the workgroups of the 256 values x (one per thread)
+  // plus carry; returns the thread's offset, and the total through tot.
+  auto block_scan = [&](int x, int carry, int &tot) {
+    const int v = x;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const int y = __shfl_up(x, o, 64);
@@ -1330,15 +1330,40 @@ __global__ __launch_bounds__(kBinThreads) void k_fbin_scan(FrameDev f, int nwg) 
     }
     if (lane == 63) wsum[wv] = x;
     __syncthreads();
-    int off = carry, tot = carry;
+    int off = carry;
+    tot = carry;
 #pragma unroll
     for (int k = 0; k < kBinThreads / 64; ++k) {
       off += k < wv ? wsum[k] : 0;
       tot += wsum[k];
     }
-    if (w < nwg) f.hist[(long long)w * nb + bin] = off + x - v;
-    carry = tot;
     __syncthreads();
+    return off + x - v;
+  };
+  int carry = 0;
+  if (nwg <= kScanRun * kBinThreads) {
+    // one round: each thread takes a run of up to kScanRun consecutive
+    // counts, all loaded at once (the counts of a bin are nb ints apart)
+    const int run = (nwg + kBinThreads - 1) / kBinThreads, w0 = tid * run;
+    int v[kScanRun], sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanRun; ++i) {
+      v[i] = (i < run && w0 + i < nwg) ? f.hist[(long long)(w0 + i) * nb + bin] : 0;
+      sum += v[i];
+    }
+    int off = block_scan(sum, 0, carry);
+#pragma unroll
+    for (int i = 0; i < kScanRun; ++i) {
+      if (i < run && w0 + i < nwg) f.hist[(long long)(w0 + i) * nb + bin] = off;
+      off += v[i];
+    }
+  } else {
+    for (int w0 = 0; w0 < nwg; w0 += kBinThreads) {
+      const int w = w0 + tid;
+      const int v = w < nwg ? f.hist[(long long)w * nb + bin] : 0;
+      const int off = block_scan(v, carry, carry);
+      if (w < nwg) f.hist[(long long)w * nb + bin] = off;
+    }
   }
   if (tid == 0) f.counters[kQueueCounters + bin] = carry;
 }
