@@ -1319,8 +1319,9 @@ __global__ __launch_bounds__(kBinThreads) void k_fbin_count(FrameDev f) {
 __global__ __launch_bounds__(kBinThreads) void k_fbin_scan(FrameDev f, int nwg) {
   __shared__ int wsum[kBinThreads / 64];
   const int nb = 8 * f.nq, bin = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  // Exclusive scan over the workgroups of the 256 values x (one per thread)
-  // plus carry; returns the thread's offset, and the total through tot.
+  // Exclusive scan of one value x per thread over the workgroup's 256
+  // threads, starting at carry: returns this thread's offset; tot receives
+  // carry plus the sum of every thread's x.
   auto block_scan = [&](int x, int carry, int &tot) {
     const int v = x;
 #pragma unroll
@@ -1357,7 +1358,7 @@ __global__ __launch_bounds__(kBinThreads) void k_fbin_scan(FrameDev f, int nwg) 
       if (i < run && w0 + i < nwg) f.hist[(long long)(w0 + i) * nb + bin] = off;
       off += v[i];
     }
-  } else {
+  } else {  // more counting workgroups: round by round, 256 counts each
     for (int w0 = 0; w0 < nwg; w0 += kBinThreads) {
       const int w = w0 + tid;
       const int v = w < nwg ? f.hist[(long long)w * nb + bin] : 0;

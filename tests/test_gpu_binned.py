@@ -98,3 +98,30 @@ def test_binned_batch_validation(dec):
     good = [dec.upload(synth.random_frame(W, H, synth.YUV420, b, (0.02, 0.1), seed=7600 + k)) for k in range(n)]
     dec.decode_batch(good, binding.default_params(validate=1))
     assert dec.sync() == 0
+
+
+def test_binned_many_count_workgroups(dec):
+    """32 gray 1032x1024 frames with 8x8 blocks: 65 counting workgroups per
+    frame, 2080 in all, more than the per-bin scan takes in one round (8
+    counts per thread), so the scan goes round by round.  Every frame must
+    equal the same frame decoded alone, bitwise."""
+    from paper_2008_10273_amd import binding
+    W, H, b, n = 1032, 1024, 8, 32
+    nblk = synth.plane_block_counts(W, H, synth.GRAY, b)[0]
+    assert ((nblk + 255) // 256) * n > 8 * 256 and nblk * n >= BINNED_MIN_BLOCKS
+    print(f"case binned b={b} {W}x{H} n={n} (scan rounds)", flush=True)
+    frames = [synth.random_frame(W, H, synth.GRAY, b, (0.02, 0.3), seed=7800 + k) for k in range(4)]
+    params = binding.default_params()
+    alone = []
+    for fr in frames:
+        d = dec.upload(fr)
+        dec.decode(d, params)
+        assert dec.sync() == 0
+        alone.append(d["out"].cpu().numpy())
+    ds = [dec.upload(frames[k % 4]) for k in range(n)]
+    for d in ds:
+        d["out"].zero_()
+    dec.decode_batch(ds, params)
+    assert dec.sync() == 0
+    for k, d in enumerate(ds):
+        np.testing.assert_array_equal(d["out"].cpu().numpy(), alone[k % 4], err_msg=f"frame {k}")
