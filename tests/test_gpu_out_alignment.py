@@ -3,7 +3,7 @@ one element, int8 by one byte): the evaluations store four pixels at a time
 only where the address allows it, so every path must write the same planes
 as into an aligned buffer, bitwise.  Paths: single frames (b = 8, 16, 32),
 a binned batch (b = 16, at least 32768 mask blocks) and a batch of 32 x 32
-blocks (the k_wide parts)."""
+blocks (the k_wide parts); stored-coefficient decodes alike."""
 import numpy as np
 import pytest
 
@@ -65,4 +65,30 @@ def test_unaligned_output_planes(dec, case, i8):
     ref = _decode(dec, [dec.upload(fr) for fr in frames], params, key, 0)
     got = _decode(dec, [dec.upload(fr) for fr in frames], params, key, 1)
     for k, (g, r) in enumerate(zip(got, ref)):
+        np.testing.assert_array_equal(g, r, err_msg=f"frame {k}")
+
+
+@pytest.mark.parametrize("i8", [0, 1])
+@pytest.mark.parametrize("b,W,H,n", [(8, 330, 250, 4), (32, 150, 90, 1)])
+def test_unaligned_output_planes_coef(dec, b, W, H, n, i8):
+    """The stored-coefficient decoder, single frame or batch, into shifted planes."""
+    from paper_2008_10273_amd import binding
+    print(f"case coef b={b} {W}x{H} n={n} int8={i8}", flush=True)
+    frames = [synth.random_frame(W, H, synth.YUV420, b, (0.02, 0.2), seed=8200 + 10 * b + k) for k in range(n)]
+    inputs = [synth.coef_inputs(fr, 20 + k) for k, fr in enumerate(frames)]
+    qp = binding.coef_params((0.25, 0.5, 0.375), 0.5)
+    params = binding.default_params(out_int8=i8)
+    key = "out_i8" if i8 else "out"
+    res = []
+    for shift in (0, 1):
+        ds = [dec.upload_coef(fr, q, c) for fr, (q, c) in zip(frames, inputs)]
+        for d in ds:
+            d[key] = _shifted(d[key], shift) if shift else torch.zeros_like(d[key])
+        if n == 1:
+            dec.decode_coef(ds[0], qp, params)
+        else:
+            dec.decode_coef_batch(ds, qp, params)
+        assert dec.sync() == 0
+        res.append([d[key].cpu().numpy() for d in ds])
+    for k, (g, r) in enumerate(zip(res[1], res[0])):
         np.testing.assert_array_equal(g, r, err_msg=f"frame {k}")
