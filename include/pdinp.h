@@ -135,8 +135,8 @@ int decode_residual(pdi_ctx *ctx, const pdi_frame *frame, const pdi_mask *mask,
  * only.  More blocks per launch keep more waves in flight, so a batch is
  * the throughput form of decode_residual; each frame's result is the same
  * as when decoded alone.  With 32x32 blocks (n > 1, outside graph capture)
- * the batch's four wave-per-block launches run side by side on three
- * streams the context creates on first use: they are forked from `stream`
+ * the batch's four wave-per-block launches run side by side on `stream`
+ * and two streams the context creates on first use, forked from `stream`
  * and joined back to it with events, so work queued on `stream` afterwards
  * (and pdi_sync) sees the whole decode; batches of different caller streams
  * share those streams.  Errors as for decode_residual. */

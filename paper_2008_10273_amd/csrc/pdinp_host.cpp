@@ -831,9 +831,11 @@ static int decode_impl(pdi_ctx *c, int n, const pdi_frame *frame, const pdi_mask
       if (!c->wf_ready) {
         pdi::WideFork w = {};
         hipError_t ce = hipSuccess;
-        for (int i = 0; i < 3 && ce == hipSuccess; ++i) ce = hipStreamCreateWithFlags(&w.aux[i], hipStreamNonBlocking);
+        for (int i = 0; i < pdi::kWideAux && ce == hipSuccess; ++i)
+          ce = hipStreamCreateWithFlags(&w.aux[i], hipStreamNonBlocking);
         if (ce == hipSuccess) ce = hipEventCreateWithFlags(&w.fork, hipEventDisableTiming);
-        for (int i = 0; i < 3 && ce == hipSuccess; ++i) ce = hipEventCreateWithFlags(&w.join[i], hipEventDisableTiming);
+        for (int i = 0; i < pdi::kWideAux && ce == hipSuccess; ++i)
+          ce = hipEventCreateWithFlags(&w.join[i], hipEventDisableTiming);
         if (ce != hipSuccess) {
           destroy_wide_fork(w);
           return hip_fail(c, ce, "streams of the wave-per-block parts");

@@ -190,13 +190,15 @@ hipError_t launch_fast(const FrameDev &f, hipStream_t stream);
 // Binned residual decode for b <= 16 (k_fbin + k_fast2): f.q / f.qof / f.nq
 // describe one queue per block shape, f.fast_wgs the k_fast2 grid.
 hipError_t launch_fast2(const FrameDev &f, hipStream_t stream);
-// The parts of a batched residual decode by k_wide on four streams: parts 1-3
-// on aux[0..2], forked from the caller's stream after the binning and joined
-// back to it with the events, part 4 on the caller's stream.
+// The parts of a batched residual decode by k_wide on three streams: part 1
+// on aux[0], parts 2 and then 3 on aux[1], forked from the caller's stream
+// after the binning and joined back to it with the events, part 4 on the
+// caller's stream.
+constexpr int kWideAux = 2;
 struct WideFork {
-  hipStream_t aux[3];
+  hipStream_t aux[kWideAux];
   hipEvent_t fork;
-  hipEvent_t join[3];
+  hipEvent_t join[kWideAux];
 };
 // binning kernel + k_wide (fork: null keeps every part on `stream`)
 hipError_t launch_wide(const FrameDev &f, hipStream_t stream, const WideFork *fork = nullptr);

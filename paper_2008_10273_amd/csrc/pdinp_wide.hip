@@ -692,14 +692,16 @@ hipError_t launch_wide(const FrameDev &f, hipStream_t stream, const WideFork *fo
     if (f.nframes > 1) {
       // batches: one launch per bin, the large-K bins first (longest solves
       // start first).  With a fork the parts run side by side, so the tail of
-      // one (the few K >= 96 blocks at 2 waves per SIMD) overlaps the others.
-      // A single frame keeps one launch: with few blocks more launches would
-      // only add their latency.
-      hipStream_t st[4] = {stream, stream, stream, stream};
+      // one (the few K >= 96 blocks at 2 waves per SIMD) overlaps the others:
+      // part 1 on one stream, parts 2 and then 3 on another, part 4 on the
+      // caller's (all four at once delays part 1, the longest).  A single
+      // frame keeps one launch: with few blocks more launches would only add
+      // their latency.
+      hipStream_t st[kWideAux] = {stream, stream};
       hipError_t e = hipSuccess;
       if (fork) {
         e = hipEventRecord(fork->fork, stream);
-        for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+        for (int i = 0; i < kWideAux && e == hipSuccess; ++i) {
           e = hipStreamWaitEvent(fork->aux[i], fork->fork, 0);
           st[i] = fork->aux[i];
         }
@@ -707,10 +709,10 @@ hipError_t launch_wide(const FrameDev &f, hipStream_t stream, const WideFork *fo
       }
       e = launch_wide_part<1>(f, grid, lds, st[0]);
       if (e == hipSuccess) e = launch_wide_part<2>(f, grid, lds, st[1]);
-      if (e == hipSuccess) e = launch_wide_part<3>(f, grid, lds, st[2]);
-      if (e == hipSuccess) e = launch_wide_part<4>(f, grid, lds, st[3]);
+      if (e == hipSuccess) e = launch_wide_part<3>(f, grid, lds, st[1]);
+      if (e == hipSuccess) e = launch_wide_part<4>(f, grid, lds, stream);
       if (fork) {  // join (also after a failed launch: the caller's stream waits for what was queued)
-        for (int i = 0; i < 3; ++i) {
+        for (int i = 0; i < kWideAux; ++i) {
           const hipError_t r = hipEventRecord(fork->join[i], fork->aux[i]);
           const hipError_t w = r == hipSuccess ? hipStreamWaitEvent(stream, fork->join[i], 0) : r;
           if (e == hipSuccess) e = w;
