@@ -58,7 +58,8 @@ EVALS = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16x2": 3}
 # choice).  Config 2: k_bin + the four k_wide parts + deferred pass, for the
 # launch choice of 4 blocks per workgroup only (the (config, frames, blocks
 # per workgroup) key); the 1- and 2-wave choices counted ~40 % more writes.
-TRAFFIC = {(1, 32): 510359722, (2, 32, 4): 462664444}
+# Config 5: k_fast in coefficient mode + k_coef_general (no launch choice).
+TRAFFIC = {(1, 32): 510359722, (2, 32, 4): 462664444, (5, 32): 463789739}
 
 
 def algorithmic_bytes(fr) -> int:
@@ -462,7 +463,8 @@ def bench_coef(args, torch, binding, synth):
                            "mean": float(lat.mean()), "of": "one frame decoded alone"},
                error_vs_oracle=err,
                roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC.get((5, B, 0)),
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": TRAFFIC.get((5, B)) if args.eval == "fp32" else None,
                          "kernel": "k_fast (coefficient mode) + k_coef_general",
                          "algorithmic_bytes_per_launch": ab, "launch_ms": 1e3 * t_step,
                          "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs},
